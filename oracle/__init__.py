@@ -1,0 +1,36 @@
+"""Plain FP64 CPU oracle of the space-time Vanka-GMG-FGMRES hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check of the entry module
+and the CPU-baseline leg of the benchmark may import this package.  It shares
+no code with the HIP library: it reads the same level data (block-sparse
+space-time Jacobians, cell->DoF maps, prolongations) and computes everything
+again with numpy / scipy, slowly and literally.
+
+Functions and what pins them (tests marked "not gpu"):
+  spacetime_matrix, cell_dofs       - pinned by the patch test of the assembly
+                                      (J U = F for exact discrete data)
+  cell_inverse, build_inverses      - pinned: J_T^-1 J_T = I to 1e-12, every
+                                      cell of every smoothed level
+  vanka_sweep                       - pinned: one cell, omega = 1 -> exact solve;
+                                      disjoint cells -> exact solve; a hand-derived
+                                      two-cell overwrite example
+  vcycle                            - pinned: one level = direct solve; no smoothing
+                                      = coarse-grid correction P J_c^-1 P^T r;
+                                      linearity in r
+  fgmres                            - pinned: identity preconditioner reproduces
+                                      scipy's GMRES residual history; minimal
+                                      residual over the explicit Krylov space;
+                                      restart >= n converges in <= n steps
+  The cell loop order and the "last update wins" reading (owner = highest
+  cell index) are readings of the paper, not fixed by it: parity unpinned by
+  the paper for that choice; the hand-derived example pins the implementation
+  of the reading.
+"""
+from .smoother import (spacetime_matrix, cell_dofs, extract_cell_matrix, cell_inverse,
+                       build_inverses, residual, vanka_sweep, OracleLevel, prepare_levels)
+from .multigrid import vcycle, coarse_inverse
+from .krylov import fgmres
+
+__all__ = ["spacetime_matrix", "cell_dofs", "extract_cell_matrix", "cell_inverse",
+           "build_inverses", "residual", "vanka_sweep", "OracleLevel", "prepare_levels",
+           "vcycle", "coarse_inverse", "fgmres"]
