@@ -1,0 +1,225 @@
+/*
+ * stv.h - C ABI of the MI355X space-time Vanka multigrid library.
+ *
+ * The library solves J d = r (the linear system of one Newton or Oseen step of
+ * the dG(k)-in-time, Q2/P1disc-in-space discretisation of the incompressible
+ * Navier-Stokes equations, Section 4.1 eq. (4.1) of Anselmann & Bause,
+ * "A geometric multigrid method for space-time finite element discretizations
+ * of the Navier-Stokes equations and its application to 3d flow simulation")
+ * by flexible GMRES preconditioned with a geometric multigrid V-cycle
+ * (Algorithm 4.1) whose smoother is the cell-based space-time Vanka operator
+ * (Section 4.2, eq. (4.6), with the damping of Section 5.3).
+ *
+ * Conventions shared by every entry point
+ *   - Status: every int-returning call returns STV_OK (0) or a negative code
+ *     below; the text of the last error of a context is stv_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Levels: index 0 is the coarsest level (the paper's g = 1, solved
+ *     directly); index n_levels-1 is the finest (g = G).
+ *   - Space-time vectors are FP64, time-inner: entry s*(k+1) + l holds
+ *     spatial DoF s at temporal DoF l.  Vectors passed to the compute calls
+ *     are DEVICE pointers owned by the caller; the calls are asynchronous on
+ *     the context's stream unless stated otherwise.
+ *   - Host arrays handed to stv_set_hierarchy are deep-copied; the caller may
+ *     free them when the call returns.
+ *   - One context serves one stream; calls on one context must not overlap
+ *     from several host threads.
+ */
+#ifndef STV_H
+#define STV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define STV_OK 0
+#define STV_EINVAL (-1)     /* invalid argument or malformed hierarchy      */
+#define STV_ENOMEM (-2)     /* device or host allocation failed             */
+#define STV_EHIP (-3)       /* a HIP runtime call failed                    */
+#define STV_ESTATE (-4)     /* call made in the wrong state                 */
+#define STV_ESINGULAR (-5)  /* zero pivot in a local or the coarse factor   */
+#define STV_ENOCONV (-6)    /* GMRES hit max_it without reaching rtol       */
+#define STV_ENUMERIC (-7)   /* NaN or Inf met in the Krylov process         */
+
+/* ---- storage of the pre-computed cell inverses (Section 4.3) ---- */
+#define STV_F64 0           /* stored and applied in FP64                   */
+#define STV_F32 1           /* factorised in FP64, stored in FP32           */
+#define STV_STORE_FULL 2    /* flag: keep every row of J_T^-1 (default keeps
+                               only the rows of DoFs the cell owns, which are
+                               the only ones the last-writer sweep uses)    */
+
+/* ---- how a sweep combines the corrections of cells sharing a DoF ---- */
+#define STV_LAST_WRITER 0   /* DoF takes the correction of the last cell in
+                               loop order that contains it (Section 4.2)     */
+#define STV_POU 1           /* average of the cells' corrections             */
+#define STV_ADDITIVE 2      /* sum of the cells' corrections                 */
+
+typedef struct stv_ctx stv_ctx;
+
+/*
+ * One level of the hierarchy (all pointers HOST, deep-copied).
+ *   n_sdofs     spatial DoFs N_s of the level (space-time size N_s*(k+1)).
+ *   bsr_rowptr  [n_sdofs+1] block-row pointers, bsr_rowptr[0] = 0.
+ *   bsr_col     [nnzb] spatial column of each block, strictly increasing per row.
+ *   bsr_val     [nnzb*(k+1)*(k+1)] block (s, s') row-major: entry i*(k+1)+l is
+ *               J[(s, i), (s', l)] (test time DoF i, trial time DoF l).
+ *   n_cells     cells of the level, in smoother loop order.
+ *   n_ls        spatial DoFs per cell: dim*3^dim + dim + 1 (21 in 2d, 85 in 3d).
+ *   cell_sdofs  [n_cells*n_ls] global spatial DoFs of each cell in local order:
+ *               velocity component-major over the lexicographic Q2 nodes, then
+ *               the dim+1 pressure modes (the spatial part of eq. (4.4)).
+ *   P_*         spatial prolongation from level-1 to this level, CSR with
+ *               n_sdofs rows and the coarser level's n_sdofs columns (identity
+ *               in time).  Ignored (may be NULL) on level 0.
+ * Every pair of DoFs sharing a cell must be present in the block pattern.
+ */
+typedef struct stv_level {
+  int32_t n_sdofs;
+  const int32_t* bsr_rowptr;
+  const int32_t* bsr_col;
+  const double* bsr_val;
+  int64_t nnzb;
+  int32_t n_cells;
+  int32_t n_ls;
+  const int32_t* cell_sdofs;
+  const int32_t* P_rowptr;
+  const int32_t* P_col;
+  const double* P_val;
+  int64_t P_nnz;
+} stv_level;
+
+/* V(nu1, nu2) cycle parameters (Algorithm 4.1; damping omega of Section 5.3). */
+typedef struct stv_mg_params {
+  int32_t nu1;      /* pre-smoothing sweeps, >= 0                */
+  int32_t nu2;      /* post-smoothing sweeps, >= 0               */
+  double omega;     /* damping of every sweep, > 0               */
+  int32_t mode;     /* STV_LAST_WRITER, STV_POU or STV_ADDITIVE  */
+} stv_mg_params;
+
+/* Flexible GMRES(restart) parameters. */
+typedef struct stv_gmres_params {
+  int32_t restart;      /* Krylov dimension per cycle, 1..256                  */
+  int32_t max_it;       /* total Arnoldi steps allowed                         */
+  double rtol;          /* stop when ||b - J x||_2 <= rtol ||b||_2             */
+  int32_t use_x0;       /* 1: start from the x passed in; 0: from x = 0        */
+  int32_t fixed_iters;  /* > 0: run exactly this many steps, ignore rtol       */
+  stv_mg_params mg;     /* preconditioner                                     */
+} stv_gmres_params;
+
+/* Results of stv_gmres_solve.  history (optional, caller-owned host array of
+ * history_cap doubles) receives ||r_j|| / ||b|| for j = 0 .. iters. */
+typedef struct stv_gmres_info {
+  int32_t iters;
+  int32_t restarts;
+  int32_t converged;
+  double true_relres;
+  double* history;
+  int32_t history_cap;
+  int32_t history_len;
+} stv_gmres_info;
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The caller owns *out until
+ * stv_destroy.  Errors: STV_EINVAL, STV_EHIP, STV_ENOMEM. */
+int stv_create(stv_ctx** out, int device, void* hip_stream);
+
+/* Free the context and all device memory it holds.  NULL is allowed. */
+void stv_destroy(stv_ctx* ctx);
+
+/* Text of the last error raised on this context ("" if none).  ctx may be
+ * NULL, which returns the text of the last failed stv_create. */
+const char* stv_last_error(const stv_ctx* ctx);
+
+/* Host-only validation of a hierarchy (the checks stv_set_hierarchy runs
+ * before touching the device): sizes, sorted unique block columns, cell DoFs
+ * in range, every cell pair present in the pattern, prolongation shapes.
+ * Writes a message naming the offending field into err (errlen bytes). */
+int stv_validate_hierarchy(int n_levels, int dim, int k, const stv_level* lv,
+                           char* err, size_t errlen);
+
+/* Upload a hierarchy (levels 0..n_levels-1, 1 <= n_levels <= 16, dim 2 or 3,
+ * 0 <= k <= 3).  Builds on the host the per-cell lists of owned DoFs (the
+ * owner of a DoF is the last cell in loop order that contains it) and the
+ * transposed prolongations.  Replaces any previous hierarchy and drops the
+ * inverses.  Synchronises the stream.  Errors: STV_EINVAL, STV_ENOMEM, STV_EHIP. */
+int stv_set_hierarchy(stv_ctx* ctx, int n_levels, int dim, int k, const stv_level* lv);
+
+/* Extract every local Jacobian J_T (the submatrix of the level matrix on the
+ * cell's DoFs, Section 4.2) on levels >= 1, invert it by Gauss-Jordan
+ * elimination with partial pivoting in FP64 and store it (Section 4.3);
+ * factor the coarsest matrix densely (its explicit inverse) in FP64.
+ * storage = STV_F64 or STV_F32, optionally | STV_STORE_FULL.  Synchronises
+ * the stream.  On a zero pivot returns STV_ESINGULAR and, if non-NULL, sets
+ * *bad_level and *bad_cell (bad_cell = -1 for the coarse matrix).
+ * Errors: STV_ESTATE (no hierarchy), STV_EINVAL, STV_ENOMEM, STV_EHIP. */
+int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_cell);
+
+/* out = r - J_level d.  r may be NULL (then out = -J d).  Device pointers,
+ * N_s*(k+1) doubles each; out must not alias r or d. */
+int stv_residual(stv_ctx* ctx, int level, const double* r, const double* d, double* out);
+
+/* n_sweeps damped Vanka sweeps on level >= 1, in place on d:
+ *   rho = r - J d (once per sweep, from the pre-sweep iterate);
+ *   for every cell T: c_T = omega J_T^-1 rho_T;
+ *   d_j += c_T(j) with T chosen per mode (STV_LAST_WRITER: the owner of j).
+ * eq. (4.6) with the damping of Section 5.3.  STV_POU and STV_ADDITIVE need
+ * inverses stored with STV_STORE_FULL.  Errors: STV_ESTATE (no inverses or
+ * incompatible storage), STV_EINVAL. */
+int stv_vanka_sweep(stv_ctx* ctx, int level, const double* r, double* d,
+                    int n_sweeps, double omega, int mode);
+
+/* r_c = P^T rho (restriction to level-1; the transpose of the prolongation,
+ * Section 4.1).  level >= 1; rho has the size of `level`, r_c of level-1. */
+int stv_restrict(stv_ctx* ctx, int level, const double* rho, double* r_c);
+
+/* d += P d_c (prolongation of a level-1 correction to `level` >= 1). */
+int stv_prolongate_add(stv_ctx* ctx, int level, const double* d_c, double* d);
+
+/* d = J_0^-1 r on the coarsest level (the direct coarse solve). */
+int stv_coarse_solve(stv_ctx* ctx, const double* r, double* d);
+
+/* d = MG(r): one V(nu1, nu2) cycle on the finest level from d = 0
+ * (Algorithm 4.1 read with the residual r_g - J_g d_g, the recursion result
+ * assigned to d_{g-1}, prolongation of d_{g-1}, post-smoothing against the
+ * original r_g).  r and d are finest-level device vectors, d must not alias r. */
+int stv_vcycle(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p);
+
+/* Solve J x = b on the finest level by right-preconditioned flexible GMRES
+ * (x = x0 + Z y with z_j = MG(v_j)), FP64 throughout.  A cycle ends when the
+ * rotated residual estimate reaches rtol ||b|| or after `restart` steps; the
+ * iterate is updated and the true residual decides convergence.  b and x are
+ * device vectors.  Synchronises the stream.  Returns STV_ENOCONV (x holds the
+ * last iterate) or STV_ENUMERIC (NaN/Inf) on failure; info is filled in all
+ * cases where it is non-NULL. */
+int stv_gmres_solve(stv_ctx* ctx, const double* b, double* x,
+                    const stv_gmres_params* p, stv_gmres_info* info);
+
+/* Copy the stored inverse of cell `cell` on `level` (>= 1) into the host array
+ * out[n_loc*n_loc], row-major in the cell-local order of eq. (4.4)
+ * (time-major: index l*n_ls + alpha), converted to FP64.  Rows not stored
+ * (the default owned-rows storage) are written as NaN.  Synchronises. */
+int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out);
+
+/* Sizes of a level: spatial DoFs, cells, local DoFs per cell (n_loc), stored
+ * inverse bytes of the level (0 before stv_build_cell_inverses). */
+int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
+                   int64_t* n_loc, int64_t* inverse_bytes);
+
+/* Per-kernel timing with HIP events on the context's stream.
+ * stv_set_timing(ctx, 1) starts recording (and clears the counters);
+ * stv_kernel_stats returns launches and total milliseconds of one kernel
+ * class: 0 = Vanka cell sweep, 1 = level residual, 2 = transfers,
+ * 3 = coarse apply, 4 = Krylov vector kernels, 5 = cell inverse build,
+ * 6 = coarse factorisation.  Synchronises the stream. */
+int stv_set_timing(stv_ctx* ctx, int on);
+int stv_kernel_stats(stv_ctx* ctx, int kernel_class, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STV_H */

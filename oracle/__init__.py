@@ -11,6 +11,9 @@ Functions and what pins them (tests marked "not gpu"):
                                       (J U = F for exact discrete data)
   cell_inverse, build_inverses      - pinned: J_T^-1 J_T = I to 1e-12, every
                                       cell of every smoothed level
+  vanka_sweep_combined              - pinned: disjoint cells -> exact solve for both
+                                      readings; hand-derived two-cell example
+  extract_cell_matrix_blocks        - pinned: equals extract_cell_matrix on C1
   vanka_sweep                       - pinned: one cell, omega = 1 -> exact solve;
                                       disjoint cells -> exact solve; a hand-derived
                                       two-cell overwrite example
@@ -27,10 +30,12 @@ Functions and what pins them (tests marked "not gpu"):
   of the reading.
 """
 from .smoother import (spacetime_matrix, cell_dofs, extract_cell_matrix, cell_inverse,
-                       build_inverses, residual, vanka_sweep, OracleLevel, prepare_levels)
+                       build_inverses, residual, vanka_sweep, vanka_sweep_combined,
+                       extract_cell_matrix_blocks, owner_cells, OracleLevel, prepare_levels)
 from .multigrid import vcycle, coarse_inverse
 from .krylov import fgmres
 
 __all__ = ["spacetime_matrix", "cell_dofs", "extract_cell_matrix", "cell_inverse",
-           "build_inverses", "residual", "vanka_sweep", "OracleLevel", "prepare_levels",
+           "build_inverses", "residual", "vanka_sweep", "vanka_sweep_combined",
+           "extract_cell_matrix_blocks", "owner_cells", "OracleLevel", "prepare_levels",
            "vcycle", "coarse_inverse", "fgmres"]

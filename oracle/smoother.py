@@ -117,3 +117,44 @@ def vanka_sweep(L: OracleLevel, r, d, omega: float):
         c = L.inv[T] @ rho[idx]
         d_new[idx] = d_old[idx] + omega * c
     return d_new
+
+
+def vanka_sweep_combined(L: OracleLevel, r, d, omega: float, average: bool):
+    """Alternative readings of the update of shared DoFs (not the paper's):
+    every cell adds omega J_T^-1 rho_T to its DoFs; with average=True the sum
+    at a DoF is divided by the number of cells containing it."""
+    rho = residual(L.J, r, d)
+    acc = np.zeros_like(d)
+    mult = np.zeros_like(d)
+    for T in range(L.dofs.shape[0]):
+        idx = L.dofs[T]
+        acc[idx] += omega * (L.inv[T] @ rho[idx])
+        mult[idx] += 1.0
+    return d + (acc / mult if average else acc)
+
+
+def extract_cell_matrix_blocks(rowptr, col, val, b: int, sdofs) -> np.ndarray:
+    """J_T read directly from the block rows of the level matrix (for single
+    cells of large levels): entry (l*n_ls + a, m*n_ls + c) = block(sd[a], sd[c])[l, m]."""
+    nls = len(sdofs)
+    val = np.asarray(val).reshape(-1, b, b)
+    out = np.zeros((b * nls, b * nls))
+    for a, s in enumerate(sdofs):
+        lo, hi = int(rowptr[s]), int(rowptr[s + 1])
+        cols = np.asarray(col[lo:hi])
+        for c, t in enumerate(sdofs):
+            q = lo + int(np.searchsorted(cols, t))
+            assert q < hi and col[q] == t, "cell pair missing from the block pattern"
+            for l in range(b):
+                for m in range(b):
+                    out[l * nls + a, m * nls + c] = val[q, l, m]
+    return out
+
+
+def owner_cells(cell_sdofs: np.ndarray, n_sdofs: int) -> np.ndarray:
+    """Cell whose update a spatial DoF keeps in the literal loop: the last one
+    (highest index) that contains it."""
+    own = np.full(n_sdofs, -1, dtype=np.int64)
+    for T in range(cell_sdofs.shape[0]):
+        own[cell_sdofs[T]] = T
+    return own

@@ -1,0 +1,273 @@
+"""MI355X space-time Vanka multigrid: Python binding of the C ABI in include/stv.h.
+
+Argument marshalling only: every step of the solver runs in the HIP library
+(_lib/libstv.so).  Device vectors are torch float64 CUDA tensors; the library
+launches on the stream current when the Solver is created.  Importing this
+module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libstv.so")
+
+STV_OK, STV_EINVAL, STV_ENOMEM, STV_EHIP, STV_ESTATE, STV_ESINGULAR, STV_ENOCONV, STV_ENUMERIC = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STV_F64, STV_F32, STV_STORE_FULL = 0, 1, 2
+STV_LAST_WRITER, STV_POU, STV_ADDITIVE = 0, 1, 2
+KERNEL_CLASSES = {"sweep": 0, "residual": 1, "transfer": 2, "coarse": 3, "krylov": 4,
+                  "inverse": 5, "coarse_factor": 6}
+_ERRNAMES = {STV_EINVAL: "STV_EINVAL", STV_ENOMEM: "STV_ENOMEM", STV_EHIP: "STV_EHIP",
+             STV_ESTATE: "STV_ESTATE", STV_ESINGULAR: "STV_ESINGULAR",
+             STV_ENOCONV: "STV_ENOCONV", STV_ENUMERIC: "STV_ENUMERIC"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                      "(run paper_2107_10561_amd/build.py or __graft_entry__.build())")
+
+
+class StvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Level(ctypes.Structure):
+    _fields_ = [("n_sdofs", ctypes.c_int32), ("bsr_rowptr", ctypes.c_void_p),
+                ("bsr_col", ctypes.c_void_p), ("bsr_val", ctypes.c_void_p),
+                ("nnzb", ctypes.c_int64), ("n_cells", ctypes.c_int32), ("n_ls", ctypes.c_int32),
+                ("cell_sdofs", ctypes.c_void_p), ("P_rowptr", ctypes.c_void_p),
+                ("P_col", ctypes.c_void_p), ("P_val", ctypes.c_void_p), ("P_nnz", ctypes.c_int64)]
+
+
+class _MG(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("mode", ctypes.c_int32)]
+
+
+class _GP(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_it", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("use_x0", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("mg", _MG)]
+
+
+class _GI(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("true_relres", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
+                ("history_len", ctypes.c_int32)]
+
+
+def _load():
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    I64P = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "stv_create": (I, [ctypes.POINTER(P), I, P]),
+        "stv_destroy": (None, [P]),
+        "stv_last_error": (ctypes.c_char_p, [P]),
+        "stv_validate_hierarchy": (I, [I, I, I, ctypes.POINTER(_Level), ctypes.c_char_p, ctypes.c_size_t]),
+        "stv_set_hierarchy": (I, [P, I, I, I, ctypes.POINTER(_Level)]),
+        "stv_build_cell_inverses": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "stv_residual": (I, [P, I, P, P, P]),
+        "stv_vanka_sweep": (I, [P, I, P, P, I, D, I]),
+        "stv_restrict": (I, [P, I, P, P]),
+        "stv_prolongate_add": (I, [P, I, P, P]),
+        "stv_coarse_solve": (I, [P, P, P]),
+        "stv_vcycle": (I, [P, P, P, ctypes.POINTER(_MG)]),
+        "stv_gmres_solve": (I, [P, P, P, ctypes.POINTER(_GP), ctypes.POINTER(_GI)]),
+        "stv_get_cell_inverse": (I, [P, I, I, P]),
+        "stv_level_info": (I, [P, I, I64P, I64P, I64P, I64P]),
+        "stv_set_timing": (I, [P, I]),
+        "stv_kernel_stats": (I, [P, I, I64P, ctypes.POINTER(D)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib = _load()
+EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarchy",
+            "stv_set_hierarchy", "stv_build_cell_inverses", "stv_residual", "stv_vanka_sweep",
+            "stv_restrict", "stv_prolongate_add", "stv_coarse_solve", "stv_vcycle",
+            "stv_gmres_solve", "stv_get_cell_inverse", "stv_level_info", "stv_set_timing",
+            "stv_kernel_stats")
+
+
+def library():
+    return _lib
+
+
+def _get(L, key):
+    return L[key] if isinstance(L, dict) else getattr(L, key)
+
+
+def _marshal_levels(levels):
+    """ABI level structs from generator levels (dicts or objects with n_sdofs,
+    rowptr, col, val, cell_sdofs, P); returns (array, keepalive)."""
+    keep = []
+    arr = (_Level * len(levels))()
+    for g, L in enumerate(levels):
+        rp = np.ascontiguousarray(_get(L, "rowptr"), dtype=np.int32)
+        col = np.ascontiguousarray(_get(L, "col"), dtype=np.int32)
+        val = np.ascontiguousarray(_get(L, "val"), dtype=np.float64).reshape(-1)
+        csd = np.ascontiguousarray(_get(L, "cell_sdofs"), dtype=np.int32)
+        keep += [rp, col, val, csd]
+        s = arr[g]
+        s.n_sdofs = int(_get(L, "n_sdofs"))
+        s.bsr_rowptr, s.bsr_col, s.bsr_val = rp.ctypes.data, col.ctypes.data, val.ctypes.data
+        s.nnzb = int(col.shape[0])
+        s.n_cells = int(csd.shape[0])
+        s.n_ls = int(csd.shape[1]) if csd.ndim == 2 else 0
+        s.cell_sdofs = csd.ctypes.data
+        Pt = _get(L, "P")
+        if Pt is not None:
+            prp = np.ascontiguousarray(Pt[0], dtype=np.int32)
+            pcol = np.ascontiguousarray(Pt[1], dtype=np.int32)
+            pval = np.ascontiguousarray(Pt[2], dtype=np.float64)
+            keep += [prp, pcol, pval]
+            s.P_rowptr, s.P_col, s.P_val = prp.ctypes.data, pcol.ctypes.data, pval.ctypes.data
+            s.P_nnz = int(pcol.shape[0])
+        else:
+            s.P_rowptr = s.P_col = s.P_val = None
+            s.P_nnz = 0
+    return arr, keep
+
+
+def validate_hierarchy(levels, dim: int, k: int):
+    """Host-only validation (no device needed).  Returns (status, message)."""
+    arr, keep = _marshal_levels(levels)
+    buf = ctypes.create_string_buffer(512)
+    rc = _lib.stv_validate_hierarchy(len(levels), dim, k, arr, buf, 512)
+    return rc, buf.value.decode()
+
+
+class Solver:
+    """One library context on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = _lib.stv_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != STV_OK:
+            raise StvError(rc, _lib.stv_last_error(None).decode())
+        self._h = h
+        self.dim = self.k = self.b = None
+        self.n_st = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.stv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != STV_OK:
+            raise StvError(rc, _lib.stv_last_error(self._h).decode())
+        return rc
+
+    def _vec(self, t, level, name):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise ValueError(f"{name} must be a float64 CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != self.n_st[level]:
+            raise ValueError(f"{name} has {t.numel()} entries, level {level} needs {self.n_st[level]}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_hierarchy(self, levels, dim: int, k: int):
+        arr, keep = _marshal_levels(levels)
+        self._check(_lib.stv_set_hierarchy(self._h, len(levels), dim, k, arr))
+        self.dim, self.k, self.b = dim, k, k + 1
+        self.n_st = [int(_get(L, "n_sdofs")) * (k + 1) for L in levels]
+        self.n_levels = len(levels)
+
+    def build_cell_inverses(self, fp32: bool = False, full: bool = False):
+        bl, bc = ctypes.c_int(-1), ctypes.c_int(-1)
+        storage = (STV_F32 if fp32 else STV_F64) | (STV_STORE_FULL if full else 0)
+        rc = _lib.stv_build_cell_inverses(self._h, storage, ctypes.byref(bl), ctypes.byref(bc))
+        if rc == STV_ESINGULAR:
+            err = StvError(rc, _lib.stv_last_error(self._h).decode())
+            err.level, err.cell = bl.value, bc.value
+            raise err
+        self._check(rc)
+
+    def residual(self, level, r, d, out):
+        rp = self._vec(r, level, "r") if r is not None else None
+        self._check(_lib.stv_residual(self._h, level, rp, self._vec(d, level, "d"),
+                                      self._vec(out, level, "out")))
+
+    def vanka_sweep(self, level, r, d, n_sweeps=1, omega=0.7, mode=STV_LAST_WRITER):
+        self._check(_lib.stv_vanka_sweep(self._h, level, self._vec(r, level, "r"),
+                                         self._vec(d, level, "d"), n_sweeps, omega, mode))
+
+    def restrict(self, level, rho, r_c):
+        self._check(_lib.stv_restrict(self._h, level, self._vec(rho, level, "rho"),
+                                      self._vec(r_c, level - 1, "r_c")))
+
+    def prolongate_add(self, level, d_c, d):
+        self._check(_lib.stv_prolongate_add(self._h, level, self._vec(d_c, level - 1, "d_c"),
+                                            self._vec(d, level, "d")))
+
+    def coarse_solve(self, r, d):
+        self._check(_lib.stv_coarse_solve(self._h, self._vec(r, 0, "r"), self._vec(d, 0, "d")))
+
+    def vcycle(self, r, d, nu1=2, nu2=2, omega=0.7, mode=STV_LAST_WRITER):
+        top = self.n_levels - 1
+        mg = _MG(nu1, nu2, omega, mode)
+        self._check(_lib.stv_vcycle(self._h, self._vec(r, top, "r"), self._vec(d, top, "d"),
+                                    ctypes.byref(mg)))
+
+    def gmres_solve(self, b, x, restart=30, max_it=1000, rtol=1e-8, use_x0=False,
+                    fixed_iters=0, nu1=2, nu2=2, omega=0.7, mode=STV_LAST_WRITER,
+                    raise_on_noconv=True):
+        top = self.n_levels - 1
+        gp = _GP(restart, max_it, rtol, int(use_x0), fixed_iters, _MG(nu1, nu2, omega, mode))
+        cap = max_it + 2 if fixed_iters == 0 else fixed_iters + 2
+        hist = (ctypes.c_double * cap)()
+        gi = _GI(0, 0, 0, 0.0, hist, cap, 0)
+        rc = _lib.stv_gmres_solve(self._h, self._vec(b, top, "b"), self._vec(x, top, "x"),
+                                  ctypes.byref(gp), ctypes.byref(gi))
+        info = dict(iters=gi.iters, restarts=gi.restarts, converged=bool(gi.converged),
+                    true_relres=gi.true_relres, history=list(hist[:gi.history_len]), status=rc)
+        if rc != STV_OK and (rc != STV_ENOCONV or raise_on_noconv):
+            self._check(rc)
+        return info
+
+    def get_cell_inverse(self, level, cell):
+        info = self.level_info(level)
+        n = info["n_loc"]
+        out = np.empty((n, n), dtype=np.float64)
+        self._check(_lib.stv_get_cell_inverse(self._h, level, cell, out.ctypes.data))
+        return out
+
+    def level_info(self, level):
+        a, b, c, d = (ctypes.c_int64() for _ in range(4))
+        self._check(_lib.stv_level_info(self._h, level, ctypes.byref(a), ctypes.byref(b),
+                                        ctypes.byref(c), ctypes.byref(d)))
+        return dict(n_sdofs=a.value, n_cells=b.value, n_loc=c.value, inverse_bytes=d.value)
+
+    def set_timing(self, on: bool):
+        self._check(_lib.stv_set_timing(self._h, int(on)))
+
+    def kernel_stats(self, name: str):
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        self._check(_lib.stv_kernel_stats(self._h, KERNEL_CLASSES[name], ctypes.byref(n),
+                                          ctypes.byref(ms)))
+        return n.value, ms.value

@@ -1,0 +1,130 @@
+// Internal declarations of the space-time Vanka multigrid library: device
+// data of a level, the context, and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stv.h"
+
+namespace stv {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxB = 4;             // k <= 3
+constexpr int kMaxRestart = 256;
+constexpr int kDotBlocks = 1024;     // partial sums per Krylov reduction
+
+enum KernelClass {
+  KC_SWEEP = 0, KC_RESIDUAL, KC_TRANSFER, KC_COARSE, KC_KRYLOV, KC_INVERSE, KC_COARSE_FACTOR, KC_COUNT
+};
+
+// Device arrays of one level.
+struct DevLevel {
+  int32_t n_s = 0, n_cells = 0, n_ls = 0;
+  int64_t nnzb = 0;
+  int32_t* rowptr = nullptr;      // [n_s+1]
+  int32_t* col = nullptr;         // [nnzb]
+  double* val = nullptr;          // [nnzb*b*b]
+  int32_t* cell_sdofs = nullptr;  // [n_cells*n_ls]
+  // owned DoFs: cell T owns own_loc[own_ptr[T] .. own_ptr[T+1]) (local alpha)
+  int32_t* own_ptr = nullptr;     // [n_cells+1]
+  uint8_t* own_loc = nullptr;     // [total owned]
+  // incidence for the POU / additive modes: spatial DoF s belongs to cells
+  // inc_cell[inc_ptr[s] .. inc_ptr[s+1]) at local index inc_loc[...]
+  int32_t* inc_ptr = nullptr;
+  int32_t* inc_cell = nullptr;
+  uint8_t* inc_loc = nullptr;
+  // prolongation from the coarser level (levels >= 1): P (n_s x n_s_coarse)
+  // and its transpose, CSR
+  int32_t* P_rowptr = nullptr; int32_t* P_col = nullptr; double* P_val = nullptr;
+  int32_t* Pt_rowptr = nullptr; int32_t* Pt_col = nullptr; double* Pt_val = nullptr;
+  int32_t n_s_coarse = 0;
+  // stored inverses (levels >= 1)
+  int64_t* inv_off = nullptr;     // [n_cells] element offset of each cell's block
+  void* inv_store = nullptr;
+  int64_t inv_elems = 0;
+  // work vectors (n_s*b each)
+  double* rho = nullptr;
+  double* r = nullptr;
+  double* d = nullptr;
+  double* corr = nullptr;         // [n_cells*n_loc] per-cell corrections (POU/additive)
+  // host copies kept for validation / export
+  std::vector<int32_t> h_own_ptr;
+  std::vector<uint8_t> h_own_loc;
+};
+
+struct TimerPair { hipEvent_t a, b; int cls; };
+
+}  // namespace stv
+
+struct stv_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int n_levels = 0, dim = 0, k = 0, b = 0;
+  stv::DevLevel lv[stv::kMaxLevels];
+  bool have_hier = false;
+  bool have_inv = false;
+  int inv_fp32 = 0;
+  int inv_full = 0;
+  // coarse dense inverse
+  double* coarse_inv = nullptr;
+  int64_t n0 = 0;
+  // Krylov workspace (finest level)
+  double* V = nullptr;          // (restart+1) x N
+  double* Z = nullptr;          // restart x N
+  double* w = nullptr;          // N
+  double* rt = nullptr;         // N (true residual)
+  double* partial = nullptr;    // kDotBlocks x 8
+  double* scal = nullptr;       // device scalars
+  double* hscal = nullptr;      // pinned host mirror
+  int ws_restart = 0;
+  int64_t ws_n = 0;
+  // timing
+  bool timing = false;
+  std::vector<stv::TimerPair> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[stv::KC_COUNT] = {};
+  double total_ms[stv::KC_COUNT] = {};
+};
+
+namespace stv {
+
+// ---- kernel launchers (each returns the hipError_t of the launch) ----
+// y = (r ? r : 0) + sx * (J x)
+hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
+                       const double* x, double* y, double sx);
+bool inverse_fits_lds(int n);
+hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const double* rho,
+                              double* d, double omega, int zero_init, int fp32, int full);
+hipError_t launch_vanka_cells_corr(hipStream_t s, int b, const DevLevel& L, const double* rho,
+                                   double omega, int fp32);
+hipError_t launch_vanka_combine(hipStream_t s, int b, const DevLevel& L, double* d, int pou);
+hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,
+                                uint8_t* status, double* gscratch, int n_slots);
+hipError_t launch_restrict(hipStream_t s, int b, const DevLevel& L, const double* rho,
+                           double* r_c);
+hipError_t launch_prolongate_add(hipStream_t s, int b, const DevLevel& L, const double* d_c,
+                                 double* d);
+hipError_t launch_fill(hipStream_t s, double* x, int64_t n, double v);
+hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
+// dense coarse level
+hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* A, int64_t n);
+hipError_t launch_gj_step(hipStream_t s, double* A, int64_t n, int p, double* prow,
+                          double* trow, double* pcol, int* piv);
+hipError_t launch_permute_cols(hipStream_t s, const double* A, double* out, int64_t n,
+                               const int* sigma);
+hipError_t launch_dense_gemv(hipStream_t s, const double* A, int64_t n, const double* x,
+                             double* y);
+// Krylov helpers: V is row-major (m vectors of length n)
+hipError_t launch_multidot(hipStream_t s, const double* V, int m, const double* w, int64_t n,
+                           double* partial, double* out);
+hipError_t launch_multiaxpy(hipStream_t s, const double* V, int m, const double* coef,
+                            double sign, double* w, int64_t n);
+hipError_t launch_scale_by_norm(hipStream_t s, const double* w, const double* nrm2, double* v,
+                                int64_t n);
+
+}  // namespace stv

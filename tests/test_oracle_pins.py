@@ -170,3 +170,26 @@ def test_fgmres_gmg_solves_c1(c1):
     assert info["converged"] and info["true_relres"] <= 1e-8
     xd = np.linalg.solve(ol[-1].J.toarray(), p.rhs)
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-6
+
+
+def test_combined_readings_two_cells_by_hand():
+    """Same example as the overwrite test.  The additive reading sums both
+    damped updates at the shared DoF: 0 + 0.5 (3/7 - 1/14) = 5/28; the averaged
+    reading divides that sum by the two cells: 5/56.  Unshared DoFs as before."""
+    J = np.array([[2., 1, 0], [1, 4, 1], [0, 2, 4]])
+    dofs = np.array([[0, 1], [1, 2]])
+    L = OracleLevel(sp.csr_matrix(J), dofs, 3, None)
+    L.inv = [oracle.cell_inverse(J[np.ix_(c, c)]) for c in dofs]
+    d0 = np.array([1.0, 0.0, -1.0])
+    add = oracle.vanka_sweep_combined(L, np.ones(3), d0, 0.5, average=False)
+    avg = oracle.vanka_sweep_combined(L, np.ones(3), d0, 0.5, average=True)
+    np.testing.assert_allclose(add, [9 / 14, 5 / 28, -5 / 14], atol=1e-15)
+    np.testing.assert_allclose(avg, [9 / 14, 5 / 56, -5 / 14], atol=1e-15)
+
+
+def test_block_extraction_matches_csr_extraction(c1):
+    p, ol = c1
+    L = p.levels[-1]
+    for T in (0, 17, L.n_cells - 1):
+        a = oracle.extract_cell_matrix_blocks(L.rowptr, L.col, L.val, p.b, L.cell_sdofs[T])
+        np.testing.assert_array_equal(a, oracle.extract_cell_matrix(ol[-1].J, ol[-1].dofs[T]))
