@@ -1,0 +1,260 @@
+"""Benchmark: Vanka-GMG-FGMRES on one MI355X.
+
+One step = the whole hot path on the resident hierarchy: build every cell
+inverse and the coarse inverse, then flexible GMRES with the V(2,2) Vanka
+multigrid preconditioner to relative residual 1e-8.  The reported value is
+Vanka cell-sweeps per second over the whole step (sweeps on all smoothed
+levels, divided by the wall time of the step including the inverse build).
+
+Default workload: the 2d channel [0,2.2]x[0,0.41], 512x128 Q2/P1disc cells,
+6 levels, dG(2) in time, Oseen at a seeded divergence-free convection field,
+nu = 1e-3, tau = 0.005, seeded N(0,1) right-hand side, FP64.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="2d-512x128-dG2",
+                    choices=["2d-512x128-dG2", "2d-16x4-dG1", "3d-128x24x24-dG1"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--nu1", type=int, default=2)
+    ap.add_argument("--nu2", type=int, default=2)
+    ap.add_argument("--omega", type=float, default=0.7)
+    return ap.parse_args()
+
+
+WORKLOADS = {
+    # name: (dim, finest cells, levels, k, tau, nu, seed, description)
+    "2d-512x128-dG2": (2, (512, 128), 6, 2, 0.005, 1e-3, 1002,
+                       "2d channel 512x128 Q2/P1disc x dG(2), 6 levels, Oseen nu=1e-3, tau=0.005"),
+    "2d-16x4-dG1": (2, (16, 4), 2, 1, 0.01, 1e-3, 1001,
+                    "2d channel 16x4 Q2/P1disc x dG(1), 2 levels, Oseen nu=1e-3, tau=0.01"),
+    "3d-128x24x24-dG1": (3, (128, 24, 24), 4, 1, 0.01, 1e-3, 1003,
+                         "3d channel 128x24x24 Q2/P1disc x dG(1), 4 levels, Oseen nu=1e-3"),
+}
+
+
+def sweep_bytes(L, b, inv_bytes, zero_init_fraction):
+    """Algorithmic bytes of one cell-sweep launch on a level: stored inverse
+    rows, cell DoF lists, owner lists and offsets, one read of the residual and
+    one read + write of the iterate (write only for a zero initial iterate)."""
+    n_st = L.n_sdofs * b
+    n_owned = L.n_sdofs                       # each spatial DoF is owned by one cell
+    idx = L.cell_sdofs.size * 4 + (L.n_cells + 1) * 4 + n_owned + L.n_cells * 8
+    vec = n_st * 8 + n_st * 8 * (2.0 - zero_init_fraction)
+    return inv_bytes + idx + vec
+
+
+def residual_bytes(L, b):
+    """Algorithmic bytes of one level residual: blocks, columns, row pointers,
+    x, r and y once each."""
+    nnzb = int(L.col.shape[0])
+    n_st = L.n_sdofs * b
+    return nnzb * (b * b * 8 + 4) + (L.n_sdofs + 1) * 4 + 3 * n_st * 8
+
+
+def cpu_baseline(spec, nu1, nu2, omega):
+    """The FP64 oracle on a bounded sample of the same workload: the same
+    channel, operator, degree and coarse grid at half the cells per axis (one
+    level fewer), full step (all inverses + FGMRES to 1e-8), one thread;
+    reported in cell-sweeps per second."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from stgen.problem import make_problem
+    dim, n, G, k, tau, nu, seed, _ = spec
+    n_s = tuple(c // 2 for c in n)
+    G_s = G - 1
+    p = make_problem(dim, n_s, G_s, k, tau, nu, seed)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ol = oracle.prepare_levels(p.levels, p.b)
+        oracle.build_inverses(ol)
+        cinv = oracle.coarse_inverse(ol[0])
+        _, info = oracle.fgmres(lambda v: ol[-1].J @ v, p.rhs,
+                                lambda v: oracle.vcycle(ol, v, nu1, nu2, omega, coarse_inv=cinv),
+                                restart=30, rtol=1e-8)
+        dt = time.perf_counter() - t0
+    cells = sum(L.n_cells for L in p.levels[1:])
+    sweeps = info["iters"] * (nu1 + nu2) * cells
+    return dict(value=sweeps / dt, unit="cell-sweeps/s", cores=1, kind="oracle",
+                sample=f"{'x'.join(map(str, n_s))} cells, {G_s} levels, same operator; "
+                       f"full step {dt:.1f} s, {info['iters']} FGMRES iterations, 1 thread",
+                seconds=dt, iters=info["iters"])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2107_10561_amd as stv
+    from stgen.problem import make_problem
+
+    spec = WORKLOADS[args.workload]
+    dim, n, G, k, tau, nu, seed, desc = spec
+    b = k + 1
+    t0 = time.time()
+    p = make_problem(dim, n, G, k, tau, nu, seed)
+    print(f"[bench] generated {desc} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    s = stv.Solver(0)
+    t0 = time.time()
+    s.set_hierarchy(p.levels, dim, k)
+    t_set = time.time() - t0
+    rhs = torch.from_numpy(p.rhs).to("cuda:0")
+    x = torch.zeros_like(rhs)
+    mg = dict(nu1=args.nu1, nu2=args.nu2, omega=args.omega)
+
+    def step(fp32=False):
+        s.build_cell_inverses(fp32=fp32)
+        return s.gmres_solve(rhs, x, restart=30, max_it=1000, rtol=1e-8, **mg)
+
+    for i in range(args.warmup):
+        info = step()
+        print(f"[bench] warmup {i}: iters {info['iters']} relres {info['true_relres']:.2e}",
+              file=sys.stderr, flush=True)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    t_inv = t_gm = 0.0
+    for i in range(args.steps):
+        a = time.perf_counter()
+        s.build_cell_inverses(fp32=False)
+        torch.cuda.synchronize()
+        m = time.perf_counter()
+        infos.append(s.gmres_solve(rhs, x, restart=30, max_it=1000, rtol=1e-8, **mg))
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        t_inv += m - a
+        t_gm += e - m
+        print(f"[bench] step {i}: inv {1e3 * (m - a):.2f} ms gmres {1e3 * (e - m):.2f} ms "
+              f"iters {infos[-1]['iters']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    iters = infos[-1]["iters"]
+    relres = infos[-1]["true_relres"]
+    cells_smoothed = sum(L.n_cells for L in p.levels[1:])
+    sweeps_per_step = iters * (args.nu1 + args.nu2) * cells_smoothed
+    total_sweeps = sum(inf["iters"] for inf in infos) * (args.nu1 + args.nu2) * cells_smoothed
+    value = total_sweeps / elapsed
+
+    # per-kernel statistics (HIP events on the library's stream, timed region only)
+    top = G - 1
+    stats = {}
+    for cls in stv.KERNEL_CLASSES:
+        nl, ms = s.kernel_stats(cls)
+        stats[cls] = dict(launches=nl, ms=ms)
+    zi = 1.0 / (args.nu1 + args.nu2) if args.nu1 > 0 else 0.0
+    inv_b = {g: s.level_info(g)["inverse_bytes"] for g in range(1, G)}
+
+    def roofline(cls, bytes_of, kernel):
+        """Aggregate over every launch of the kernel in the timed region (the
+        population rocprofv3's per-kernel average covers) plus the finest level."""
+        tb = tms = 0.0
+        tn = 0
+        for g in range(1, G):
+            n_g, ms_g = s.kernel_stats(cls, g)
+            tb += n_g * bytes_of(g)
+            tms += ms_g
+            tn += n_g
+        n_f, ms_f = s.kernel_stats(cls, top)
+        gbs = tb / (tms / 1e3) / 1e9 if tms > 0 else 0.0
+        gbs_f = bytes_of(top) / (ms_f / n_f / 1e3) / 1e9 if n_f else 0.0
+        return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
+                    bytes_per_launch=int(tb / max(tn, 1)), avg_launch_ms=round(tms / max(tn, 1), 5),
+                    launches=tn, finest_gbs=round(gbs_f, 1),
+                    finest_frac=round(gbs_f / HBM_PEAK_GBS, 4),
+                    finest_bytes_per_launch=int(bytes_of(top)),
+                    finest_avg_launch_ms=round(ms_f / max(n_f, 1), 5))
+
+    roof_sweep = roofline("sweep", lambda g: sweep_bytes(p.levels[g], b, inv_b[g], zi),
+                          "Vanka cell sweep (k_vanka), all smoothed levels")
+    roof_res = roofline("residual", lambda g: residual_bytes(p.levels[g], b),
+                        "block-sparse level residual (k_spmv), levels >= 1")
+    dominant = roof_sweep if stats["sweep"]["ms"] >= stats["residual"]["ms"] else roof_res
+    s.set_timing(False)
+
+    fp32 = None
+    if not args.no_fp32:
+        step(fp32=True)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        reps = max(1, min(3, args.steps))
+        for _ in range(reps):
+            inf32 = step(fp32=True)
+        torch.cuda.synchronize()
+        t32 = (time.perf_counter() - a) / reps
+        fp32 = dict(ms_per_step=round(1e3 * t32, 3), iters=inf32["iters"],
+                    true_relres=inf32["true_relres"],
+                    inverse_bytes_finest=s.level_info(top)["inverse_bytes"])
+        print(f"[bench] fp32 step {1e3 * t32:.2f} ms iters {inf32['iters']}", file=sys.stderr,
+              flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(spec, args.nu1, args.nu2, args.omega)
+        cpu = {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in cb.items()
+               if k_ in ("value", "unit", "cores", "kind", "sample")}
+
+    out = {
+        "metric": "GMG-GMRES time to rel. residual 1e-8; Vanka cell-sweeps/s + HBM GB/s, FP64 vs FP32",
+        "value": round(value, 1),
+        "unit": "cell-sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "cells_finest": int(np.prod(n)), "levels": G,
+                   "spacetime_dofs_finest": int(p.levels[-1].n_sdofs * b), "k": k,
+                   "cycle": f"V({args.nu1},{args.nu2})", "omega": args.omega, "restart": 30,
+                   "rtol": 1e-8, "parallelism": "single GPU"},
+        "time_to_solution_ms": round(ms_per_step, 3),
+        "t_inv_ms": round(1e3 * t_inv / args.steps, 3),
+        "t_gmres_ms": round(1e3 * t_gm / args.steps, 3),
+        "t_set_hierarchy_s": round(t_set, 3),
+        "gmres_iters": iters,
+        "true_relres": relres,
+        "cell_sweeps_per_step": sweeps_per_step,
+        "kernel_ms_per_step": {k_: round(v["ms"] / args.steps, 3) for k_, v in stats.items()},
+        "roofline": dominant,
+        "roofline_sweep": roof_sweep,
+        "roofline_residual": roof_res,
+        "fp32_inverses": fp32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -75,7 +75,8 @@ typedef struct stv_ctx stv_ctx;
  *   P_*         spatial prolongation from level-1 to this level, CSR with
  *               n_sdofs rows and the coarser level's n_sdofs columns (identity
  *               in time).  Ignored (may be NULL) on level 0.
- * Every pair of DoFs sharing a cell must be present in the block pattern.
+ * A pair of DoFs sharing a cell may be absent from the block pattern; its
+ * block is then zero (in J and in every local Jacobian J_T).
  */
 typedef struct stv_level {
   int32_t n_sdofs;
@@ -136,7 +137,8 @@ const char* stv_last_error(const stv_ctx* ctx);
 
 /* Host-only validation of a hierarchy (the checks stv_set_hierarchy runs
  * before touching the device): sizes, sorted unique block columns, cell DoFs
- * in range, every cell pair present in the pattern, prolongation shapes.
+ * in range and distinct within a cell, every DoF in some cell, prolongation
+ * shapes.
  * Writes a message naming the offending field into err (errlen bytes). */
 int stv_validate_hierarchy(int n_levels, int dim, int k, const stv_level* lv,
                            char* err, size_t errlen);
@@ -212,11 +214,13 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
 /* Per-kernel timing with HIP events on the context's stream.
  * stv_set_timing(ctx, 1) starts recording (and clears the counters);
  * stv_kernel_stats returns launches and total milliseconds of one kernel
- * class: 0 = Vanka cell sweep, 1 = level residual, 2 = transfers,
- * 3 = coarse apply, 4 = Krylov vector kernels, 5 = cell inverse build,
- * 6 = coarse factorisation.  Synchronises the stream. */
+ * class on one level (level = -1: all levels): 0 = Vanka cell sweep,
+ * 1 = level residual / matrix-vector product, 2 = transfers, 3 = coarse
+ * apply, 4 = Krylov vector kernels, 5 = cell inverse build, 6 = coarse
+ * factorisation.  Synchronises the stream. */
 int stv_set_timing(stv_ctx* ctx, int on);
-int stv_kernel_stats(stv_ctx* ctx, int kernel_class, int64_t* launches, double* total_ms);
+int stv_kernel_stats(stv_ctx* ctx, int kernel_class, int level, int64_t* launches,
+                     double* total_ms);
 
 #ifdef __cplusplus
 }

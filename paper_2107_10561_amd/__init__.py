@@ -82,7 +82,7 @@ def _load():
         "stv_get_cell_inverse": (I, [P, I, I, P]),
         "stv_level_info": (I, [P, I, I64P, I64P, I64P, I64P]),
         "stv_set_timing": (I, [P, I]),
-        "stv_kernel_stats": (I, [P, I, I64P, ctypes.POINTER(D)]),
+        "stv_kernel_stats": (I, [P, I, I, I64P, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -266,8 +266,9 @@ class Solver:
     def set_timing(self, on: bool):
         self._check(_lib.stv_set_timing(self._h, int(on)))
 
-    def kernel_stats(self, name: str):
+    def kernel_stats(self, name: str, level: int = -1):
+        """(launches, total ms) of one kernel class on one level (-1: all levels)."""
         n, ms = ctypes.c_int64(), ctypes.c_double()
-        self._check(_lib.stv_kernel_stats(self._h, KERNEL_CLASSES[name], ctypes.byref(n),
+        self._check(_lib.stv_kernel_stats(self._h, KERNEL_CLASSES[name], level, ctypes.byref(n),
                                           ctypes.byref(ms)))
         return n.value, ms.value

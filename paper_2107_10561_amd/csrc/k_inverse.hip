@@ -2,13 +2,14 @@
 // (Section 4.2: J_T is the submatrix of the level matrix on the cell's DoFs;
 // Section 4.3: the inverses are pre-computed once per Jacobian and stored).
 //
-// One workgroup per cell: the n_loc x n_loc block is gathered from the
-// block-sparse level matrix (binary search of each cell pair in its block
-// row), inverted in place by Gauss-Jordan elimination with partial pivoting
-// in FP64, and written out column-major, FP64 or FP32, keeping either every
-// row or only the rows of the DoFs the cell owns.
-// Blocks that fit are held in LDS; larger ones (3d, k >= 1) live in a global
-// scratch slot per persistent workgroup, with the pivot row/column in LDS.
+// One workgroup per cell.  The n x n block (n = B * NLS) lives in registers:
+// wave w holds rows i = w + NW*k, lane holds columns j = lane + 64*c.  The
+// block is gathered from the block-sparse level matrix through the cell's
+// block-position map (absent pairs are zero), inverted by Gauss-Jordan
+// elimination with partial pivoting in FP64,
+// and written row-major, FP64 or FP32, keeping either every row or only the
+// rows of the DoFs the cell owns.  Each elimination step exchanges only the
+// pivot column and two rows through LDS (double-buffered, two barriers).
 // Cell-local order inside the kernel is (alpha, l) -> alpha*B + l, matching
 // the time-inner global layout.
 #include "stv_internal.h"
@@ -17,224 +18,370 @@ namespace stv {
 
 __device__ __forceinline__ int32_t find_block(const int32_t* __restrict__ col, int32_t lo,
                                               int32_t hi, int32_t key) {
+  const int32_t end = hi;
   while (lo < hi) {
     const int32_t mid = (lo + hi) >> 1;
     if (col[mid] < key) lo = mid + 1; else hi = mid;
   }
-  return lo;
+  return (lo < end && col[lo] == key) ? lo : -1;
 }
 
-template <int B>
-__device__ void extract_block(double* A, int lda, const int32_t* __restrict__ rowptr,
-                              const int32_t* __restrict__ col, const double* __restrict__ val,
-                              const int32_t* __restrict__ sd, int n_ls) {
-  const int npairs = n_ls * n_ls;
-  for (int pr = threadIdx.x; pr < npairs; pr += blockDim.x) {
-    const int a = pr / n_ls;
-    const int bb = pr - a * n_ls;
-    const int32_t row = sd[a];
-    const int32_t pos = find_block(col, rowptr[row], rowptr[row + 1], sd[bb]);
-    const double* blk = val + (int64_t)pos * (B * B);
-#pragma unroll
-    for (int i = 0; i < B; ++i)
-#pragma unroll
-      for (int l = 0; l < B; ++l) A[(int64_t)(a * B + i) * lda + bb * B + l] = blk[i * B + l];
-  }
+// Block position of every cell DoF pair (alpha, beta) in the block-sparse
+// level matrix (-1 when the pair is absent, i.e. a zero block); built once
+// per hierarchy, it turns the extraction of J_T into independent loads.
+__global__ void k_build_posmap(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                               const int32_t* __restrict__ csd, int n_ls, int64_t n_pairs,
+                               int32_t* __restrict__ posmap) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_pairs) return;
+  const int64_t per = (int64_t)n_ls * n_ls;
+  const int64_t T = e / per;
+  const int pr = (int)(e - T * per);
+  const int a = pr / n_ls;
+  const int32_t* sd = csd + T * n_ls;
+  const int32_t row = sd[a];
+  posmap[e] = find_block(col, rowptr[row], rowptr[row + 1], sd[pr - a * n_ls]);
 }
 
-// In-place Gauss-Jordan inversion with partial pivoting of the n x n row-major
-// matrix A (leading dimension lda).  Each step: every wavefront finds the
-// pivot row r of column p redundantly (largest magnitude, lowest index on
-// ties); the pivot row, old row p and column p are copied to LDS; then every
-// element is rewritten from its own old value and the copies only, so no
-// element is read by one thread and written by another within a step.
-// pivrow[p] = r is recorded; the column order is restored at the store.
-__device__ void gj_invert(double* A, int lda, int n, double* prow, double* trow, double* pcol,
-                          int* pivrow, int* sing) {
-  const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  const int lane = tid & 63;
-  const int wv = tid >> 6;
-  const int nw = nt >> 6;
-  for (int p = 0; p < n; ++p) {
-    double best = -1.0;
-    int bi = 0x7fffffff;
-    for (int i = p + lane; i < n; i += 64) {
-      const double v = fabs(A[(int64_t)i * lda + p]);
-      if (v > best) { best = v; bi = i; }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const int r = (bi < n) ? bi : p;   // no finite candidate (NaN column): flagged below
-    for (int j = tid; j < n; j += nt) {
-      prow[j] = A[(int64_t)r * lda + j];
-      trow[j] = A[(int64_t)p * lda + j];
-      pcol[j] = A[(int64_t)j * lda + p];
-    }
-    if (tid == 0) {
-      pivrow[p] = r;
-      if (bi >= n) *sing = 1;
-    }
-    __syncthreads();
-    const double piv = prow[p];
-    if (tid == 0 && !(piv != 0.0)) *sing = 1;
-    const double ipiv = (piv != 0.0) ? 1.0 / piv : 0.0;
-    for (int i = wv; i < n; i += nw) {
-      double* Ai = A + (int64_t)i * lda;
-      if (i == p) {
-        for (int j = lane; j < n; j += 64) Ai[j] = (j == p) ? ipiv : prow[j] * ipiv;
-      } else {
-        const double f = ((i == r) ? pcol[p] : pcol[i]) * ipiv;
-        const double* src = (i == r) ? trow : Ai;
-        for (int j = lane; j < n; j += 64) Ai[j] = (j == p) ? -f : fma(-f, prow[j], src[j]);
-      }
-    }
-    __syncthreads();
-  }
+hipError_t launch_build_posmap(hipStream_t s, const DevLevel& L) {
+  const int64_t n = (int64_t)L.n_cells * L.n_ls * L.n_ls;
+  k_build_posmap<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L.rowptr, L.col, L.cell_sdofs,
+                                                            L.n_ls, n, L.posmap);
+  return hipGetLastError();
 }
 
-// The row swaps of the elimination act as column swaps on the inverse,
-// applied in reverse step order: inverse(:, j) = A(:, sigma[j]).
-__device__ void gj_sigma(int* sigma, const int* pivrow, int n) {
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < n; ++j) sigma[j] = j;
-    for (int p = n - 1; p >= 0; --p) {
-      const int q = pivrow[p];
-      const int t = sigma[p];
-      sigma[p] = sigma[q];
-      sigma[q] = t;
-    }
-  }
-  __syncthreads();
-}
+typedef double stv_d4 __attribute__((ext_vector_type(4)));
 
-template <int B>
-__device__ void store_inverse(const double* A, int lda, int n, const int* sigma,
-                              const uint8_t* __restrict__ own_loc, int o0, int n_own, int full,
-                              void* store, int64_t off, int fp32) {
-  const int R = full ? n : n_own * B;
-  const int64_t total = (int64_t)R * n;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int j = (int)(e / R);
-    const int o = (int)(e - (int64_t)j * R);
-    int i;
-    if (full) {
-      i = o;
-    } else {
-      const int os = o / B;
-      i = own_loc[o0 + os] * B + (o - os * B);
-    }
-    const double v = A[(int64_t)i * lda + sigma[j]];
-    if (fp32) ((float*)store)[off + e] = (float)v;
-    else ((double*)store)[off + e] = v;
-  }
-}
-
-template <int B>
-__global__ void __launch_bounds__(256) k_inverse_lds(
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, const int32_t* __restrict__ csd, int n_ls,
+// Blocked Gauss-Jordan inversion on FP64 matrix cores.  The block, padded
+// with an identity to NP = 16*NT, lives in the accumulator layout of
+// v_mfma_f64_16x16x4f64: wave w holds tile row w, and lane l, register v of
+// tile tj holds element (16w + 4v + (l >> 4), 16tj + (l & 15)).
+// Pivot panels of 4 columns are eliminated by wave 0 in LDS with partial
+// pivoting over the rows not yet used as pivots (no row interchanges: the
+// pivot row of step p is recorded as rpiv[p]).  The panel's effect on every
+// other column is the rank-4 update A += W B with W = (E - I)(:, pivot rows)
+// and B = the pivot rows before the panel, one MFMA per 16x16 tile.  At the
+// end element (rho, q) of the in-place result belongs to row rinv[rho] and
+// column rpiv[q] of the inverse.
+template <int B, int NLS>
+__global__ void __launch_bounds__(((B * NLS + 15) / 16) * 64)
+__attribute__((amdgpu_waves_per_eu(1, (B * NLS > 128 ? 2 : 8)))) k_inverse_mfma(
+    const int32_t* __restrict__ posmap, const double* __restrict__ val,
     const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
     const int64_t* __restrict__ inv_off, void* store, int fp32, uint8_t* status) {
-  extern __shared__ double sm[];
+  constexpr int N = B * NLS;
+  constexpr int NT = (N + 15) / 16;
+  constexpr int NP = 16 * NT;
+  constexpr int NCH = (NP + 63) / 64;
+  __shared__ double panel[NP][4];
+  __shared__ double brow[4][NP];
+  __shared__ int rpiv[NP];
+  __shared__ int rinv[NP];
+  __shared__ uint8_t used[NP];
+  __shared__ int rowmap[N];
   __shared__ int sing;
-  const int n = n_ls * B;
-  const int lda = n | 1;
-  double* A = sm;
-  double* prow = A + (size_t)n * lda;
-  double* trow = prow + n;
-  double* pcol = trow + n;
-  int* pivrow = (int*)(pcol + n);
-  int* sigma = pivrow + n;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int lr = lane >> 4;   // row offset inside a 4-row group
+  const int lc = lane & 15;   // column inside a tile
   const int T = blockIdx.x;
-  if (threadIdx.x == 0) sing = 0;
-  extract_block<B>(A, lda, rowptr, col, val, csd + (int64_t)T * n_ls, n_ls);
+  const int32_t* pos = posmap + (int64_t)T * (NLS * NLS);
+
+  if (tid == 0) sing = 0;
+  for (int i = tid; i < NP; i += NT * 64) used[i] = 0;
+  for (int i = tid; i < N; i += NT * 64) rowmap[i] = full ? i : -1;
   __syncthreads();
-  gj_invert(A, lda, n, prow, trow, pcol, pivrow, &sing);
-  gj_sigma(sigma, pivrow, n);
-  const int o0 = own_ptr[T];
-  store_inverse<B>(A, lda, n, sigma, own_loc, o0, own_ptr[T + 1] - o0, full, store, inv_off[T],
-                   fp32);
-  if (threadIdx.x == 0) status[T] = (uint8_t)sing;
+  if (!full) {
+    const int o0 = own_ptr[T], no = own_ptr[T + 1] - o0;
+    for (int e = tid; e < no * B; e += NT * 64) {
+      const int os = e / B;
+      rowmap[own_loc[o0 + os] * B + (e - os * B)] = e;
+    }
+  }
+
+  stv_d4 acc[NT];
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + 4 * v + lr;
+      const int col = 16 * tj + lc;
+      double x;
+      if (row < N && col < N) {
+        const int al = row / B, be = col / B;
+        const int32_t q = pos[al * NLS + be];
+        x = q >= 0 ? val[(int64_t)q * (B * B) + (row - al * B) * B + (col - be * B)] : 0.0;
+      } else {
+        x = (row == col) ? 1.0 : 0.0;
+      }
+      acc[tj][v] = x;
+    }
+  }
+
+#pragma unroll
+  for (int tc = 0; tc < NT; ++tc) {
+    for (int q4 = 0; q4 < 4; ++q4) {
+      const int c0 = 4 * q4;          // first panel column inside tile column tc
+      const int p0 = 16 * tc + c0;
+      // (a) panel columns -> LDS
+      if (lc >= c0 && lc < c0 + 4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) panel[16 * w + 4 * v + lr][lc - c0] = acc[tc][v];
+      }
+      __syncthreads();
+      // (b) wave 0 eliminates the panel (partial pivoting over unused rows)
+      if (w == 0) {
+        for (int t = 0; t < 4; ++t) {
+          const int p = p0 + t;
+          double best = -1.0;
+          int bi = 0x7fffffff;
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) {
+            const int rho = lane + 64 * ch;
+            if (rho < NP && !used[rho]) {
+              const double v = fabs(panel[rho][t]);
+              if (v > best) { best = v; bi = rho; }
+            }
+          }
+          double m = best;
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+          int cand = (best == m) ? bi : 0x7fffffff;
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off, 64));
+          int r = cand;
+          if (r >= NP) {   // no finite candidate (NaN column): lowest unused row
+            int u = 0x7fffffff;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+              const int rho = lane + 64 * ch;
+              if (rho < NP && !used[rho]) u = min(u, rho);
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) u = min(u, __shfl_xor(u, off, 64));
+            r = u;
+            if (lane == 0) sing = 1;
+          }
+          const double piv = panel[r][t];
+          if (lane == 0) {
+            if (!(m > 0.0) || !(piv != 0.0)) sing = 1;
+            rpiv[p] = r;
+            used[r] = 1;
+          }
+          const double ipiv = (piv != 0.0) ? 1.0 / piv : 0.0;
+          double pr[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) pr[c] = panel[r][c];
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) {
+            const int rho = lane + 64 * ch;
+            if (rho < NP) {
+              if (rho == r) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) panel[rho][c] = (c == t) ? ipiv : pr[c] * ipiv;
+              } else {
+                const double f = panel[rho][t] * ipiv;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                  panel[rho][c] = (c == t) ? -f : fma(-f, pr[c], panel[rho][c]);
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // (c) the owners publish the four pivot rows as they were before the panel
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = rpiv[p0 + t];
+        if (w == (r >> 4) && lr == (r & 3)) {
+          const int vr = (r & 15) >> 2;
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj) {
+            const stv_d4 a4 = acc[tj];
+            const double x = vr == 0 ? a4[0] : vr == 1 ? a4[1] : vr == 2 ? a4[2] : a4[3];
+            brow[t][16 * tj + lc] = x;
+          }
+        }
+      }
+      __syncthreads();
+      // (d) rank-4 update of every tile, then the panel columns take the
+      // eliminated panel values
+      {
+        const int rho = 16 * w + lc;
+        const int t = lr;
+        const double a = panel[rho][t] - ((rho == rpiv[p0 + t]) ? 1.0 : 0.0);
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+          const double bv = brow[lr][16 * tj + lc];
+          acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[tj], 0, 0, 0);
+        }
+        if (lc >= c0 && lc < c0 + 4) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[tc][v] = panel[16 * w + 4 * v + lr][lc - c0];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // row of the inverse held by in-place row rho, and the store
+  for (int p = tid; p < NP; p += NT * 64) rinv[rpiv[p]] = p;
+  if (tid == 0) status[T] = (uint8_t)sing;
+  __syncthreads();
+  const int64_t off = inv_off[T];
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) {
+    const int q = 16 * tj + lc;
+    const int j = rpiv[q];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rho = 16 * w + 4 * v + lr;
+      const int p = rinv[rho];
+      if (p < N && j < N) {
+        const int o = rowmap[p];
+        if (o >= 0) {
+          const int64_t e = off + (int64_t)o * N + j;
+          if (fp32) ((float*)store)[e] = (float)acc[tj][v];
+          else ((double*)store)[e] = acc[tj][v];
+        }
+      }
+    }
+  }
 }
 
-template <int B>
+// Fallback for blocks too large for registers (n > 256): the same
+// elimination on a global scratch copy, one persistent workgroup per slot.
 __global__ void __launch_bounds__(256) k_inverse_global(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, const int32_t* __restrict__ csd, int n_ls, int n_cells,
+    const double* __restrict__ val, const int32_t* __restrict__ csd, int B, int NLS, int n_cells,
     const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
     const int64_t* __restrict__ inv_off, void* store, int fp32, uint8_t* status,
     double* gscratch) {
   extern __shared__ double sm[];
   __shared__ int sing;
-  const int n = n_ls * B;
-  const int lda = n | 1;
-  double* A = gscratch + (int64_t)blockIdx.x * n * lda;
+  const int n = B * NLS;
+  double* A = gscratch + (int64_t)blockIdx.x * n * n;
   double* prow = sm;
   double* trow = prow + n;
   double* pcol = trow + n;
   int* pivrow = (int*)(pcol + n);
   int* sigma = pivrow + n;
+  int* rowmap = sigma + n;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
   for (int T = blockIdx.x; T < n_cells; T += gridDim.x) {
-    if (threadIdx.x == 0) sing = 0;
-    extract_block<B>(A, lda, rowptr, col, val, csd + (int64_t)T * n_ls, n_ls);
-    __threadfence_block();
+    const int32_t* sd = csd + (int64_t)T * NLS;
+    if (tid == 0) sing = 0;
+    for (int64_t e = tid; e < (int64_t)n * n; e += nt) {
+      const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+      const int al = i / B, be = j / B;
+      const int32_t row = sd[al];
+      const int32_t q = find_block(col, rowptr[row], rowptr[row + 1], sd[be]);
+      A[e] = q >= 0 ? val[(int64_t)q * B * B + (i - al * B) * B + (j - be * B)] : 0.0;
+    }
+    for (int i = tid; i < n; i += nt) rowmap[i] = full ? i : -1;
     __syncthreads();
-    gj_invert(A, lda, n, prow, trow, pcol, pivrow, &sing);
-    gj_sigma(sigma, pivrow, n);
-    const int o0 = own_ptr[T];
-    store_inverse<B>(A, lda, n, sigma, own_loc, o0, own_ptr[T + 1] - o0, full, store,
-                     inv_off[T], fp32);
-    if (threadIdx.x == 0) status[T] = (uint8_t)sing;
+    if (!full) {
+      const int o0 = own_ptr[T], no = own_ptr[T + 1] - o0;
+      for (int e = tid; e < no * B; e += nt) rowmap[own_loc[o0 + e / B] * B + e % B] = e;
+    }
+    for (int p = 0; p < n; ++p) {
+      double best = -1.0;
+      int bi = 0x7fffffff;
+      for (int i = p + lane; i < n; i += 64) {
+        const double v = fabs(A[(int64_t)i * n + p]);
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      const int r = (bi < n) ? bi : p;
+      for (int j = tid; j < n; j += nt) {
+        prow[j] = A[(int64_t)r * n + j];
+        trow[j] = A[(int64_t)p * n + j];
+        pcol[j] = A[(int64_t)j * n + p];
+      }
+      if (tid == 0) {
+        pivrow[p] = r;
+        if (!(best > 0.0)) sing = 1;
+      }
+      __syncthreads();
+      const double piv = prow[p];
+      const double ipiv = (piv != 0.0) ? 1.0 / piv : 0.0;
+      for (int i = wv; i < n; i += nw) {
+        double* Ai = A + (int64_t)i * n;
+        if (i == p) {
+          for (int j = lane; j < n; j += 64) Ai[j] = (j == p) ? ipiv : prow[j] * ipiv;
+        } else {
+          const double f = ((i == r) ? pcol[p] : pcol[i]) * ipiv;
+          const double* src = (i == r) ? trow : Ai;
+          for (int j = lane; j < n; j += 64) Ai[j] = (j == p) ? -f : fma(-f, prow[j], src[j]);
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      for (int j = 0; j < n; ++j) sigma[j] = j;
+      for (int p = n - 1; p >= 0; --p) {
+        const int q = pivrow[p];
+        const int t = sigma[p];
+        sigma[p] = sigma[q];
+        sigma[q] = t;
+      }
+      status[T] = (uint8_t)sing;
+    }
+    __syncthreads();
+    const int64_t off = inv_off[T];
+    for (int64_t e = tid; e < (int64_t)n * n; e += nt) {
+      const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+      const int o = rowmap[i];
+      if (o < 0) continue;
+      const double v = A[(int64_t)i * n + sigma[j]];
+      if (fp32) ((float*)store)[off + (int64_t)o * n + j] = (float)v;
+      else ((double*)store)[off + (int64_t)o * n + j] = v;
+    }
     __syncthreads();
   }
 }
 
-static size_t lds_bytes_resident(int n) {
-  const int lda = n | 1;
-  return sizeof(double) * ((size_t)n * lda + 3 * (size_t)n) + sizeof(int) * 2 * (size_t)n;
+bool inverse_fits_regs(int b, int n_ls) {
+  return (n_ls == 21 && b >= 1 && b <= 4) || (n_ls == 85 && b >= 1 && b <= 3);
 }
 
-// Largest LDS footprint used by one workgroup (the device offers 160 KiB).
-constexpr size_t kLdsBudget = 150 * 1024;
 
-bool inverse_fits_lds(int n) { return lds_bytes_resident(n) <= kLdsBudget; }
-
-template <int B>
-static hipError_t inverse_b(hipStream_t s, const DevLevel& L, int fp32, int full,
-                            uint8_t* status, double* gscratch, int n_slots) {
-  const int n = L.n_ls * B;
-  if (inverse_fits_lds(n)) {
-    const size_t shm = lds_bytes_resident(n);
-    hipError_t e = hipFuncSetAttribute((const void*)k_inverse_lds<B>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    k_inverse_lds<B><<<L.n_cells, 256, shm, s>>>(L.rowptr, L.col, L.val, L.cell_sdofs, L.n_ls,
-                                                 L.own_ptr, L.own_loc, full, L.inv_off,
-                                                 L.inv_store, fp32, status);
-  } else {
-    const size_t shm = sizeof(double) * 3 * (size_t)n + sizeof(int) * 2 * (size_t)n;
-    k_inverse_global<B><<<n_slots, 256, shm, s>>>(L.rowptr, L.col, L.val, L.cell_sdofs, L.n_ls,
-                                                  L.n_cells, L.own_ptr, L.own_loc, full,
-                                                  L.inv_off, L.inv_store, fp32, status,
-                                                  gscratch);
-  }
+template <int B, int NLS>
+static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full, uint8_t* status) {
+  constexpr int NT = (B * NLS + 15) / 16;
+  k_inverse_mfma<B, NLS><<<L.n_cells, NT * 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc,
+                                                       full, L.inv_off, L.inv_store, fp32, status);
   return hipGetLastError();
 }
 
 hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,
                                 uint8_t* status, double* gscratch, int n_slots) {
-  switch (b) {
-    case 1: return inverse_b<1>(s, L, fp32, full, status, gscratch, n_slots);
-    case 2: return inverse_b<2>(s, L, fp32, full, status, gscratch, n_slots);
-    case 3: return inverse_b<3>(s, L, fp32, full, status, gscratch, n_slots);
-    case 4: return inverse_b<4>(s, L, fp32, full, status, gscratch, n_slots);
+  if (L.n_ls == 21) {
+    switch (b) {
+      case 1: return inv_mfma<1, 21>(s, L, fp32, full, status);
+      case 2: return inv_mfma<2, 21>(s, L, fp32, full, status);
+      case 3: return inv_mfma<3, 21>(s, L, fp32, full, status);
+      case 4: return inv_mfma<4, 21>(s, L, fp32, full, status);
+    }
+  } else if (L.n_ls == 85) {
+    switch (b) {
+      case 1: return inv_mfma<1, 85>(s, L, fp32, full, status);
+      case 2: return inv_mfma<2, 85>(s, L, fp32, full, status);
+      case 3: return inv_mfma<3, 85>(s, L, fp32, full, status);
+      default: break;
+    }
   }
-  return hipErrorInvalidValue;
+  const int n = L.n_ls * b;
+  const size_t shm = sizeof(double) * 3 * (size_t)n + sizeof(int) * 3 * (size_t)n;
+  k_inverse_global<<<n_slots, 256, shm, s>>>(L.rowptr, L.col, L.val, L.cell_sdofs, b, L.n_ls,
+                                             L.n_cells, L.own_ptr, L.own_loc, full, L.inv_off,
+                                             L.inv_store, fp32, status, gscratch);
+  return hipGetLastError();
 }
 
 }  // namespace stv

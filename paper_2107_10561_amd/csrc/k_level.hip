@@ -11,152 +11,207 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Transpose-reduce: NV (a power of two, 2..64) per-lane partial sums are
+// summed over the wavefront; afterwards the lanes L with L / (64 / NV) == v
+// hold the total of value v.  Each halving step exchanges half of the values
+// with the partner lane, so the cost is about NV + log2(64 / NV) shuffles.
+template <int CNT, int M, int NV>
+__device__ __forceinline__ void fold_level(double (&p)[NV], int lane) {
+  if constexpr (CNT > 1) {
+    const bool hi = lane & M;
+#pragma unroll
+    for (int t = 0; t < CNT / 2; ++t) {
+      const double keep = hi ? p[t + CNT / 2] : p[t];
+      const double send = hi ? p[t] : p[t + CNT / 2];
+      p[t] = keep + __shfl_xor(send, M, 64);
+    }
+    fold_level<CNT / 2, M / 2, NV>(p, lane);
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ double fold(double (&p)[NV], int lane) {
+  fold_level<NV, 32, NV>(p, lane);
+  double u = p[0];
+#pragma unroll
+  for (int m = 32 / NV; m >= 1; m >>= 1) u += __shfl_xor(u, m, 64);
+  return u;
+}
+
 // ---------------------------------------------------------------------------
 // Level residual y = r + sx J x  (sx = -1: r - J x; r == nullptr: sx J x).
-// One 64-lane wavefront per block row.  Lane (q_off, j) streams block column
-// j of every (64/B)-th block of the row, so consecutive lanes read
-// consecutive doubles of the row's value array; B partial sums per lane are
-// folded across the wavefront at the end.
-template <int B>
-__global__ void __launch_bounds__(256) k_spmv(const int32_t* __restrict__ rowptr,
-                                              const int32_t* __restrict__ col,
-                                              const double* __restrict__ val,
-                                              const double* __restrict__ r,
-                                              const double* __restrict__ x,
-                                              double* __restrict__ y, int32_t n_rows, double sx) {
+// RPW consecutive block rows per 64-lane wavefront: the rows' blocks are
+// contiguous, so lane (q_off, j) streams block column j of every (64/B)-th
+// block of the whole range (consecutive lanes read consecutive doubles),
+// keeping RPW*B partial sums that one transpose-reduce folds at the end.
+// Two rows per wavefront was measured fastest (one row leaves too few bytes
+// in flight per wavefront, more rows cost registers).
+template <int B, int RPW>
+__global__ void __launch_bounds__(256) k_spmv_rows(const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ r,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ y, int32_t n_rows,
+                                                   double sx) {
   constexpr int NQ = 64 / B;
+  constexpr int NV = RPW * B;
+  constexpr int NVP = NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : 32;
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n_rows) return;  // uniform per wavefront
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
+  if (row0 >= n_rows) return;  // uniform per wavefront
   const int qo = lane / B;
   const int j = lane - qo * B;
-  const int32_t q0 = rowptr[row], q1 = rowptr[row + 1];
-  double acc[B];
+  int32_t rp[RPW + 1];
 #pragma unroll
-  for (int i = 0; i < B; ++i) acc[i] = 0.0;
+  for (int t = 0; t <= RPW; ++t) rp[t] = rowptr[min(row0 + t, n_rows)];
+  double acc[NVP];
+#pragma unroll
+  for (int v = 0; v < NVP; ++v) acc[v] = 0.0;
   if (qo < NQ) {
-#pragma unroll 2
-    for (int32_t q = q0 + qo; q < q1; q += NQ) {
+#pragma unroll 4
+    for (int32_t q = rp[0] + qo; q < rp[RPW]; q += NQ) {
       const int32_t c = col[q];
       const double xv = x[(int64_t)c * B + j];
       const double* vb = val + (int64_t)q * (B * B) + j;
+      int rr = 0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) acc[i] = fma(vb[i * B], xv, acc[i]);
+      for (int t = 1; t < RPW; ++t) rr += (q >= rp[t]) ? 1 : 0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const double pv = vb[i * B] * xv;
+#pragma unroll
+        for (int t = 0; t < RPW; ++t) acc[t * B + i] += (rr == t) ? pv : 0.0;
+      }
     }
   }
-#pragma unroll
-  for (int i = 0; i < B; ++i) acc[i] = wave_sum(acc[i]);
-  if (lane < B) {
-    double a = acc[0];
-#pragma unroll
-    for (int i = 1; i < B; ++i)
-      if (lane == i) a = acc[i];
-    const int64_t o = (int64_t)row * B + lane;
-    y[o] = r ? fma(sx, a, r[o]) : sx * a;
+  const double sum = fold<NVP>(acc, lane);
+  constexpr int SPAN = 64 / NVP;
+  const int v = lane / SPAN;
+  if ((lane % SPAN) == 0 && v < NV) {
+    const int t = v / B, i = v - (v / B) * B;
+    const int row = row0 + t;
+    if (row < n_rows) {
+      const int64_t o = (int64_t)row * B + i;
+      y[o] = r ? fma(sx, sum, r[o]) : sx * sum;
+    }
   }
 }
 
 hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r, const double* x,
                        double* y, double sx) {
-  dim3 grid((L.n_s + 3) / 4), block(256);
+  constexpr int RPW = 2;
+  dim3 grid((L.n_s + 4 * RPW - 1) / (4 * RPW)), block(256);
   switch (b) {
-    case 1: k_spmv<1><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 2: k_spmv<2><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 3: k_spmv<3><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 4: k_spmv<4><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 1: k_spmv_rows<1, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 2: k_spmv_rows<2, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 3: k_spmv_rows<3, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 4: k_spmv_rows<4, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Vanka cell sweep, last-writer form.  One wavefront per cell T:
-//   rho_T  <- gather of the level residual on the cell's n_loc DoFs (LDS),
-//   c      <- J_T^-1 rho_T for the rows of the DoFs T owns,
-//   d_j    <- d_j + omega c_j  (or omega c_j for a zero initial iterate).
-// Every DoF has exactly one owner (the last cell in loop order containing
-// it), so the stores are disjoint: no atomics, deterministic.
-// Inverse blocks are column-major per cell (element (i, j) at j*ld + i), so
-// the lanes of one row chunk read consecutive addresses of a column.  When
-// the cell has at most 32 stored rows, 64/R columns are read per step.
-template <int B, typename TS>
-__global__ void __launch_bounds__(64) k_vanka(const double* __restrict__ rho,
-                                             double* __restrict__ d,
-                                             const int32_t* __restrict__ csd, int n_ls,
-                                             const int32_t* __restrict__ own_ptr,
-                                             const uint8_t* __restrict__ own_loc,
-                                             const int64_t* __restrict__ inv_off,
-                                             const TS* __restrict__ store, double omega,
-                                             int zero_init, int full) {
-  extern __shared__ double sm[];
-  const int n_loc = n_ls * B;
-  double* xs = sm;
-  double* part = sm + n_loc;
-  const int T = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int32_t* sd = csd + (int64_t)T * n_ls;
-  for (int e = lane; e < n_loc; e += 64) {
-    const int be = e / B;
-    const int l = e - be * B;
-    xs[e] = rho[(int64_t)sd[be] * B + l];
+// Vanka cell sweep.  One 64-lane wavefront per cell T (four cells per
+// workgroup, no LDS, no barriers): lane j holds rho_T[j] for the columns
+// j = lane + 64c of the cell-local order (alpha, l) -> alpha*B + l, gathered
+// straight from the level residual.  The stored inverse rows are row-major,
+// so each row is one contiguous, fully coalesced read; rows are processed 8 at
+// a time and their 64 partial sums are folded by a transpose-reduce after
+// which lanes 8t..8t+7 hold row t.  Last-writer form: only the rows of the
+// DoFs the cell owns are computed and written (d_j += omega c_j, or
+// = omega c_j for a zero initial iterate); every DoF has exactly one owner,
+// so the stores are disjoint (no atomics, deterministic).
+// Row r of the cell's stored block as this lane's partial product.
+template <int N, int NC, typename TS>
+__device__ __forceinline__ double row_dot(const TS* __restrict__ Ar, const double (&x)[NC],
+                                          int lane) {
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = lane + 64 * c;
+    if (j < N) acc = fma((double)Ar[j], x[c], acc);
   }
-  __syncthreads();
+  return acc;
+}
+
+template <int B, int NLS, typename TS>
+__global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
+                                              double* __restrict__ d,
+                                              const int32_t* __restrict__ csd,
+                                              const int32_t* __restrict__ own_ptr,
+                                              const uint8_t* __restrict__ own_loc,
+                                              const int64_t* __restrict__ inv_off,
+                                              const TS* __restrict__ store, double omega,
+                                              int zero_init, int full, int n_cells) {
+  constexpr int N = B * NLS;
+  constexpr int NC = (N + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int T = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (T >= n_cells) return;  // uniform per wavefront
+  const int32_t* sd = csd + (int64_t)T * NLS;
   const int o0 = own_ptr[T];
   const int R = (own_ptr[T + 1] - o0) * B;
   const TS* A = store + inv_off[T];
-  if (!full && R <= 32) {
-    const int S = 64 / R;
-    const int i = lane % R;
-    const int js = lane / R;
-    double acc = 0.0;
-    if (js < S) {
-      const TS* Ai = A + i;
-#pragma unroll 4
-      for (int j = js; j < n_loc; j += S) acc = fma((double)Ai[(int64_t)j * R], xs[j], acc);
-    }
-    part[lane] = acc;
-    __syncthreads();
-    if (lane < R) {
-      double sacc = 0.0;
-      for (int t = 0; t < S; ++t) sacc += part[lane + t * R];
-      const int o = lane / B;
-      const int l = lane - o * B;
-      const int64_t g = (int64_t)sd[own_loc[o0 + o]] * B + l;
-      d[g] = zero_init ? omega * sacc : d[g] + omega * sacc;
-    }
-  } else {
-    const int ld = full ? n_loc : R;
-    for (int i0 = 0; i0 < R; i0 += 64) {
-      const int i = i0 + lane;
-      if (i < R) {
-        const int o = i / B;
-        const int l = i - o * B;
-        const int alpha = own_loc[o0 + o];
-        const TS* Ai = A + (full ? alpha * B + l : i);
-        double acc = 0.0;
-#pragma unroll 4
-        for (int j = 0; j < n_loc; ++j) acc = fma((double)Ai[(int64_t)j * ld], xs[j], acc);
-        const int64_t g = (int64_t)sd[alpha] * B + l;
-        d[g] = zero_init ? omega * acc : d[g] + omega * acc;
-      }
+  double x[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = lane + 64 * c;
+    x[c] = 0.0;
+    if (j < N) {
+      const int be = j / B;
+      x[c] = rho[(int64_t)sd[be] * B + (j - be * B)];
     }
   }
+  // groups of 8 owned rows: 8 row reads in flight, then one fold (keeping
+  // more groups in flight was measured slower: it costs occupancy)
+  for (int r0 = 0; r0 < R; r0 += 8) {
+    double p[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int row = r0 + t;
+      p[t] = 0.0;
+      if (row < R) {
+        int srow = row;
+        if (full) {
+          const int os = row / B;
+          srow = own_loc[o0 + os] * B + (row - os * B);
+        }
+        p[t] = row_dot<N, NC, TS>(A + (int64_t)srow * N, x, lane);
+      }
+    }
+    const double sum = fold<8>(p, lane);
+    const int row = r0 + (lane >> 3);
+    if ((lane & 7) == 0 && row < R) {
+      const int os = row / B;
+      const int64_t g = (int64_t)sd[own_loc[o0 + os]] * B + (row - os * B);
+      d[g] = zero_init ? omega * sum : fma(omega, sum, d[g]);
+    }
+  }
+}
+
+template <int B, int NLS>
+static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, double* d,
+                           double omega, int zero_init, int fp32, int full) {
+  const unsigned grid = (unsigned)((L.n_cells + 3) / 4);
+  if (fp32)
+    k_vanka<B, NLS, float><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
+                                                L.inv_off, (const float*)L.inv_store, omega,
+                                                zero_init, full, L.n_cells);
+  else
+    k_vanka<B, NLS, double><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
+                                                 L.inv_off, (const double*)L.inv_store, omega,
+                                                 zero_init, full, L.n_cells);
+  return hipGetLastError();
 }
 
 template <int B>
 static hipError_t vanka_b(hipStream_t s, const DevLevel& L, const double* rho, double* d,
                           double omega, int zero_init, int fp32, int full) {
-  const size_t shm = sizeof(double) * (size_t)(L.n_ls * B + 64);
-  if (fp32)
-    k_vanka<B, float><<<L.n_cells, 64, shm, s>>>(rho, d, L.cell_sdofs, L.n_ls, L.own_ptr,
-                                                 L.own_loc, L.inv_off, (const float*)L.inv_store,
-                                                 omega, zero_init, full);
-  else
-    k_vanka<B, double><<<L.n_cells, 64, shm, s>>>(rho, d, L.cell_sdofs, L.n_ls, L.own_ptr,
-                                                  L.own_loc, L.inv_off,
-                                                  (const double*)L.inv_store, omega, zero_init,
-                                                  full);
-  return hipGetLastError();
+  if (L.n_ls == 21) return vanka_bn<B, 21>(s, L, rho, d, omega, zero_init, fp32, full);
+  if (L.n_ls == 85) return vanka_bn<B, 85>(s, L, rho, d, omega, zero_init, fp32, full);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const double* rho,
@@ -172,8 +227,9 @@ hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const dou
 
 // ---------------------------------------------------------------------------
 // Averaged / additive forms: every cell writes its full damped correction
-// omega J_T^-1 rho_T to corr[T*n_loc + (alpha*B + l)]; a second kernel sums,
-// per DoF and in cell order, the corrections of the cells containing it.
+// omega J_T^-1 rho_T to corr[T*n_loc + (alpha*B + l)] (needs every stored
+// row); a second kernel sums, per DoF and in cell order, the corrections of
+// the cells containing it.
 template <int B, typename TS>
 __global__ void __launch_bounds__(64) k_vanka_corr(const double* __restrict__ rho,
                                                   double* __restrict__ corr,
@@ -193,7 +249,7 @@ __global__ void __launch_bounds__(64) k_vanka_corr(const double* __restrict__ rh
   const TS* A = store + inv_off[T];
   for (int i = lane; i < n_loc; i += 64) {
     double acc = 0.0;
-    for (int j = 0; j < n_loc; ++j) acc = fma((double)A[(int64_t)j * n_loc + i], sm[j], acc);
+    for (int j = 0; j < n_loc; ++j) acc = fma((double)A[(int64_t)i * n_loc + j], sm[j], acc);
     corr[(int64_t)T * n_loc + i] = omega * acc;
   }
 }

@@ -80,7 +80,7 @@ void free_level(DevLevel& L) {
   dfree(L.own_ptr); dfree(L.own_loc); dfree(L.inc_ptr); dfree(L.inc_cell); dfree(L.inc_loc);
   dfree(L.P_rowptr); dfree(L.P_col); dfree(L.P_val);
   dfree(L.Pt_rowptr); dfree(L.Pt_col); dfree(L.Pt_val);
-  dfree(L.inv_off); dfree(L.inv_store);
+  dfree(L.inv_off); dfree(L.inv_store); dfree(L.posmap);
   dfree(L.rho); dfree(L.r); dfree(L.d); dfree(L.corr);
   L = DevLevel();
 }
@@ -114,18 +114,21 @@ hipEvent_t get_event(stv_ctx* ctx) {
 struct Timed {
   stv_ctx* ctx;
   int cls;
+  int level;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  Timed(stv_ctx* c, int k) : ctx(c), cls(k) {
+  Timed(stv_ctx* c, int k, int g = 0, hipStream_t on = nullptr)
+      : ctx(c), cls(k), level(g), st(on ? on : c->stream) {
     if (ctx->timing) {
       a = get_event(ctx);
-      (void)hipEventRecord(a, ctx->stream);
+      (void)hipEventRecord(a, st);
     }
   }
   void done() {
     if (ctx->timing && a) {
       hipEvent_t b = get_event(ctx);
-      (void)hipEventRecord(b, ctx->stream);
-      ctx->pending.push_back({a, b, cls});
+      (void)hipEventRecord(b, st);
+      ctx->pending.push_back({a, b, cls, level});
       a = nullptr;
     }
   }
@@ -135,8 +138,8 @@ void resolve_timers(stv_ctx* ctx) {
   for (auto& t : ctx->pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
-      ctx->launches[t.cls] += 1;
-      ctx->total_ms[t.cls] += ms;
+      ctx->launches[t.cls][t.level] += 1;
+      ctx->total_ms[t.cls][t.level] += ms;
     }
     ctx->pool.push_back(t.a);
     ctx->pool.push_back(t.b);
@@ -189,9 +192,7 @@ bool validate_impl(int n_levels, int dim, int k, const stv_level* lv, std::strin
         return bad(g, "cell_sdofs out of range (cell " + std::to_string(e / nls) + ")");
       seen[(size_t)s] = 1;
     }
-    for (int32_t s = 0; s < L.n_sdofs; ++s)
-      if (!seen[(size_t)s]) return bad(g, "spatial DoF " + std::to_string(s) + " belongs to no cell");
-    // distinct DoFs per cell and every cell pair present in the block pattern
+    // distinct DoFs per cell (cell pairs absent from the block pattern are zero)
     const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<int64_t> bad_cell(nth, -1);
     std::vector<int> bad_kind(nth, 0);
@@ -201,12 +202,8 @@ bool validate_impl(int n_levels, int dim, int k, const stv_level* lv, std::strin
         for (int64_t c = t; c < L.n_cells; c += nth) {
           const int32_t* sd = L.cell_sdofs + c * nls;
           for (int a = 0; a < nls && bad_cell[t] < 0; ++a) {
-            const int32_t* b0 = L.bsr_col + L.bsr_rowptr[sd[a]];
-            const int32_t* b1 = L.bsr_col + L.bsr_rowptr[sd[a] + 1];
-            for (int bb = 0; bb < nls; ++bb) {
-              if (bb != a && sd[bb] == sd[a]) { bad_cell[t] = c; bad_kind[t] = 1; break; }
-              if (!std::binary_search(b0, b1, sd[bb])) { bad_cell[t] = c; bad_kind[t] = 2; break; }
-            }
+            for (int bb = a + 1; bb < nls; ++bb)
+              if (sd[bb] == sd[a]) { bad_cell[t] = c; bad_kind[t] = 1; break; }
           }
           if (bad_cell[t] >= 0) return;
         }
@@ -215,9 +212,9 @@ bool validate_impl(int n_levels, int dim, int k, const stv_level* lv, std::strin
     for (auto& x : th) x.join();
     for (unsigned t = 0; t < nth; ++t)
       if (bad_cell[t] >= 0)
-        return bad(g, std::string(bad_kind[t] == 1 ? "repeated DoF in cell "
-                                                   : "block pattern misses a DoF pair of cell ") +
-                          std::to_string(bad_cell[t]));
+        return bad(g, "repeated DoF in cell " + std::to_string(bad_cell[t]));
+    for (int32_t s = 0; s < L.n_sdofs; ++s)
+      if (!seen[(size_t)s]) return bad(g, "spatial DoF " + std::to_string(s) + " belongs to no cell");
     if (g > 0) {
       const stv_level& C = lv[g - 1];
       if (!L.P_rowptr || !L.P_col || !L.P_val)
@@ -244,14 +241,14 @@ int check_ctx(stv_ctx* ctx, bool need_hier, bool need_inv) {
 
 // ---------------------------------------------------------------- level ops
 int residual(stv_ctx* ctx, int g, const double* r, const double* x, double* y) {
-  Timed t(ctx, KC_RESIDUAL);
+  Timed t(ctx, KC_RESIDUAL, g);
   STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], r, x, y, -1.0));
   t.done();
   return STV_OK;
 }
 
 int matvec(stv_ctx* ctx, int g, const double* x, double* y) {
-  Timed t(ctx, KC_RESIDUAL);
+  Timed t(ctx, KC_RESIDUAL, g);
   STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], nullptr, x, y, 1.0));
   t.done();
   return STV_OK;
@@ -262,7 +259,7 @@ int cell_pass(stv_ctx* ctx, int g, const double* rho, double* d, double omega, i
   DevLevel& L = ctx->lv[g];
   const int b = ctx->b;
   if (mode == STV_LAST_WRITER) {
-    Timed t(ctx, KC_SWEEP);
+    Timed t(ctx, KC_SWEEP, g);
     STV_HIP(launch_vanka_cells(ctx->stream, b, L, rho, d, omega, zero_init, ctx->inv_fp32,
                                ctx->inv_full));
     t.done();
@@ -270,7 +267,7 @@ int cell_pass(stv_ctx* ctx, int g, const double* rho, double* d, double omega, i
   }
   if (!L.corr) STV_TRY(dalloc(ctx, &L.corr, (size_t)L.n_cells * L.n_ls * b));
   if (zero_init) STV_HIP(launch_fill(ctx->stream, d, (int64_t)L.n_s * b, 0.0));
-  Timed t(ctx, KC_SWEEP);
+  Timed t(ctx, KC_SWEEP, g);
   STV_HIP(launch_vanka_cells_corr(ctx->stream, b, L, rho, omega, ctx->inv_fp32));
   STV_HIP(launch_vanka_combine(ctx->stream, b, L, d, mode == STV_POU ? 1 : 0));
   t.done();
@@ -315,13 +312,13 @@ int vcycle_level(stv_ctx* ctx, int g, const double* r, double* d, const stv_mg_p
   STV_TRY(sweeps(ctx, g, r, d, p.nu1, p.omega, p.mode, true));
   STV_TRY(residual(ctx, g, r, d, L.rho));
   {
-    Timed t(ctx, KC_TRANSFER);
+    Timed t(ctx, KC_TRANSFER, g);
     STV_HIP(launch_restrict(ctx->stream, b, L, L.rho, C.r));
     t.done();
   }
   STV_TRY(vcycle_level(ctx, g - 1, C.r, C.d, p));
   {
-    Timed t(ctx, KC_TRANSFER);
+    Timed t(ctx, KC_TRANSFER, g);
     STV_HIP(launch_prolongate_add(ctx->stream, b, L, C.d, d));
     t.done();
   }
@@ -394,6 +391,13 @@ int stv_create(stv_ctx** out, int device, void* hip_stream) {
   if (!ctx) { g_create_err = "host allocation failed"; return STV_ENOMEM; }
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+    g_create_err = "creation of the internal stream/events failed";
+    delete ctx;
+    return STV_EHIP;
+  }
   if (hipMalloc((void**)&ctx->scal, sizeof(double) * 4 * kScalR) != hipSuccess ||
       hipHostMalloc((void**)&ctx->hscal, sizeof(double) * 4 * kScalR, hipHostMallocDefault) !=
           hipSuccess) {
@@ -415,6 +419,12 @@ void stv_destroy(stv_ctx* ctx) {
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
   for (auto& t : ctx->pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
 }
 
@@ -487,6 +497,10 @@ int stv_set_hierarchy(stv_ctx* ctx, int n_levels, int dim, int k, const stv_leve
       STV_TRY(upload(ctx, &L.inc_cell, icell.data(), icell.size()));
       STV_TRY(upload(ctx, &L.inc_loc, iloc.data(), iloc.size()));
     }
+    if (g > 0) {
+      STV_TRY(dalloc(ctx, &L.posmap, (size_t)H.n_cells * nls * nls));
+      STV_HIP(launch_build_posmap(ctx->stream, L));
+    }
     const size_t nst = (size_t)H.n_sdofs * b;
     STV_TRY(dalloc(ctx, &L.rho, nst));
     if (g < n_levels - 1) {
@@ -517,6 +531,7 @@ int stv_set_hierarchy(stv_ctx* ctx, int n_levels, int dim, int k, const stv_leve
       STV_TRY(upload(ctx, &L.Pt_val, tv.data(), tv.size()));
     }
   }
+  STV_HIP(hipStreamSynchronize(ctx->stream));
   ctx->have_hier = true;
   return STV_OK;
 }
@@ -529,12 +544,26 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   const int full = (storage & STV_STORE_FULL) ? 1 : 0;
   if (storage & ~(STV_F32 | STV_STORE_FULL)) return fail(ctx, STV_EINVAL, "unknown storage flags");
   STV_HIP(hipSetDevice(ctx->device));
+  STV_HIP(hipStreamSynchronize(ctx->stream));
   free_inverses(ctx);
   ctx->inv_fp32 = fp32;
   ctx->inv_full = full;
   const int b = ctx->b;
   hipStream_t s = ctx->stream;
-  for (int g = 1; g < ctx->n_levels; ++g) {
+  hipStream_t side = ctx->side;
+  // ---- allocations (host-side offsets of every cell's stored rows)
+  std::vector<uint8_t*> status((size_t)ctx->n_levels, nullptr);
+  std::vector<double*> scratch((size_t)ctx->n_levels, nullptr);
+  std::vector<int> slots((size_t)ctx->n_levels, 0);
+  double *A = nullptr, *Bbuf = nullptr;
+  int *piv = nullptr, *sig = nullptr;
+  auto cleanup = [&]() {
+    for (auto& p : status) dfree(p);
+    for (auto& p : scratch) dfree(p);
+    dfree(A); dfree(Bbuf); dfree(piv); dfree(sig);
+  };
+  int rc = STV_OK;
+  for (int g = 1; g < ctx->n_levels && rc == STV_OK; ++g) {
     DevLevel& L = ctx->lv[g];
     const int n = L.n_ls * b;
     std::vector<int64_t> off((size_t)L.n_cells);
@@ -544,91 +573,114 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
       const int rows = full ? n : (L.h_own_ptr[(size_t)c + 1] - L.h_own_ptr[(size_t)c]) * b;
       tot += (int64_t)rows * n;
     }
-    STV_TRY(upload(ctx, &L.inv_off, off.data(), off.size()));
+    if ((rc = upload(ctx, &L.inv_off, off.data(), off.size())) != STV_OK) break;
     if (fp32) {
       float* p = nullptr;
-      STV_TRY(dalloc(ctx, &p, (size_t)tot));
+      rc = dalloc(ctx, &p, (size_t)tot);
       L.inv_store = p;
     } else {
       double* p = nullptr;
-      STV_TRY(dalloc(ctx, &p, (size_t)tot));
+      rc = dalloc(ctx, &p, (size_t)tot);
       L.inv_store = p;
     }
+    if (rc != STV_OK) break;
     L.inv_elems = tot;
-    uint8_t* status = nullptr;
-    STV_TRY(dalloc(ctx, &status, (size_t)L.n_cells));
-    double* scratch = nullptr;
-    int slots = 0;
-    if (!inverse_fits_lds(n)) {
-      slots = std::min<int>(L.n_cells, 1024);
-      const int lda = n | 1;
-      int rc = dalloc(ctx, &scratch, (size_t)slots * n * lda);
-      if (rc != STV_OK) { dfree(status); return rc; }
+    if ((rc = dalloc(ctx, &status[(size_t)g], (size_t)L.n_cells)) != STV_OK) break;
+    if (!inverse_fits_regs(b, L.n_ls)) {
+      slots[(size_t)g] = std::min<int>(L.n_cells, 1024);
+      rc = dalloc(ctx, &scratch[(size_t)g], (size_t)slots[(size_t)g] * n * n);
     }
-    Timed t(ctx, KC_INVERSE);
-    hipError_t e = launch_cell_inverses(s, b, L, fp32, full, status, scratch, slots);
+  }
+  DevLevel& L0 = ctx->lv[0];
+  const int64_t n0 = (int64_t)L0.n_s * b;
+  if (rc == STV_OK && n0 > 12288) rc = fail(ctx, STV_EINVAL, "coarse level larger than 12288 unknowns");
+  const int nb = gj_panel_width(n0);
+  const int64_t np = (n0 + nb - 1) / nb * nb;
+  if (rc == STV_OK) {
+    ctx->n0 = n0;
+    if ((rc = dalloc(ctx, &A, (size_t)(np * np))) == STV_OK &&
+        (rc = dalloc(ctx, &ctx->coarse_inv, (size_t)(n0 * n0))) == STV_OK &&
+        (rc = dalloc(ctx, &Bbuf, (size_t)(nb * np))) == STV_OK &&
+        (rc = dalloc(ctx, &piv, (size_t)np)) == STV_OK)
+      rc = dalloc(ctx, &sig, (size_t)np);
+  }
+  if (rc != STV_OK) {
+    cleanup();
+    free_inverses(ctx);
+    return rc;
+  }
+  // ---- launch: cell inverses on the caller's stream, coarse factorisation
+  // on the internal stream (it starts after everything queued before it)
+  hipError_t e = hipEventRecord(ctx->ev_fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
+  for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
+    Timed t(ctx, KC_INVERSE, g);
+    e = launch_cell_inverses(s, b, ctx->lv[g], fp32, full, status[(size_t)g], scratch[(size_t)g],
+                             slots[(size_t)g]);
     t.done();
-    std::vector<uint8_t> hs((size_t)L.n_cells);
-    if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), status, hs.size(), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    dfree(status);
-    dfree(scratch);
-    if (e != hipSuccess)
-      return fail(ctx, STV_EHIP, std::string("cell inverse build failed: ") + hipGetErrorString(e));
-    for (int32_t c = 0; c < L.n_cells; ++c)
-      if (hs[(size_t)c]) {
+  }
+  {
+    Timed t(ctx, KC_COARSE_FACTOR, 0, side);
+    if (e == hipSuccess) e = launch_fill(side, A, np * np, 0.0);
+    if (e == hipSuccess) e = launch_bsr_to_dense(side, b, L0, A, np);
+    if (e == hipSuccess) e = launch_set_diag(side, A, np, n0, np);
+    if (e == hipSuccess) e = launch_gj_blocked(side, A, np, piv, Bbuf);
+    t.done();
+  }
+  std::vector<int> hp((size_t)np);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), piv, sizeof(int) * np, hipMemcpyDeviceToHost, side);
+  if (e == hipSuccess) e = hipStreamSynchronize(side);
+  bool coarse_singular = false;
+  std::vector<int> sigma((size_t)np);
+  if (e == hipSuccess) {
+    for (int64_t p = 0; p < np; ++p)
+      if (hp[(size_t)p] < 0) coarse_singular = true;
+    if (!coarse_singular) {
+      for (int64_t j = 0; j < np; ++j) sigma[(size_t)j] = (int)j;
+      for (int64_t p = np - 1; p >= 0; --p) std::swap(sigma[(size_t)p], sigma[(size_t)hp[(size_t)p]]);
+      for (int64_t j = 0; j < n0; ++j)
+        if (sigma[(size_t)j] >= n0) coarse_singular = true;
+    }
+    if (!coarse_singular) {
+      Timed t(ctx, KC_COARSE_FACTOR, 0, side);
+      e = hipMemcpyAsync(sig, sigma.data(), sizeof(int) * np, hipMemcpyHostToDevice, side);
+      if (e == hipSuccess) e = launch_permute_cols(side, A, np, ctx->coarse_inv, n0, sig);
+      t.done();
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
+  std::vector<std::vector<uint8_t>> hs((size_t)ctx->n_levels);
+  for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
+    hs[(size_t)g].resize((size_t)ctx->lv[g].n_cells);
+    e = hipMemcpyAsync(hs[(size_t)g].data(), status[(size_t)g], hs[(size_t)g].size(),
+                       hipMemcpyDeviceToHost, s);
+  }
+  {
+    // both streams drain before any buffer is released, on every path
+    const hipError_t e1 = hipStreamSynchronize(s);
+    const hipError_t e2 = hipStreamSynchronize(side);
+    if (e == hipSuccess) e = (e1 != hipSuccess) ? e1 : e2;
+  }
+  cleanup();
+  if (e != hipSuccess) {
+    free_inverses(ctx);
+    return fail(ctx, STV_EHIP, std::string("inverse build failed: ") + hipGetErrorString(e));
+  }
+  for (int g = 1; g < ctx->n_levels; ++g)
+    for (int32_t c = 0; c < ctx->lv[g].n_cells; ++c)
+      if (hs[(size_t)g][(size_t)c]) {
         if (bad_level) *bad_level = g;
         if (bad_cell) *bad_cell = c;
+        free_inverses(ctx);
         return fail(ctx, STV_ESINGULAR,
                     "zero pivot in J_T of level " + std::to_string(g) + " cell " + std::to_string(c));
       }
-  }
-  // coarse level: dense Gauss-Jordan inverse
-  {
-    DevLevel& L0 = ctx->lv[0];
-    const int64_t n = (int64_t)L0.n_s * b;
-    ctx->n0 = n;
-    double *A = nullptr, *prow = nullptr, *trow = nullptr, *pcol = nullptr;
-    int* piv = nullptr;
-    int* sig = nullptr;
-    STV_TRY(dalloc(ctx, &A, (size_t)(n * n)));
-    auto cleanup = [&]() { dfree(A); dfree(prow); dfree(trow); dfree(pcol); dfree(piv); dfree(sig); };
-    int rc = STV_OK;
-    if ((rc = dalloc(ctx, &ctx->coarse_inv, (size_t)(n * n))) != STV_OK ||
-        (rc = dalloc(ctx, &prow, (size_t)n)) != STV_OK || (rc = dalloc(ctx, &trow, (size_t)n)) != STV_OK ||
-        (rc = dalloc(ctx, &pcol, (size_t)n)) != STV_OK || (rc = dalloc(ctx, &piv, (size_t)n)) != STV_OK ||
-        (rc = dalloc(ctx, &sig, (size_t)n)) != STV_OK) {
-      cleanup();
-      return rc;
-    }
-    Timed t(ctx, KC_COARSE_FACTOR);
-    hipError_t e = launch_fill(s, A, n * n, 0.0);
-    if (e == hipSuccess) e = launch_bsr_to_dense(s, b, L0, A, n);
-    for (int64_t p = 0; p < n && e == hipSuccess; ++p) e = launch_gj_step(s, A, n, (int)p, prow, trow, pcol, piv);
-    std::vector<int> hp((size_t)n);
-    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), piv, sizeof(int) * n, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      cleanup();
-      return fail(ctx, STV_EHIP, std::string("coarse factorisation failed: ") + hipGetErrorString(e));
-    }
-    for (int64_t p = 0; p < n; ++p)
-      if (hp[(size_t)p] < 0) {
-        cleanup();
-        if (bad_level) *bad_level = 0;
-        if (bad_cell) *bad_cell = -1;
-        return fail(ctx, STV_ESINGULAR, "zero pivot in the coarse matrix at step " + std::to_string(p));
-      }
-    std::vector<int> sigma((size_t)n);
-    for (int64_t j = 0; j < n; ++j) sigma[(size_t)j] = (int)j;
-    for (int64_t p = n - 1; p >= 0; --p) std::swap(sigma[(size_t)p], sigma[(size_t)hp[(size_t)p]]);
-    e = hipMemcpy(sig, sigma.data(), sizeof(int) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_permute_cols(s, A, ctx->coarse_inv, n, sig);
-    t.done();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    cleanup();
-    if (e != hipSuccess)
-      return fail(ctx, STV_EHIP, std::string("coarse inverse failed: ") + hipGetErrorString(e));
+  if (coarse_singular) {
+    if (bad_level) *bad_level = 0;
+    if (bad_cell) *bad_cell = -1;
+    free_inverses(ctx);
+    return fail(ctx, STV_ESINGULAR, "zero pivot in the coarse matrix");
   }
   ctx->have_inv = true;
   return STV_OK;
@@ -857,7 +909,7 @@ int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out) {
     const int row = l * nls + alpha;   // eq. (4.4) order
     for (int j = 0; j < n; ++j) {
       const int beta = j / b, lj = j % b;
-      out[(int64_t)row * n + lj * nls + beta] = blk[(size_t)j * R + o];
+      out[(int64_t)row * n + lj * nls + beta] = blk[(size_t)o * n + j];   // stored row-major
     }
   }
   return STV_OK;
@@ -880,17 +932,27 @@ int stv_set_timing(stv_ctx* ctx, int on) {
   STV_HIP(hipStreamSynchronize(ctx->stream));
   resolve_timers(ctx);
   ctx->timing = on != 0;
-  for (int c = 0; c < KC_COUNT; ++c) { ctx->launches[c] = 0; ctx->total_ms[c] = 0.0; }
+  for (int c = 0; c < KC_COUNT; ++c)
+    for (int g = 0; g < kMaxLevels; ++g) { ctx->launches[c][g] = 0; ctx->total_ms[c][g] = 0.0; }
   return STV_OK;
 }
 
-int stv_kernel_stats(stv_ctx* ctx, int kernel_class, int64_t* launches, double* total_ms) {
+int stv_kernel_stats(stv_ctx* ctx, int kernel_class, int level, int64_t* launches,
+                     double* total_ms) {
   if (!ctx) return STV_EINVAL;
   if (kernel_class < 0 || kernel_class >= KC_COUNT) return fail(ctx, STV_EINVAL, "unknown kernel class");
+  if (level < -1 || level >= kMaxLevels) return fail(ctx, STV_EINVAL, "level out of range");
   STV_HIP(hipStreamSynchronize(ctx->stream));
   resolve_timers(ctx);
-  if (launches) *launches = ctx->launches[kernel_class];
-  if (total_ms) *total_ms = ctx->total_ms[kernel_class];
+  int64_t n = 0;
+  double ms = 0.0;
+  for (int g = 0; g < kMaxLevels; ++g)
+    if (level < 0 || g == level) {
+      n += ctx->launches[kernel_class][g];
+      ms += ctx->total_ms[kernel_class][g];
+    }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
   return STV_OK;
 }
 

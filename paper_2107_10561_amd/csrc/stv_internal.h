@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/stv.h"
+#include "stv.h"
 
 namespace stv {
 
@@ -42,6 +42,8 @@ struct DevLevel {
   int32_t* P_rowptr = nullptr; int32_t* P_col = nullptr; double* P_val = nullptr;
   int32_t* Pt_rowptr = nullptr; int32_t* Pt_col = nullptr; double* Pt_val = nullptr;
   int32_t n_s_coarse = 0;
+  // block position of each cell DoF pair (levels >= 1), n_cells * n_ls^2
+  int32_t* posmap = nullptr;
   // stored inverses (levels >= 1)
   int64_t* inv_off = nullptr;     // [n_cells] element offset of each cell's block
   void* inv_store = nullptr;
@@ -56,13 +58,15 @@ struct DevLevel {
   std::vector<uint8_t> h_own_loc;
 };
 
-struct TimerPair { hipEvent_t a, b; int cls; };
+struct TimerPair { hipEvent_t a, b; int cls; int level; };
 
 }  // namespace stv
 
 struct stv_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;     // internal stream: coarse factorisation overlaps the cell inverses
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   int n_levels = 0, dim = 0, k = 0, b = 0;
   stv::DevLevel lv[stv::kMaxLevels];
@@ -87,8 +91,8 @@ struct stv_ctx {
   bool timing = false;
   std::vector<stv::TimerPair> pending;
   std::vector<hipEvent_t> pool;
-  int64_t launches[stv::KC_COUNT] = {};
-  double total_ms[stv::KC_COUNT] = {};
+  int64_t launches[stv::KC_COUNT][stv::kMaxLevels] = {};
+  double total_ms[stv::KC_COUNT][stv::kMaxLevels] = {};
 };
 
 namespace stv {
@@ -97,7 +101,8 @@ namespace stv {
 // y = (r ? r : 0) + sx * (J x)
 hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
                        const double* x, double* y, double sx);
-bool inverse_fits_lds(int n);
+bool inverse_fits_regs(int b, int n_ls);
+hipError_t launch_build_posmap(hipStream_t s, const DevLevel& L);
 hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const double* rho,
                               double* d, double omega, int zero_init, int fp32, int full);
 hipError_t launch_vanka_cells_corr(hipStream_t s, int b, const DevLevel& L, const double* rho,
@@ -113,9 +118,10 @@ hipError_t launch_fill(hipStream_t s, double* x, int64_t n, double v);
 hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 // dense coarse level
 hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* A, int64_t n);
-hipError_t launch_gj_step(hipStream_t s, double* A, int64_t n, int p, double* prow,
-                          double* trow, double* pcol, int* piv);
-hipError_t launch_permute_cols(hipStream_t s, const double* A, double* out, int64_t n,
+int gj_panel_width(int64_t n);
+hipError_t launch_gj_blocked(hipStream_t s, double* A, int64_t n, int* piv, double* Bbuf);
+hipError_t launch_set_diag(hipStream_t s, double* A, int64_t lda, int64_t from, int64_t to);
+hipError_t launch_permute_cols(hipStream_t s, const double* A, int64_t lda, double* out, int64_t n,
                                const int* sigma);
 hipError_t launch_dense_gemv(hipStream_t s, const double* A, int64_t n, const double* x,
                              double* y);

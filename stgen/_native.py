@@ -30,9 +30,9 @@ def lib():
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         L.stgen_row_bounds.argtypes = [i32, i32, i32, P, P]
         L.stgen_row_bounds.restype = None
-        L.stgen_pattern.argtypes = [i32, i32, i32, P, P, P, P, P]
+        L.stgen_pattern.argtypes = [i32, i32, i32, P, P, P, ctypes.c_int, P, P, P, P]
         L.stgen_pattern.restype = None
-        L.stgen_scatter.argtypes = [i32, i32, P, i64, i64, P, ctypes.c_int, P, P, P, P, P, P, P]
+        L.stgen_scatter.argtypes = [i32, i32, P, i64, i64, P, ctypes.c_int, P, P, P, P, P, P, P, P]
         L.stgen_scatter.restype = None
         _lib = L
     return _lib

@@ -151,11 +151,37 @@ def mass_operator(mesh: Mesh, const):
     return M
 
 
-def bsr_pattern(mesh: Mesh, cell_sdofs: np.ndarray):
-    """Block-row pattern: all spatial pairs sharing a cell (sorted columns)."""
+def dof_kinds(mesh: Mesh) -> np.ndarray:
+    """Kind of each spatial DoF: velocity component 0..dim-1, or dim for pressure."""
+    d = mesh.dim
+    kind = np.full(mesh.n_sdofs, d, dtype=np.uint8)
+    kind[: d * mesh.n_vnodes] = np.tile(np.arange(d, dtype=np.uint8), mesh.n_vnodes)
+    return kind
+
+
+def coupling_table(dim: int, pattern: str) -> np.ndarray:
+    """Which kinds couple.  'full': every pair of DoFs sharing a cell.
+    'oseen': drop the blocks the Oseen operator leaves structurally zero
+    (different velocity components, pressure-pressure)."""
+    if pattern == "full":
+        return np.ones((dim + 1, dim + 1), dtype=np.uint8)
+    if pattern == "oseen":
+        t = np.eye(dim + 1, dtype=np.uint8)
+        t[:dim, dim] = 1
+        t[dim, :dim] = 1
+        t[dim, dim] = 0
+        return t
+    raise ValueError(pattern)
+
+
+def bsr_pattern(mesh: Mesh, cell_sdofs: np.ndarray, pattern: str = "oseen"):
+    """Block-row pattern: pairs of spatial DoFs sharing a cell whose kinds
+    couple (sorted columns)."""
     L = lib()
     ns, nc, nls = mesh.n_sdofs, mesh.n_cells, mesh.n_ls
     csd = np.ascontiguousarray(cell_sdofs, dtype=np.int32)
+    kind = dof_kinds(mesh)
+    table = np.ascontiguousarray(coupling_table(mesh.dim, pattern))
     bound = np.zeros(ns, dtype=np.int64)
     L.stgen_row_bounds(ns, nc, nls, csd.ctypes.data, bound.ctypes.data)
     bptr = np.zeros(ns + 1, dtype=np.int64)
@@ -163,16 +189,20 @@ def bsr_pattern(mesh: Mesh, cell_sdofs: np.ndarray):
     scratch = np.empty(int(bptr[-1]), dtype=np.int32)
     fill = np.empty(ns, dtype=np.int64)
     rowptr = np.empty(ns + 1, dtype=np.int64)
-    L.stgen_pattern(ns, nc, nls, csd.ctypes.data, bptr.ctypes.data, scratch.ctypes.data,
-                    fill.ctypes.data, rowptr.ctypes.data)
+    L.stgen_pattern(ns, nc, nls, csd.ctypes.data, bptr.ctypes.data, kind.ctypes.data,
+                    mesh.dim + 1, table.ctypes.data, scratch.ctypes.data, fill.ctypes.data,
+                    rowptr.ctypes.data)
     col = scratch[: int(rowptr[-1])].copy()
     del scratch
     return rowptr, col
 
 
-def assemble_level(mesh: Mesh, k: int, tau: float, nu_cell, conv, chunk: int = 4096):
+def assemble_level(mesh: Mesh, k: int, tau: float, nu_cell, conv, chunk: int = 4096,
+                   pattern: str = "oseen"):
     """Space-time block-sparse Jacobian of one level.
 
+    pattern 'oseen' stores only the blocks the Oseen operator can make nonzero;
+    'full' stores every pair of DoFs sharing a cell (explicit zeros included).
     Returns dict(rowptr int64, col int32, val float64 (nnzb, b, b), cell_sdofs).
     """
     ref = RefData(mesh.dim)
@@ -183,16 +213,19 @@ def assemble_level(mesh: Mesh, k: int, tau: float, nu_cell, conv, chunk: int = 4
     tw = np.ascontiguousarray(tau * w)
     Ct = np.ascontiguousarray(C)
     csd = mesh.cell_sdofs()
-    rowptr, col = bsr_pattern(mesh, csd)
+    rowptr, col = bsr_pattern(mesh, csd, pattern)
     nnzb = int(rowptr[-1])
     val = np.zeros((nnzb, b, b))
     colour = mesh.colours()
     L = lib()
     nls = mesh.n_ls
+    dropped = np.zeros(1, dtype=np.int64)
     for c0 in range(0, mesh.n_cells, chunk):
         cells = np.arange(c0, min(mesh.n_cells, c0 + chunk))
         Ae = np.ascontiguousarray(cell_operators(mesh, ref, const, nu_cell, conv, cells))
         L.stgen_scatter(nls, b, csd.ctypes.data, c0, len(cells), colour.ctypes.data, 1 << mesh.dim,
                         Ae.ctypes.data, Me.ctypes.data, Ct.ctypes.data, tw.ctypes.data,
-                        rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+                        rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, dropped.ctypes.data)
+        if dropped[0]:
+            raise RuntimeError(f"pattern '{pattern}' drops {dropped[0]} nonzero entries")
     return dict(rowptr=rowptr, col=col, val=val, cell_sdofs=csd)

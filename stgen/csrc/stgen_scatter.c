@@ -37,20 +37,25 @@ void stgen_row_bounds(int32_t n_sdofs, int32_t n_cells, int32_t n_ls,
  * scratch (the caller copies rowptr[n] entries out). */
 void stgen_pattern(int32_t n_sdofs, int32_t n_cells, int32_t n_ls,
                    const int32_t* cell_sdofs, const int64_t* bptr,
+                   const uint8_t* kind, int n_kinds, const uint8_t* coupling,
                    int32_t* scratch, int64_t* fill, int64_t* rowptr) {
+  /* kind[s] classifies spatial DoF s; coupling[kr * n_kinds + kc] != 0 keeps
+   * the blocks between kinds kr (row) and kc (column). */
   for (int64_t r = 0; r < n_sdofs; ++r) fill[r] = bptr[r];
   for (int64_t c = 0; c < n_cells; ++c) {
     const int32_t* sd = cell_sdofs + c * n_ls;
     for (int a = 0; a < n_ls; ++a) {
       int32_t row = sd[a];
-      memcpy(scratch + fill[row], sd, sizeof(int32_t) * (size_t)n_ls);
-      fill[row] += n_ls;
+      const uint8_t* cp = coupling + (size_t)kind[row] * n_kinds;
+      for (int bb = 0; bb < n_ls; ++bb)
+        if (cp[kind[sd[bb]]]) scratch[fill[row]++] = sd[bb];
     }
   }
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t r = 0; r < n_sdofs; ++r) {
     int32_t* seg = scratch + bptr[r];
-    int64_t n = bptr[r + 1] - bptr[r];
+    int64_t n;
+    n = fill[r] - bptr[r];
     qsort(seg, (size_t)n, sizeof(int32_t), cmp_i32);
     int64_t u = 0;
     for (int64_t e = 0; e < n; ++e)
@@ -68,11 +73,12 @@ void stgen_pattern(int32_t n_sdofs, int32_t n_cells, int32_t n_ls,
 }
 
 static int64_t find_col(const int32_t* col, int64_t lo, int64_t hi, int32_t key) {
+  const int64_t end = hi;
   while (lo < hi) {
     int64_t mid = lo + (hi - lo) / 2;
     if (col[mid] < key) lo = mid + 1; else hi = mid;
   }
-  return lo;
+  return (lo < end && col[lo] == key) ? lo : -1;
 }
 
 /* Scatter a chunk of cells [c0, c0+nc) whose element operators Ae are given
@@ -84,9 +90,12 @@ void stgen_scatter(int32_t n_ls, int32_t b, const int32_t* cell_sdofs,
                    int64_t c0, int64_t nc, const uint8_t* colour, int n_colours,
                    const double* Ae, const double* Me, const double* Ct,
                    const double* tw, const int64_t* rowptr, const int32_t* col,
-                   double* val) {
+                   double* val, int64_t* dropped_nonzeros) {
+  /* Pairs absent from the pattern must carry exactly zero; any nonzero
+   * contribution to such a pair is counted in *dropped_nonzeros. */
+  int64_t dropped = 0;
   for (int col_id = 0; col_id < n_colours; ++col_id) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(+ : dropped)
     for (int64_t t = 0; t < nc; ++t) {
       int64_t c = c0 + t;
       if (colour[c] != col_id) continue;
@@ -97,6 +106,10 @@ void stgen_scatter(int32_t n_ls, int32_t b, const int32_t* cell_sdofs,
         for (int bb = 0; bb < n_ls; ++bb) {
           int64_t pos = find_col(col, rowptr[row], rowptr[row + 1], sd[bb]);
           double m = Me[a * n_ls + bb], aa = A[a * n_ls + bb];
+          if (pos < 0) {
+            if (m != 0.0 || aa != 0.0) ++dropped;
+            continue;
+          }
           double* blk = val + pos * (int64_t)b * b;
           for (int i = 0; i < b; ++i)
             for (int l = 0; l < b; ++l)
@@ -105,4 +118,5 @@ void stgen_scatter(int32_t n_ls, int32_t b, const int32_t* cell_sdofs,
       }
     }
   }
+  *dropped_nonzeros = dropped;
 }

@@ -203,3 +203,24 @@ def test_prolongation_reproduces_coarse_functions(dim):
     Uf = interpolate(fm, 0, 1.0, 0.0, vf, pco)
     Uc = interpolate(cm, 0, 1.0, 0.0, vf, pco)
     np.testing.assert_allclose(P @ Uc, Uf, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (3, 1)])
+def test_oseen_pattern_drops_only_zero_blocks(dim, k):
+    """The compact pattern stores the same operator as the full cell-pair pattern."""
+    from stgen.problem import Convection
+    n = (4, 2) if dim == 2 else (2, 2, 2)
+    ext = (2.2, 0.41) if dim == 2 else (2.5, 0.41, 0.41)
+    m = Mesh(dim, n, ext)
+    rng = np.random.default_rng(0)
+    conv = Convection(dim, ext, rng.standard_normal(4) if dim == 2 else rng.standard_normal((4, 3)))
+    nu = np.full(m.n_cells, 1e-3)
+    mats = []
+    for pat in ("full", "oseen"):
+        A = assemble_level(m, k, 0.01, nu, conv, pattern=pat)
+        mats.append(sp.bsr_matrix((A["val"], A["col"], A["rowptr"]),
+                                  shape=(m.n_sdofs * (k + 1),) * 2).toarray())
+    np.testing.assert_array_equal(mats[0], mats[1])
+    full = assemble_level(m, k, 0.01, nu, conv, pattern="full")
+    comp = assemble_level(m, k, 0.01, nu, conv, pattern="oseen")
+    assert comp["rowptr"][-1] < 0.75 * full["rowptr"][-1]
