@@ -555,12 +555,13 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   std::vector<uint8_t*> status((size_t)ctx->n_levels, nullptr);
   std::vector<double*> scratch((size_t)ctx->n_levels, nullptr);
   std::vector<int> slots((size_t)ctx->n_levels, 0);
-  double *A = nullptr, *Bbuf = nullptr;
-  int *piv = nullptr, *sig = nullptr;
+  double *A = nullptr, *Bbuf = nullptr, *pbuf = nullptr;
+  int *piv = nullptr, *rinv_d = nullptr;
+  uint8_t* used = nullptr;
   auto cleanup = [&]() {
     for (auto& p : status) dfree(p);
     for (auto& p : scratch) dfree(p);
-    dfree(A); dfree(Bbuf); dfree(piv); dfree(sig);
+    dfree(A); dfree(Bbuf); dfree(pbuf); dfree(piv); dfree(rinv_d); dfree(used);
   };
   int rc = STV_OK;
   for (int g = 1; g < ctx->n_levels && rc == STV_OK; ++g) {
@@ -601,8 +602,10 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if ((rc = dalloc(ctx, &A, (size_t)(np * np))) == STV_OK &&
         (rc = dalloc(ctx, &ctx->coarse_inv, (size_t)(n0 * n0))) == STV_OK &&
         (rc = dalloc(ctx, &Bbuf, (size_t)(nb * np))) == STV_OK &&
-        (rc = dalloc(ctx, &piv, (size_t)np)) == STV_OK)
-      rc = dalloc(ctx, &sig, (size_t)np);
+        (rc = dalloc(ctx, &pbuf, (size_t)(2 * nb * np))) == STV_OK &&
+        (rc = dalloc(ctx, &piv, (size_t)np)) == STV_OK &&
+        (rc = dalloc(ctx, &used, (size_t)np)) == STV_OK)
+      rc = dalloc(ctx, &rinv_d, (size_t)np);
   }
   if (rc != STV_OK) {
     cleanup();
@@ -624,27 +627,29 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (e == hipSuccess) e = launch_fill(side, A, np * np, 0.0);
     if (e == hipSuccess) e = launch_bsr_to_dense(side, b, L0, A, np);
     if (e == hipSuccess) e = launch_set_diag(side, A, np, n0, np);
-    if (e == hipSuccess) e = launch_gj_blocked(side, A, np, piv, Bbuf);
+    if (e == hipSuccess) e = hipMemsetAsync(used, 0, (size_t)np, side);
+    if (e == hipSuccess) e = launch_gj_blocked(side, A, np, piv, used, Bbuf, pbuf);
     t.done();
   }
   std::vector<int> hp((size_t)np);
   if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), piv, sizeof(int) * np, hipMemcpyDeviceToHost, side);
   if (e == hipSuccess) e = hipStreamSynchronize(side);
   bool coarse_singular = false;
-  std::vector<int> sigma((size_t)np);
+  std::vector<int> rinv((size_t)np, -1);
   if (e == hipSuccess) {
-    for (int64_t p = 0; p < np; ++p)
-      if (hp[(size_t)p] < 0) coarse_singular = true;
-    if (!coarse_singular) {
-      for (int64_t j = 0; j < np; ++j) sigma[(size_t)j] = (int)j;
-      for (int64_t p = np - 1; p >= 0; --p) std::swap(sigma[(size_t)p], sigma[(size_t)hp[(size_t)p]]);
-      for (int64_t j = 0; j < n0; ++j)
-        if (sigma[(size_t)j] >= n0) coarse_singular = true;
+    for (int64_t p = 0; p < np; ++p) {
+      const int r = hp[(size_t)p];
+      if (r < 0 || r >= np || rinv[(size_t)r] >= 0) { coarse_singular = true; break; }
+      rinv[(size_t)r] = (int)p;
     }
+    // the real block must pivot within itself (the padding is an identity)
+    for (int64_t p = 0; p < n0 && !coarse_singular; ++p)
+      if (hp[(size_t)p] >= n0) coarse_singular = true;
     if (!coarse_singular) {
       Timed t(ctx, KC_COARSE_FACTOR, 0, side);
-      e = hipMemcpyAsync(sig, sigma.data(), sizeof(int) * np, hipMemcpyHostToDevice, side);
-      if (e == hipSuccess) e = launch_permute_cols(side, A, np, ctx->coarse_inv, n0, sig);
+      e = hipMemcpyAsync(rinv_d, rinv.data(), sizeof(int) * np, hipMemcpyHostToDevice, side);
+      if (e == hipSuccess) e = launch_gj_unpermute(side, A, np, ctx->coarse_inv, n0, piv, rinv_d);
+      if (e == hipSuccess) e = hipStreamSynchronize(side);   // rinv (host) outlives the copy
       t.done();
     }
   }

@@ -119,10 +119,12 @@ hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 // dense coarse level
 hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* A, int64_t n);
 int gj_panel_width(int64_t n);
-hipError_t launch_gj_blocked(hipStream_t s, double* A, int64_t n, int* piv, double* Bbuf);
+// Bbuf: nb x n; pbuf: 2 x n x nb (two panel buffers)
+hipError_t launch_gj_blocked(hipStream_t s, double* A, int64_t n, int* rpiv, uint8_t* used,
+                             double* Bbuf, double* pbuf);
 hipError_t launch_set_diag(hipStream_t s, double* A, int64_t lda, int64_t from, int64_t to);
-hipError_t launch_permute_cols(hipStream_t s, const double* A, int64_t lda, double* out, int64_t n,
-                               const int* sigma);
+hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t lda, double* out, int64_t n,
+                               const int* rpiv, const int* rinv);
 hipError_t launch_dense_gemv(hipStream_t s, const double* A, int64_t n, const double* x,
                              double* y);
 // Krylov helpers: V is row-major (m vectors of length n)
