@@ -261,3 +261,73 @@ def test_nan_rhs_and_max_it(stv):
     assert ei.value.code == stv.STV_ENUMERIC
     info = s.gmres_solve(to_dev(p.rhs), x, max_it=1, raise_on_noconv=False)
     assert info["status"] == stv.STV_ENOCONV and info["iters"] == 1 and not info["converged"]
+
+
+def _solve_case(stv, dim, n, G, k, seed):
+    p = make_problem_cached(dim, n, G, k, seed)
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, dim, k)
+    s.build_cell_inverses()
+    return p, s
+
+
+_cases = {}
+
+
+def make_problem_cached(dim, n, G, k, seed):
+    from stgen.problem import make_problem
+    key = (dim, n, G, k, seed)
+    if key not in _cases:
+        _cases[key] = make_problem(dim, n, G, k, 0.01, 1e-3, seed)
+    return _cases[key]
+
+
+def test_ragged_cell_counts(stv):
+    """6x2 fine / 3x1 coarse: cell and row counts that fill no launch tile."""
+    p, s = _solve_case(stv, 2, (6, 2), 2, 1, 31)
+    ol = oracle.prepare_levels(p.levels, p.b)
+    oracle.build_inverses(ol)
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(ol[-1].n_st)
+    d0 = rng.standard_normal(ol[-1].n_st)
+    dd = to_dev(d0)
+    s.vanka_sweep(1, to_dev(r), dd, 1, 0.7)
+    assert relerr(to_host(dd), oracle.vanka_sweep(ol[-1], r, d0, 0.7)) <= 1e-12
+    x = to_dev(np.zeros(ol[-1].n_st))
+    s.vcycle(to_dev(r), x, 2, 2, 0.7)
+    assert relerr(to_host(x), oracle.vcycle(ol, r, 2, 2, 0.7)) <= 1e-11
+    s.close()
+
+
+def test_single_level_hierarchy(stv):
+    """One level: the V-cycle is the direct coarse solve and GMRES converges at once."""
+    p, s = _solve_case(stv, 2, (4, 2), 1, 1, 32)
+    J = oracle.prepare_levels(p.levels, p.b)[0].J.toarray()
+    x = to_dev(np.zeros(J.shape[0]))
+    s.vcycle(to_dev(p.rhs), x, 2, 2, 0.7)
+    assert relerr(to_host(x), np.linalg.solve(J, p.rhs)) <= 1e-11
+    x = to_dev(np.zeros(J.shape[0]))
+    info = s.gmres_solve(to_dev(p.rhs), x)
+    assert info["converged"] and info["iters"] <= 2
+    s.close()
+
+
+def test_one_cell_fine_level_is_exact(stv):
+    """Smallest hierarchy: 2x2 fine cells over a 1x1 coarse cell, omega = 1."""
+    p, s = _solve_case(stv, 2, (2, 2), 2, 1, 33)
+    ol = oracle.prepare_levels(p.levels, p.b)
+    oracle.build_inverses(ol)
+    r = np.random.default_rng(8).standard_normal(ol[-1].n_st)
+    x = to_dev(np.zeros(ol[-1].n_st))
+    s.vcycle(to_dev(r), x, 1, 1, 1.0)
+    assert relerr(to_host(x), oracle.vcycle(ol, r, 1, 1, 1.0)) <= 1e-11
+    s.close()
+
+
+def test_zero_rhs(stv):
+    p, ol = problem("c1_2d_dg1")
+    s = solver(stv, "c1_2d_dg1")
+    x = to_dev(np.ones(ol[-1].n_st))
+    info = s.gmres_solve(to_dev(np.zeros(ol[-1].n_st)), x)
+    assert info["converged"] and info["iters"] == 0
+    assert not np.any(to_host(x))
