@@ -24,6 +24,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_2d512x128_dG2.json")
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the counter record in profiles/, or None when
+    there is none for this workload or the kernel source changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload or kernel not in rec:
+        return None
+    src = os.path.join(ROOT, rec["kernel_source"])
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if sha != rec.get("kernel_source_sha256"):
+        return None
+    return int(rec[kernel]["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -170,7 +191,7 @@ def main():
     zi = 1.0 / (args.nu1 + args.nu2) if args.nu1 > 0 else 0.0
     inv_b = {g: s.level_info(g)["inverse_bytes"] for g in range(1, G)}
 
-    def roofline(cls, bytes_of, kernel):
+    def roofline(cls, bytes_of, kernel, traffic_key):
         """Aggregate over every launch of the kernel in the timed region (the
         population rocprofv3's per-kernel average covers) plus the finest level."""
         tb = tms = 0.0
@@ -184,7 +205,8 @@ def main():
         gbs = tb / (tms / 1e3) / 1e9 if tms > 0 else 0.0
         gbs_f = bytes_of(top) / (ms_f / n_f / 1e3) / 1e9 if n_f else 0.0
         return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel,
+                    frac=round(gbs / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(args.workload, traffic_key), kernel=kernel,
                     bytes_per_launch=int(tb / max(tn, 1)), avg_launch_ms=round(tms / max(tn, 1), 5),
                     launches=tn, finest_gbs=round(gbs_f, 1),
                     finest_frac=round(gbs_f / HBM_PEAK_GBS, 4),
@@ -192,9 +214,9 @@ def main():
                     finest_avg_launch_ms=round(ms_f / max(n_f, 1), 5))
 
     roof_sweep = roofline("sweep", lambda g: sweep_bytes(p.levels[g], b, inv_b[g], zi),
-                          "Vanka cell sweep (k_vanka), all smoothed levels")
+                          "Vanka cell sweep (k_vanka), all smoothed levels", "k_vanka")
     roof_res = roofline("residual", lambda g: residual_bytes(p.levels[g], b),
-                        "block-sparse level residual (k_spmv), levels >= 1")
+                        "block-sparse level residual (k_spmv), levels >= 1", "k_spmv")
     dominant = roof_sweep if stats["sweep"]["ms"] >= stats["residual"]["ms"] else roof_res
     s.set_timing(False)
 
