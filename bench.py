@@ -59,17 +59,22 @@ def parse():
     ap.add_argument("--nu1", type=int, default=2)
     ap.add_argument("--nu2", type=int, default=2)
     ap.add_argument("--omega", type=float, default=0.7)
+    ap.add_argument("--coarse-algo", default="auto", choices=["auto", "panels", "slabs"])
     return ap.parse_args()
 
 
 WORKLOADS = {
-    # name: (dim, finest cells, levels, k, tau, nu, seed, description)
+    # name: (dim, finest cells, levels, k, tau, nu, seed, description,
+    #        CPU-baseline sample: (finest cells, levels) of the same operator)
     "2d-512x128-dG2": (2, (512, 128), 6, 2, 0.005, 1e-3, 1002,
-                       "2d channel 512x128 Q2/P1disc x dG(2), 6 levels, Oseen nu=1e-3, tau=0.005"),
+                       "2d channel 512x128 Q2/P1disc x dG(2), 6 levels, Oseen nu=1e-3, tau=0.005",
+                       ((256, 64), 5)),
     "2d-16x4-dG1": (2, (16, 4), 2, 1, 0.01, 1e-3, 1001,
-                    "2d channel 16x4 Q2/P1disc x dG(1), 2 levels, Oseen nu=1e-3, tau=0.01"),
+                    "2d channel 16x4 Q2/P1disc x dG(1), 2 levels, Oseen nu=1e-3, tau=0.01",
+                    ((16, 4), 2)),
     "3d-128x24x24-dG1": (3, (128, 24, 24), 4, 1, 0.01, 1e-3, 1003,
-                         "3d channel 128x24x24 Q2/P1disc x dG(1), 4 levels, Oseen nu=1e-3"),
+                         "3d channel 128x24x24 Q2/P1disc x dG(1), 4 levels, Oseen nu=1e-3, tau=0.01",
+                         ((32, 8, 8), 3)),
 }
 
 
@@ -94,16 +99,14 @@ def residual_bytes(L, b):
 
 def cpu_baseline(spec, nu1, nu2, omega):
     """The FP64 oracle on a bounded sample of the same workload: the same
-    channel, operator, degree and coarse grid at half the cells per axis (one
-    level fewer), full step (all inverses + FGMRES to 1e-8), one thread;
+    channel, operator and degree on a smaller mesh (the sample field of the
+    workload), full step (all inverses + FGMRES to 1e-8), one thread;
     reported in cell-sweeps per second."""
     from threadpoolctl import threadpool_limits
 
     import oracle
     from stgen.problem import make_problem
-    dim, n, G, k, tau, nu, seed, _ = spec
-    n_s = tuple(c // 2 for c in n)
-    G_s = G - 1
+    dim, n, G, k, tau, nu, seed, _, (n_s, G_s) = spec
     p = make_problem(dim, n_s, G_s, k, tau, nu, seed)
     with threadpool_limits(1):
         t0 = time.perf_counter()
@@ -134,12 +137,13 @@ def main():
     from stgen.problem import make_problem
 
     spec = WORKLOADS[args.workload]
-    dim, n, G, k, tau, nu, seed, desc = spec
+    dim, n, G, k, tau, nu, seed, desc, _ = spec
     b = k + 1
     t0 = time.time()
     p = make_problem(dim, n, G, k, tau, nu, seed)
     print(f"[bench] generated {desc} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     s = stv.Solver(0)
+    s.set_coarse_algorithm(args.coarse_algo)
     t0 = time.time()
     s.set_hierarchy(p.levels, dim, k)
     t_set = time.time() - t0

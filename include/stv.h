@@ -211,6 +211,16 @@ int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out);
 int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
                    int64_t* n_loc, int64_t* inverse_bytes);
 
+/* Options (take effect at the next stv_build_cell_inverses):
+ *   STV_OPT_COARSE_ALGO: how the coarsest matrix is inverted by Gauss-Jordan
+ *   elimination with partial pivoting: 0 = chosen by size (default),
+ *   1 = one level of narrow panels, each updating the whole matrix,
+ *   2 = slabs of 64 columns eliminated by narrow panels, then one rank-64
+ *   update of the rest on the matrix cores.  Both give the same pivots.
+ * Errors: STV_EINVAL (unknown option or value). */
+#define STV_OPT_COARSE_ALGO 1
+int stv_set_option(stv_ctx* ctx, int option, int64_t value);
+
 /* Per-kernel timing with HIP events on the context's stream.
  * stv_set_timing(ctx, 1) starts recording (and clears the counters);
  * stv_kernel_stats returns launches and total milliseconds of one kernel

@@ -62,6 +62,9 @@ class _GI(ctypes.Structure):
 
 
 def _load():
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded (same soname), so one runtime owns the device, streams and memory
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     I64P = ctypes.POINTER(ctypes.c_int64)
@@ -82,6 +85,7 @@ def _load():
         "stv_get_cell_inverse": (I, [P, I, I, P]),
         "stv_level_info": (I, [P, I, I64P, I64P, I64P, I64P]),
         "stv_set_timing": (I, [P, I]),
+        "stv_set_option": (I, [P, I, ctypes.c_int64]),
         "stv_kernel_stats": (I, [P, I, I, I64P, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
@@ -96,7 +100,9 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_set_hierarchy", "stv_build_cell_inverses", "stv_residual", "stv_vanka_sweep",
             "stv_restrict", "stv_prolongate_add", "stv_coarse_solve", "stv_vcycle",
             "stv_gmres_solve", "stv_get_cell_inverse", "stv_level_info", "stv_set_timing",
-            "stv_kernel_stats")
+            "stv_kernel_stats", "stv_set_option")
+
+COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2}
 
 
 def library():
@@ -262,6 +268,10 @@ class Solver:
         self._check(_lib.stv_level_info(self._h, level, ctypes.byref(a), ctypes.byref(b),
                                         ctypes.byref(c), ctypes.byref(d)))
         return dict(n_sdofs=a.value, n_cells=b.value, n_loc=c.value, inverse_bytes=d.value)
+
+    def set_coarse_algorithm(self, name: str):
+        """Dense inversion of the coarsest matrix: "auto", "panels" or "slabs"."""
+        self._check(_lib.stv_set_option(self._h, 1, COARSE_ALGOS[name]))
 
     def set_timing(self, on: bool):
         self._check(_lib.stv_set_timing(self._h, int(on)))

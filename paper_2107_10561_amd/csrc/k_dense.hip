@@ -7,6 +7,8 @@
 
 namespace stv {
 
+typedef double stv_d4 __attribute__((ext_vector_type(4)));
+
 template <int B>
 __global__ void k_bsr_to_dense(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                const double* __restrict__ val, double* __restrict__ A, int64_t n,
@@ -40,45 +42,54 @@ hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* 
 // rpiv[p]; at the end A^-1(p, j) = S(rpiv[p], rinv[j]) for the in-place
 // result S (rinv the inverse permutation).
 // Panel of NB columns [p0, p0+NB), kept in a contiguous row-major buffer
-// (n x NB): one 512-thread workgroup holds it in registers (thread t owns
-// rows t + 512 m) and eliminates it.  The panel columns then hold the columns
+// (n x NB): one TPB-thread workgroup holds it in registers (thread t owns
+// rows t + TPB m) and eliminates it.  The panel columns then hold the columns
 // rpiv[p0..] of the accumulated elimination matrix E; every other column j
-// (earlier panels included) is brought up to date at once by the rank-NB
-// update  A(:, j) += (E - I)(:, rpiv[p0+t]) * A(rpiv[p0+t], j)  (pivot rows
-// read before it), which also writes the eliminated panel back into A and
-// copies the next panel's updated columns into the other panel buffer.
+// is brought up to date by the rank-NB update
+//   A(:, j) += (E - I)(:, rpiv[p0+t]) * A(rpiv[p0+t], j)
+// with the pivot rows read before it: the panel kernel copies those rows of
+// the matrix being updated (S, ncs columns, row stride lds) to Bout once the
+// pivots are known, since nothing else writes S while it runs.
 // rpiv[p] = -1 marks a step without a nonzero finite pivot (singular).
-template <int RPT, int NB>
-__global__ void __launch_bounds__(512) k_gj_panel(double* __restrict__ pbuf, int64_t n, int p0,
+template <int RPT, int NB, int TPB>
+__global__ void __launch_bounds__(TPB) k_gj_panel(double* __restrict__ pbuf, int64_t n, int p0,
                                                   int* __restrict__ rpiv,
-                                                  uint8_t* __restrict__ used) {
+                                                  uint8_t* __restrict__ used,
+                                                  const double* __restrict__ S, int64_t lds,
+                                                  int64_t ncs, double* __restrict__ Bout) {
   // per step, each wavefront publishes its best candidate (magnitude, row)
   // together with that row's panel values; one barrier, then every thread
-  // picks the winner among the 8 candidates (double-buffered by step parity)
-  __shared__ double wbest[2][8];
-  __shared__ int widx[2][8];
-  __shared__ double wrow[2][8][NB];
+  // picks the winner among the NW candidates (double-buffered by step parity)
+  constexpr int NW = TPB / 64;
+  __shared__ double wbest[2][NW];
+  __shared__ int widx[2][NW];
+  __shared__ double wrow[2][NW][NB];
   __shared__ int rloc[NB];     // pivot records, written to global memory once at the end
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, kept in an SGPR
   double P[RPT][NB];
-  unsigned umask = 0;   // bit m: row tid + 512 m already used as a pivot
+  unsigned umask = 0;   // bit m: row tid + TPB m already used as a pivot
+  // 32-bit offsets (n * NB < 2^28) let the loads and stores address from
+  // the uniform base pointer instead of holding a 64-bit address per row
+  const unsigned nu = (unsigned)n;
 #pragma unroll
   for (int m = 0; m < RPT; ++m) {
-    const int64_t i = tid + 512 * m;
+    const unsigned i = (unsigned)tid + TPB * m;
 #pragma unroll
-    for (int t = 0; t < NB; ++t) P[m][t] = (i < n) ? pbuf[i * NB + t] : 0.0;
-    if (i >= n || used[i]) umask |= 1u << m;
+    for (int t = 0; t < NB; ++t) P[m][t] = (i < nu) ? pbuf[i * NB + t] : 0.0;
+    if (i >= nu || used[i]) umask |= 1u << m;
   }
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     const int par = t & 1;
     double best = -1.0;
-    int bi = 0x7fffffff;
+    int bm = -1;
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
       const double v = fabs(P[m][t]);
-      if (!(umask & (1u << m)) && v > best) { best = v; bi = tid + 512 * m; }
+      if (!(umask & (1u << m)) && v > best) { best = v; bm = m; }
     }
+    int bi = bm >= 0 ? tid + TPB * bm : 0x7fffffff;
     // wave argmax (largest magnitude, lowest row on ties)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -89,10 +100,10 @@ __global__ void __launch_bounds__(512) k_gj_panel(double* __restrict__ pbuf, int
     bi = __builtin_amdgcn_readfirstlane(bi);   // identical in every lane
     if (lane == 0) { wbest[par][wv] = best; widx[par][wv] = bi; }
     if (bi < 0x7fffffff) {
-      const int mo = bi / 512;                 // wave-uniform: one scalar-branched write
+      const int mo = bi / TPB;                 // wave-uniform: one scalar-branched write
 #pragma unroll
       for (int m = 0; m < RPT; ++m)
-        if (m == mo && tid == bi - 512 * m) {
+        if (m == mo && tid == bi - TPB * m) {
 #pragma unroll
           for (int c = 0; c < NB; ++c) wrow[par][wv][c] = P[m][c];
         }
@@ -102,7 +113,7 @@ __global__ void __launch_bounds__(512) k_gj_panel(double* __restrict__ pbuf, int
     int cand = widx[par][0];
     int win = 0;
 #pragma unroll
-    for (int w2 = 1; w2 < 8; ++w2) {
+    for (int w2 = 1; w2 < NW; ++w2) {
       const double ob = wbest[par][w2];
       const int oi = widx[par][w2];
       if (ob > mx || (ob == mx && oi < cand)) { mx = ob; cand = oi; win = w2; }
@@ -118,9 +129,10 @@ __global__ void __launch_bounds__(512) k_gj_panel(double* __restrict__ pbuf, int
     for (int c = 0; c < NB; ++c) pr[c] = wrow[par][win][c];
     const double pv = pr[t];
     const double ipiv = (pv != 0.0) ? 1.0 / pv : 0.0;
+    const int dr = r - tid;
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
-      const bool isr = (tid + 512 * m == r);
+      const bool isr = (dr == TPB * m);
       if (isr) umask |= 1u << m;
       // pivot row: (src 0, factor -1/piv); other rows: (own value, factor a_it/piv)
       const double f = isr ? -ipiv : P[m][t] * ipiv;
@@ -132,8 +144,8 @@ __global__ void __launch_bounds__(512) k_gj_panel(double* __restrict__ pbuf, int
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < RPT; ++m) {
-    const int64_t i = tid + 512 * m;
-    if (i < n) {
+    const unsigned i = (unsigned)tid + TPB * m;
+    if (i < nu) {
 #pragma unroll
       for (int t = 0; t < NB; ++t) pbuf[i * NB + t] = P[m][t];
     }
@@ -143,18 +155,31 @@ __global__ void __launch_bounds__(512) k_gj_panel(double* __restrict__ pbuf, int
     rpiv[p0 + tid] = r;
     if (r >= 0) used[r] = 1;
   }
+  // pivot rows of S before the update (row r < n always holds when r >= 0)
+  for (int64_t e = tid; e < NB * ncs; e += TPB) {
+    const int t = (int)(e / ncs);
+    const int64_t c = e - t * ncs;
+    const int r = rloc[t];
+    Bout[e] = r >= 0 ? S[(int64_t)r * lds + c] : 0.0;
+  }
 }
 
-// First panel: columns [0, NB) of A into the row-major panel buffer.
-__global__ void k_gj_load_panel(const double* __restrict__ A, int64_t n, int nb,
-                                double* __restrict__ pbuf) {
+// out (rows x nb, row-major) = columns [c0, c0+nb) of A (row stride lda).
+__global__ void k_gj_load_panel(const double* __restrict__ A, int64_t lda, int64_t rows,
+                                int64_t c0, int nb, double* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * nb) return;
+  if (e >= rows * nb) return;
   const int64_t i = e / nb;
-  pbuf[e] = A[i * n + (e - i * nb)];
+  out[e] = A[i * lda + c0 + (e - i * nb)];
 }
 
-// Pivot rows of the panel as they were before its update (right factor).
+static hipError_t load_panel(hipStream_t s, const double* A, int64_t lda, int64_t rows, int64_t c0,
+                             int nb, double* out) {
+  k_gj_load_panel<<<(unsigned)((rows * nb + 255) / 256), 256, 0, s>>>(A, lda, rows, c0, nb, out);
+  return hipGetLastError();
+}
+
+// Pivot rows rpiv[p0..p0+nb) of A (n x n) before an update: Bbuf (nb x n).
 __global__ void k_gj_gather_rows(const double* __restrict__ A, int64_t n, int p0, int nb,
                                  const int* __restrict__ rpiv, double* __restrict__ Bbuf) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -211,19 +236,16 @@ __global__ void __launch_bounds__(256) k_gj_rank_update(double* __restrict__ A, 
   }
 }
 
-template <int RPT, int NB>
+// One-level variant: every panel updates the whole matrix (rank NB).
+template <int RPT, int NB, int TPB>
 static hipError_t gj_blocked(hipStream_t s, double* A, int64_t n, int* rpiv, uint8_t* used,
                              double* Bbuf, double* pbuf) {
   double* pb[2] = {pbuf, pbuf + n * NB};
-  k_gj_load_panel<<<(unsigned)((n * NB + 255) / 256), 256, 0, s>>>(A, n, NB, pb[0]);
-  hipError_t e = hipGetLastError();
+  hipError_t e = load_panel(s, A, n, n, 0, NB, pb[0]);
   if (e != hipSuccess) return e;
   int cur = 0;
   for (int64_t p0 = 0; p0 < n; p0 += NB, cur ^= 1) {
-    k_gj_panel<RPT, NB><<<1, 512, 0, s>>>(pb[cur], n, (int)p0, rpiv, used);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_gj_gather_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(A, n, (int)p0, NB, rpiv, Bbuf);
+    k_gj_panel<RPT, NB, TPB><<<1, TPB, 0, s>>>(pb[cur], n, (int)p0, rpiv, used, A, n, n, Bbuf);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)((n + 15) / 16));
@@ -234,19 +256,212 @@ static hipError_t gj_blocked(hipStream_t s, double* A, int64_t n, int* rpiv, uin
   return hipSuccess;
 }
 
-// n must be a multiple of the panel width chosen here (the caller pads).
-int gj_panel_width(int64_t n) {
-  if (n <= 2560) return 12;
-  if (n <= 5120) return 8;
-  return 4;
+// Two-level variant.  The columns are processed in slabs of NO: a slab is
+// kept in its own contiguous buffer Sb (n x NO) and eliminated by panels of
+// NB whose rank-NB updates touch only the slab; the slab then holds the
+// columns rpiv[j0..j0+NO) of its accumulated elimination matrix, and the rest
+// of the matrix takes one rank-NO update on the FP64 matrix cores.
+
+// Rank-NB update inside the slab: Sb(i, c) += sum_t (pcur(i, t) - [i ==
+// rp[t]]) Bin(t, c) for c outside [q0, q0+NB), Sb(i, q0+t) = pcur(i, t); the
+// next panel's updated columns are copied to pnext.  64 rows per workgroup.
+template <int NB, int NO>
+__global__ void __launch_bounds__(256) k_gj_slab_inner(double* __restrict__ Sb, int64_t n, int q0,
+                                                       const int* __restrict__ rp,
+                                                       const double* __restrict__ pcur,
+                                                       const double* __restrict__ Bin,
+                                                       double* __restrict__ pnext) {
+  constexpr int RG = 256 / NO;   // row lanes per workgroup
+  __shared__ double W[64][NB];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  for (int e = tid; e < 64 * NB; e += 256) {
+    const int di = e / NB, t = e - di * NB;
+    const int64_t i = i0 + di;
+    W[di][t] = (i < n) ? pcur[i * NB + t] - ((i == rp[t]) ? 1.0 : 0.0) : 0.0;
+  }
+  __syncthreads();
+  const int c = tid % NO, rq = tid / NO;
+  const bool inpan = (c >= q0 && c < q0 + NB);
+  const bool nxt = (c >= q0 + NB && c < q0 + 2 * NB);
+  double bcol[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) bcol[t] = Bin[t * NO + c];
+  for (int di = rq; di < 64; di += RG) {
+    const int64_t i = i0 + di;
+    if (i >= n) break;
+    if (inpan) {
+      Sb[i * NO + c] = pcur[i * NB + (c - q0)];
+      continue;
+    }
+    double acc = Sb[i * NO + c];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) acc = fma(W[di][t], bcol[t], acc);
+    Sb[i * NO + c] = acc;
+    if (nxt) pnext[i * NB + (c - q0 - NB)] = acc;
+  }
 }
 
-hipError_t launch_gj_blocked(hipStream_t s, double* A, int64_t n, int* rpiv, uint8_t* used,
-                             double* Bbuf, double* pbuf) {
-  if (n <= 2560) return gj_blocked<5, 12>(s, A, n, rpiv, used, Bbuf, pbuf);
-  if (n <= 5120) return gj_blocked<10, 8>(s, A, n, rpiv, used, Bbuf, pbuf);
-  if (n <= 12288) return gj_blocked<24, 4>(s, A, n, rpiv, used, Bbuf, pbuf);
-  return hipErrorInvalidValue;
+// Rank-NO update of A (n x n, n a multiple of 64) outside the slab:
+//   A(i, j) += sum_q (Sb(i, q) - [i == rp[q]]) Bg(q, j),
+// the slab's own columns take Sb, and the next slab's updated columns are
+// copied to Snext (and its first nbn columns to pnext).  One 64 x 64 tile per
+// workgroup; each wavefront owns a 32 x 32 quarter as 2 x 2 accumulator tiles
+// of v_mfma_f64_16x16x4f64 (lane l, register v of a tile holds element
+// (4v + (l >> 4), l & 15)); the factors pass through LDS 32 columns of K at a
+// time, which keeps four workgroups resident per compute unit.
+template <int NO>
+__global__ void __launch_bounds__(256) k_gj_slab_update(double* __restrict__ A, int64_t n,
+                                                        int64_t j0, const int* __restrict__ rp,
+                                                        const double* __restrict__ Sb,
+                                                        const double* __restrict__ Bg,
+                                                        double* __restrict__ Snext,
+                                                        double* __restrict__ pnext, int nbn) {
+  constexpr int KC = 32;
+  __shared__ double Ws[64][KC + 1];
+  __shared__ double Bs[KC][64 + 2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, jt = (int64_t)blockIdx.x * 64;
+  if (jt >= j0 && jt < j0 + NO) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      *(double2*)&A[(i0 + r) * n + jt + c] = *(const double2*)&Sb[(i0 + r) * NO + (jt - j0) + c];
+    }
+    return;
+  }
+  const int rb = 32 * (w >> 1), cb = 32 * (w & 1), lr = lane >> 4, lc = lane & 15;
+  stv_d4 acc[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc[ti][tj][v] = A[(i0 + rb + 16 * ti + 4 * v + lr) * n + jt + cb + 16 * tj + lc];
+  for (int kc = 0; kc < NO; kc += KC) {
+    if (kc) __syncthreads();
+    // 64 x KC of the left factor and KC x 64 of the right one, 16-byte loads
+#pragma unroll
+    for (int e = tid; e < 64 * KC / 2; e += 256) {
+      const int r = e / (KC / 2), c = 2 * (e % (KC / 2));
+      const double2 x = *(const double2*)&Sb[(i0 + r) * NO + kc + c];
+      Ws[r][c] = x.x;
+      Ws[r][c + 1] = x.y;
+    }
+#pragma unroll
+    for (int e = tid; e < KC * 32; e += 256) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      *(double2*)&Bs[r][c] = *(const double2*)&Bg[(int64_t)(kc + r) * n + jt + c];
+    }
+    __syncthreads();
+    if (tid < KC) {
+      const int r = rp[kc + tid];
+      if (r >= i0 && r < i0 + 64) Ws[r - i0][tid] -= 1.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      double a[2], bv[2];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) a[ti] = Ws[rb + 16 * ti + lc][4 * kk + lr];
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) bv[tj] = Bs[4 * kk + lr][cb + 16 * tj + lc];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+  }
+  const bool nxt = (jt >= j0 + NO && jt < j0 + 2 * NO);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + rb + 16 * ti + 4 * v + lr;
+        const int64_t j = jt + cb + 16 * tj + lc;
+        A[i * n + j] = acc[ti][tj][v];
+        if (nxt) {
+          const int64_t c = j - j0 - NO;
+          Snext[i * NO + c] = acc[ti][tj][v];
+          if (c < nbn) pnext[i * nbn + c] = acc[ti][tj][v];
+        }
+      }
+}
+
+template <int RPT, int NB, int TPB, int NO>
+static hipError_t gj_slab(hipStream_t s, double* A, int64_t n, int* rpiv, uint8_t* used,
+                          double* Bg, double* Sbuf, double* pbuf, double* Bin) {
+  double* sb[2] = {Sbuf, Sbuf + n * NO};
+  double* pb[2] = {pbuf, pbuf + n * NB};
+  hipError_t e = load_panel(s, A, n, n, 0, NO, sb[0]);
+  if (e == hipSuccess) e = load_panel(s, sb[0], NO, n, 0, NB, pb[0]);
+  if (e != hipSuccess) return e;
+  int cs = 0, cp = 0;
+  const unsigned nt = (unsigned)(n / 64);
+  for (int64_t j0 = 0; j0 < n; j0 += NO, cs ^= 1) {
+    for (int q0 = 0; q0 < NO; q0 += NB, cp ^= 1) {
+      k_gj_panel<RPT, NB, TPB><<<1, TPB, 0, s>>>(pb[cp], n, (int)(j0 + q0), rpiv, used, sb[cs],
+                                                NO, NO, Bin);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      k_gj_slab_inner<NB, NO><<<nt, 256, 0, s>>>(sb[cs], n, q0, rpiv + j0 + q0, pb[cp], Bin,
+                                                 pb[cp ^ 1]);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    k_gj_gather_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(A, n, (int)j0, NO, rpiv, Bg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_gj_slab_update<NO><<<dim3(nt, nt), 256, 0, s>>>(A, n, j0, rpiv + j0, sb[cs], Bg,
+                                                       sb[cs ^ 1], pb[cp], NB);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Panel configurations (panel width, threads, rows per thread, slab width);
+// the largest order each one holds is RPT * TPB.
+struct GjCfg { int nb, tpb, rpt, no; };
+static const GjCfg kCfg1[3] = {{12, 512, 5, 0}, {8, 512, 10, 0}, {4, 768, 15, 0}};
+static const GjCfg kCfg2[3] = {{8, 512, 5, 64}, {8, 512, 10, 64}, {4, 768, 15, 128}};
+
+GjPlan gj_plan(int64_t n, int algo) {
+  GjPlan p{};
+  p.algo = algo == 0 ? ((n > 1024) ? 2 : 1) : algo;
+  const GjCfg* cfg = p.algo == 1 ? kCfg1 : kCfg2;
+  p.cfg = 2;
+  for (int c = 0; c < 3; ++c) {
+    const int pad = p.algo == 1 ? cfg[c].nb : cfg[c].no;
+    if ((n + pad - 1) / pad * pad <= (int64_t)cfg[c].rpt * cfg[c].tpb) { p.cfg = c; break; }
+  }
+  p.nb = cfg[p.cfg].nb;
+  p.no = cfg[p.cfg].no;
+  p.pad = p.algo == 1 ? p.nb : p.no;
+  p.max_n = (int64_t)cfg[p.cfg].rpt * cfg[p.cfg].tpb;
+  return p;
+}
+
+// A is n x n with n a multiple of plan.pad and at most plan.max_n; Bbuf
+// holds max(nb, no) x n, pbuf 2 x n x nb, Sbuf 2 x n x no, Bin nb x no.
+hipError_t launch_gj(hipStream_t s, const GjPlan& p, double* A, int64_t n, int* rpiv,
+                     uint8_t* used, double* Bbuf, double* pbuf, double* Sbuf, double* Bin) {
+  if (n > p.max_n || n % p.pad) return hipErrorInvalidValue;
+  if (p.algo == 1) {
+    switch (p.cfg) {
+      case 0: return gj_blocked<5, 12, 512>(s, A, n, rpiv, used, Bbuf, pbuf);
+      case 1: return gj_blocked<10, 8, 512>(s, A, n, rpiv, used, Bbuf, pbuf);
+      default: return gj_blocked<15, 4, 768>(s, A, n, rpiv, used, Bbuf, pbuf);
+    }
+  }
+  switch (p.cfg) {
+    case 0: return gj_slab<5, 8, 512, 64>(s, A, n, rpiv, used, Bbuf, Sbuf, pbuf, Bin);
+    case 1: return gj_slab<10, 8, 512, 64>(s, A, n, rpiv, used, Bbuf, Sbuf, pbuf, Bin);
+    default: return gj_slab<15, 4, 768, 128>(s, A, n, rpiv, used, Bbuf, Sbuf, pbuf, Bin);
+  }
 }
 
 __global__ void k_set_diag(double* __restrict__ A, int64_t lda, int64_t from, int64_t to) {

@@ -65,7 +65,7 @@ typedef double stv_d4 __attribute__((ext_vector_type(4)));
 // column rpiv[q] of the inverse.
 template <int B, int NLS>
 __global__ void __launch_bounds__(((B * NLS + 15) / 16) * 64)
-__attribute__((amdgpu_waves_per_eu(1, (B * NLS > 128 ? 2 : 8)))) k_inverse_mfma(
+__attribute__((amdgpu_waves_per_eu((((B * NLS + 15) / 16) + 3) / 4, 8))) k_inverse_mfma(
     const int32_t* __restrict__ posmap, const double* __restrict__ val,
     const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
     const int64_t* __restrict__ inv_off, void* store, int fp32, uint8_t* status) {
@@ -119,7 +119,9 @@ __attribute__((amdgpu_waves_per_eu(1, (B * NLS > 128 ? 2 : 8)))) k_inverse_mfma(
     }
   }
 
-#pragma unroll
+  // tile column tc is a run-time index: the accumulator tiles are selected
+  // by compile-time comparisons so that they stay in registers
+#pragma unroll 1
   for (int tc = 0; tc < NT; ++tc) {
     for (int q4 = 0; q4 < 4; ++q4) {
       const int c0 = 4 * q4;          // first panel column inside tile column tc
@@ -127,7 +129,11 @@ __attribute__((amdgpu_waves_per_eu(1, (B * NLS > 128 ? 2 : 8)))) k_inverse_mfma(
       // (a) panel columns -> LDS
       if (lc >= c0 && lc < c0 + 4) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) panel[16 * w + 4 * v + lr][lc - c0] = acc[tc][v];
+        for (int tj = 0; tj < NT; ++tj)
+          if (tj == tc) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) panel[16 * w + 4 * v + lr][lc - c0] = acc[tj][v];
+          }
       }
       __syncthreads();
       // (b) wave 0 eliminates the panel (partial pivoting over unused rows)
@@ -219,7 +225,11 @@ __attribute__((amdgpu_waves_per_eu(1, (B * NLS > 128 ? 2 : 8)))) k_inverse_mfma(
         }
         if (lc >= c0 && lc < c0 + 4) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[tc][v] = panel[16 * w + 4 * v + lr][lc - c0];
+          for (int tj = 0; tj < NT; ++tj)
+            if (tj == tc) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[tj][v] = panel[16 * w + 4 * v + lr][lc - c0];
+            }
         }
       }
       __syncthreads();

@@ -555,13 +555,14 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   std::vector<uint8_t*> status((size_t)ctx->n_levels, nullptr);
   std::vector<double*> scratch((size_t)ctx->n_levels, nullptr);
   std::vector<int> slots((size_t)ctx->n_levels, 0);
-  double *A = nullptr, *Bbuf = nullptr, *pbuf = nullptr;
+  double *A = nullptr, *Bbuf = nullptr, *pbuf = nullptr, *Sbuf = nullptr, *Bin = nullptr;
   int *piv = nullptr, *rinv_d = nullptr;
   uint8_t* used = nullptr;
   auto cleanup = [&]() {
     for (auto& p : status) dfree(p);
     for (auto& p : scratch) dfree(p);
-    dfree(A); dfree(Bbuf); dfree(pbuf); dfree(piv); dfree(rinv_d); dfree(used);
+    dfree(A); dfree(Bbuf); dfree(pbuf); dfree(Sbuf); dfree(Bin); dfree(piv); dfree(rinv_d);
+    dfree(used);
   };
   int rc = STV_OK;
   for (int g = 1; g < ctx->n_levels && rc == STV_OK; ++g) {
@@ -594,15 +595,19 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   }
   DevLevel& L0 = ctx->lv[0];
   const int64_t n0 = (int64_t)L0.n_s * b;
-  if (rc == STV_OK && n0 > 12288) rc = fail(ctx, STV_EINVAL, "coarse level larger than 12288 unknowns");
-  const int nb = gj_panel_width(n0);
-  const int64_t np = (n0 + nb - 1) / nb * nb;
+  const GjPlan plan = gj_plan(n0, ctx->coarse_algo);
+  const int64_t np = (n0 + plan.pad - 1) / plan.pad * plan.pad;
+  if (rc == STV_OK && np > plan.max_n)
+    rc = fail(ctx, STV_EINVAL, "coarse level larger than " + std::to_string(plan.max_n) + " unknowns");
   if (rc == STV_OK) {
     ctx->n0 = n0;
+    const int64_t nbo = std::max(plan.nb, plan.no);
     if ((rc = dalloc(ctx, &A, (size_t)(np * np))) == STV_OK &&
         (rc = dalloc(ctx, &ctx->coarse_inv, (size_t)(n0 * n0))) == STV_OK &&
-        (rc = dalloc(ctx, &Bbuf, (size_t)(nb * np))) == STV_OK &&
-        (rc = dalloc(ctx, &pbuf, (size_t)(2 * nb * np))) == STV_OK &&
+        (rc = dalloc(ctx, &Bbuf, (size_t)(nbo * np))) == STV_OK &&
+        (rc = dalloc(ctx, &pbuf, (size_t)(2 * plan.nb * np))) == STV_OK &&
+        (plan.no == 0 || (rc = dalloc(ctx, &Sbuf, (size_t)(2 * plan.no * np))) == STV_OK) &&
+        (plan.no == 0 || (rc = dalloc(ctx, &Bin, (size_t)(plan.nb * plan.no))) == STV_OK) &&
         (rc = dalloc(ctx, &piv, (size_t)np)) == STV_OK &&
         (rc = dalloc(ctx, &used, (size_t)np)) == STV_OK)
       rc = dalloc(ctx, &rinv_d, (size_t)np);
@@ -628,7 +633,7 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (e == hipSuccess) e = launch_bsr_to_dense(side, b, L0, A, np);
     if (e == hipSuccess) e = launch_set_diag(side, A, np, n0, np);
     if (e == hipSuccess) e = hipMemsetAsync(used, 0, (size_t)np, side);
-    if (e == hipSuccess) e = launch_gj_blocked(side, A, np, piv, used, Bbuf, pbuf);
+    if (e == hipSuccess) e = launch_gj(side, plan, A, np, piv, used, Bbuf, pbuf, Sbuf, Bin);
     t.done();
   }
   std::vector<int> hp((size_t)np);
@@ -930,6 +935,18 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells, 
   if (n_loc) *n_loc = (int64_t)L.n_ls * ctx->b;
   if (inverse_bytes) *inverse_bytes = L.inv_elems * (ctx->inv_fp32 ? 4 : 8);
   return STV_OK;
+}
+
+int stv_set_option(stv_ctx* ctx, int option, int64_t value) {
+  if (!ctx) return STV_EINVAL;
+  switch (option) {
+    case STV_OPT_COARSE_ALGO:
+      if (value < 0 || value > 2) return fail(ctx, STV_EINVAL, "coarse algorithm must be 0, 1 or 2");
+      ctx->coarse_algo = (int)value;
+      return STV_OK;
+    default:
+      return fail(ctx, STV_EINVAL, "unknown option");
+  }
 }
 
 int stv_set_timing(stv_ctx* ctx, int on) {

@@ -77,6 +77,7 @@ struct stv_ctx {
   // coarse dense inverse
   double* coarse_inv = nullptr;
   int64_t n0 = 0;
+  int coarse_algo = 0;          // STV_OPT_COARSE_ALGO
   // Krylov workspace (finest level)
   double* V = nullptr;          // (restart+1) x N
   double* Z = nullptr;          // restart x N
@@ -118,10 +119,14 @@ hipError_t launch_fill(hipStream_t s, double* x, int64_t n, double v);
 hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 // dense coarse level
 hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* A, int64_t n);
-int gj_panel_width(int64_t n);
-// Bbuf: nb x n; pbuf: 2 x n x nb (two panel buffers)
-hipError_t launch_gj_blocked(hipStream_t s, double* A, int64_t n, int* rpiv, uint8_t* used,
-                             double* Bbuf, double* pbuf);
+// Dense Gauss-Jordan plan: algo 1 = one level of panels (width nb), 2 = slabs
+// of no columns eliminated by panels of nb; the matrix is padded to a
+// multiple of pad; max_n is the largest supported order.
+struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; };
+GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */);
+// Bbuf: max(nb, no) x n; pbuf: 2 x n x nb; Sbuf: 2 x n x no; Bin: nb x no
+hipError_t launch_gj(hipStream_t s, const GjPlan& p, double* A, int64_t n, int* rpiv,
+                     uint8_t* used, double* Bbuf, double* pbuf, double* Sbuf, double* Bin);
 hipError_t launch_set_diag(hipStream_t s, double* A, int64_t lda, int64_t from, int64_t to);
 hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t lda, double* out, int64_t n,
                                const int* rpiv, const int* rinv);
