@@ -150,6 +150,35 @@ int stv_validate_hierarchy(int n_levels, int dim, int k, const stv_level* lv,
  * inverses.  Synchronises the stream.  Errors: STV_EINVAL, STV_ENOMEM, STV_EHIP. */
 int stv_set_hierarchy(stv_ctx* ctx, int n_levels, int dim, int k, const stv_level* lv);
 
+/* Upload n_inst independent hierarchies as one batch (same dim and k; each
+ * instance i has n_levels[i] levels, levels[i] pointing to its level array,
+ * index 0 the coarsest; every array is validated as in stv_set_hierarchy and
+ * deep-copied).  The instances are packed into block-diagonal levels aligned
+ * at their finest level: packed level D-1 (D = max n_levels) holds every
+ * instance's finest level, instance i's own level l sits at packed level
+ * D - n_levels[i] + l, its rows after those of the instances before it.
+ * Every other call then acts on all instances at once: finest-level vectors
+ * are the instances' vectors concatenated (stv_instance_layout gives each
+ * offset), a V-cycle runs every instance's own V-cycle (an instance whose
+ * coarsest level is packed level g is solved directly there), and
+ * stv_gmres_solve runs an independent FGMRES per instance, in lockstep, each
+ * with its own Krylov space, stopping test and true residual
+ * (stv_instance_info).  A single hierarchy is the batch of one.  Replaces any
+ * previous hierarchy.  Errors as stv_set_hierarchy (messages name the
+ * instance); STV_EINVAL if a packed level exceeds 32-bit indexing. */
+int stv_set_batch(stv_ctx* ctx, int n_inst, int dim, int k, const int* n_levels,
+                  const stv_level* const* levels);
+
+/* Where instance inst lives: its number of levels, the first spatial row
+ * of its finest level in the packed finest level and its spatial row count
+ * (vector elements: times k+1). */
+int stv_instance_layout(stv_ctx* ctx, int inst, int* n_levels, int64_t* row_offset,
+                        int64_t* n_rows);
+
+/* Result of the last stv_gmres_solve for instance inst (iters, restarts,
+ * converged, true_relres; no history). */
+int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info);
+
 /* Extract every local Jacobian J_T (the submatrix of the level matrix on the
  * cell's DoFs, Section 4.2) on levels >= 1, invert it by Gauss-Jordan
  * elimination with partial pivoting in FP64 and store it (Section 4.3);
@@ -181,7 +210,8 @@ int stv_restrict(stv_ctx* ctx, int level, const double* rho, double* r_c);
 /* d += P d_c (prolongation of a level-1 correction to `level` >= 1). */
 int stv_prolongate_add(stv_ctx* ctx, int level, const double* d_c, double* d);
 
-/* d = J_0^-1 r on the coarsest level (the direct coarse solve). */
+/* d = J_0^-1 r on the coarsest level (the direct coarse solve; for a batch,
+ * the instances whose coarsest level is packed level 0). */
 int stv_coarse_solve(stv_ctx* ctx, const double* r, double* d);
 
 /* d = MG(r): one V(nu1, nu2) cycle on the finest level from d = 0

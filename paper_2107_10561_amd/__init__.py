@@ -86,6 +86,9 @@ def _load():
         "stv_level_info": (I, [P, I, I64P, I64P, I64P, I64P]),
         "stv_set_timing": (I, [P, I]),
         "stv_set_option": (I, [P, I, ctypes.c_int64]),
+        "stv_set_batch": (I, [P, I, I, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.POINTER(_Level))]),
+        "stv_instance_layout": (I, [P, I, ctypes.POINTER(I), I64P, I64P]),
+        "stv_instance_info": (I, [P, I, ctypes.POINTER(_GI)]),
         "stv_kernel_stats": (I, [P, I, I, I64P, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
@@ -100,7 +103,8 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_set_hierarchy", "stv_build_cell_inverses", "stv_residual", "stv_vanka_sweep",
             "stv_restrict", "stv_prolongate_add", "stv_coarse_solve", "stv_vcycle",
             "stv_gmres_solve", "stv_get_cell_inverse", "stv_level_info", "stv_set_timing",
-            "stv_kernel_stats", "stv_set_option")
+            "stv_kernel_stats", "stv_set_option", "stv_set_batch", "stv_instance_layout",
+            "stv_instance_info")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2}
 
@@ -200,9 +204,46 @@ class Solver:
     def set_hierarchy(self, levels, dim: int, k: int):
         arr, keep = _marshal_levels(levels)
         self._check(_lib.stv_set_hierarchy(self._h, len(levels), dim, k, arr))
+        self.n_inst = 1
         self.dim, self.k, self.b = dim, k, k + 1
         self.n_st = [int(_get(L, "n_sdofs")) * (k + 1) for L in levels]
         self.n_levels = len(levels)
+
+    def set_batch(self, hierarchies, dim: int, k: int):
+        """Upload many independent hierarchies (a list of level lists, each
+        coarsest first) as one batch; finest-level vectors are then the
+        instances' vectors concatenated (see instance_layout)."""
+        n = len(hierarchies)
+        marsh = [_marshal_levels(levels) for levels in hierarchies]
+        nlev = (ctypes.c_int * n)(*[len(levels) for levels in hierarchies])
+        ptrs = (ctypes.POINTER(_Level) * n)(*[ctypes.cast(a, ctypes.POINTER(_Level)) for a, _ in marsh])
+        self._check(_lib.stv_set_batch(self._h, n, dim, k, nlev, ptrs))
+        self.dim, self.k, self.b = dim, k, k + 1
+        D = max(len(levels) for levels in hierarchies)
+        self.n_levels = D
+        self.n_st = []
+        for g in range(D):
+            tot = 0
+            for levels in hierarchies:
+                l = g - (D - len(levels))
+                if l >= 0:
+                    tot += int(_get(levels[l], "n_sdofs"))
+            self.n_st.append(tot * (k + 1))
+        self.n_inst = n
+
+    def instance_layout(self, inst: int):
+        """(levels, first vector element, vector length) of an instance on the
+        packed finest level."""
+        nl, off, rows = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.stv_instance_layout(self._h, inst, ctypes.byref(nl), ctypes.byref(off),
+                                             ctypes.byref(rows)))
+        return nl.value, off.value * self.b, rows.value * self.b
+
+    def instance_info(self, inst: int):
+        gi = _GI()
+        self._check(_lib.stv_instance_info(self._h, inst, ctypes.byref(gi)))
+        return dict(iters=gi.iters, restarts=gi.restarts, converged=bool(gi.converged),
+                    true_relres=gi.true_relres)
 
     def build_cell_inverses(self, fp32: bool = False, full: bool = False):
         bl, bc = ctypes.c_int(-1), ctypes.c_int(-1)

@@ -1,36 +1,45 @@
-// Dense coarse level (the direct solve of Algorithm 4.1 on the coarsest
-// grid): the level matrix is expanded to a dense FP64 array (padded with an
+// Dense coarse levels (the direct solve of Algorithm 4.1 on the coarsest
+// grid): each coarse matrix is expanded to a dense FP64 array (padded with an
 // identity block to a multiple of the panel width), inverted once by blocked
 // Gauss-Jordan elimination with partial pivoting, and applied as a dense
-// matrix-vector product in every V-cycle.
+// matrix-vector product in every V-cycle.  Every kernel takes a batch index in
+// blockIdx.z: a group of equally sized coarse matrices (one per instance of a
+// batched hierarchy) is inverted by the same launches, each matrix and work
+// buffer at its own stride.
 #include "stv_internal.h"
 
 namespace stv {
 
 typedef double stv_d4 __attribute__((ext_vector_type(4)));
 
+// Dense copy of member z's rows of its level matrix (columns shifted by the
+// member's first row; the blocks of a member couple only its own rows).
 template <int B>
-__global__ void k_bsr_to_dense(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                               const double* __restrict__ val, double* __restrict__ A, int64_t n,
-                               int32_t n_rows) {
+__global__ void k_bsr_to_dense(const CoarseDesc* __restrict__ desc, double* __restrict__ A,
+                               int64_t sA, int64_t n) {
+  const CoarseDesc D = desc[blockIdx.z];
   const int32_t row = blockIdx.x;
-  if (row >= n_rows) return;
-  for (int32_t q = rowptr[row] + threadIdx.x; q < rowptr[row + 1]; q += blockDim.x) {
-    const int64_t c = col[q];
+  if (row >= D.n_s) return;
+  double* Az = A + blockIdx.z * sA;
+  const int32_t gr = D.row_off + row;
+  for (int32_t q = D.rowptr[gr] + threadIdx.x; q < D.rowptr[gr + 1]; q += blockDim.x) {
+    const int64_t c = D.col[q] - D.row_off;
 #pragma unroll
     for (int i = 0; i < B; ++i)
 #pragma unroll
       for (int l = 0; l < B; ++l)
-        A[((int64_t)row * B + i) * n + c * B + l] = val[(int64_t)q * B * B + i * B + l];
+        Az[((int64_t)row * B + i) * n + c * B + l] = D.val[(int64_t)q * B * B + i * B + l];
   }
 }
 
-hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* A, int64_t n) {
+hipError_t launch_bsr_to_dense(hipStream_t s, int b, const CoarseDesc* desc, int cnt,
+                               int32_t max_rows, double* A, int64_t sA, int64_t n) {
+  dim3 grid((unsigned)max_rows, 1, (unsigned)cnt);
   switch (b) {
-    case 1: k_bsr_to_dense<1><<<L.n_s, 64, 0, s>>>(L.rowptr, L.col, L.val, A, n, L.n_s); break;
-    case 2: k_bsr_to_dense<2><<<L.n_s, 64, 0, s>>>(L.rowptr, L.col, L.val, A, n, L.n_s); break;
-    case 3: k_bsr_to_dense<3><<<L.n_s, 64, 0, s>>>(L.rowptr, L.col, L.val, A, n, L.n_s); break;
-    case 4: k_bsr_to_dense<4><<<L.n_s, 64, 0, s>>>(L.rowptr, L.col, L.val, A, n, L.n_s); break;
+    case 1: k_bsr_to_dense<1><<<grid, 64, 0, s>>>(desc, A, sA, n); break;
+    case 2: k_bsr_to_dense<2><<<grid, 64, 0, s>>>(desc, A, sA, n); break;
+    case 3: k_bsr_to_dense<3><<<grid, 64, 0, s>>>(desc, A, sA, n); break;
+    case 4: k_bsr_to_dense<4><<<grid, 64, 0, s>>>(desc, A, sA, n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -52,11 +61,17 @@ hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* 
 // pivots are known, since nothing else writes S while it runs.
 // rpiv[p] = -1 marks a step without a nonzero finite pivot (singular).
 template <int RPT, int NB, int TPB>
-__global__ void __launch_bounds__(TPB) k_gj_panel(double* __restrict__ pbuf, int64_t n, int p0,
-                                                  int* __restrict__ rpiv,
-                                                  uint8_t* __restrict__ used,
-                                                  const double* __restrict__ S, int64_t lds,
-                                                  int64_t ncs, double* __restrict__ Bout) {
+__global__ void __launch_bounds__(TPB) k_gj_panel(double* __restrict__ pbuf, int64_t sP, int64_t n,
+                                                  int p0, int* __restrict__ rpiv,
+                                                  uint8_t* __restrict__ used, int64_t sV,
+                                                  const double* __restrict__ S, int64_t sS,
+                                                  int64_t lds, int64_t ncs,
+                                                  double* __restrict__ Bout, int64_t sBo) {
+  pbuf += blockIdx.z * sP;
+  rpiv += blockIdx.z * sV;
+  used += blockIdx.z * sV;
+  S += blockIdx.z * sS;
+  Bout += blockIdx.z * sBo;
   // per step, each wavefront publishes its best candidate (magnitude, row)
   // together with that row's panel values; one barrier, then every thread
   // picks the winner among the NW candidates (double-buffered by step parity)
@@ -165,25 +180,31 @@ __global__ void __launch_bounds__(TPB) k_gj_panel(double* __restrict__ pbuf, int
 }
 
 // out (rows x nb, row-major) = columns [c0, c0+nb) of A (row stride lda).
-__global__ void k_gj_load_panel(const double* __restrict__ A, int64_t lda, int64_t rows,
-                                int64_t c0, int nb, double* __restrict__ out) {
+__global__ void k_gj_load_panel(const double* __restrict__ A, int64_t sA, int64_t lda,
+                                int64_t rows, int64_t c0, int nb, double* __restrict__ out,
+                                int64_t sO) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * nb) return;
   const int64_t i = e / nb;
-  out[e] = A[i * lda + c0 + (e - i * nb)];
+  out[blockIdx.z * sO + e] = A[blockIdx.z * sA + i * lda + c0 + (e - i * nb)];
 }
 
-static hipError_t load_panel(hipStream_t s, const double* A, int64_t lda, int64_t rows, int64_t c0,
-                             int nb, double* out) {
-  k_gj_load_panel<<<(unsigned)((rows * nb + 255) / 256), 256, 0, s>>>(A, lda, rows, c0, nb, out);
+static hipError_t load_panel(hipStream_t s, int cnt, const double* A, int64_t sA, int64_t lda,
+                             int64_t rows, int64_t c0, int nb, double* out, int64_t sO) {
+  dim3 grid((unsigned)((rows * nb + 255) / 256), 1, (unsigned)cnt);
+  k_gj_load_panel<<<grid, 256, 0, s>>>(A, sA, lda, rows, c0, nb, out, sO);
   return hipGetLastError();
 }
 
 // Pivot rows rpiv[p0..p0+nb) of A (n x n) before an update: Bbuf (nb x n).
-__global__ void k_gj_gather_rows(const double* __restrict__ A, int64_t n, int p0, int nb,
-                                 const int* __restrict__ rpiv, double* __restrict__ Bbuf) {
+__global__ void k_gj_gather_rows(const double* __restrict__ A, int64_t sA, int64_t n, int p0,
+                                 int nb, const int* __restrict__ rpiv, int64_t sV,
+                                 double* __restrict__ Bbuf, int64_t sB) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  A += blockIdx.z * sA;
+  rpiv += blockIdx.z * sV;
+  Bbuf += blockIdx.z * sB;
   for (int t = 0; t < nb; ++t) {
     const int r = rpiv[p0 + t];
     Bbuf[(int64_t)t * n + j] = r >= 0 ? A[(int64_t)r * n + j] : 0.0;
@@ -197,12 +218,19 @@ __global__ void k_gj_gather_rows(const double* __restrict__ A, int64_t n, int p0
 // right factor in registers, and the rows of A are read and written fully
 // coalesced.
 template <int NB>
-__global__ void __launch_bounds__(256) k_gj_rank_update(double* __restrict__ A, int64_t n, int p0,
-                                                        const int* __restrict__ rpiv,
+__global__ void __launch_bounds__(256) k_gj_rank_update(double* __restrict__ A, int64_t sA,
+                                                        int64_t n, int p0,
+                                                        const int* __restrict__ rpiv, int64_t sV,
                                                         const double* __restrict__ pcur,
+                                                        double* __restrict__ pnext, int64_t sP,
                                                         const double* __restrict__ Bbuf,
-                                                        double* __restrict__ pnext) {
+                                                        int64_t sB) {
   __shared__ double W[16][NB];
+  A += blockIdx.z * sA;
+  rpiv += blockIdx.z * sV;
+  pcur += blockIdx.z * sP;
+  pnext += blockIdx.z * sP;
+  Bbuf += blockIdx.z * sB;
   const int64_t i0 = (int64_t)blockIdx.y * 16;
   for (int e = threadIdx.x; e < 16 * NB; e += 256) {
     const int di = e / NB, t = e - di * NB;
@@ -238,18 +266,19 @@ __global__ void __launch_bounds__(256) k_gj_rank_update(double* __restrict__ A, 
 
 // One-level variant: every panel updates the whole matrix (rank NB).
 template <int RPT, int NB, int TPB>
-static hipError_t gj_blocked(hipStream_t s, double* A, int64_t n, int* rpiv, uint8_t* used,
-                             double* Bbuf, double* pbuf) {
-  double* pb[2] = {pbuf, pbuf + n * NB};
-  hipError_t e = load_panel(s, A, n, n, 0, NB, pb[0]);
+static hipError_t gj_blocked(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
+  double* pb[2] = {w.P, w.P + n * NB};
+  hipError_t e = load_panel(s, cnt, w.A, w.sA, n, n, 0, NB, pb[0], w.sP);
   if (e != hipSuccess) return e;
   int cur = 0;
   for (int64_t p0 = 0; p0 < n; p0 += NB, cur ^= 1) {
-    k_gj_panel<RPT, NB, TPB><<<1, TPB, 0, s>>>(pb[cur], n, (int)p0, rpiv, used, A, n, n, Bbuf);
+    k_gj_panel<RPT, NB, TPB><<<dim3(1, 1, cnt), TPB, 0, s>>>(
+        pb[cur], w.sP, n, (int)p0, w.rpiv, w.used, w.sV, w.A, w.sA, n, n, w.B, w.sB);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((n + 15) / 16));
-    k_gj_rank_update<NB><<<grid, 256, 0, s>>>(A, n, (int)p0, rpiv, pb[cur], Bbuf, pb[cur ^ 1]);
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((n + 15) / 16), (unsigned)cnt);
+    k_gj_rank_update<NB><<<grid, 256, 0, s>>>(w.A, w.sA, n, (int)p0, w.rpiv, w.sV, pb[cur],
+                                               pb[cur ^ 1], w.sP, w.B, w.sB);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -266,13 +295,20 @@ static hipError_t gj_blocked(hipStream_t s, double* A, int64_t n, int* rpiv, uin
 // rp[t]]) Bin(t, c) for c outside [q0, q0+NB), Sb(i, q0+t) = pcur(i, t); the
 // next panel's updated columns are copied to pnext.  64 rows per workgroup.
 template <int NB, int NO>
-__global__ void __launch_bounds__(256) k_gj_slab_inner(double* __restrict__ Sb, int64_t n, int q0,
-                                                       const int* __restrict__ rp,
+__global__ void __launch_bounds__(256) k_gj_slab_inner(double* __restrict__ Sb, int64_t sS,
+                                                       int64_t n, int q0,
+                                                       const int* __restrict__ rp, int64_t sV,
                                                        const double* __restrict__ pcur,
+                                                       double* __restrict__ pnext, int64_t sP,
                                                        const double* __restrict__ Bin,
-                                                       double* __restrict__ pnext) {
+                                                       int64_t sBin) {
   constexpr int RG = 256 / NO;   // row lanes per workgroup
   __shared__ double W[64][NB];
+  Sb += blockIdx.z * sS;
+  rp += blockIdx.z * sV;
+  pcur += blockIdx.z * sP;
+  pnext += blockIdx.z * sP;
+  Bin += blockIdx.z * sBin;
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * 64;
   for (int e = tid; e < 64 * NB; e += 256) {
@@ -311,13 +347,21 @@ __global__ void __launch_bounds__(256) k_gj_slab_inner(double* __restrict__ Sb, 
 // (4v + (l >> 4), l & 15)); the factors pass through LDS 32 columns of K at a
 // time, which keeps four workgroups resident per compute unit.
 template <int NO>
-__global__ void __launch_bounds__(256) k_gj_slab_update(double* __restrict__ A, int64_t n,
-                                                        int64_t j0, const int* __restrict__ rp,
+__global__ void __launch_bounds__(256) k_gj_slab_update(double* __restrict__ A, int64_t sA,
+                                                        int64_t n, int64_t j0,
+                                                        const int* __restrict__ rp, int64_t sV,
                                                         const double* __restrict__ Sb,
-                                                        const double* __restrict__ Bg,
-                                                        double* __restrict__ Snext,
-                                                        double* __restrict__ pnext, int nbn) {
+                                                        double* __restrict__ Snext, int64_t sS,
+                                                        const double* __restrict__ Bg, int64_t sB,
+                                                        double* __restrict__ pnext, int64_t sP,
+                                                        int nbn) {
   constexpr int KC = 32;
+  A += blockIdx.z * sA;
+  rp += blockIdx.z * sV;
+  Sb += blockIdx.z * sS;
+  Snext += blockIdx.z * sS;
+  Bg += blockIdx.z * sB;
+  pnext += blockIdx.z * sP;
   __shared__ double Ws[64][KC + 1];
   __shared__ double Bs[KC][64 + 2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -392,31 +436,32 @@ __global__ void __launch_bounds__(256) k_gj_slab_update(double* __restrict__ A, 
 }
 
 template <int RPT, int NB, int TPB, int NO>
-static hipError_t gj_slab(hipStream_t s, double* A, int64_t n, int* rpiv, uint8_t* used,
-                          double* Bg, double* Sbuf, double* pbuf, double* Bin) {
-  double* sb[2] = {Sbuf, Sbuf + n * NO};
-  double* pb[2] = {pbuf, pbuf + n * NB};
-  hipError_t e = load_panel(s, A, n, n, 0, NO, sb[0]);
-  if (e == hipSuccess) e = load_panel(s, sb[0], NO, n, 0, NB, pb[0]);
+static hipError_t gj_slab(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
+  double* sb[2] = {w.S, w.S + n * NO};
+  double* pb[2] = {w.P, w.P + n * NB};
+  hipError_t e = load_panel(s, cnt, w.A, w.sA, n, n, 0, NO, sb[0], w.sS);
+  if (e == hipSuccess) e = load_panel(s, cnt, sb[0], w.sS, NO, n, 0, NB, pb[0], w.sP);
   if (e != hipSuccess) return e;
   int cs = 0, cp = 0;
   const unsigned nt = (unsigned)(n / 64);
   for (int64_t j0 = 0; j0 < n; j0 += NO, cs ^= 1) {
     for (int q0 = 0; q0 < NO; q0 += NB, cp ^= 1) {
-      k_gj_panel<RPT, NB, TPB><<<1, TPB, 0, s>>>(pb[cp], n, (int)(j0 + q0), rpiv, used, sb[cs],
-                                                NO, NO, Bin);
+      k_gj_panel<RPT, NB, TPB><<<dim3(1, 1, cnt), TPB, 0, s>>>(
+          pb[cp], w.sP, n, (int)(j0 + q0), w.rpiv, w.used, w.sV, sb[cs], w.sS, NO, NO, w.Bin,
+          w.sBin);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
-      k_gj_slab_inner<NB, NO><<<nt, 256, 0, s>>>(sb[cs], n, q0, rpiv + j0 + q0, pb[cp], Bin,
-                                                 pb[cp ^ 1]);
+      k_gj_slab_inner<NB, NO><<<dim3(nt, 1, cnt), 256, 0, s>>>(
+          sb[cs], w.sS, n, q0, w.rpiv + j0 + q0, w.sV, pb[cp], pb[cp ^ 1], w.sP, w.Bin, w.sBin);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    k_gj_gather_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(A, n, (int)j0, NO, rpiv, Bg);
+    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), 1, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, (int)j0, NO, w.rpiv, w.sV, w.B, w.sB);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_gj_slab_update<NO><<<dim3(nt, nt), 256, 0, s>>>(A, n, j0, rpiv + j0, sb[cs], Bg,
-                                                       sb[cs ^ 1], pb[cp], NB);
+    k_gj_slab_update<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, pb[cp], w.sP, NB);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -445,71 +490,89 @@ GjPlan gj_plan(int64_t n, int algo) {
   return p;
 }
 
-// A is n x n with n a multiple of plan.pad and at most plan.max_n; Bbuf
-// holds max(nb, no) x n, pbuf 2 x n x nb, Sbuf 2 x n x no, Bin nb x no.
-hipError_t launch_gj(hipStream_t s, const GjPlan& p, double* A, int64_t n, int* rpiv,
-                     uint8_t* used, double* Bbuf, double* pbuf, double* Sbuf, double* Bin) {
-  if (n > p.max_n || n % p.pad) return hipErrorInvalidValue;
+// cnt matrices of order n (a multiple of plan.pad, at most plan.max_n) at
+// the strides of w.
+hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt) {
+  if (n > p.max_n || n % p.pad || cnt < 1) return hipErrorInvalidValue;
   if (p.algo == 1) {
     switch (p.cfg) {
-      case 0: return gj_blocked<5, 12, 512>(s, A, n, rpiv, used, Bbuf, pbuf);
-      case 1: return gj_blocked<10, 8, 512>(s, A, n, rpiv, used, Bbuf, pbuf);
-      default: return gj_blocked<15, 4, 768>(s, A, n, rpiv, used, Bbuf, pbuf);
+      case 0: return gj_blocked<5, 12, 512>(s, w, n, cnt);
+      case 1: return gj_blocked<10, 8, 512>(s, w, n, cnt);
+      default: return gj_blocked<15, 4, 768>(s, w, n, cnt);
     }
   }
   switch (p.cfg) {
-    case 0: return gj_slab<5, 8, 512, 64>(s, A, n, rpiv, used, Bbuf, Sbuf, pbuf, Bin);
-    case 1: return gj_slab<10, 8, 512, 64>(s, A, n, rpiv, used, Bbuf, Sbuf, pbuf, Bin);
-    default: return gj_slab<15, 4, 768, 128>(s, A, n, rpiv, used, Bbuf, Sbuf, pbuf, Bin);
+    case 0: return gj_slab<5, 8, 512, 64>(s, w, n, cnt);
+    case 1: return gj_slab<10, 8, 512, 64>(s, w, n, cnt);
+    default: return gj_slab<15, 4, 768, 128>(s, w, n, cnt);
   }
 }
 
-__global__ void k_set_diag(double* __restrict__ A, int64_t lda, int64_t from, int64_t to) {
-  const int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < to) A[i * lda + i] = 1.0;
+// Identity on the padding rows [n_s*b, n) of every member.
+__global__ void k_set_diag(const CoarseDesc* __restrict__ desc, int b, double* __restrict__ A,
+                           int64_t sA, int64_t n) {
+  const int64_t i = (int64_t)desc[blockIdx.z].n_s * b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[blockIdx.z * sA + i * n + i] = 1.0;
 }
 
-hipError_t launch_set_diag(hipStream_t s, double* A, int64_t lda, int64_t from, int64_t to) {
-  if (to <= from) return hipSuccess;
-  k_set_diag<<<(unsigned)((to - from + 255) / 256), 256, 0, s>>>(A, lda, from, to);
+hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b, double* A,
+                           int64_t sA, int64_t n) {
+  dim3 grid((unsigned)((n + 255) / 256), 1, (unsigned)cnt);
+  k_set_diag<<<grid, 256, 0, s>>>(desc, b, A, sA, n);
   return hipGetLastError();
 }
 
-// out (n x n, compact): out(i, j) = S(rpiv[i], rinv[j]) from the in-place
-// result S (stride lda), which is the inverse of the original matrix.
-__global__ void k_gj_unpermute(const double* __restrict__ S, int64_t lda, double* __restrict__ out,
-                               int64_t n, const int* __restrict__ rpiv,
-                               const int* __restrict__ rinv) {
+// Member z's inverse (n0 x n0, row-major, at desc.inv_off of out):
+// out(i, j) = S(rpiv[i], rinv[j]) from the in-place result S (order n).
+__global__ void k_gj_unpermute(const double* __restrict__ S, int64_t sA, int64_t n,
+                               const int* __restrict__ rpiv, const int* __restrict__ rinv,
+                               int64_t sV, const CoarseDesc* __restrict__ desc, int b,
+                               double* __restrict__ out) {
+  const CoarseDesc D = desc[blockIdx.z];
+  const int64_t n0 = (int64_t)D.n_s * b;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = blockIdx.y;
-  if (j < n) out[i * n + j] = S[(int64_t)rpiv[i] * lda + rinv[j]];
+  if (i >= n0 || j >= n0) return;
+  const int* rp = rpiv + blockIdx.z * sV;
+  const int* ri = rinv + blockIdx.z * sV;
+  out[D.inv_off + i * n0 + j] = S[blockIdx.z * sA + (int64_t)rp[i] * n + ri[j]];
 }
 
-hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t lda, double* out, int64_t n,
-                               const int* rpiv, const int* rinv) {
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)n), block(256);
-  k_gj_unpermute<<<grid, block, 0, s>>>(S, lda, out, n, rpiv, rinv);
+hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t sA, int64_t n,
+                               const int* rpiv, const int* rinv, int64_t sV,
+                               const CoarseDesc* desc, int cnt, int b, int64_t max_n0,
+                               double* out) {
+  dim3 grid((unsigned)((max_n0 + 255) / 256), (unsigned)max_n0, (unsigned)cnt), block(256);
+  k_gj_unpermute<<<grid, block, 0, s>>>(S, sA, n, rpiv, rinv, sV, desc, b, out);
   return hipGetLastError();
 }
 
-// y = A x, one wavefront per row of the row-major dense inverse.
-__global__ void __launch_bounds__(256) k_dense_gemv(const double* __restrict__ A, int64_t n,
+// y = A x on every member's rows: one wavefront per row of a member's
+// row-major dense inverse (member z in blockIdx.z).
+__global__ void __launch_bounds__(256) k_dense_gemv(const CoarseDesc* __restrict__ desc, int b,
+                                                    const double* __restrict__ inv,
                                                     const double* __restrict__ x,
                                                     double* __restrict__ y) {
+  const CoarseDesc D = desc[blockIdx.z];
+  const int64_t n0 = (int64_t)D.n_s * b;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const double* Ar = A + row * n;
+  if (row >= n0) return;
+  const int64_t vo = (int64_t)D.row_off * b;
+  const double* Ar = inv + D.inv_off + row * n0;
+  const double* xz = x + vo;
   double acc = 0.0;
-  for (int64_t j = lane; j < n; j += 64) acc = fma(Ar[j], x[j], acc);
+  for (int64_t j = lane; j < n0; j += 64) acc = fma(Ar[j], xz[j], acc);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[row] = acc;
+  if (lane == 0) y[vo + row] = acc;
 }
 
-hipError_t launch_dense_gemv(hipStream_t s, const double* A, int64_t n, const double* x,
-                             double* y) {
-  k_dense_gemv<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(A, n, x, y);
+hipError_t launch_dense_gemv(hipStream_t s, const CoarseDesc* desc, int cnt, int b,
+                             int64_t max_n0, const double* inv, const double* x, double* y) {
+  if (cnt < 1) return hipSuccess;
+  dim3 grid((unsigned)((max_n0 + 3) / 4), 1, (unsigned)cnt);
+  k_dense_gemv<<<grid, 256, 0, s>>>(desc, b, inv, x, y);
   return hipGetLastError();
 }
 

@@ -266,7 +266,7 @@ __global__ void k_vanka_combine(const double* __restrict__ corr, double* __restr
   const int e0 = inc_ptr[s], e1 = inc_ptr[s + 1];
   double acc = 0.0;
   for (int e = e0; e < e1; ++e) acc += corr[(int64_t)inc_cell[e] * n_loc + inc_loc[e] * B + l];
-  if (pou) acc /= (double)(e1 - e0);
+  if (pou && e1 > e0) acc /= (double)(e1 - e0);   // rows of directly solved members have no cell
   d[idx] += acc;
 }
 

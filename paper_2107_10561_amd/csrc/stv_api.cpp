@@ -72,6 +72,7 @@ void free_inverses(stv_ctx* ctx) {
     ctx->lv[g].inv_elems = 0;
   }
   dfree(ctx->coarse_inv);
+  ctx->coarse_elems = 0;
   ctx->have_inv = false;
 }
 
@@ -93,8 +94,19 @@ void free_workspace(stv_ctx* ctx) {
 
 void free_hierarchy(stv_ctx* ctx) {
   free_inverses(ctx);
-  for (int g = 0; g < kMaxLevels; ++g) free_level(ctx->lv[g]);
+  for (int g = 0; g < kMaxLevels; ++g) {
+    free_level(ctx->lv[g]);
+    dfree(ctx->d_coarse[g]);
+    ctx->h_coarse[g].clear();
+    ctx->coarse_max_n0[g] = 0;
+  }
   free_workspace(ctx);
+  dfree(ctx->seg_off);
+  ctx->n_inst = 0;
+  ctx->inst_levels.clear();
+  ctx->inst_row.clear();
+  ctx->inst_info.clear();
+  ctx->max_seg = 0;
   ctx->have_hier = false;
   ctx->n_levels = 0;
 }
@@ -296,20 +308,30 @@ int sweeps(stv_ctx* ctx, int g, const double* r, double* d, int n, double omega,
   return STV_OK;
 }
 
-int coarse_apply(stv_ctx* ctx, const double* r, double* d) {
-  Timed t(ctx, KC_COARSE);
-  STV_HIP(launch_dense_gemv(ctx->stream, ctx->coarse_inv, ctx->n0, r, d));
+// d = J_c^-1 r on the rows of every coarse member stored on level g.
+int coarse_apply(stv_ctx* ctx, int g, const double* r, double* d) {
+  const int cnt = (int)ctx->h_coarse[g].size();
+  if (cnt == 0) return STV_OK;
+  Timed t(ctx, KC_COARSE, g);
+  STV_HIP(launch_dense_gemv(ctx->stream, ctx->d_coarse[g], cnt, ctx->b, ctx->coarse_max_n0[g],
+                            ctx->coarse_inv, r, d));
   t.done();
   return STV_OK;
 }
 
+// One V-cycle on level g from d = 0.  Every member of a packed level is
+// either smoothed there (it has a coarser level) or solved directly (level g
+// is its coarsest); the two kinds own disjoint rows, the level operators are
+// block diagonal over members, and the coarse rows are written after the
+// smoother, which touches only its own cells' rows.
 int vcycle_level(stv_ctx* ctx, int g, const double* r, double* d, const stv_mg_params& p) {
-  if (g == 0) return coarse_apply(ctx, r, d);
   DevLevel& L = ctx->lv[g];
+  if (g == 0 || L.n_cells == 0) return coarse_apply(ctx, g, r, d);
   DevLevel& C = ctx->lv[g - 1];
   const int b = ctx->b;
   if (p.nu1 == 0) STV_HIP(launch_fill(ctx->stream, d, (int64_t)L.n_s * b, 0.0));
   STV_TRY(sweeps(ctx, g, r, d, p.nu1, p.omega, p.mode, true));
+  STV_TRY(coarse_apply(ctx, g, r, d));
   STV_TRY(residual(ctx, g, r, d, L.rho));
   {
     Timed t(ctx, KC_TRANSFER, g);
@@ -340,32 +362,279 @@ int ensure_workspace(stv_ctx* ctx, int m) {
   const int64_t n = (int64_t)ctx->lv[ctx->n_levels - 1].n_s * ctx->b;
   if (ctx->ws_restart >= m && ctx->ws_n == n) return STV_OK;
   free_workspace(ctx);
+  const Segs sg{ctx->seg_off, ctx->n_inst, ctx->max_seg};
   STV_TRY(dalloc(ctx, &ctx->V, (size_t)(m + 1) * n));
   STV_TRY(dalloc(ctx, &ctx->Z, (size_t)m * n));
   STV_TRY(dalloc(ctx, &ctx->w, (size_t)n));
   STV_TRY(dalloc(ctx, &ctx->rt, (size_t)n));
-  STV_TRY(dalloc(ctx, &ctx->partial, (size_t)kDotBlocks * 8));
+  STV_TRY(dalloc(ctx, &ctx->partial, (size_t)ctx->n_inst * seg_blocks(sg) * 8));
   ctx->ws_restart = m;
   ctx->ws_n = n;
   return STV_OK;
 }
 
-// scal layout (device and pinned host mirror):
-//   [0, R)        h1 (first Gram-Schmidt pass)
-//   [R, 2R)       h2 (second pass)
-//   [2R]          ||w||^2
-//   [2R+1]        scratch norm^2
-//   [3R, 4R)      y (host -> device)
+// Scalar buffers (device and pinned host mirror), S = instances, R = kScalR:
+//   h1 (first Gram-Schmidt pass)   [0, S R)        instance z at z R
+//   h2 (second pass)               [S R, 2 S R)
+//   ||w||^2                        [2 S R, 2 S R + S)
+//   scratch norms^2                [2 S R + S, 2 S R + 2 S)
+//   y (host -> device)             [2 S R + 2 S, 3 S R + 2 S)
 constexpr int kScalR = kMaxRestart + 2;
+struct ScalLayout {
+  int64_t S;
+  int64_t h1(int64_t z) const { return z * kScalR; }
+  int64_t h2(int64_t z) const { return S * kScalR + z * kScalR; }
+  int64_t nrm() const { return 2 * S * kScalR; }
+  int64_t aux() const { return 2 * S * kScalR + S; }
+  int64_t y(int64_t z) const { return 2 * S * kScalR + 2 * S + z * kScalR; }
+  int64_t total() const { return 3 * S * kScalR + 2 * S; }
+};
 
-int dot_to_host(stv_ctx* ctx, const double* a, const double* b, int64_t n, double* out) {
+int ensure_scalars(stv_ctx* ctx, int64_t S) {
+  if (ctx->scal_segs >= S && ctx->scal) return STV_OK;
+  dfree(ctx->scal);
+  if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+  ctx->hscal = nullptr;
+  ctx->scal_segs = 0;
+  const ScalLayout lay{S};
+  STV_TRY(dalloc(ctx, &ctx->scal, (size_t)lay.total()));
+  if (hipHostMalloc((void**)&ctx->hscal, sizeof(double) * lay.total(), hipHostMallocDefault) !=
+      hipSuccess) {
+    ctx->hscal = nullptr;
+    return fail(ctx, STV_ENOMEM, "pinned allocation of the scalar buffer failed");
+  }
+  ctx->scal_segs = S;
+  return STV_OK;
+}
+
+// out[z] = a_z . b_z for every instance segment z of two finest-level vectors
+int dots_to_host(stv_ctx* ctx, const double* a, const double* b, int64_t n,
+                 std::vector<double>& out) {
+  const ScalLayout lay{ctx->scal_segs};
+  const Segs sg{ctx->seg_off, ctx->n_inst, ctx->max_seg};
   Timed t(ctx, KC_KRYLOV);
-  STV_HIP(launch_multidot(ctx->stream, a, 1, b, n, ctx->partial, ctx->scal + 2 * kScalR + 1));
+  STV_HIP(launch_multidot(ctx->stream, a, 1, b, n, sg, ctx->partial, ctx->scal + lay.aux(), 1));
   t.done();
-  STV_HIP(hipMemcpyAsync(ctx->hscal + 2 * kScalR + 1, ctx->scal + 2 * kScalR + 1, sizeof(double),
-                         hipMemcpyDeviceToHost, ctx->stream));
+  STV_HIP(hipMemcpyAsync(ctx->hscal + lay.aux(), ctx->scal + lay.aux(),
+                         sizeof(double) * ctx->n_inst, hipMemcpyDeviceToHost, ctx->stream));
   STV_HIP(hipStreamSynchronize(ctx->stream));
-  *out = ctx->hscal[2 * kScalR + 1];
+  out.assign(ctx->hscal + lay.aux(), ctx->hscal + lay.aux() + ctx->n_inst);
+  return STV_OK;
+}
+
+// ---------------------------------------------------------------- set-up
+// Pack n_inst hierarchies into block-diagonal levels aligned at the finest
+// level: instance i with G_i levels occupies packed levels D-G_i .. D-1
+// (D = max G_i), its own level l at packed level D-G_i+l, rows (and cells)
+// in instance order.  A single hierarchy is the case n_inst = 1.
+int setup_packed(stv_ctx* ctx, int n_inst, int dim, int k, const int* nlev,
+                 const stv_level* const* lvs) {
+  std::string msg;
+  for (int i = 0; i < n_inst; ++i) {
+    if (!validate_impl(nlev[i], dim, k, lvs[i], msg))
+      return fail(ctx, STV_EINVAL, n_inst > 1 ? "instance " + std::to_string(i) + ": " + msg : msg);
+  }
+  int D = 0;
+  for (int i = 0; i < n_inst; ++i) D = std::max(D, nlev[i]);
+  const int b = k + 1;
+  const int nls = n_ls_of(dim);
+  // member i is present on packed level g from level g - (D - G_i) of its own
+  auto local = [&](int i, int g) { return g - (D - nlev[i]); };
+  // packed sizes must fit the 32-bit indices of the kernels
+  for (int g = 0; g < D; ++g) {
+    int64_t ns = 0, nz = 0, nc = 0, pz = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      const int l = local(i, g);
+      if (l < 0) continue;
+      const stv_level& H = lvs[i][l];
+      ns += H.n_sdofs;
+      nz += H.nnzb;
+      if (l > 0) { nc += H.n_cells; pz += H.P_nnz; }
+    }
+    if (ns * b >= INT32_MAX || nz >= INT32_MAX || nc * nls >= INT32_MAX || pz >= INT32_MAX)
+      return fail(ctx, STV_EINVAL, "packed level " + std::to_string(g) + " exceeds 32-bit indexing");
+  }
+  STV_HIP(hipSetDevice(ctx->device));
+  STV_HIP(hipStreamSynchronize(ctx->stream));
+  free_hierarchy(ctx);
+  STV_TRY(ensure_scalars(ctx, n_inst));
+  ctx->n_levels = D;
+  ctx->dim = dim;
+  ctx->k = k;
+  ctx->b = b;
+  ctx->n_inst = n_inst;
+  ctx->inst_levels.assign(nlev, nlev + n_inst);
+  ctx->inst_info.assign((size_t)n_inst, InstInfo());
+  std::vector<std::vector<int32_t>> roff((size_t)D, std::vector<int32_t>((size_t)n_inst, -1));
+  for (int g = 0; g < D; ++g) {
+    DevLevel& L = ctx->lv[g];
+    // offsets of the members: rows, blocks, cells (smoothed members only)
+    int32_t ns = 0;
+    int64_t nz = 0, ncell = 0, ncell_all = 0, pnz = 0;
+    std::vector<int64_t> zoff((size_t)n_inst, 0), coff((size_t)n_inst, -1), poff((size_t)n_inst, 0);
+    for (int i = 0; i < n_inst; ++i) {
+      const int l = local(i, g);
+      if (l < 0) continue;
+      const stv_level& H = lvs[i][l];
+      roff[(size_t)g][(size_t)i] = ns;
+      zoff[(size_t)i] = nz;
+      ns += H.n_sdofs;
+      nz += H.nnzb;
+      ncell_all += H.n_cells;
+      if (l > 0) {
+        coff[(size_t)i] = ncell;
+        ncell += H.n_cells;
+        poff[(size_t)i] = pnz;
+        pnz += H.P_nnz;
+      }
+    }
+    L.n_s = ns;
+    L.nnzb = nz;
+    L.n_cells = (int32_t)ncell;
+    L.n_cells_all = ncell_all;
+    L.n_ls = nls;
+    // block rows (column indices shifted by the member's first row)
+    {
+      std::vector<int32_t> rp((size_t)ns + 1, 0), cl;
+      const bool shift = n_inst > 1;
+      if (shift) cl.resize((size_t)nz);
+      for (int i = 0; i < n_inst; ++i) {
+        const int l = local(i, g);
+        if (l < 0) continue;
+        const stv_level& H = lvs[i][l];
+        const int32_t r0 = roff[(size_t)g][(size_t)i];
+        for (int32_t s = 0; s <= H.n_sdofs; ++s) rp[(size_t)r0 + s] = (int32_t)(zoff[(size_t)i] + H.bsr_rowptr[s]);
+        if (shift)
+          for (int64_t q = 0; q < H.nnzb; ++q) cl[(size_t)(zoff[(size_t)i] + q)] = H.bsr_col[q] + r0;
+      }
+      STV_TRY(upload(ctx, &L.rowptr, rp.data(), rp.size()));
+      if (shift) STV_TRY(upload(ctx, &L.col, cl.data(), cl.size()));
+      else STV_TRY(upload(ctx, &L.col, lvs[0][local(0, g)].bsr_col, (size_t)nz));
+      STV_TRY(dalloc(ctx, &L.val, (size_t)nz * b * b));
+      for (int i = 0; i < n_inst; ++i) {
+        const int l = local(i, g);
+        if (l < 0) continue;
+        const stv_level& H = lvs[i][l];
+        STV_HIP(hipMemcpy(L.val + zoff[(size_t)i] * b * b, H.bsr_val,
+                          sizeof(double) * (size_t)H.nnzb * b * b, hipMemcpyHostToDevice));
+      }
+    }
+    // cells of the smoothed members, their owned DoFs (the owner of a DoF is
+    // the last cell in loop order that contains it) and the incidence lists
+    {
+      std::vector<int32_t> csd((size_t)ncell * nls);
+      L.h_own_ptr.assign((size_t)ncell + 1, 0);
+      L.h_own_loc.clear();
+      std::vector<int32_t> ip((size_t)ns + 1, 0);
+      for (int i = 0; i < n_inst; ++i) {
+        const int l = local(i, g);
+        if (l <= 0) continue;
+        const stv_level& H = lvs[i][l];
+        const int32_t r0 = roff[(size_t)g][(size_t)i];
+        const int64_t c0 = coff[(size_t)i];
+        std::vector<int32_t> owner((size_t)H.n_sdofs, -1);
+        for (int32_t c = 0; c < H.n_cells; ++c)
+          for (int a = 0; a < nls; ++a) owner[(size_t)H.cell_sdofs[(int64_t)c * nls + a]] = c;
+        for (int32_t c = 0; c < H.n_cells; ++c) {
+          for (int a = 0; a < nls; ++a) {
+            const int32_t sd = H.cell_sdofs[(int64_t)c * nls + a];
+            csd[(size_t)((c0 + c) * nls + a)] = sd + r0;
+            if (owner[(size_t)sd] == c) L.h_own_loc.push_back((uint8_t)a);
+            ip[(size_t)(r0 + sd) + 1]++;
+          }
+          L.h_own_ptr[(size_t)(c0 + c) + 1] = (int32_t)L.h_own_loc.size();
+        }
+      }
+      for (int32_t r = 0; r < ns; ++r) ip[(size_t)r + 1] += ip[(size_t)r];
+      std::vector<int32_t> fillp(ip.begin(), ip.end() - 1);
+      std::vector<int32_t> icell((size_t)ip.back());
+      std::vector<uint8_t> iloc((size_t)ip.back());
+      for (int64_t c = 0; c < ncell; ++c)
+        for (int a = 0; a < nls; ++a) {
+          const int32_t r = csd[(size_t)(c * nls + a)];
+          icell[(size_t)fillp[(size_t)r]] = (int32_t)c;
+          iloc[(size_t)fillp[(size_t)r]++] = (uint8_t)a;
+        }
+      STV_TRY(upload(ctx, &L.cell_sdofs, csd.data(), csd.size()));
+      STV_TRY(upload(ctx, &L.own_ptr, L.h_own_ptr.data(), L.h_own_ptr.size()));
+      STV_TRY(upload(ctx, &L.own_loc, L.h_own_loc.data(), L.h_own_loc.size()));
+      STV_TRY(upload(ctx, &L.inc_ptr, ip.data(), ip.size()));
+      STV_TRY(upload(ctx, &L.inc_cell, icell.data(), icell.size()));
+      STV_TRY(upload(ctx, &L.inc_loc, iloc.data(), iloc.size()));
+    }
+    if (ncell > 0) {
+      STV_TRY(dalloc(ctx, &L.posmap, (size_t)ncell * nls * nls));
+      STV_HIP(launch_build_posmap(ctx->stream, L));
+    }
+    const size_t nst = (size_t)ns * b;
+    STV_TRY(dalloc(ctx, &L.rho, nst));
+    if (g < D - 1) {
+      STV_TRY(dalloc(ctx, &L.r, nst));
+      STV_TRY(dalloc(ctx, &L.d, nst));
+    }
+    // prolongation from packed level g-1 (rows of coarse members stay empty)
+    if (g > 0) {
+      const int32_t nc = ctx->lv[g - 1].n_s;
+      L.n_s_coarse = nc;
+      std::vector<int32_t> prp((size_t)ns + 1, 0), pcl((size_t)pnz);
+      std::vector<double> pvl((size_t)pnz);
+      for (int i = 0; i < n_inst; ++i) {
+        const int l = local(i, g);
+        if (l <= 0) continue;
+        const stv_level& H = lvs[i][l];
+        const int32_t r0 = roff[(size_t)g][(size_t)i];
+        const int32_t cc0 = roff[(size_t)g - 1][(size_t)i];
+        const int64_t q0 = poff[(size_t)i];
+        for (int32_t s = 0; s < H.n_sdofs; ++s)
+          prp[(size_t)(r0 + s) + 1] = H.P_rowptr[s + 1] - H.P_rowptr[s];
+        for (int64_t q = 0; q < H.P_nnz; ++q) {
+          pcl[(size_t)(q0 + q)] = H.P_col[q] + cc0;
+          pvl[(size_t)(q0 + q)] = H.P_val[q];
+        }
+      }
+      for (int32_t r = 0; r < ns; ++r) prp[(size_t)r + 1] += prp[(size_t)r];
+      STV_TRY(upload(ctx, &L.P_rowptr, prp.data(), prp.size()));
+      STV_TRY(upload(ctx, &L.P_col, pcl.data(), pcl.size()));
+      STV_TRY(upload(ctx, &L.P_val, pvl.data(), pvl.size()));
+      // transpose (coarse rows, fine rows ascending within each)
+      std::vector<int32_t> tp((size_t)nc + 1, 0);
+      for (int64_t q = 0; q < pnz; ++q) tp[(size_t)pcl[(size_t)q] + 1]++;
+      for (int32_t c = 0; c < nc; ++c) tp[(size_t)c + 1] += tp[(size_t)c];
+      std::vector<int32_t> fillp(tp.begin(), tp.end() - 1);
+      std::vector<int32_t> tc((size_t)pnz);
+      std::vector<double> tv((size_t)pnz);
+      for (int32_t r = 0; r < ns; ++r)
+        for (int32_t q = prp[(size_t)r]; q < prp[(size_t)r + 1]; ++q) {
+          const int32_t c = pcl[(size_t)q];
+          tc[(size_t)fillp[(size_t)c]] = r;
+          tv[(size_t)fillp[(size_t)c]++] = pvl[(size_t)q];
+        }
+      STV_TRY(upload(ctx, &L.Pt_rowptr, tp.data(), tp.size()));
+      STV_TRY(upload(ctx, &L.Pt_col, tc.data(), tc.size()));
+      STV_TRY(upload(ctx, &L.Pt_val, tv.data(), tv.size()));
+    }
+    // the members solved directly on this level
+    for (int i = 0; i < n_inst; ++i) {
+      if (local(i, g) != 0) continue;
+      CoarseDesc c{L.rowptr, L.col, L.val, roff[(size_t)g][(size_t)i], lvs[i][0].n_sdofs, 0};
+      ctx->h_coarse[g].push_back(c);
+      ctx->coarse_max_n0[g] = std::max<int64_t>(ctx->coarse_max_n0[g], (int64_t)c.n_s * b);
+    }
+  }
+  // instance segments of the finest level
+  ctx->inst_row.assign((size_t)n_inst + 1, 0);
+  std::vector<int64_t> seg((size_t)n_inst + 1, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    ctx->inst_row[(size_t)i] = roff[(size_t)D - 1][(size_t)i];
+    ctx->inst_row[(size_t)i + 1] = roff[(size_t)D - 1][(size_t)i] + lvs[i][nlev[i] - 1].n_sdofs;
+  }
+  int64_t mx = 0;
+  for (int i = 0; i <= n_inst; ++i) seg[(size_t)i] = ctx->inst_row[(size_t)i] * b;
+  for (int i = 0; i < n_inst; ++i) mx = std::max(mx, seg[(size_t)i + 1] - seg[(size_t)i]);
+  ctx->max_seg = mx;
+  STV_TRY(upload(ctx, &ctx->seg_off, seg.data(), seg.size()));
+  STV_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->have_hier = true;
   return STV_OK;
 }
 
@@ -398,11 +667,12 @@ int stv_create(stv_ctx** out, int device, void* hip_stream) {
     delete ctx;
     return STV_EHIP;
   }
-  if (hipMalloc((void**)&ctx->scal, sizeof(double) * 4 * kScalR) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->hscal, sizeof(double) * 4 * kScalR, hipHostMallocDefault) !=
-          hipSuccess) {
+  if (ensure_scalars(ctx, 1) != STV_OK) {
     g_create_err = "allocation of the scalar buffers failed";
-    if (ctx->scal) (void)hipFree(ctx->scal);
+    dfree(ctx->scal);
+    (void)hipStreamDestroy(ctx->side);
+    (void)hipEventDestroy(ctx->ev_fork);
+    (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
     return STV_ENOMEM;
   }
@@ -444,96 +714,15 @@ int stv_validate_hierarchy(int n_levels, int dim, int k, const stv_level* lv, ch
 
 int stv_set_hierarchy(stv_ctx* ctx, int n_levels, int dim, int k, const stv_level* lv) {
   if (!ctx) return STV_EINVAL;
-  std::string msg;
-  if (!validate_impl(n_levels, dim, k, lv, msg)) return fail(ctx, STV_EINVAL, msg);
-  STV_HIP(hipSetDevice(ctx->device));
-  STV_HIP(hipStreamSynchronize(ctx->stream));
-  free_hierarchy(ctx);
-  ctx->n_levels = n_levels;
-  ctx->dim = dim;
-  ctx->k = k;
-  ctx->b = k + 1;
-  const int b = ctx->b;
-  for (int g = 0; g < n_levels; ++g) {
-    const stv_level& H = lv[g];
-    DevLevel& L = ctx->lv[g];
-    L.n_s = H.n_sdofs;
-    L.n_cells = H.n_cells;
-    L.n_ls = H.n_ls;
-    L.nnzb = H.nnzb;
-    const int nls = H.n_ls;
-    STV_TRY(upload(ctx, &L.rowptr, H.bsr_rowptr, (size_t)H.n_sdofs + 1));
-    STV_TRY(upload(ctx, &L.col, H.bsr_col, (size_t)H.nnzb));
-    STV_TRY(upload(ctx, &L.val, H.bsr_val, (size_t)H.nnzb * b * b));
-    STV_TRY(upload(ctx, &L.cell_sdofs, H.cell_sdofs, (size_t)H.n_cells * nls));
-    // owner of each spatial DoF: the last cell in loop order containing it
-    std::vector<int32_t> owner((size_t)H.n_sdofs, -1);
-    for (int32_t c = 0; c < H.n_cells; ++c)
-      for (int a = 0; a < nls; ++a) owner[(size_t)H.cell_sdofs[(int64_t)c * nls + a]] = c;
-    L.h_own_ptr.assign((size_t)H.n_cells + 1, 0);
-    L.h_own_loc.clear();
-    for (int32_t c = 0; c < H.n_cells; ++c) {
-      for (int a = 0; a < nls; ++a)
-        if (owner[(size_t)H.cell_sdofs[(int64_t)c * nls + a]] == c) L.h_own_loc.push_back((uint8_t)a);
-      L.h_own_ptr[(size_t)c + 1] = (int32_t)L.h_own_loc.size();
-    }
-    STV_TRY(upload(ctx, &L.own_ptr, L.h_own_ptr.data(), L.h_own_ptr.size()));
-    STV_TRY(upload(ctx, &L.own_loc, L.h_own_loc.data(), L.h_own_loc.size()));
-    // incidence DoF -> (cell, local index), cells in loop order
-    {
-      std::vector<int32_t> ip((size_t)H.n_sdofs + 1, 0);
-      for (int64_t e = 0; e < (int64_t)H.n_cells * nls; ++e) ip[(size_t)H.cell_sdofs[e] + 1]++;
-      for (int32_t s = 0; s < H.n_sdofs; ++s) ip[(size_t)s + 1] += ip[(size_t)s];
-      std::vector<int32_t> fillp(ip.begin(), ip.end() - 1);
-      std::vector<int32_t> icell((size_t)ip.back());
-      std::vector<uint8_t> iloc((size_t)ip.back());
-      for (int32_t c = 0; c < H.n_cells; ++c)
-        for (int a = 0; a < nls; ++a) {
-          const int32_t s = H.cell_sdofs[(int64_t)c * nls + a];
-          icell[(size_t)fillp[(size_t)s]] = c;
-          iloc[(size_t)fillp[(size_t)s]++] = (uint8_t)a;
-        }
-      STV_TRY(upload(ctx, &L.inc_ptr, ip.data(), ip.size()));
-      STV_TRY(upload(ctx, &L.inc_cell, icell.data(), icell.size()));
-      STV_TRY(upload(ctx, &L.inc_loc, iloc.data(), iloc.size()));
-    }
-    if (g > 0) {
-      STV_TRY(dalloc(ctx, &L.posmap, (size_t)H.n_cells * nls * nls));
-      STV_HIP(launch_build_posmap(ctx->stream, L));
-    }
-    const size_t nst = (size_t)H.n_sdofs * b;
-    STV_TRY(dalloc(ctx, &L.rho, nst));
-    if (g < n_levels - 1) {
-      STV_TRY(dalloc(ctx, &L.r, nst));
-      STV_TRY(dalloc(ctx, &L.d, nst));
-    }
-    if (g > 0) {
-      const int32_t nc = lv[g - 1].n_sdofs;
-      L.n_s_coarse = nc;
-      STV_TRY(upload(ctx, &L.P_rowptr, H.P_rowptr, (size_t)H.n_sdofs + 1));
-      STV_TRY(upload(ctx, &L.P_col, H.P_col, (size_t)H.P_nnz));
-      STV_TRY(upload(ctx, &L.P_val, H.P_val, (size_t)H.P_nnz));
-      // transpose (coarse rows, fine rows ascending within each)
-      std::vector<int32_t> tp((size_t)nc + 1, 0);
-      for (int64_t q = 0; q < H.P_nnz; ++q) tp[(size_t)H.P_col[q] + 1]++;
-      for (int32_t c = 0; c < nc; ++c) tp[(size_t)c + 1] += tp[(size_t)c];
-      std::vector<int32_t> fillp(tp.begin(), tp.end() - 1);
-      std::vector<int32_t> tc((size_t)H.P_nnz);
-      std::vector<double> tv((size_t)H.P_nnz);
-      for (int32_t s = 0; s < H.n_sdofs; ++s)
-        for (int32_t q = H.P_rowptr[s]; q < H.P_rowptr[s + 1]; ++q) {
-          const int32_t c = H.P_col[q];
-          tc[(size_t)fillp[(size_t)c]] = s;
-          tv[(size_t)fillp[(size_t)c]++] = H.P_val[q];
-        }
-      STV_TRY(upload(ctx, &L.Pt_rowptr, tp.data(), tp.size()));
-      STV_TRY(upload(ctx, &L.Pt_col, tc.data(), tc.size()));
-      STV_TRY(upload(ctx, &L.Pt_val, tv.data(), tv.size()));
-    }
-  }
-  STV_HIP(hipStreamSynchronize(ctx->stream));
-  ctx->have_hier = true;
-  return STV_OK;
+  return setup_packed(ctx, 1, dim, k, &n_levels, &lv);
+}
+
+int stv_set_batch(stv_ctx* ctx, int n_inst, int dim, int k, const int* n_levels,
+                  const stv_level* const* levels) {
+  if (!ctx) return STV_EINVAL;
+  if (n_inst < 1 || n_inst > 65535) return fail(ctx, STV_EINVAL, "n_inst must be in [1, 65535]");
+  if (!n_levels || !levels) return fail(ctx, STV_EINVAL, "n_levels and levels must not be NULL");
+  return setup_packed(ctx, n_inst, dim, k, n_levels, levels);
 }
 
 int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_cell) {
@@ -551,22 +740,48 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   const int b = ctx->b;
   hipStream_t s = ctx->stream;
   hipStream_t side = ctx->side;
-  // ---- allocations (host-side offsets of every cell's stored rows)
+  // ---- cell inverse storage (host-side offsets of every cell's stored rows)
   std::vector<uint8_t*> status((size_t)ctx->n_levels, nullptr);
   std::vector<double*> scratch((size_t)ctx->n_levels, nullptr);
   std::vector<int> slots((size_t)ctx->n_levels, 0);
-  double *A = nullptr, *Bbuf = nullptr, *pbuf = nullptr, *Sbuf = nullptr, *Bin = nullptr;
-  int *piv = nullptr, *rinv_d = nullptr;
-  uint8_t* used = nullptr;
+  // ---- coarse members grouped by order: one batched elimination per group
+  struct Member { int g; int idx; int64_t n0; };
+  struct Group {
+    int64_t n0 = 0, np = 0;
+    GjPlan plan{};
+    std::vector<Member> mem;
+    CoarseDesc* d_desc = nullptr;
+    GjWork w{};
+    int* rinv = nullptr;
+  };
+  std::vector<Group> groups;
+  int64_t coarse_total = 0;
+  for (int g = 0; g < ctx->n_levels; ++g)
+    for (size_t q = 0; q < ctx->h_coarse[g].size(); ++q) {
+      CoarseDesc& c = ctx->h_coarse[g][q];
+      const int64_t n0 = (int64_t)c.n_s * b;
+      c.inv_off = coarse_total;
+      coarse_total += n0 * n0;
+      size_t gi = 0;
+      while (gi < groups.size() && groups[gi].n0 != n0) ++gi;
+      if (gi == groups.size()) {
+        groups.emplace_back();
+        groups.back().n0 = n0;
+      }
+      groups[gi].mem.push_back({g, (int)q, n0});
+    }
   auto cleanup = [&]() {
     for (auto& p : status) dfree(p);
     for (auto& p : scratch) dfree(p);
-    dfree(A); dfree(Bbuf); dfree(pbuf); dfree(Sbuf); dfree(Bin); dfree(piv); dfree(rinv_d);
-    dfree(used);
+    for (auto& G : groups) {
+      dfree(G.d_desc); dfree(G.w.A); dfree(G.w.rpiv); dfree(G.w.used); dfree(G.w.B);
+      dfree(G.w.P); dfree(G.w.S); dfree(G.w.Bin); dfree(G.rinv);
+    }
   };
   int rc = STV_OK;
-  for (int g = 1; g < ctx->n_levels && rc == STV_OK; ++g) {
+  for (int g = 0; g < ctx->n_levels && rc == STV_OK; ++g) {
     DevLevel& L = ctx->lv[g];
+    if (L.n_cells == 0) continue;
     const int n = L.n_ls * b;
     std::vector<int64_t> off((size_t)L.n_cells);
     int64_t tot = 0;
@@ -593,81 +808,122 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
       rc = dalloc(ctx, &scratch[(size_t)g], (size_t)slots[(size_t)g] * n * n);
     }
   }
-  DevLevel& L0 = ctx->lv[0];
-  const int64_t n0 = (int64_t)L0.n_s * b;
-  const GjPlan plan = gj_plan(n0, ctx->coarse_algo);
-  const int64_t np = (n0 + plan.pad - 1) / plan.pad * plan.pad;
-  if (rc == STV_OK && np > plan.max_n)
-    rc = fail(ctx, STV_EINVAL, "coarse level larger than " + std::to_string(plan.max_n) + " unknowns");
   if (rc == STV_OK) {
-    ctx->n0 = n0;
-    const int64_t nbo = std::max(plan.nb, plan.no);
-    if ((rc = dalloc(ctx, &A, (size_t)(np * np))) == STV_OK &&
-        (rc = dalloc(ctx, &ctx->coarse_inv, (size_t)(n0 * n0))) == STV_OK &&
-        (rc = dalloc(ctx, &Bbuf, (size_t)(nbo * np))) == STV_OK &&
-        (rc = dalloc(ctx, &pbuf, (size_t)(2 * plan.nb * np))) == STV_OK &&
-        (plan.no == 0 || (rc = dalloc(ctx, &Sbuf, (size_t)(2 * plan.no * np))) == STV_OK) &&
-        (plan.no == 0 || (rc = dalloc(ctx, &Bin, (size_t)(plan.nb * plan.no))) == STV_OK) &&
-        (rc = dalloc(ctx, &piv, (size_t)np)) == STV_OK &&
-        (rc = dalloc(ctx, &used, (size_t)np)) == STV_OK)
-      rc = dalloc(ctx, &rinv_d, (size_t)np);
+    ctx->coarse_elems = coarse_total;
+    rc = dalloc(ctx, &ctx->coarse_inv, (size_t)coarse_total);
+  }
+  for (auto& G : groups) {
+    if (rc != STV_OK) break;
+    G.plan = gj_plan(G.n0, ctx->coarse_algo);
+    G.np = (G.n0 + G.plan.pad - 1) / G.plan.pad * G.plan.pad;
+    if (G.np > G.plan.max_n) {
+      rc = fail(ctx, STV_EINVAL, "coarse level larger than " + std::to_string(G.plan.max_n) + " unknowns");
+      break;
+    }
+    const int64_t cnt = (int64_t)G.mem.size(), np = G.np;
+    const int64_t nbo = std::max(G.plan.nb, G.plan.no);
+    GjWork& w = G.w;
+    w.sA = np * np;
+    w.sV = np;
+    w.sB = nbo * np;
+    w.sP = 2 * G.plan.nb * np;
+    w.sS = 2 * (int64_t)G.plan.no * np;
+    w.sBin = (int64_t)G.plan.nb * G.plan.no;
+    std::vector<CoarseDesc> hd;
+    for (const Member& m : G.mem) hd.push_back(ctx->h_coarse[m.g][(size_t)m.idx]);
+    if ((rc = upload(ctx, &G.d_desc, hd.data(), hd.size())) != STV_OK ||
+        (rc = dalloc(ctx, &w.A, (size_t)(cnt * w.sA))) != STV_OK ||
+        (rc = dalloc(ctx, &w.rpiv, (size_t)(cnt * w.sV))) != STV_OK ||
+        (rc = dalloc(ctx, &w.used, (size_t)(cnt * w.sV))) != STV_OK ||
+        (rc = dalloc(ctx, &w.B, (size_t)(cnt * w.sB))) != STV_OK ||
+        (rc = dalloc(ctx, &w.P, (size_t)(cnt * w.sP))) != STV_OK ||
+        (rc = dalloc(ctx, &G.rinv, (size_t)(cnt * w.sV))) != STV_OK)
+      break;
+    if (G.plan.no > 0 && ((rc = dalloc(ctx, &w.S, (size_t)(cnt * w.sS))) != STV_OK ||
+                          (rc = dalloc(ctx, &w.Bin, (size_t)(cnt * w.sBin))) != STV_OK))
+      break;
+  }
+  // device descriptors of the members per level (inverse offsets now known)
+  for (int g = 0; g < ctx->n_levels && rc == STV_OK; ++g) {
+    dfree(ctx->d_coarse[g]);
+    if (!ctx->h_coarse[g].empty())
+      rc = upload(ctx, &ctx->d_coarse[g], ctx->h_coarse[g].data(), ctx->h_coarse[g].size());
   }
   if (rc != STV_OK) {
     cleanup();
     free_inverses(ctx);
     return rc;
   }
-  // ---- launch: cell inverses on the caller's stream, coarse factorisation
+  // ---- launch: cell inverses on the caller's stream, coarse factorisations
   // on the internal stream (it starts after everything queued before it)
   hipError_t e = hipEventRecord(ctx->ev_fork, s);
   if (e == hipSuccess) e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
   for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
+    if (ctx->lv[g].n_cells == 0) continue;
     Timed t(ctx, KC_INVERSE, g);
     e = launch_cell_inverses(s, b, ctx->lv[g], fp32, full, status[(size_t)g], scratch[(size_t)g],
                              slots[(size_t)g]);
     t.done();
   }
-  {
+  for (auto& G : groups) {
+    if (e != hipSuccess) break;
     Timed t(ctx, KC_COARSE_FACTOR, 0, side);
-    if (e == hipSuccess) e = launch_fill(side, A, np * np, 0.0);
-    if (e == hipSuccess) e = launch_bsr_to_dense(side, b, L0, A, np);
-    if (e == hipSuccess) e = launch_set_diag(side, A, np, n0, np);
-    if (e == hipSuccess) e = hipMemsetAsync(used, 0, (size_t)np, side);
-    if (e == hipSuccess) e = launch_gj(side, plan, A, np, piv, used, Bbuf, pbuf, Sbuf, Bin);
+    const int cnt = (int)G.mem.size();
+    int32_t max_rows = 0;
+    for (const Member& m : G.mem) max_rows = std::max(max_rows, ctx->h_coarse[m.g][(size_t)m.idx].n_s);
+    e = launch_fill(side, G.w.A, cnt * G.w.sA, 0.0);
+    if (e == hipSuccess) e = launch_bsr_to_dense(side, b, G.d_desc, cnt, max_rows, G.w.A, G.w.sA, G.np);
+    if (e == hipSuccess) e = launch_set_diag(side, G.d_desc, cnt, b, G.w.A, G.w.sA, G.np);
+    if (e == hipSuccess) e = hipMemsetAsync(G.w.used, 0, (size_t)(cnt * G.w.sV), side);
+    if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt);
     t.done();
   }
-  std::vector<int> hp((size_t)np);
-  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), piv, sizeof(int) * np, hipMemcpyDeviceToHost, side);
-  if (e == hipSuccess) e = hipStreamSynchronize(side);
+  // pivot records -> inverse permutations (host), then the unpermuted inverses
   bool coarse_singular = false;
-  std::vector<int> rinv((size_t)np, -1);
-  if (e == hipSuccess) {
-    for (int64_t p = 0; p < np; ++p) {
-      const int r = hp[(size_t)p];
-      if (r < 0 || r >= np || rinv[(size_t)r] >= 0) { coarse_singular = true; break; }
-      rinv[(size_t)r] = (int)p;
+  int sing_level = -1;
+  std::vector<std::vector<int>> rinvs(groups.size());
+  for (size_t gi = 0; gi < groups.size() && e == hipSuccess && !coarse_singular; ++gi) {
+    Group& G = groups[gi];
+    const int cnt = (int)G.mem.size();
+    std::vector<int> hp((size_t)(cnt * G.w.sV));
+    e = hipMemcpyAsync(hp.data(), G.w.rpiv, sizeof(int) * hp.size(), hipMemcpyDeviceToHost, side);
+    if (e == hipSuccess) e = hipStreamSynchronize(side);
+    if (e != hipSuccess) break;
+    std::vector<int>& rv = rinvs[gi];
+    rv.assign(hp.size(), -1);
+    for (int z = 0; z < cnt && !coarse_singular; ++z) {
+      const int* pz = hp.data() + (size_t)z * G.w.sV;
+      int* rz = rv.data() + (size_t)z * G.w.sV;
+      for (int64_t p = 0; p < G.np; ++p) {
+        const int r = pz[p];
+        if (r < 0 || r >= G.np || rz[r] >= 0) { coarse_singular = true; break; }
+        rz[r] = (int)p;
+      }
+      // the real block must pivot within itself (the padding is an identity)
+      for (int64_t p = 0; p < G.n0 && !coarse_singular; ++p)
+        if (pz[p] >= G.n0) coarse_singular = true;
+      if (coarse_singular) sing_level = G.mem[(size_t)z].g;
     }
-    // the real block must pivot within itself (the padding is an identity)
-    for (int64_t p = 0; p < n0 && !coarse_singular; ++p)
-      if (hp[(size_t)p] >= n0) coarse_singular = true;
-    if (!coarse_singular) {
-      Timed t(ctx, KC_COARSE_FACTOR, 0, side);
-      e = hipMemcpyAsync(rinv_d, rinv.data(), sizeof(int) * np, hipMemcpyHostToDevice, side);
-      if (e == hipSuccess) e = launch_gj_unpermute(side, A, np, ctx->coarse_inv, n0, piv, rinv_d);
-      if (e == hipSuccess) e = hipStreamSynchronize(side);   // rinv (host) outlives the copy
-      t.done();
-    }
+    if (coarse_singular) break;
+    Timed t(ctx, KC_COARSE_FACTOR, 0, side);
+    e = hipMemcpyAsync(G.rinv, rv.data(), sizeof(int) * rv.size(), hipMemcpyHostToDevice, side);
+    if (e == hipSuccess)
+      e = launch_gj_unpermute(side, G.w.A, G.w.sA, G.np, G.w.rpiv, G.rinv, G.w.sV, G.d_desc, cnt, b,
+                              G.n0, ctx->coarse_inv);
+    t.done();
   }
   if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, side);
   if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
   std::vector<std::vector<uint8_t>> hs((size_t)ctx->n_levels);
   for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
+    if (ctx->lv[g].n_cells == 0) continue;
     hs[(size_t)g].resize((size_t)ctx->lv[g].n_cells);
     e = hipMemcpyAsync(hs[(size_t)g].data(), status[(size_t)g], hs[(size_t)g].size(),
                        hipMemcpyDeviceToHost, s);
   }
   {
-    // both streams drain before any buffer is released, on every path
+    // both streams drain before any buffer is released, on every path (the
+    // host permutations outlive their copies)
     const hipError_t e1 = hipStreamSynchronize(s);
     const hipError_t e2 = hipStreamSynchronize(side);
     if (e == hipSuccess) e = (e1 != hipSuccess) ? e1 : e2;
@@ -678,7 +934,7 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     return fail(ctx, STV_EHIP, std::string("inverse build failed: ") + hipGetErrorString(e));
   }
   for (int g = 1; g < ctx->n_levels; ++g)
-    for (int32_t c = 0; c < ctx->lv[g].n_cells; ++c)
+    for (int32_t c = 0; c < (int32_t)hs[(size_t)g].size(); ++c)
       if (hs[(size_t)g][(size_t)c]) {
         if (bad_level) *bad_level = g;
         if (bad_cell) *bad_cell = c;
@@ -687,10 +943,10 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
                     "zero pivot in J_T of level " + std::to_string(g) + " cell " + std::to_string(c));
       }
   if (coarse_singular) {
-    if (bad_level) *bad_level = 0;
+    if (bad_level) *bad_level = sing_level;
     if (bad_cell) *bad_cell = -1;
     free_inverses(ctx);
-    return fail(ctx, STV_ESINGULAR, "zero pivot in the coarse matrix");
+    return fail(ctx, STV_ESINGULAR, "zero pivot in a coarse matrix (level " + std::to_string(sing_level) + ")");
   }
   ctx->have_inv = true;
   return STV_OK;
@@ -736,7 +992,7 @@ int stv_prolongate_add(stv_ctx* ctx, int level, const double* d_c, double* d) {
 int stv_coarse_solve(stv_ctx* ctx, const double* r, double* d) {
   STV_TRY(check_ctx(ctx, true, true));
   if (!r || !d || r == d) return fail(ctx, STV_EINVAL, "r, d must be distinct non-NULL vectors");
-  return coarse_apply(ctx, r, d);
+  return coarse_apply(ctx, 0, r, d);
 }
 
 int stv_vcycle(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p) {
@@ -760,135 +1016,213 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
   STV_TRY(ensure_workspace(ctx, m));
   const int G = ctx->n_levels - 1;
   const int64_t n = ctx->ws_n;
+  const int S = ctx->n_inst;
+  const ScalLayout lay{ctx->scal_segs};
+  const Segs sg{ctx->seg_off, S, ctx->max_seg};
   hipStream_t s = ctx->stream;
   double* hs = ctx->hscal;
-  int iters = 0, restarts = 0, hist_len = 0;
+  // every instance runs its own FGMRES; the instances advance in lockstep
+  // (one V-cycle and one matrix product serve all of them) and an instance
+  // that has stopped only carries its iterate along
+  struct Inst {
+    double bnorm = 0, target = 0, beta = 0;
+    bool done = false, cyc = false;
+    int iters = 0, restarts = 0, j_end = 0;
+    std::vector<double> H, cs, sn, gv;
+  };
+  std::vector<Inst> in((size_t)S);
+  int hist_len = 0;
   auto push_hist = [&](double v) {
     if (info && info->history && hist_len < info->history_cap) info->history[hist_len] = v;
     ++hist_len;
   };
-  auto finish = [&](int conv, double relres, int rc) {
+  auto finish = [&](int rc) {
+    int conv = 1, it = 0, rs = 0;
+    double rr = 0.0;
+    for (int z = 0; z < S; ++z) {
+      const Inst& I = in[(size_t)z];
+      const double rel = I.bnorm > 0 ? I.beta / I.bnorm : 0.0;
+      InstInfo& o = ctx->inst_info[(size_t)z];
+      o.iters = I.iters;
+      o.restarts = I.restarts;
+      o.relres = rel;
+      o.converged = (rel <= p->rtol) ? 1 : 0;
+      conv &= o.converged;
+      it = std::max(it, I.iters);
+      rs = std::max(rs, I.restarts);
+      rr = std::isnan(rel) || std::isnan(rr) ? NAN : std::max(rr, rel);
+    }
     if (info) {
-      info->iters = iters;
-      info->restarts = restarts;
+      info->iters = it;
+      info->restarts = rs;
       info->converged = conv;
-      info->true_relres = relres;
+      info->true_relres = rr;
       info->history_len = std::min(hist_len, info->history ? info->history_cap : 0);
     }
     resolve_timers(ctx);
     return rc;
   };
+  auto inst_name = [&](int z) { return S > 1 ? " of instance " + std::to_string(z) : std::string(); };
   if (!p->use_x0) STV_HIP(launch_fill(s, x, n, 0.0));
-  double bn2 = 0.0;
-  STV_TRY(dot_to_host(ctx, bvec, bvec, n, &bn2));
-  const double bnorm = std::sqrt(bn2);
-  if (!std::isfinite(bnorm)) return finish(0, NAN, fail(ctx, STV_ENUMERIC, "NaN/Inf in the right-hand side"));
-  if (bnorm == 0.0) {
-    STV_HIP(launch_fill(s, x, n, 0.0));
-    STV_HIP(hipStreamSynchronize(s));
-    return finish(1, 0.0, STV_OK);
+  std::vector<double> v2;
+  STV_TRY(dots_to_host(ctx, bvec, bvec, n, v2));
+  for (int z = 0; z < S; ++z) {
+    Inst& I = in[(size_t)z];
+    I.bnorm = std::sqrt(v2[(size_t)z]);
+    if (!std::isfinite(I.bnorm)) {
+      I.beta = NAN;
+      return finish(fail(ctx, STV_ENUMERIC, "NaN/Inf in the right-hand side" + inst_name(z)));
+    }
+    I.target = p->rtol * I.bnorm;
+    if (I.bnorm == 0.0) {
+      const int64_t o0 = ctx->inst_row[(size_t)z] * ctx->b, o1 = ctx->inst_row[(size_t)z + 1] * ctx->b;
+      STV_HIP(launch_fill(s, x + o0, o1 - o0, 0.0));
+      I.done = true;
+    }
   }
-  const double target = p->rtol * bnorm;
   STV_TRY(residual(ctx, G, bvec, x, ctx->rt));
-  double beta2 = 0.0;
-  STV_TRY(dot_to_host(ctx, ctx->rt, ctx->rt, n, &beta2));
-  double beta = std::sqrt(beta2);
-  if (!std::isfinite(beta)) return finish(0, NAN, fail(ctx, STV_ENUMERIC, "NaN/Inf in the initial residual"));
-  push_hist(beta / bnorm);
-  bool converged = beta <= target && p->fixed_iters == 0;
+  STV_TRY(dots_to_host(ctx, ctx->rt, ctx->rt, n, v2));
+  double hmax = 0.0;
+  for (int z = 0; z < S; ++z) {
+    Inst& I = in[(size_t)z];
+    if (I.bnorm == 0.0) { I.beta = 0.0; continue; }
+    I.beta = std::sqrt(v2[(size_t)z]);
+    if (!std::isfinite(I.beta))
+      return finish(fail(ctx, STV_ENUMERIC, "NaN/Inf in the initial residual" + inst_name(z)));
+    if (I.beta <= I.target && p->fixed_iters == 0) I.done = true;
+    hmax = std::max(hmax, I.beta / I.bnorm);
+  }
+  push_hist(hmax);
   const int budget = p->fixed_iters > 0 ? p->fixed_iters : p->max_it;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);
-  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
-  double* d_nrm = ctx->scal + 2 * kScalR;
-  double* d_rt2 = ctx->scal + 2 * kScalR + 1;
-  while (!converged && iters < budget) {
-    std::fill(H.begin(), H.end(), 0.0);
+  for (auto& I : in) {
+    I.H.assign((size_t)(m + 1) * m, 0.0);
+    I.cs.assign((size_t)m, 0.0);
+    I.sn.assign((size_t)m, 0.0);
+    I.gv.assign((size_t)m + 1, 0.0);
+  }
+  auto any_cycle = [&]() {
+    for (const auto& I : in) if (I.cyc) return true;
+    return false;
+  };
+  for (;;) {
+    for (auto& I : in) {
+      I.cyc = !I.done && I.iters < budget;
+      I.j_end = 0;
+    }
+    if (!any_cycle()) break;
+    for (int z = 0; z < S; ++z) {
+      Inst& I = in[(size_t)z];
+      std::fill(I.H.begin(), I.H.end(), 0.0);
+      std::fill(I.gv.begin(), I.gv.end(), 0.0);
+      I.gv[0] = I.beta;
+      hs[lay.aux() + z] = I.cyc ? v2[(size_t)z] : 0.0;   // ||rt_z||^2 as reduced on the device
+    }
+    STV_HIP(hipMemcpyAsync(ctx->scal + lay.aux(), hs + lay.aux(), sizeof(double) * S,
+                           hipMemcpyHostToDevice, s));
     {
       Timed t(ctx, KC_KRYLOV);
-      STV_HIP(launch_scale_by_norm(s, ctx->rt, d_rt2, ctx->V, n));   // d_rt2 = ||rt||^2
+      STV_HIP(launch_scale_by_norm(s, ctx->rt, ctx->scal + lay.aux(), 1, ctx->V, sg));
       t.done();
     }
-    std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
-    int j_end = 0;
-    for (int j = 0; j < m; ++j) {
+    int jmax = 0;
+    for (int j = 0; j < m && any_cycle(); ++j) {
       double* vj = ctx->V + (int64_t)j * n;
       double* zj = ctx->Z + (int64_t)j * n;
       STV_TRY(vcycle_level(ctx, G, vj, zj, p->mg));
       STV_TRY(matvec(ctx, G, zj, ctx->w));
       {
         Timed t(ctx, KC_KRYLOV);
-        STV_HIP(launch_multidot(s, ctx->V, j + 1, ctx->w, n, ctx->partial, ctx->scal));
-        STV_HIP(launch_multiaxpy(s, ctx->V, j + 1, ctx->scal, -1.0, ctx->w, n));
-        STV_HIP(launch_multidot(s, ctx->V, j + 1, ctx->w, n, ctx->partial, ctx->scal + kScalR));
-        STV_HIP(launch_multiaxpy(s, ctx->V, j + 1, ctx->scal + kScalR, -1.0, ctx->w, n));
-        STV_HIP(launch_multidot(s, ctx->w, 1, ctx->w, n, ctx->partial, d_nrm));
-        STV_HIP(launch_scale_by_norm(s, ctx->w, d_nrm, ctx->V + (int64_t)(j + 1) * n, n));
+        STV_HIP(launch_multidot(s, ctx->V, j + 1, ctx->w, n, sg, ctx->partial, ctx->scal + lay.h1(0), kScalR));
+        STV_HIP(launch_multiaxpy(s, ctx->V, j + 1, ctx->scal + lay.h1(0), kScalR, -1.0, ctx->w, n, sg));
+        STV_HIP(launch_multidot(s, ctx->V, j + 1, ctx->w, n, sg, ctx->partial, ctx->scal + lay.h2(0), kScalR));
+        STV_HIP(launch_multiaxpy(s, ctx->V, j + 1, ctx->scal + lay.h2(0), kScalR, -1.0, ctx->w, n, sg));
+        STV_HIP(launch_multidot(s, ctx->w, 1, ctx->w, n, sg, ctx->partial, ctx->scal + lay.nrm(), 1));
+        STV_HIP(launch_scale_by_norm(s, ctx->w, ctx->scal + lay.nrm(), 1, ctx->V + (int64_t)(j + 1) * n, sg));
         t.done();
       }
-      STV_HIP(hipMemcpyAsync(hs, ctx->scal, sizeof(double) * (2 * kScalR + 1), hipMemcpyDeviceToHost, s));
+      STV_HIP(hipMemcpyAsync(hs, ctx->scal, sizeof(double) * (lay.nrm() + S), hipMemcpyDeviceToHost, s));
       STV_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) Hij(i, j) = hs[i] + hs[kScalR + i];
-      const double hn = std::sqrt(hs[2 * kScalR]);
-      Hij(j + 1, j) = hn;
-      for (int i = 0; i <= j + 1; ++i)
-        if (!std::isfinite(Hij(i, j))) {
-          resolve_timers(ctx);
-          return finish(0, NAN, fail(ctx, STV_ENUMERIC, "NaN/Inf in the Arnoldi process at step " + std::to_string(iters)));
+      jmax = j + 1;
+      double hist = 0.0;
+      bool any = false;
+      for (int z = 0; z < S; ++z) {
+        Inst& I = in[(size_t)z];
+        if (!I.cyc) continue;
+        auto Hij = [&](int i, int jj) -> double& { return I.H[(size_t)i * m + jj]; };
+        for (int i = 0; i <= j; ++i) Hij(i, j) = hs[lay.h1(z) + i] + hs[lay.h2(z) + i];
+        const double hn = std::sqrt(hs[lay.nrm() + z]);
+        Hij(j + 1, j) = hn;
+        for (int i = 0; i <= j + 1; ++i)
+          if (!std::isfinite(Hij(i, j))) {
+            I.beta = NAN;
+            return finish(fail(ctx, STV_ENUMERIC, "NaN/Inf in the Arnoldi process at step " +
+                                                      std::to_string(I.iters) + inst_name(z)));
+          }
+        const bool breakdown = hn == 0.0;
+        for (int i = 0; i < j; ++i) {
+          const double tmp = I.cs[(size_t)i] * Hij(i, j) + I.sn[(size_t)i] * Hij(i + 1, j);
+          Hij(i + 1, j) = -I.sn[(size_t)i] * Hij(i, j) + I.cs[(size_t)i] * Hij(i + 1, j);
+          Hij(i, j) = tmp;
         }
-      const bool breakdown = hn == 0.0;
-      for (int i = 0; i < j; ++i) {
-        const double tmp = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
-        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
-        Hij(i, j) = tmp;
+        const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+        I.cs[(size_t)j] = Hij(j, j) / den;
+        I.sn[(size_t)j] = Hij(j + 1, j) / den;
+        Hij(j, j) = den;
+        Hij(j + 1, j) = 0.0;
+        I.gv[(size_t)j + 1] = -I.sn[(size_t)j] * I.gv[(size_t)j];
+        I.gv[(size_t)j] = I.cs[(size_t)j] * I.gv[(size_t)j];
+        ++I.iters;
+        I.j_end = j + 1;
+        hist = std::max(hist, std::fabs(I.gv[(size_t)j + 1]) / I.bnorm);
+        any = true;
+        if (p->fixed_iters > 0) {
+          if (I.iters >= p->fixed_iters || breakdown) I.cyc = false;
+        } else if (std::fabs(I.gv[(size_t)j + 1]) <= I.target || I.iters >= p->max_it || breakdown) {
+          I.cyc = false;
+        }
       }
-      const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
-      cs[j] = Hij(j, j) / den;
-      sn[j] = Hij(j + 1, j) / den;
-      Hij(j, j) = den;
-      Hij(j + 1, j) = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      ++iters;
-      j_end = j + 1;
-      push_hist(std::fabs(gv[j + 1]) / bnorm);
-      if (p->fixed_iters > 0) {
-        if (iters >= p->fixed_iters || breakdown) break;
-      } else if (std::fabs(gv[j + 1]) <= target || iters >= p->max_it || breakdown) {
-        break;
+      if (any) push_hist(hist);
+    }
+    // x += Z y per instance, y = R^-1 g (back substitution on the rotated
+    // Hessenberg matrix); instances without steps this cycle take y = 0
+    for (int z = 0; z < S; ++z) {
+      Inst& I = in[(size_t)z];
+      double* yz = hs + lay.y(z);
+      for (int i = 0; i < jmax; ++i) yz[i] = 0.0;
+      for (int i = I.j_end - 1; i >= 0; --i) {
+        double acc = I.gv[(size_t)i];
+        for (int l = i + 1; l < I.j_end; ++l) acc -= I.H[(size_t)i * m + l] * yz[l];
+        yz[i] = acc / I.H[(size_t)i * m + i];
       }
     }
-    // y = R^-1 g (back substitution on the rotated Hessenberg matrix)
-    std::vector<double> y((size_t)j_end);
-    for (int i = j_end - 1; i >= 0; --i) {
-      double acc = gv[i];
-      for (int l = i + 1; l < j_end; ++l) acc -= Hij(i, l) * y[(size_t)l];
-      y[(size_t)i] = acc / Hij(i, i);
-    }
-    for (int i = 0; i < j_end; ++i) hs[3 * kScalR + i] = y[(size_t)i];
-    STV_HIP(hipMemcpyAsync(ctx->scal + 3 * kScalR, hs + 3 * kScalR, sizeof(double) * j_end,
+    STV_HIP(hipMemcpyAsync(ctx->scal + lay.y(0), hs + lay.y(0), sizeof(double) * S * kScalR,
                            hipMemcpyHostToDevice, s));
     {
       Timed t(ctx, KC_KRYLOV);
-      STV_HIP(launch_multiaxpy(s, ctx->Z, j_end, ctx->scal + 3 * kScalR, 1.0, x, n));
+      STV_HIP(launch_multiaxpy(s, ctx->Z, jmax, ctx->scal + lay.y(0), kScalR, 1.0, x, n, sg));
       t.done();
     }
     STV_TRY(residual(ctx, G, bvec, x, ctx->rt));
-    STV_TRY(dot_to_host(ctx, ctx->rt, ctx->rt, n, &beta2));
-    beta = std::sqrt(beta2);
-    ++restarts;
-    if (!std::isfinite(beta)) return finish(0, NAN, fail(ctx, STV_ENUMERIC, "NaN/Inf in the true residual"));
-    if (p->fixed_iters == 0 && beta <= target) converged = true;
-    if (beta == 0.0) {
-      converged = p->fixed_iters == 0 || iters >= p->fixed_iters;
-      break;
+    STV_TRY(dots_to_host(ctx, ctx->rt, ctx->rt, n, v2));
+    for (int z = 0; z < S; ++z) {
+      Inst& I = in[(size_t)z];
+      if (I.j_end == 0) continue;
+      I.beta = std::sqrt(v2[(size_t)z]);
+      ++I.restarts;
+      if (!std::isfinite(I.beta))
+        return finish(fail(ctx, STV_ENUMERIC, "NaN/Inf in the true residual" + inst_name(z)));
+      if (p->fixed_iters == 0 && I.beta <= I.target) I.done = true;
+      if (p->fixed_iters > 0 && I.iters >= p->fixed_iters) I.done = true;
+      if (I.beta == 0.0) I.done = true;
     }
   }
-  const double relres = beta / bnorm;
-  const int conv = relres <= p->rtol ? 1 : 0;
-  if (p->fixed_iters == 0 && !conv)
-    return finish(0, relres, fail(ctx, STV_ENOCONV, "GMRES did not reach rtol within max_it steps"));
-  return finish(conv, relres, STV_OK);
+  if (p->fixed_iters == 0)
+    for (int z = 0; z < S; ++z) {
+      const Inst& I = in[(size_t)z];
+      if (I.bnorm > 0.0 && !(I.beta / I.bnorm <= p->rtol))
+        return finish(fail(ctx, STV_ENOCONV, "GMRES did not reach rtol within max_it steps" + inst_name(z)));
+    }
+  return finish(STV_OK);
 }
 
 int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out) {
@@ -931,9 +1265,32 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells, 
   if (level < 0 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level out of range");
   const DevLevel& L = ctx->lv[level];
   if (n_sdofs) *n_sdofs = L.n_s;
-  if (n_cells) *n_cells = L.n_cells;
+  if (n_cells) *n_cells = L.n_cells_all;
   if (n_loc) *n_loc = (int64_t)L.n_ls * ctx->b;
   if (inverse_bytes) *inverse_bytes = L.inv_elems * (ctx->inv_fp32 ? 4 : 8);
+  return STV_OK;
+}
+
+int stv_instance_layout(stv_ctx* ctx, int inst, int* n_levels, int64_t* row_offset,
+                        int64_t* n_rows) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (inst < 0 || inst >= ctx->n_inst) return fail(ctx, STV_EINVAL, "instance out of range");
+  if (n_levels) *n_levels = ctx->inst_levels[(size_t)inst];
+  if (row_offset) *row_offset = ctx->inst_row[(size_t)inst];
+  if (n_rows) *n_rows = ctx->inst_row[(size_t)inst + 1] - ctx->inst_row[(size_t)inst];
+  return STV_OK;
+}
+
+int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (inst < 0 || inst >= ctx->n_inst) return fail(ctx, STV_EINVAL, "instance out of range");
+  if (!info) return fail(ctx, STV_EINVAL, "info is NULL");
+  const InstInfo& o = ctx->inst_info[(size_t)inst];
+  info->iters = o.iters;
+  info->restarts = o.restarts;
+  info->converged = o.converged;
+  info->true_relres = o.relres;
+  info->history_len = 0;
   return STV_OK;
 }
 

@@ -56,7 +56,34 @@ struct DevLevel {
   // host copies kept for validation / export
   std::vector<int32_t> h_own_ptr;
   std::vector<uint8_t> h_own_loc;
+  int64_t n_cells_all = 0;        // cells of every member, the coarse ones included
 };
+
+// One dense coarse member: an instance whose coarsest level is stored in the
+// packed level that holds rowptr/col/val, at spatial rows [row_off,
+// row_off + n_s); its inverse (n_s*b square, row-major) sits at inv_off of
+// the coarse store.
+struct CoarseDesc {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  int32_t row_off, n_s;
+  int64_t inv_off;
+};
+
+// Work buffers of a batched dense Gauss-Jordan inversion: each array holds
+// one slice per matrix at the given stride (elements).
+struct GjWork {
+  double* A; int64_t sA;          // n x n matrices
+  int* rpiv; uint8_t* used; int64_t sV;   // n pivot records / flags
+  double* B; int64_t sB;          // pivot rows, max(nb, no) x n
+  double* P; int64_t sP;          // two panel buffers, 2 x n x nb
+  double* S; int64_t sS;          // two slab buffers, 2 x n x no
+  double* Bin; int64_t sBin;      // pivot rows of a slab, nb x no
+};
+
+// Results of the last solve for one instance.
+struct InstInfo { int iters = 0, restarts = 0, converged = 0; double relres = 0.0; };
 
 struct TimerPair { hipEvent_t a, b; int cls; int level; };
 
@@ -74,10 +101,22 @@ struct stv_ctx {
   bool have_inv = false;
   int inv_fp32 = 0;
   int inv_full = 0;
-  // coarse dense inverse
-  double* coarse_inv = nullptr;
-  int64_t n0 = 0;
+  // instances: a single hierarchy is one instance; a batch packs many into
+  // block-diagonal levels aligned at their finest level
+  int n_inst = 0;
+  std::vector<int> inst_levels;       // levels of each instance
+  std::vector<int64_t> inst_row;      // first spatial row on the finest level (+ total)
+  int64_t* seg_off = nullptr;         // device: first vector element per instance (+ total)
+  int64_t max_seg = 0;                // longest instance vector on the finest level
+  std::vector<stv::InstInfo> inst_info;
+  // dense coarse members, per packed level (host and device descriptors)
+  std::vector<stv::CoarseDesc> h_coarse[stv::kMaxLevels];
+  stv::CoarseDesc* d_coarse[stv::kMaxLevels] = {};
+  int64_t coarse_max_n0[stv::kMaxLevels] = {};
+  double* coarse_inv = nullptr;       // every member's inverse
+  int64_t coarse_elems = 0;
   int coarse_algo = 0;          // STV_OPT_COARSE_ALGO
+  int64_t scal_segs = 0;        // instances the scalar buffers are sized for
   // Krylov workspace (finest level)
   double* V = nullptr;          // (restart+1) x N
   double* Z = nullptr;          // restart x N
@@ -118,26 +157,32 @@ hipError_t launch_prolongate_add(hipStream_t s, int b, const DevLevel& L, const 
 hipError_t launch_fill(hipStream_t s, double* x, int64_t n, double v);
 hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 // dense coarse level
-hipError_t launch_bsr_to_dense(hipStream_t s, int b, const DevLevel& L, double* A, int64_t n);
+hipError_t launch_bsr_to_dense(hipStream_t s, int b, const CoarseDesc* desc, int cnt,
+                               int32_t max_rows, double* A, int64_t sA, int64_t n);
 // Dense Gauss-Jordan plan: algo 1 = one level of panels (width nb), 2 = slabs
 // of no columns eliminated by panels of nb; the matrix is padded to a
 // multiple of pad; max_n is the largest supported order.
 struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; };
 GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */);
-// Bbuf: max(nb, no) x n; pbuf: 2 x n x nb; Sbuf: 2 x n x no; Bin: nb x no
-hipError_t launch_gj(hipStream_t s, const GjPlan& p, double* A, int64_t n, int* rpiv,
-                     uint8_t* used, double* Bbuf, double* pbuf, double* Sbuf, double* Bin);
-hipError_t launch_set_diag(hipStream_t s, double* A, int64_t lda, int64_t from, int64_t to);
-hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t lda, double* out, int64_t n,
-                               const int* rpiv, const int* rinv);
-hipError_t launch_dense_gemv(hipStream_t s, const double* A, int64_t n, const double* x,
-                             double* y);
-// Krylov helpers: V is row-major (m vectors of length n)
+hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt);
+hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b, double* A,
+                           int64_t sA, int64_t n);
+hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t sA, int64_t n,
+                               const int* rpiv, const int* rinv, int64_t sV,
+                               const CoarseDesc* desc, int cnt, int b, int64_t max_n0,
+                               double* out);
+hipError_t launch_dense_gemv(hipStream_t s, const CoarseDesc* desc, int cnt, int b,
+                             int64_t max_n0, const double* inv, const double* x, double* y);
+// Krylov helpers, per instance segment: V is row-major (m vectors of length
+// n); segment z covers elements [seg[z], seg[z+1]); nseg segments, the
+// longest of max_seg elements.  Scalars of segment z sit at z * stride.
+struct Segs { const int64_t* seg; int nseg; int64_t max_seg; };
+int seg_blocks(const Segs& g);   // partial-sum blocks per segment
 hipError_t launch_multidot(hipStream_t s, const double* V, int m, const double* w, int64_t n,
-                           double* partial, double* out);
+                           const Segs& g, double* partial, double* out, int64_t ostride);
 hipError_t launch_multiaxpy(hipStream_t s, const double* V, int m, const double* coef,
-                            double sign, double* w, int64_t n);
-hipError_t launch_scale_by_norm(hipStream_t s, const double* w, const double* nrm2, double* v,
-                                int64_t n);
+                            int64_t cstride, double sign, double* w, int64_t n, const Segs& g);
+hipError_t launch_scale_by_norm(hipStream_t s, const double* w, const double* nrm2,
+                                int64_t nstride, double* v, const Segs& g);
 
 }  // namespace stv
