@@ -53,13 +53,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d-512x128-dG2",
-                    choices=["2d-512x128-dG2", "2d-16x4-dG1", "3d-128x24x24-dG1"])
+                    choices=["2d-512x128-dG2", "2d-16x4-dG1", "3d-128x24x24-dG1",
+                             "batched-256-2d-dG1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--nu1", type=int, default=2)
     ap.add_argument("--nu2", type=int, default=2)
     ap.add_argument("--omega", type=float, default=0.7)
     ap.add_argument("--coarse-algo", default="auto", choices=["auto", "panels", "slabs"])
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph-leg", action="store_true")
+    ap.add_argument("--nu-sweep", action="store_true",
+                    help="instead of the timing line: FGMRES iterations of the batched "
+                         "instances against viscosity, undamped and damped smoother")
     return ap.parse_args()
 
 
@@ -76,6 +82,10 @@ WORKLOADS = {
                          "3d channel 128x24x24 Q2/P1disc x dG(1), 4 levels, Oseen nu=1e-3, tau=0.01",
                          ((32, 8, 8), 3)),
 }
+# 256 independent 2d dG(1) instances (finest 32x8 .. 128x32, nu in [5e-4, 5e-3],
+# seeds 2000 + j), one batch, FP32-stored inverses, FP64 FGMRES
+BATCHED = "batched-256-2d-dG1"
+N_BATCH = 256
 
 
 def sweep_bytes(L, b, inv_bytes, zero_init_fraction):
@@ -97,36 +107,113 @@ def residual_bytes(L, b):
     return nnzb * (b * b * 8 + 4) + (L.n_sdofs + 1) * 4 + 3 * n_st * 8
 
 
-def cpu_baseline(spec, nu1, nu2, omega):
-    """The FP64 oracle on a bounded sample of the same workload: the same
-    channel, operator and degree on a smaller mesh (the sample field of the
-    workload), full step (all inverses + FGMRES to 1e-8), one thread;
-    reported in cell-sweeps per second."""
+def cpu_baseline(workload, nu1, nu2, omega):
+    """The FP64 oracle on a bounded sample of the same workload, full step
+    (all inverses + FGMRES to 1e-8) per instance, one thread; reported in
+    cell-sweeps per second.  Single hierarchies: the same channel, operator
+    and degree on a smaller mesh (the sample field of the workload); the
+    batch: its first eight instances."""
     from threadpoolctl import threadpool_limits
 
     import oracle
-    from stgen.problem import make_problem
-    dim, n, G, k, tau, nu, seed, _, (n_s, G_s) = spec
-    p = make_problem(dim, n_s, G_s, k, tau, nu, seed)
+    from stgen.problem import batched_instance, make_problem
+    if workload == BATCHED:
+        probs = [batched_instance(j) for j in range(8)]
+        what = ("the batch's first 8 instances (" +
+                ", ".join("x".join(map(str, p.meta["n_fine"])) for p in probs) + " cells)")
+    else:
+        dim, n, G, k, tau, nu, seed, _, (n_s, G_s) = WORKLOADS[workload]
+        probs = [make_problem(dim, n_s, G_s, k, tau, nu, seed)]
+        what = f"{'x'.join(map(str, n_s))} cells, {G_s} levels, same operator"
+    sweeps = 0
+    its = []
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        ol = oracle.prepare_levels(p.levels, p.b)
-        oracle.build_inverses(ol)
-        cinv = oracle.coarse_inverse(ol[0])
-        _, info = oracle.fgmres(lambda v: ol[-1].J @ v, p.rhs,
-                                lambda v: oracle.vcycle(ol, v, nu1, nu2, omega, coarse_inv=cinv),
-                                restart=30, rtol=1e-8)
+        for p in probs:
+            ol = oracle.prepare_levels(p.levels, p.b)
+            oracle.build_inverses(ol)
+            cinv = oracle.coarse_inverse(ol[0])
+            _, info = oracle.fgmres(lambda v: ol[-1].J @ v, p.rhs,
+                                    lambda v: oracle.vcycle(ol, v, nu1, nu2, omega, coarse_inv=cinv),
+                                    restart=30, rtol=1e-8)
+            sweeps += info["iters"] * (nu1 + nu2) * sum(L.n_cells for L in p.levels[1:])
+            its.append(info["iters"])
         dt = time.perf_counter() - t0
-    cells = sum(L.n_cells for L in p.levels[1:])
-    sweeps = info["iters"] * (nu1 + nu2) * cells
     return dict(value=sweeps / dt, unit="cell-sweeps/s", cores=1, kind="oracle",
-                sample=f"{'x'.join(map(str, n_s))} cells, {G_s} levels, same operator; "
-                       f"full step {dt:.1f} s, {info['iters']} FGMRES iterations, 1 thread",
-                seconds=dt, iters=info["iters"])
+                sample=f"{what}; full step {dt:.1f} s, FGMRES iterations {its}, 1 thread",
+                seconds=dt, iters=its)
+
+
+def load_workload(name):
+    """Hierarchies (a list, one per instance), dim, k, right-hand sides,
+    description, and whether the step stores the inverses in FP32."""
+    from stgen.problem import batched_instance, make_problem
+    if name == BATCHED:
+        probs = [batched_instance(j) for j in range(N_BATCH)]
+        desc = ("256 independent 2d channels Q2/P1disc x dG(1), finest 32x8/64x16/96x24/128x32, "
+                "3-5 levels, Oseen nu in [5e-4, 5e-3], tau=0.01, one batch")
+        return probs, 2, 1, desc, True
+    dim, n, G, k, tau, nu, seed, desc, _ = WORKLOADS[name]
+    return [make_problem(dim, n, G, k, tau, nu, seed)], dim, k, desc, False
+
+
+def packed_members(probs):
+    """Per packed level g (finest aligned): [(level object, smoothed?)]."""
+    D = max(len(p.levels) for p in probs)
+    out = []
+    for g in range(D):
+        mem = []
+        for p in probs:
+            l = g - (D - len(p.levels))
+            if l >= 0:
+                mem.append((p.levels[l], l > 0))
+        out.append(mem)
+    return out
+
+
+def nu_sweep(args):
+    """Iterations to 1e-8 of the 256 batched instances (each its own seeded
+    viscosity) with the undamped (omega = 1) and damped (omega = 0.7)
+    smoother, grouped by viscosity and finest grid."""
+    import torch
+
+    import paper_2107_10561_amd as stv
+    from stgen.problem import batched_instance
+    probs = [batched_instance(j) for j in range(N_BATCH)]
+    s = stv.Solver(0)
+    s.set_batch([p.levels for p in probs], 2, 1)
+    s.build_cell_inverses(fp32=False)
+    rhs = torch.from_numpy(np.concatenate([p.rhs for p in probs])).to("cuda:0")
+    nus = np.array([p.nu for p in probs])
+    edges = np.geomspace(5e-4, 5e-3, 5)
+    out = {}
+    for omega in (1.0, 0.7):
+        x = torch.zeros_like(rhs)
+        info = s.gmres_solve(rhs, x, restart=30, max_it=1000, rtol=1e-8, nu1=args.nu1,
+                             nu2=args.nu2, omega=omega, raise_on_noconv=False)
+        its = np.array([s.instance_info(i)["iters"] for i in range(N_BATCH)])
+        conv = np.array([s.instance_info(i)["converged"] for i in range(N_BATCH)])
+        rows = []
+        for a, b_ in zip(edges[:-1], edges[1:]):
+            for size in ((32, 8), (64, 16), (96, 24), (128, 32)):
+                sel = (nus >= a) & (nus <= b_) & np.array([p.meta["n_fine"] == size for p in probs])
+                if sel.any():
+                    rows.append(dict(nu=[float(a), float(b_)], finest="x".join(map(str, size)),
+                                     instances=int(sel.sum()), mean_iters=round(float(its[sel].mean()), 2),
+                                     max_iters=int(its[sel].max())))
+        out[f"omega={omega}"] = dict(all_converged=bool(conv.all()), max_iters=int(its.max()),
+                                     mean_iters=round(float(its.mean()), 2), table=rows)
+        print(f"[nu-sweep] omega {omega}: mean {its.mean():.2f} max {its.max()} "
+              f"converged {conv.all()} ({info['iters']} lockstep steps)", file=sys.stderr, flush=True)
+    print(json.dumps({"nu_sweep": out, "cycle": f"V({args.nu1},{args.nu2})", "instances": N_BATCH,
+                      "data": "synthetic"}), flush=True)
 
 
 def main():
     args = parse()
+    if args.nu_sweep:
+        nu_sweep(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding is a design note, not a measured path.", file=sys.stderr)
@@ -134,29 +221,44 @@ def main():
     import torch
 
     import paper_2107_10561_amd as stv
-    from stgen.problem import make_problem
 
-    spec = WORKLOADS[args.workload]
-    dim, n, G, k, tau, nu, seed, desc, _ = spec
-    b = k + 1
     t0 = time.time()
-    p = make_problem(dim, n, G, k, tau, nu, seed)
+    probs, dim, k, desc, primary_fp32 = load_workload(args.workload)
+    b = k + 1
     print(f"[bench] generated {desc} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     s = stv.Solver(0)
     s.set_coarse_algorithm(args.coarse_algo)
     t0 = time.time()
-    s.set_hierarchy(p.levels, dim, k)
+    if len(probs) == 1:
+        s.set_hierarchy(probs[0].levels, dim, k)
+    else:
+        s.set_batch([p.levels for p in probs], dim, k)
     t_set = time.time() - t0
-    rhs = torch.from_numpy(p.rhs).to("cuda:0")
+    G = s.n_levels
+    members = packed_members(probs)
+    rhs_h = np.concatenate([p.rhs for p in probs])
+    rhs = torch.from_numpy(rhs_h).to("cuda:0")
     x = torch.zeros_like(rhs)
     mg = dict(nu1=args.nu1, nu2=args.nu2, omega=args.omega)
+    cells_smoothed = [sum(L.n_cells for L in p.levels[1:]) for p in probs]
 
-    def step(fp32=False):
+    def step(fp32):
         s.build_cell_inverses(fp32=fp32)
         return s.gmres_solve(rhs, x, restart=30, max_it=1000, rtol=1e-8, **mg)
 
+    def useful_sweeps():
+        return sum(s.instance_info(i)["iters"] * c for i, c in enumerate(cells_smoothed)) * \
+            (args.nu1 + args.nu2)
+
+    shapes = None
+    if not args.no_autotune:
+        s.build_cell_inverses(fp32=primary_fp32)
+        t0 = time.time()
+        shapes = {str(g): list(v) for g, v in s.autotune().items() if g > 0}
+        print(f"[bench] autotuned launch shapes in {time.time() - t0:.2f} s: {shapes}",
+              file=sys.stderr, flush=True)
     for i in range(args.warmup):
-        info = step()
+        info = step(primary_fp32)
         print(f"[bench] warmup {i}: iters {info['iters']} relres {info['true_relres']:.2e}",
               file=sys.stderr, flush=True)
     s.set_timing(True)
@@ -164,14 +266,16 @@ def main():
     t0 = time.perf_counter()
     infos = []
     t_inv = t_gm = 0.0
+    total_sweeps = 0
     for i in range(args.steps):
         a = time.perf_counter()
-        s.build_cell_inverses(fp32=False)
+        s.build_cell_inverses(fp32=primary_fp32)
         torch.cuda.synchronize()
         m = time.perf_counter()
         infos.append(s.gmres_solve(rhs, x, restart=30, max_it=1000, rtol=1e-8, **mg))
         torch.cuda.synchronize()
         e = time.perf_counter()
+        total_sweeps += useful_sweeps()
         t_inv += m - a
         t_gm += e - m
         print(f"[bench] step {i}: inv {1e3 * (m - a):.2f} ms gmres {1e3 * (e - m):.2f} ms "
@@ -181,9 +285,7 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     iters = infos[-1]["iters"]
     relres = infos[-1]["true_relres"]
-    cells_smoothed = sum(L.n_cells for L in p.levels[1:])
-    sweeps_per_step = iters * (args.nu1 + args.nu2) * cells_smoothed
-    total_sweeps = sum(inf["iters"] for inf in infos) * (args.nu1 + args.nu2) * cells_smoothed
+    sweeps_per_step = useful_sweeps()
     value = total_sweeps / elapsed
 
     # per-kernel statistics (HIP events on the library's stream, timed region only)
@@ -193,7 +295,13 @@ def main():
         nl, ms = s.kernel_stats(cls)
         stats[cls] = dict(launches=nl, ms=ms)
     zi = 1.0 / (args.nu1 + args.nu2) if args.nu1 > 0 else 0.0
-    inv_b = {g: s.level_info(g)["inverse_bytes"] for g in range(1, G)}
+    inv_b = {g: s.level_info(g)["inverse_bytes"] for g in range(G)}
+
+    def sweep_bytes_packed(g):
+        return inv_b[g] + sum(sweep_bytes(L, b, 0, zi) for L, sm in members[g] if sm)
+
+    def residual_bytes_packed(g):
+        return sum(residual_bytes(L, b) for L, _ in members[g])
 
     def roofline(cls, bytes_of, kernel, traffic_key):
         """Aggregate over every launch of the kernel in the timed region (the
@@ -217,33 +325,53 @@ def main():
                     finest_bytes_per_launch=int(bytes_of(top)),
                     finest_avg_launch_ms=round(ms_f / max(n_f, 1), 5))
 
-    roof_sweep = roofline("sweep", lambda g: sweep_bytes(p.levels[g], b, inv_b[g], zi),
+    roof_sweep = roofline("sweep", sweep_bytes_packed,
                           "Vanka cell sweep (k_vanka), all smoothed levels", "k_vanka")
-    roof_res = roofline("residual", lambda g: residual_bytes(p.levels[g], b),
+    roof_res = roofline("residual", residual_bytes_packed,
                         "block-sparse level residual (k_spmv), levels >= 1", "k_spmv")
     dominant = roof_sweep if stats["sweep"]["ms"] >= stats["residual"]["ms"] else roof_res
     s.set_timing(False)
 
-    fp32 = None
+    # the other storage precision of the inverses, same solve
+    other = None
     if not args.no_fp32:
-        step(fp32=True)
+        alt = not primary_fp32
+        step(alt)
         torch.cuda.synchronize()
         a = time.perf_counter()
         reps = max(1, min(3, args.steps))
         for _ in range(reps):
-            inf32 = step(fp32=True)
+            inf_alt = step(alt)
         torch.cuda.synchronize()
-        t32 = (time.perf_counter() - a) / reps
-        fp32 = dict(ms_per_step=round(1e3 * t32, 3), iters=inf32["iters"],
-                    true_relres=inf32["true_relres"],
-                    inverse_bytes_finest=s.level_info(top)["inverse_bytes"])
-        print(f"[bench] fp32 step {1e3 * t32:.2f} ms iters {inf32['iters']}", file=sys.stderr,
+        t_alt = (time.perf_counter() - a) / reps
+        other = dict(ms_per_step=round(1e3 * t_alt, 3), iters=inf_alt["iters"],
+                     true_relres=inf_alt["true_relres"],
+                     inverse_bytes_finest=s.level_info(top)["inverse_bytes"])
+        print(f"[bench] {'fp32' if alt else 'fp64'} step {1e3 * t_alt:.2f} ms "
+              f"iters {inf_alt['iters']}", file=sys.stderr, flush=True)
+
+    # the same step with the V-cycle replayed from a captured HIP graph
+    graph_leg = None
+    if not args.no_graph_leg:
+        s.set_graph(True)
+        step(primary_fp32)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        reps = max(1, min(3, args.steps))
+        for _ in range(reps):
+            inf_g = step(primary_fp32)
+        torch.cuda.synchronize()
+        t_g = (time.perf_counter() - a) / reps
+        s.set_graph(False)
+        graph_leg = dict(ms_per_step=round(1e3 * t_g, 3), iters=inf_g["iters"],
+                         true_relres=inf_g["true_relres"])
+        print(f"[bench] graph step {1e3 * t_g:.2f} ms iters {inf_g['iters']}", file=sys.stderr,
               flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(spec, args.nu1, args.nu2, args.omega)
+        cb = cpu_baseline(args.workload, args.nu1, args.nu2, args.omega)
         cpu = {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in cb.items()
                if k_ in ("value", "unit", "cores", "kind", "sample")}
 
@@ -258,12 +386,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64, inverses stored f32" if primary_fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "cells_finest": int(np.prod(n)), "levels": G,
-                   "spacetime_dofs_finest": int(p.levels[-1].n_sdofs * b), "k": k,
-                   "cycle": f"V({args.nu1},{args.nu2})", "omega": args.omega, "restart": 30,
-                   "rtol": 1e-8, "parallelism": "single GPU"},
+        "config": {"workload": desc, "instances": len(probs),
+                   "cells_finest": int(sum(p.levels[-1].n_cells for p in probs)), "levels": G,
+                   "spacetime_dofs_finest": int(sum(p.levels[-1].n_sdofs for p in probs) * b),
+                   "k": k, "cycle": f"V({args.nu1},{args.nu2})", "omega": args.omega,
+                   "restart": 30, "rtol": 1e-8, "parallelism": "single GPU"},
         "time_to_solution_ms": round(ms_per_step, 3),
         "t_inv_ms": round(1e3 * t_inv / args.steps, 3),
         "t_gmres_ms": round(1e3 * t_gm / args.steps, 3),
@@ -275,7 +404,9 @@ def main():
         "roofline": dominant,
         "roofline_sweep": roof_sweep,
         "roofline_residual": roof_res,
-        "fp32_inverses": fp32,
+        ("fp64_inverses" if primary_fp32 else "fp32_inverses"): other,
+        "graph_replay": graph_leg,
+        "launch_shapes": shapes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

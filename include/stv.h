@@ -249,7 +249,34 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
  *   update of the rest on the matrix cores.  Both give the same pivots.
  * Errors: STV_EINVAL (unknown option or value). */
 #define STV_OPT_COARSE_ALGO 1
+/*   STV_OPT_GRAPH: 1 = the V-cycle (stv_vcycle and the preconditioner of
+ *   stv_gmres_solve) is captured once into a HIP graph and replayed: one
+ *   graph launch plus two vector copies instead of one launch per kernel.
+ *   The graph is recaptured when the hierarchy, the inverses or the cycle
+ *   parameters change.  Per-kernel timing then reports the whole replay
+ *   (class 7) instead of the kernels inside it.  0 = eager launches
+ *   (default).  Results are identical in both modes. */
+#define STV_OPT_GRAPH 2
 int stv_set_option(stv_ctx* ctx, int option, int64_t value);
+
+/* Launch shapes of the level kernels of one level: spmv_rows = block rows
+ * per wavefront of the residual (1..4, default 2); sweep_wgs = workgroups
+ * of the Vanka sweep, 0 (default) for one wavefront per cell, otherwise a
+ * persistent launch of that many workgroups whose wavefronts stride over the
+ * cells.  The residual's summation order depends on spmv_rows (results
+ * agree to rounding); the sweep's results do not depend on sweep_wgs.
+ * Errors: STV_ESTATE (no hierarchy), STV_EINVAL. */
+int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs);
+
+/* Autotuner: on every smoothed level, time each residual shape (1..4 rows
+ * per wavefront) and each sweep shape (one wavefront per cell, or persistent
+ * grids of 2, 4, 8, 16 workgroups per compute unit) on the device, five
+ * launches each after one untimed launch, and keep the fastest.  Needs the
+ * inverses (the sweep is timed with the stored ones); uses temporary device
+ * vectors; the hierarchy's data are not modified.  If choices is non-NULL
+ * it receives, for level g < cap/2, choices[2g] = rows per wavefront and
+ * choices[2g+1] = sweep workgroups.  Synchronises the stream. */
+int stv_autotune(stv_ctx* ctx, int* choices, int cap);
 
 /* Per-kernel timing with HIP events on the context's stream.
  * stv_set_timing(ctx, 1) starts recording (and clears the counters);
@@ -257,7 +284,7 @@ int stv_set_option(stv_ctx* ctx, int option, int64_t value);
  * class on one level (level = -1: all levels): 0 = Vanka cell sweep,
  * 1 = level residual / matrix-vector product, 2 = transfers, 3 = coarse
  * apply, 4 = Krylov vector kernels, 5 = cell inverse build, 6 = coarse
- * factorisation.  Synchronises the stream. */
+ * factorisation, 7 = V-cycle graph replay.  Synchronises the stream. */
 int stv_set_timing(stv_ctx* ctx, int on);
 int stv_kernel_stats(stv_ctx* ctx, int kernel_class, int level, int64_t* launches,
                      double* total_ms);

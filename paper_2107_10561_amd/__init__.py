@@ -20,7 +20,7 @@ STV_OK, STV_EINVAL, STV_ENOMEM, STV_EHIP, STV_ESTATE, STV_ESINGULAR, STV_ENOCONV
 STV_F64, STV_F32, STV_STORE_FULL = 0, 1, 2
 STV_LAST_WRITER, STV_POU, STV_ADDITIVE = 0, 1, 2
 KERNEL_CLASSES = {"sweep": 0, "residual": 1, "transfer": 2, "coarse": 3, "krylov": 4,
-                  "inverse": 5, "coarse_factor": 6}
+                  "inverse": 5, "coarse_factor": 6, "graph": 7}
 _ERRNAMES = {STV_EINVAL: "STV_EINVAL", STV_ENOMEM: "STV_ENOMEM", STV_EHIP: "STV_EHIP",
              STV_ESTATE: "STV_ESTATE", STV_ESINGULAR: "STV_ESINGULAR",
              STV_ENOCONV: "STV_ENOCONV", STV_ENUMERIC: "STV_ENUMERIC"}
@@ -89,6 +89,8 @@ def _load():
         "stv_set_batch": (I, [P, I, I, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.POINTER(_Level))]),
         "stv_instance_layout": (I, [P, I, ctypes.POINTER(I), I64P, I64P]),
         "stv_instance_info": (I, [P, I, ctypes.POINTER(_GI)]),
+        "stv_set_launch": (I, [P, I, I, I]),
+        "stv_autotune": (I, [P, ctypes.POINTER(I), I]),
         "stv_kernel_stats": (I, [P, I, I, I64P, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
@@ -104,7 +106,7 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_restrict", "stv_prolongate_add", "stv_coarse_solve", "stv_vcycle",
             "stv_gmres_solve", "stv_get_cell_inverse", "stv_level_info", "stv_set_timing",
             "stv_kernel_stats", "stv_set_option", "stv_set_batch", "stv_instance_layout",
-            "stv_instance_info")
+            "stv_instance_info", "stv_set_launch", "stv_autotune")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2}
 
@@ -313,6 +315,22 @@ class Solver:
     def set_coarse_algorithm(self, name: str):
         """Dense inversion of the coarsest matrix: "auto", "panels" or "slabs"."""
         self._check(_lib.stv_set_option(self._h, 1, COARSE_ALGOS[name]))
+
+    def set_launch(self, level: int, spmv_rows: int, sweep_wgs: int):
+        """Launch shapes of one level's residual and sweep kernels."""
+        self._check(_lib.stv_set_launch(self._h, level, spmv_rows, sweep_wgs))
+
+    def autotune(self):
+        """Time the launch shapes on the device and keep the fastest; returns
+        {level: (rows per wavefront, sweep workgroups)}."""
+        cap = 2 * self.n_levels
+        ch = (ctypes.c_int * cap)()
+        self._check(_lib.stv_autotune(self._h, ch, cap))
+        return {g: (ch[2 * g], ch[2 * g + 1]) for g in range(self.n_levels)}
+
+    def set_graph(self, on: bool):
+        """Replay the V-cycle from a captured HIP graph (identical results)."""
+        self._check(_lib.stv_set_option(self._h, 2, int(bool(on))))
 
     def set_timing(self, on: bool):
         self._check(_lib.stv_set_timing(self._h, int(on)))

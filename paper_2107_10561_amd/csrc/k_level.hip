@@ -44,8 +44,8 @@ __device__ __forceinline__ double fold(double (&p)[NV], int lane) {
 // contiguous, so lane (q_off, j) streams block column j of every (64/B)-th
 // block of the whole range (consecutive lanes read consecutive doubles),
 // keeping RPW*B partial sums that one transpose-reduce folds at the end.
-// Two rows per wavefront was measured fastest (one row leaves too few bytes
-// in flight per wavefront, more rows cost registers).
+// The rows per wavefront (1-4) are a per-level launch parameter: few rows
+// leave lanes idle at the end of the range, many cost registers.
 template <int B, int RPW>
 __global__ void __launch_bounds__(256) k_spmv_rows(const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col,
@@ -98,18 +98,30 @@ __global__ void __launch_bounds__(256) k_spmv_rows(const int32_t* __restrict__ r
   }
 }
 
-hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r, const double* x,
-                       double* y, double sx) {
-  constexpr int RPW = 2;
-  dim3 grid((L.n_s + 4 * RPW - 1) / (4 * RPW)), block(256);
-  switch (b) {
-    case 1: k_spmv_rows<1, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 2: k_spmv_rows<2, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 3: k_spmv_rows<3, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 4: k_spmv_rows<4, RPW><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+template <int B>
+static hipError_t spmv_b(hipStream_t s, const DevLevel& L, const double* r, const double* x,
+                         double* y, double sx) {
+  const int rpw = L.spmv_rpw;
+  dim3 grid((L.n_s + 4 * rpw - 1) / (4 * rpw)), block(256);
+  switch (rpw) {
+    case 1: k_spmv_rows<B, 1><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 2: k_spmv_rows<B, 2><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 3: k_spmv_rows<B, 3><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 4: k_spmv_rows<B, 4><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r, const double* x,
+                       double* y, double sx) {
+  switch (b) {
+    case 1: return spmv_b<1>(s, L, r, x, y, sx);
+    case 2: return spmv_b<2>(s, L, r, x, y, sx);
+    case 3: return spmv_b<3>(s, L, r, x, y, sx);
+    case 4: return spmv_b<4>(s, L, r, x, y, sx);
+  }
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -148,8 +160,9 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
   constexpr int N = B * NLS;
   constexpr int NC = (N + 63) / 64;
   const int lane = threadIdx.x & 63;
-  const int T = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (T >= n_cells) return;  // uniform per wavefront
+  // one cell per wavefront and step; a grid smaller than the cell count makes
+  // the launch persistent (each wavefront strides over the cells)
+  for (int T = blockIdx.x * 4 + (threadIdx.x >> 6); T < n_cells; T += gridDim.x * 4) {
   const int32_t* sd = csd + (int64_t)T * NLS;
   const int o0 = own_ptr[T];
   const int R = (own_ptr[T + 1] - o0) * B;
@@ -189,12 +202,14 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
       d[g] = zero_init ? omega * sum : fma(omega, sum, d[g]);
     }
   }
+  }
 }
 
 template <int B, int NLS>
 static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, double* d,
                            double omega, int zero_init, int fp32, int full) {
-  const unsigned grid = (unsigned)((L.n_cells + 3) / 4);
+  unsigned grid = (unsigned)((L.n_cells + 3) / 4);
+  if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
   if (fp32)
     k_vanka<B, NLS, float><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
                                                 L.inv_off, (const float*)L.inv_store, omega,

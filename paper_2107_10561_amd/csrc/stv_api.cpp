@@ -65,7 +65,18 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+void free_graph(stv_ctx* ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  dfree(ctx->g_in);
+  dfree(ctx->g_out);
+}
+
 void free_inverses(stv_ctx* ctx) {
+  ++ctx->generation;
+  free_graph(ctx);
   for (int g = 0; g < kMaxLevels; ++g) {
     dfree(ctx->lv[g].inv_off);
     dfree(ctx->lv[g].inv_store);
@@ -345,6 +356,66 @@ int vcycle_level(stv_ctx* ctx, int g, const double* r, double* d, const stv_mg_p
     t.done();
   }
   STV_TRY(sweeps(ctx, g, r, d, p.nu2, p.omega, p.mode, false));
+  return STV_OK;
+}
+
+// Capture one V-cycle (finest level, g_in -> g_out) into a HIP graph.  The
+// capture runs the ordinary launch sequence on an internal stream with the
+// per-kernel timers off; nothing in it allocates, synchronises or sets
+// memory with a memset (zero fills are kernels).
+int ensure_graph(stv_ctx* ctx, const stv_mg_params& p) {
+  int64_t om = 0;
+  std::memcpy(&om, &p.omega, sizeof(om));
+  const int64_t key[6] = {ctx->generation, p.nu1, p.nu2, om, p.mode, 0};
+  if (ctx->graph_exec && std::equal(key, key + 6, ctx->graph_key)) return STV_OK;
+  free_graph(ctx);
+  const int G = ctx->n_levels - 1;
+  const int64_t n = (int64_t)ctx->lv[G].n_s * ctx->b;
+  STV_TRY(dalloc(ctx, &ctx->g_in, (size_t)n));
+  STV_TRY(dalloc(ctx, &ctx->g_out, (size_t)n));
+  if (p.mode != STV_LAST_WRITER)
+    for (int g = 1; g < ctx->n_levels; ++g) {
+      DevLevel& L = ctx->lv[g];
+      if (L.n_cells > 0 && !L.corr) STV_TRY(dalloc(ctx, &L.corr, (size_t)L.n_cells * L.n_ls * ctx->b));
+    }
+  STV_HIP(hipStreamSynchronize(ctx->stream));
+  const bool timing = ctx->timing;
+  hipStream_t saved = ctx->stream;
+  ctx->timing = false;
+  ctx->stream = ctx->cap_stream;
+  hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
+  int rc = STV_OK;
+  if (e == hipSuccess) {
+    rc = vcycle_level(ctx, G, ctx->g_in, ctx->g_out, p);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &gr);
+    ctx->graph = gr;
+    if (e2 != hipSuccess) e = e2;
+  }
+  ctx->stream = saved;
+  ctx->timing = timing;
+  if (rc != STV_OK) { free_graph(ctx); return rc; }
+  if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    free_graph(ctx);
+    return fail(ctx, STV_EHIP, std::string("V-cycle graph capture failed: ") + hipGetErrorString(e));
+  }
+  std::copy(key, key + 6, ctx->graph_key);
+  return STV_OK;
+}
+
+// d = MG(r) on the finest level: eager launches, or the captured graph.
+int precond_apply(stv_ctx* ctx, const double* r, double* d, const stv_mg_params& p) {
+  const int G = ctx->n_levels - 1;
+  if (!ctx->use_graph) return vcycle_level(ctx, G, r, d, p);
+  STV_TRY(ensure_graph(ctx, p));
+  const int64_t n = (int64_t)ctx->lv[G].n_s * ctx->b;
+  Timed t(ctx, KC_GRAPH, G);
+  STV_HIP(launch_copy(ctx->stream, r, ctx->g_in, n));
+  STV_HIP(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+  STV_HIP(launch_copy(ctx->stream, ctx->g_out, d, n));
+  t.done();
+  ++ctx->graph_replays;
   return STV_OK;
 }
 
@@ -661,6 +732,7 @@ int stv_create(stv_ctx** out, int device, void* hip_stream) {
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
     g_create_err = "creation of the internal stream/events failed";
@@ -692,6 +764,10 @@ void stv_destroy(stv_ctx* ctx) {
   if (ctx->side) {
     (void)hipStreamSynchronize(ctx->side);
     (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->cap_stream) {
+    (void)hipStreamSynchronize(ctx->cap_stream);
+    (void)hipStreamDestroy(ctx->cap_stream);
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
@@ -999,7 +1075,7 @@ int stv_vcycle(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p)
   STV_TRY(check_ctx(ctx, true, true));
   STV_TRY(check_mg(ctx, p));
   if (!r || !d || r == d) return fail(ctx, STV_EINVAL, "r, d must be distinct non-NULL vectors");
-  return vcycle_level(ctx, ctx->n_levels - 1, r, d, *p);
+  return precond_apply(ctx, r, d, *p);
 }
 
 int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres_params* p,
@@ -1128,7 +1204,7 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
     for (int j = 0; j < m && any_cycle(); ++j) {
       double* vj = ctx->V + (int64_t)j * n;
       double* zj = ctx->Z + (int64_t)j * n;
-      STV_TRY(vcycle_level(ctx, G, vj, zj, p->mg));
+      STV_TRY(precond_apply(ctx, vj, zj, p->mg));
       STV_TRY(matvec(ctx, G, zj, ctx->w));
       {
         Timed t(ctx, KC_KRYLOV);
@@ -1294,12 +1370,105 @@ int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info) {
   return STV_OK;
 }
 
+int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (level < 0 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level out of range");
+  if (spmv_rows < 1 || spmv_rows > 4) return fail(ctx, STV_EINVAL, "spmv_rows must be in [1, 4]");
+  if (sweep_wgs < 0) return fail(ctx, STV_EINVAL, "sweep_wgs must be >= 0");
+  STV_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->lv[level].spmv_rpw = spmv_rows;
+  ctx->lv[level].sweep_wgs = sweep_wgs;
+  ++ctx->generation;   // a captured V-cycle holds the old launch shapes
+  free_graph(ctx);
+  return STV_OK;
+}
+
+int stv_autotune(stv_ctx* ctx, int* choices, int cap) {
+  STV_TRY(check_ctx(ctx, true, true));
+  const int b = ctx->b;
+  hipStream_t s = ctx->stream;
+  int64_t nmax = 0;
+  for (int g = 0; g < ctx->n_levels; ++g) nmax = std::max<int64_t>(nmax, (int64_t)ctx->lv[g].n_s * b);
+  double *x = nullptr, *r = nullptr, *y = nullptr;
+  auto cleanup = [&]() { dfree(x); dfree(r); dfree(y); };
+  if (dalloc(ctx, &x, (size_t)nmax) != STV_OK || dalloc(ctx, &r, (size_t)nmax) != STV_OK ||
+      dalloc(ctx, &y, (size_t)nmax) != STV_OK) {
+    cleanup();
+    return STV_ENOMEM;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_fill(s, x, nmax, 1.0);
+  if (e == hipSuccess) e = launch_fill(s, r, nmax, 0.5);
+  // average milliseconds of reps launches of f after one untimed launch
+  auto time_it = [&](auto&& f, double& ms) -> hipError_t {
+    const int reps = 5;
+    hipError_t er = f();
+    if (er == hipSuccess) er = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && er == hipSuccess; ++i) er = f();
+    if (er == hipSuccess) er = hipEventRecord(e1, s);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (er == hipSuccess) er = hipEventElapsedTime(&t, e0, e1);
+    ms = t / reps;
+    return er;
+  };
+  for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
+    DevLevel& L = ctx->lv[g];
+    if (L.n_cells == 0) continue;
+    int best_r = L.spmv_rpw;
+    double best = 1e30;
+    for (int rpw = 1; rpw <= 4 && e == hipSuccess; ++rpw) {
+      L.spmv_rpw = rpw;
+      double ms = 0;
+      e = time_it([&]() { return launch_spmv(s, b, L, r, x, y, -1.0); }, ms);
+      if (ms < best) { best = ms; best_r = rpw; }
+    }
+    L.spmv_rpw = best_r;
+    int best_w = 0;
+    best = 1e30;
+    int cu = 256;
+    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    const int full_grid = (L.n_cells + 3) / 4;
+    const int cand[5] = {0, 2 * cu, 4 * cu, 8 * cu, 16 * cu};
+    for (int c = 0; c < 5 && e == hipSuccess; ++c) {
+      if (c > 0 && cand[c] >= full_grid) break;
+      L.sweep_wgs = cand[c];
+      double ms = 0;
+      e = time_it([&]() {
+        return launch_vanka_cells(s, b, L, x, y, 0.7, 0, ctx->inv_fp32, ctx->inv_full);
+      }, ms);
+      if (ms < best) { best = ms; best_w = cand[c]; }
+    }
+    L.sweep_wgs = best_w;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const hipError_t es = hipStreamSynchronize(s);
+  cleanup();
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return fail(ctx, STV_EHIP, std::string("autotune failed: ") + hipGetErrorString(e));
+  ++ctx->generation;
+  free_graph(ctx);
+  if (choices)
+    for (int g = 0; g < ctx->n_levels && 2 * g + 1 < cap; ++g) {
+      choices[2 * g] = ctx->lv[g].spmv_rpw;
+      choices[2 * g + 1] = ctx->lv[g].sweep_wgs;
+    }
+  return STV_OK;
+}
+
 int stv_set_option(stv_ctx* ctx, int option, int64_t value) {
   if (!ctx) return STV_EINVAL;
   switch (option) {
     case STV_OPT_COARSE_ALGO:
       if (value < 0 || value > 2) return fail(ctx, STV_EINVAL, "coarse algorithm must be 0, 1 or 2");
       ctx->coarse_algo = (int)value;
+      return STV_OK;
+    case STV_OPT_GRAPH:
+      if (value < 0 || value > 1) return fail(ctx, STV_EINVAL, "graph option must be 0 or 1");
+      ctx->use_graph = (int)value;
       return STV_OK;
     default:
       return fail(ctx, STV_EINVAL, "unknown option");

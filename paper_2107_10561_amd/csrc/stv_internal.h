@@ -18,7 +18,8 @@ constexpr int kMaxRestart = 256;
 constexpr int kDotBlocks = 1024;     // partial sums per Krylov reduction
 
 enum KernelClass {
-  KC_SWEEP = 0, KC_RESIDUAL, KC_TRANSFER, KC_COARSE, KC_KRYLOV, KC_INVERSE, KC_COARSE_FACTOR, KC_COUNT
+  KC_SWEEP = 0, KC_RESIDUAL, KC_TRANSFER, KC_COARSE, KC_KRYLOV, KC_INVERSE, KC_COARSE_FACTOR,
+  KC_GRAPH, KC_COUNT
 };
 
 // Device arrays of one level.
@@ -57,6 +58,9 @@ struct DevLevel {
   std::vector<int32_t> h_own_ptr;
   std::vector<uint8_t> h_own_loc;
   int64_t n_cells_all = 0;        // cells of every member, the coarse ones included
+  // launch shapes (chosen by the autotuner or set explicitly)
+  int spmv_rpw = 2;               // block rows per wavefront of the residual, 1..4
+  int sweep_wgs = 0;              // workgroups of a persistent sweep (0: one wavefront per cell)
 };
 
 // One dense coarse member: an instance whose coarsest level is stored in the
@@ -117,6 +121,18 @@ struct stv_ctx {
   int64_t coarse_elems = 0;
   int coarse_algo = 0;          // STV_OPT_COARSE_ALGO
   int64_t scal_segs = 0;        // instances the scalar buffers are sized for
+  // V-cycle replayed from a captured HIP graph (STV_OPT_GRAPH): the graph
+  // reads g_in and writes g_out; it is captured on cap_stream and replayed
+  // on the caller's stream, and recaptured when its key changes
+  int use_graph = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double* g_in = nullptr;
+  double* g_out = nullptr;
+  int64_t graph_key[6] = {};    // generation, nu1, nu2, omega bits, mode, launches tuned
+  int64_t generation = 0;       // bumped by every hierarchy / inverse change
+  int64_t graph_replays = 0;
   // Krylov workspace (finest level)
   double* V = nullptr;          // (restart+1) x N
   double* Z = nullptr;          // restart x N
