@@ -230,6 +230,41 @@ int stv_vcycle(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p)
 int stv_gmres_solve(stv_ctx* ctx, const double* b, double* x,
                     const stv_gmres_params* p, stv_gmres_info* info);
 
+/* Adjoint solves: the same V-cycle and FGMRES for the transposed system
+ * J^T x = b.  The level operators become J_g^T (built once per hierarchy on
+ * first use), the smoother the Vanka sweep of J^T, whose local inverses
+ * (J_T^T)^-1 = (J_T^-1)^T are the stored ones read transposed (so the
+ * inverses must be built with STV_STORE_FULL), with the same owner rule;
+ * the transfers are unchanged and the coarse solve applies the transposed
+ * coarse inverse.  Last-writer mode only.  Errors as stv_vcycle /
+ * stv_gmres_solve, and STV_ESTATE without full inverses. */
+int stv_vcycle_transposed(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p);
+int stv_gmres_solve_transposed(stv_ctx* ctx, const double* b, double* x,
+                               const stv_gmres_params* p, stv_gmres_info* info);
+
+/* Cellwise bilinear form of two device vectors of `level` (time-inner):
+ *   out[T] = sum_l tw[l] sum_{alpha,beta} lam[s_alpha, l] K_T[alpha][beta] x[s_beta, l]
+ * for every smoothed cell T of the level, with the spatial matrix
+ * K_T = sum_{e = kptr[T]}^{kptr[T+1]-1} kw[e] Kref[kidx[e]] built from n_ref
+ * reference matrices (n_ls x n_ls row-major each, in the spatial order of
+ * eq. (4.4)).  With K_T the viscosity derivative of the cell's element
+ * matrix this is the per-cell term lam_c^T K_c x_c of an adjoint gradient.
+ * Kref, kptr, kidx, kw, tw are host arrays (copied); lam, x, out device
+ * (out: one double per cell).  Synchronises.  Errors: STV_EINVAL. */
+int stv_cell_contract(stv_ctx* ctx, int level, const double* lam, const double* x, int n_ref,
+                      const double* Kref, const int32_t* kptr, const int32_t* kidx,
+                      const double* kw, const double* tw, double* out);
+
+/* out[k] = sum over cell cells[k]'s DoFs of lam times f[k] (f: host, n x
+ * n_loc, cell-local order alpha*(k+1) + l); out is a device array of n
+ * doubles.  Synchronises.  Errors: STV_EINVAL. */
+int stv_cell_dot(stv_ctx* ctx, int level, const double* lam, int n, const int32_t* cells,
+                 const double* f, double* out);
+
+/* out[i] = a_i . b_i for every instance i of two finest-level device vectors
+ * (out: host array of n_inst doubles).  Synchronises. */
+int stv_dot(stv_ctx* ctx, const double* a, const double* b, double* out);
+
 /* Copy the stored inverse of cell `cell` on `level` (>= 1) into the host array
  * out[n_loc*n_loc], row-major in the cell-local order of eq. (4.4)
  * (time-major: index l*n_ls + alpha), converted to FP64.  Rows not stored

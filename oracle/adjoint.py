@@ -17,10 +17,9 @@ import scipy.sparse.linalg as sla
 
 
 def solve_and_adjoint(J, b, q):
-    """x = J^-1 b and lam = J^-T q (sparse LU)."""
-    x = sla.spsolve(J.tocsc(), b)
-    lam = sla.spsolve(J.T.tocsc(), q)
-    return x, lam
+    """x = J^-1 b and lam = J^-T q (one sparse LU, used both ways)."""
+    lu = sla.splu(J.tocsc())
+    return lu.solve(b), lu.solve(q, trans="T")
 
 
 def cell_contraction(lam, x, cell_sdofs, b, refs, ref_ptr, ref_idx, ref_w, tw):

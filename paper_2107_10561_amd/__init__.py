@@ -90,6 +90,11 @@ def _load():
         "stv_instance_layout": (I, [P, I, ctypes.POINTER(I), I64P, I64P]),
         "stv_instance_info": (I, [P, I, ctypes.POINTER(_GI)]),
         "stv_set_launch": (I, [P, I, I, I]),
+        "stv_vcycle_transposed": (I, [P, P, P, ctypes.POINTER(_MG)]),
+        "stv_gmres_solve_transposed": (I, [P, P, P, ctypes.POINTER(_GP), ctypes.POINTER(_GI)]),
+        "stv_cell_contract": (I, [P, I, P, P, I, P, P, P, P, P, P]),
+        "stv_cell_dot": (I, [P, I, P, I, P, P, P]),
+        "stv_dot": (I, [P, P, P, P]),
         "stv_autotune": (I, [P, ctypes.POINTER(I), I]),
         "stv_kernel_stats": (I, [P, I, I, I64P, ctypes.POINTER(D)]),
     }
@@ -106,7 +111,8 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_restrict", "stv_prolongate_add", "stv_coarse_solve", "stv_vcycle",
             "stv_gmres_solve", "stv_get_cell_inverse", "stv_level_info", "stv_set_timing",
             "stv_kernel_stats", "stv_set_option", "stv_set_batch", "stv_instance_layout",
-            "stv_instance_info", "stv_set_launch", "stv_autotune")
+            "stv_instance_info", "stv_set_launch", "stv_autotune", "stv_vcycle_transposed",
+            "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2}
 
@@ -298,6 +304,54 @@ class Solver:
         if rc != STV_OK and (rc != STV_ENOCONV or raise_on_noconv):
             self._check(rc)
         return info
+
+    def vcycle_transposed(self, r, d, nu1=2, nu2=2, omega=0.7):
+        top = self.n_levels - 1
+        mg = _MG(nu1, nu2, omega, STV_LAST_WRITER)
+        self._check(_lib.stv_vcycle_transposed(self._h, self._vec(r, top, "r"),
+                                               self._vec(d, top, "d"), ctypes.byref(mg)))
+
+    def gmres_solve_transposed(self, b, x, restart=30, max_it=1000, rtol=1e-8, use_x0=False,
+                               fixed_iters=0, nu1=2, nu2=2, omega=0.7, raise_on_noconv=True):
+        """Solve J^T x = b (inverses built with full=True)."""
+        top = self.n_levels - 1
+        gp = _GP(restart, max_it, rtol, int(use_x0), fixed_iters,
+                 _MG(nu1, nu2, omega, STV_LAST_WRITER))
+        gi = _GI(0, 0, 0, 0.0, None, 0, 0)
+        rc = _lib.stv_gmres_solve_transposed(self._h, self._vec(b, top, "b"),
+                                             self._vec(x, top, "x"), ctypes.byref(gp),
+                                             ctypes.byref(gi))
+        info = dict(iters=gi.iters, restarts=gi.restarts, converged=bool(gi.converged),
+                    true_relres=gi.true_relres, status=rc)
+        if rc != STV_OK and (rc != STV_ENOCONV or raise_on_noconv):
+            self._check(rc)
+        return info
+
+    def cell_contract(self, level, lam, x, refs, kptr, kidx, kw, tw, out):
+        """out[T] = sum_l tw[l] lam_T,l . K_T x_T,l, K_T = sum kw refs[kidx] (device out)."""
+        refs = np.ascontiguousarray(refs, dtype=np.float64)
+        kptr = np.ascontiguousarray(kptr, dtype=np.int32)
+        kidx = np.ascontiguousarray(kidx, dtype=np.int32)
+        kw = np.ascontiguousarray(kw, dtype=np.float64)
+        tw = np.ascontiguousarray(tw, dtype=np.float64)
+        self._check(_lib.stv_cell_contract(
+            self._h, level, self._vec(lam, level, "lam"), self._vec(x, level, "x"),
+            int(refs.shape[0]), refs.ctypes.data, kptr.ctypes.data, kidx.ctypes.data,
+            kw.ctypes.data, tw.ctypes.data, ctypes.c_void_p(out.data_ptr())))
+
+    def cell_dot(self, level, lam, cells, f, out):
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(_lib.stv_cell_dot(self._h, level, self._vec(lam, level, "lam"),
+                                      int(cells.size), cells.ctypes.data, f.ctypes.data,
+                                      ctypes.c_void_p(out.data_ptr())))
+
+    def dot(self, a, b):
+        """Per-instance dot products of two finest-level vectors (host list)."""
+        top = self.n_levels - 1
+        out = (ctypes.c_double * self.n_inst)()
+        self._check(_lib.stv_dot(self._h, self._vec(a, top, "a"), self._vec(b, top, "b"), out))
+        return list(out)
 
     def get_cell_inverse(self, level, cell):
         info = self.level_info(level)

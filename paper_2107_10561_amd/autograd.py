@@ -1,0 +1,101 @@
+"""Differentiable space-time solve.
+
+SpaceTimeSolve.apply(nu, U, data, opts) returns x with J(nu) x = b(nu, U) on
+the finest level, solved by the library's FGMRES + Vanka-GMG.  Its backward
+pass solves the adjoint system J^T lam = dL/dx with the transposed
+Vanka-GMG (the stored inverses read transposed) and forms
+
+  dL/dnu_c = -lam_c^T (W_tau (x) K_c) x_c + U lam_c^T F_c,
+  dL/dU    = lam^T (F_0 + sum_c nu_c F_c),
+
+for an operator affine in each cell's viscosity, J = J_0 + sum_c nu_c
+(W_tau (x) K_c), and a right-hand side b = U (F_0 + sum_c nu_c F_c); the
+cellwise terms are computed on the device by the library's contraction
+kernels.  `data` describes the problem (attributes below); the hierarchy for
+a given viscosity comes from data.build(nu).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import Solver
+
+
+class AdjointData:
+    """Problem description for SpaceTimeSolve.
+
+    build(nu) -> list of levels, coarsest first, for the
+    per-cell viscosity nu of the finest level; dim, k; refs (R, n_ls, n_ls),
+    kptr, kidx, kw (K_c per finest cell), tw (time weights of K_c); F0
+    (time-inner vector), in_cells, Fc (n_in, n_ls, k+1): the right-hand side
+    for U = 1.
+    """
+
+    def __init__(self, build, dim, k, refs, kptr, kidx, kw, tw, F0, in_cells, Fc):
+        self.build, self.dim, self.k = build, dim, k
+        self.refs, self.kptr, self.kidx, self.kw, self.tw = refs, kptr, kidx, kw, tw
+        self.F0, self.in_cells, self.Fc = F0, np.asarray(in_cells, np.int32), Fc
+
+    def rhs_hat(self, nu, cell_sdofs):
+        """F0 + sum_c nu_c F_c (U = 1), time-inner."""
+        b = self.k + 1
+        out = self.F0.copy()
+        for i in range(b):
+            np.add.at(out, cell_sdofs[self.in_cells].reshape(-1).astype(np.int64) * b + i,
+                      (nu[self.in_cells][:, None] * self.Fc[:, :, i]).reshape(-1))
+        return out
+
+
+class SolveOptions:
+    def __init__(self, device=0, fp32=False, rtol=1e-10, restart=30, max_it=1000):
+        self.device, self.fp32, self.rtol = device, fp32, rtol
+        self.restart, self.max_it = restart, max_it
+        self.solver = None
+        self.last_info = {}
+
+
+class SpaceTimeSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, nu, U, data, opts):
+        nu_h = nu.detach().cpu().numpy().astype(np.float64)
+        U_h = float(U.detach().cpu())
+        levels = data.build(nu_h)
+        if opts.solver is None:
+            opts.solver = Solver(opts.device)
+        s = opts.solver
+        s.set_hierarchy(levels, data.dim, data.k)
+        s.build_cell_inverses(fp32=opts.fp32, full=True)
+        csd = np.asarray(levels[-1].cell_sdofs)
+        bhat = data.rhs_hat(nu_h, csd)
+        dev = torch.device("cuda", opts.device)
+        bh = torch.from_numpy(bhat).to(dev)
+        b = U_h * bh
+        x = torch.zeros_like(b)
+        info = s.gmres_solve(b, x, restart=opts.restart, max_it=opts.max_it, rtol=opts.rtol)
+        opts.last_info["forward"] = info
+        ctx.save_for_backward(x, bh)
+        ctx.data, ctx.opts, ctx.U, ctx.nu_dev, ctx.nu_dtype = data, opts, U_h, nu.device, nu.dtype
+        ctx.n_cells = csd.shape[0]
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        x, bh = ctx.saved_tensors
+        data, opts, s = ctx.data, ctx.opts, ctx.opts.solver
+        lam = torch.zeros_like(x)
+        info = s.gmres_solve_transposed(gx.contiguous().to(torch.float64), lam,
+                                        restart=opts.restart, max_it=opts.max_it, rtol=opts.rtol)
+        opts.last_info["adjoint"] = info
+        G = s.n_levels - 1
+        con = torch.empty(ctx.n_cells, dtype=torch.float64, device=x.device)
+        s.cell_contract(G, lam, x, data.refs, data.kptr, data.kidx, data.kw, data.tw, con)
+        fdot = torch.empty(len(data.in_cells), dtype=torch.float64, device=x.device)
+        nin = len(data.in_cells)
+        s.cell_dot(G, lam, data.in_cells, data.Fc.reshape(nin, -1), fdot)
+        grad_nu = -con
+        grad_nu.index_add_(0, torch.from_numpy(data.in_cells.astype(np.int64)).to(x.device),
+                           ctx.U * fdot)
+        gU = s.dot(lam, bh)[0]
+        return (grad_nu.to(ctx.nu_dev, ctx.nu_dtype),
+                torch.tensor(gU, dtype=torch.float64), None, None)

@@ -568,6 +568,33 @@ __global__ void __launch_bounds__(256) k_dense_gemv(const CoarseDesc* __restrict
   if (lane == 0) y[vo + row] = acc;
 }
 
+// y = A^T x on every member's rows (the direct solve of the transposed
+// coarse matrix, (A^T)^-1 = (A^-1)^T): thread per column, coalesced over the
+// columns of each row of the stored inverse.
+__global__ void __launch_bounds__(256) k_dense_gemv_t(const CoarseDesc* __restrict__ desc, int b,
+                                                      const double* __restrict__ inv,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ y) {
+  const CoarseDesc D = desc[blockIdx.z];
+  const int64_t n0 = (int64_t)D.n_s * b;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n0) return;
+  const int64_t vo = (int64_t)D.row_off * b;
+  const double* A = inv + D.inv_off;
+  const double* xz = x + vo;
+  double acc = 0.0;
+  for (int64_t i = 0; i < n0; ++i) acc = fma(A[i * n0 + j], xz[i], acc);
+  y[vo + j] = acc;
+}
+
+hipError_t launch_dense_gemv_t(hipStream_t s, const CoarseDesc* desc, int cnt, int b,
+                               int64_t max_n0, const double* inv, const double* x, double* y) {
+  if (cnt < 1) return hipSuccess;
+  dim3 grid((unsigned)((max_n0 + 255) / 256), 1, (unsigned)cnt);
+  k_dense_gemv_t<<<grid, 256, 0, s>>>(desc, b, inv, x, y);
+  return hipGetLastError();
+}
+
 hipError_t launch_dense_gemv(hipStream_t s, const CoarseDesc* desc, int cnt, int b,
                              int64_t max_n0, const double* inv, const double* x, double* y) {
   if (cnt < 1) return hipSuccess;

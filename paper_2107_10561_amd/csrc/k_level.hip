@@ -99,29 +99,61 @@ __global__ void __launch_bounds__(256) k_spmv_rows(const int32_t* __restrict__ r
 }
 
 template <int B>
-static hipError_t spmv_b(hipStream_t s, const DevLevel& L, const double* r, const double* x,
-                         double* y, double sx) {
+static hipError_t spmv_b(hipStream_t s, const DevLevel& L, bool tr, const double* r,
+                         const double* x, double* y, double sx) {
   const int rpw = L.spmv_rpw;
+  const int32_t* rp = tr ? L.rowptr_t : L.rowptr;
+  const int32_t* cl = tr ? L.col_t : L.col;
+  const double* vl = tr ? L.val_t : L.val;
+  if (!rp || !cl || !vl) return hipErrorInvalidValue;
   dim3 grid((L.n_s + 4 * rpw - 1) / (4 * rpw)), block(256);
   switch (rpw) {
-    case 1: k_spmv_rows<B, 1><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 2: k_spmv_rows<B, 2><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 3: k_spmv_rows<B, 3><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
-    case 4: k_spmv_rows<B, 4><<<grid, block, 0, s>>>(L.rowptr, L.col, L.val, r, x, y, L.n_s, sx); break;
+    case 1: k_spmv_rows<B, 1><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
+    case 2: k_spmv_rows<B, 2><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
+    case 3: k_spmv_rows<B, 3><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
+    case 4: k_spmv_rows<B, 4><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r, const double* x,
-                       double* y, double sx) {
+                       double* y, double sx, bool transposed) {
   switch (b) {
-    case 1: return spmv_b<1>(s, L, r, x, y, sx);
-    case 2: return spmv_b<2>(s, L, r, x, y, sx);
-    case 3: return spmv_b<3>(s, L, r, x, y, sx);
-    case 4: return spmv_b<4>(s, L, r, x, y, sx);
+    case 1: return spmv_b<1>(s, L, transposed, r, x, y, sx);
+    case 2: return spmv_b<2>(s, L, transposed, r, x, y, sx);
+    case 3: return spmv_b<3>(s, L, transposed, r, x, y, sx);
+    case 4: return spmv_b<4>(s, L, transposed, r, x, y, sx);
   }
   return hipErrorInvalidValue;
+}
+
+// Values of the transposed level matrix: block qt of J^T is the transpose of
+// block src[qt] of J (the pattern of J^T is built on the host).
+template <int B>
+__global__ void k_bsr_transpose_vals(const double* __restrict__ val,
+                                     const int32_t* __restrict__ src, double* __restrict__ val_t,
+                                     int64_t nnzb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnzb * B * B) return;
+  const int64_t qt = e / (B * B);
+  const int ij = (int)(e - qt * (B * B));
+  const int i = ij / B, l = ij - i * B;
+  val_t[e] = val[(int64_t)src[qt] * (B * B) + l * B + i];
+}
+
+hipError_t launch_bsr_transpose_vals(hipStream_t s, int b, const double* val, const int32_t* src,
+                                     double* val_t, int64_t nnzb) {
+  const int64_t n = nnzb * b * b;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  switch (b) {
+    case 1: k_bsr_transpose_vals<1><<<grid, 256, 0, s>>>(val, src, val_t, nnzb); break;
+    case 2: k_bsr_transpose_vals<2><<<grid, 256, 0, s>>>(val, src, val_t, nnzb); break;
+    case 3: k_bsr_transpose_vals<3><<<grid, 256, 0, s>>>(val, src, val_t, nnzb); break;
+    case 4: k_bsr_transpose_vals<4><<<grid, 256, 0, s>>>(val, src, val_t, nnzb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -238,6 +270,228 @@ hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const dou
     case 4: return vanka_b<4>(s, L, rho, d, omega, zero_init, fp32, full);
   }
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Vanka sweep of the transposed operator J^T.  Its local inverse is
+// (J_T^T)^-1 = (J_T^-1)^T, the stored full inverse read transposed: with the
+// residual rho_T of J^T in lane j = lane + 64c, the correction
+// c_o = sum_j (J_T^-1)[j][o] rho_j is accumulated row by row (each stored row
+// one coalesced read, rho_j broadcast from its lane); the owner rule and the
+// update are those of the forward sweep.  Needs every stored row.
+template <int B, int NLS, typename TS>
+__global__ void __launch_bounds__(256) k_vanka_t(const double* __restrict__ rho,
+                                                double* __restrict__ d,
+                                                const int32_t* __restrict__ csd,
+                                                const int32_t* __restrict__ own_ptr,
+                                                const uint8_t* __restrict__ own_loc,
+                                                const int64_t* __restrict__ inv_off,
+                                                const TS* __restrict__ store, double omega,
+                                                int zero_init, int n_cells) {
+  constexpr int N = B * NLS;
+  constexpr int NC = (N + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  for (int T = blockIdx.x * 4 + (threadIdx.x >> 6); T < n_cells; T += gridDim.x * 4) {
+    const int32_t* sd = csd + (int64_t)T * NLS;
+    const int o0 = own_ptr[T];
+    const int no = own_ptr[T + 1] - o0;
+    const TS* A = store + inv_off[T];
+    double x[NC], acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = lane + 64 * c;
+      x[c] = 0.0;
+      acc[c] = 0.0;
+      if (j < N) {
+        const int be = j / B;
+        x[c] = rho[(int64_t)sd[be] * B + (j - be * B)];
+      }
+    }
+#pragma unroll
+    for (int cj = 0; cj < NC; ++cj) {
+      const int jn = (N - 64 * cj) < 64 ? (N - 64 * cj) : 64;
+      for (int jl = 0; jl < jn; ++jl) {
+        const double rj = __shfl(x[cj], jl, 64);
+        const TS* Ar = A + (int64_t)(64 * cj + jl) * N;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int o = lane + 64 * c;
+          if (o < N) acc[c] = fma((double)Ar[o], rj, acc[c]);
+        }
+      }
+    }
+    for (int os = 0; os < no; ++os) {
+      const int alpha = own_loc[o0 + os];
+#pragma unroll
+      for (int l = 0; l < B; ++l) {
+        const int o = alpha * B + l;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (o == lane + 64 * c) {
+            const int64_t g = (int64_t)sd[alpha] * B + l;
+            d[g] = zero_init ? omega * acc[c] : fma(omega, acc[c], d[g]);
+          }
+      }
+    }
+  }
+}
+
+template <int B, int NLS>
+static hipError_t vanka_t_bn(hipStream_t s, const DevLevel& L, const double* rho, double* d,
+                             double omega, int zero_init, int fp32) {
+  unsigned grid = (unsigned)((L.n_cells + 3) / 4);
+  if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
+  if (fp32)
+    k_vanka_t<B, NLS, float><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
+                                                  L.inv_off, (const float*)L.inv_store, omega,
+                                                  zero_init, L.n_cells);
+  else
+    k_vanka_t<B, NLS, double><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
+                                                   L.inv_off, (const double*)L.inv_store, omega,
+                                                   zero_init, L.n_cells);
+  return hipGetLastError();
+}
+
+template <int B>
+static hipError_t vanka_t_b(hipStream_t s, const DevLevel& L, const double* rho, double* d,
+                            double omega, int zero_init, int fp32) {
+  if (L.n_ls == 21) return vanka_t_bn<B, 21>(s, L, rho, d, omega, zero_init, fp32);
+  if (L.n_ls == 85) return vanka_t_bn<B, 85>(s, L, rho, d, omega, zero_init, fp32);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_vanka_cells_t(hipStream_t s, int b, const DevLevel& L, const double* rho,
+                                double* d, double omega, int zero_init, int fp32) {
+  switch (b) {
+    case 1: return vanka_t_b<1>(s, L, rho, d, omega, zero_init, fp32);
+    case 2: return vanka_t_b<2>(s, L, rho, d, omega, zero_init, fp32);
+    case 3: return vanka_t_b<3>(s, L, rho, d, omega, zero_init, fp32);
+    case 4: return vanka_t_b<4>(s, L, rho, d, omega, zero_init, fp32);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Cellwise bilinear forms of two level vectors.  out[T] = sum_l tw[l]
+// sum_{alpha, beta} lam[alpha, l] K_T[alpha][beta] x[beta, l] with
+// K_T = sum_e kw[e] Kref[kidx[e]] (e in [kptr[T], kptr[T+1]); n_ls x n_ls
+// spatial reference matrices): one wavefront per cell, lane j = alpha*B + l
+// forms (K_T x)_j with x broadcast from its lane, then a wavefront sum.
+template <int B, int NLS>
+__global__ void __launch_bounds__(256) k_cell_contract(
+    const double* __restrict__ lam, const double* __restrict__ x,
+    const int32_t* __restrict__ csd, int n_cells, const double* __restrict__ Kref,
+    const int32_t* __restrict__ kptr, const int32_t* __restrict__ kidx,
+    const double* __restrict__ kw, const double* __restrict__ tw, double* __restrict__ out) {
+  constexpr int N = B * NLS;
+  constexpr int NC = (N + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int T = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (T >= n_cells) return;  // uniform per wavefront
+  const int32_t* sd = csd + (int64_t)T * NLS;
+  double xv[NC], lv[NC], y[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = lane + 64 * c;
+    xv[c] = lv[c] = y[c] = 0.0;
+    if (j < N) {
+      const int be = j / B;
+      const int64_t g = (int64_t)sd[be] * B + (j - be * B);
+      xv[c] = x[g];
+      lv[c] = lam[g];
+    }
+  }
+  for (int e = kptr[T]; e < kptr[T + 1]; ++e) {
+    const double* K = Kref + (int64_t)kidx[e] * NLS * NLS;
+    const double w = kw[e];
+#pragma unroll
+    for (int cj = 0; cj < NC; ++cj) {
+      const int jn = (N - 64 * cj) < 64 ? (N - 64 * cj) : 64;
+      for (int jl = 0; jl < jn; ++jl) {
+        const int j = 64 * cj + jl;
+        const int beta = j / B, lj = j - beta * B;
+        const double xj = w * __shfl(xv[cj], jl, 64);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int o = lane + 64 * c;
+          if (o < N && (o - (o / B) * B) == lj) y[c] = fma(K[(o / B) * NLS + beta], xj, y[c]);
+        }
+      }
+    }
+  }
+  double sacc = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int o = lane + 64 * c;
+    if (o < N) sacc = fma(tw[o - (o / B) * B] * lv[c], y[c], sacc);
+  }
+  sacc = wave_sum(sacc);
+  if (lane == 0) out[T] = sacc;
+}
+
+// out[k] = sum_j lam[cell k's DoF j] f[k*N + j] (f in the cell-local order
+// alpha*B + l) for the listed cells.
+template <int B, int NLS>
+__global__ void __launch_bounds__(256) k_cell_dot(const double* __restrict__ lam,
+                                                  const int32_t* __restrict__ csd,
+                                                  const int32_t* __restrict__ cells, int n,
+                                                  const double* __restrict__ f,
+                                                  double* __restrict__ out) {
+  constexpr int N = B * NLS;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= n) return;
+  const int32_t* sd = csd + (int64_t)cells[k] * NLS;
+  double acc = 0.0;
+  for (int j = lane; j < N; j += 64) {
+    const int be = j / B;
+    acc = fma(lam[(int64_t)sd[be] * B + (j - be * B)], f[(int64_t)k * N + j], acc);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) out[k] = acc;
+}
+
+hipError_t launch_cell_contract(hipStream_t s, int b, const DevLevel& L, const double* lam,
+                                const double* x, const double* Kref, const int32_t* kptr,
+                                const int32_t* kidx, const double* kw, const double* tw,
+                                double* out) {
+  const unsigned grid = (unsigned)((L.n_cells + 3) / 4);
+#define STV_CC(BB, NN)                                                                    \
+  k_cell_contract<BB, NN><<<grid, 256, 0, s>>>(lam, x, L.cell_sdofs, L.n_cells, Kref, kptr, \
+                                               kidx, kw, tw, out)
+  if (L.n_ls == 21) {
+    switch (b) { case 1: STV_CC(1, 21); break; case 2: STV_CC(2, 21); break;
+                 case 3: STV_CC(3, 21); break; case 4: STV_CC(4, 21); break;
+                 default: return hipErrorInvalidValue; }
+  } else if (L.n_ls == 85) {
+    switch (b) { case 1: STV_CC(1, 85); break; case 2: STV_CC(2, 85); break;
+                 case 3: STV_CC(3, 85); break; case 4: STV_CC(4, 85); break;
+                 default: return hipErrorInvalidValue; }
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef STV_CC
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_dot(hipStream_t s, int b, const DevLevel& L, const double* lam,
+                           const int32_t* cells, int n, const double* f, double* out) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 3) / 4);
+#define STV_CD(BB, NN) k_cell_dot<BB, NN><<<grid, 256, 0, s>>>(lam, L.cell_sdofs, cells, n, f, out)
+  if (L.n_ls == 21) {
+    switch (b) { case 1: STV_CD(1, 21); break; case 2: STV_CD(2, 21); break;
+                 case 3: STV_CD(3, 21); break; case 4: STV_CD(4, 21); break;
+                 default: return hipErrorInvalidValue; }
+  } else if (L.n_ls == 85) {
+    switch (b) { case 1: STV_CD(1, 85); break; case 2: STV_CD(2, 85); break;
+                 case 3: STV_CD(3, 85); break; case 4: STV_CD(4, 85); break;
+                 default: return hipErrorInvalidValue; }
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef STV_CD
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

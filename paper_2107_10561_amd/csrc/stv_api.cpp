@@ -94,6 +94,7 @@ void free_level(DevLevel& L) {
   dfree(L.Pt_rowptr); dfree(L.Pt_col); dfree(L.Pt_val);
   dfree(L.inv_off); dfree(L.inv_store); dfree(L.posmap);
   dfree(L.rho); dfree(L.r); dfree(L.d); dfree(L.corr);
+  dfree(L.rowptr_t); dfree(L.col_t); dfree(L.val_t);
   L = DevLevel();
 }
 
@@ -265,14 +266,14 @@ int check_ctx(stv_ctx* ctx, bool need_hier, bool need_inv) {
 // ---------------------------------------------------------------- level ops
 int residual(stv_ctx* ctx, int g, const double* r, const double* x, double* y) {
   Timed t(ctx, KC_RESIDUAL, g);
-  STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], r, x, y, -1.0));
+  STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], r, x, y, -1.0, ctx->transposed != 0));
   t.done();
   return STV_OK;
 }
 
 int matvec(stv_ctx* ctx, int g, const double* x, double* y) {
   Timed t(ctx, KC_RESIDUAL, g);
-  STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], nullptr, x, y, 1.0));
+  STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], nullptr, x, y, 1.0, ctx->transposed != 0));
   t.done();
   return STV_OK;
 }
@@ -281,6 +282,12 @@ int cell_pass(stv_ctx* ctx, int g, const double* rho, double* d, double omega, i
               int mode) {
   DevLevel& L = ctx->lv[g];
   const int b = ctx->b;
+  if (ctx->transposed) {
+    Timed t(ctx, KC_SWEEP, g);
+    STV_HIP(launch_vanka_cells_t(ctx->stream, b, L, rho, d, omega, zero_init, ctx->inv_fp32));
+    t.done();
+    return STV_OK;
+  }
   if (mode == STV_LAST_WRITER) {
     Timed t(ctx, KC_SWEEP, g);
     STV_HIP(launch_vanka_cells(ctx->stream, b, L, rho, d, omega, zero_init, ctx->inv_fp32,
@@ -324,8 +331,12 @@ int coarse_apply(stv_ctx* ctx, int g, const double* r, double* d) {
   const int cnt = (int)ctx->h_coarse[g].size();
   if (cnt == 0) return STV_OK;
   Timed t(ctx, KC_COARSE, g);
-  STV_HIP(launch_dense_gemv(ctx->stream, ctx->d_coarse[g], cnt, ctx->b, ctx->coarse_max_n0[g],
-                            ctx->coarse_inv, r, d));
+  if (ctx->transposed)
+    STV_HIP(launch_dense_gemv_t(ctx->stream, ctx->d_coarse[g], cnt, ctx->b, ctx->coarse_max_n0[g],
+                                ctx->coarse_inv, r, d));
+  else
+    STV_HIP(launch_dense_gemv(ctx->stream, ctx->d_coarse[g], cnt, ctx->b, ctx->coarse_max_n0[g],
+                              ctx->coarse_inv, r, d));
   t.done();
   return STV_OK;
 }
@@ -366,7 +377,7 @@ int vcycle_level(stv_ctx* ctx, int g, const double* r, double* d, const stv_mg_p
 int ensure_graph(stv_ctx* ctx, const stv_mg_params& p) {
   int64_t om = 0;
   std::memcpy(&om, &p.omega, sizeof(om));
-  const int64_t key[6] = {ctx->generation, p.nu1, p.nu2, om, p.mode, 0};
+  const int64_t key[6] = {ctx->generation, p.nu1, p.nu2, om, p.mode, ctx->transposed};
   if (ctx->graph_exec && std::equal(key, key + 6, ctx->graph_key)) return STV_OK;
   free_graph(ctx);
   const int G = ctx->n_levels - 1;
@@ -417,6 +428,49 @@ int precond_apply(stv_ctx* ctx, const double* r, double* d, const stv_mg_params&
   t.done();
   ++ctx->graph_replays;
   return STV_OK;
+}
+
+// Pattern and values of J^T on every level (once per hierarchy): the
+// pattern by a counting sort of the block columns on the host, the values by
+// a block-transposing gather on the device.
+int ensure_transpose(stv_ctx* ctx) {
+  const int b = ctx->b;
+  for (int g = 0; g < ctx->n_levels; ++g) {
+    DevLevel& L = ctx->lv[g];
+    if (L.val_t) continue;
+    std::vector<int32_t> rp((size_t)L.n_s + 1), cl((size_t)L.nnzb);
+    STV_HIP(hipMemcpy(rp.data(), L.rowptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
+    STV_HIP(hipMemcpy(cl.data(), L.col, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost));
+    std::vector<int32_t> tp((size_t)L.n_s + 1, 0), tc((size_t)L.nnzb), src((size_t)L.nnzb);
+    for (int64_t q = 0; q < L.nnzb; ++q) tp[(size_t)cl[(size_t)q] + 1]++;
+    for (int32_t r = 0; r < L.n_s; ++r) tp[(size_t)r + 1] += tp[(size_t)r];
+    std::vector<int32_t> fillp(tp.begin(), tp.end() - 1);
+    for (int32_t r = 0; r < L.n_s; ++r)
+      for (int32_t q = rp[(size_t)r]; q < rp[(size_t)r + 1]; ++q) {
+        const int32_t c = cl[(size_t)q];
+        tc[(size_t)fillp[(size_t)c]] = r;           // rows ascending: columns of J^T sorted
+        src[(size_t)fillp[(size_t)c]++] = q;
+      }
+    int32_t* dsrc = nullptr;
+    STV_TRY(upload(ctx, &L.rowptr_t, tp.data(), tp.size()));
+    STV_TRY(upload(ctx, &L.col_t, tc.data(), tc.size()));
+    STV_TRY(dalloc(ctx, &L.val_t, (size_t)L.nnzb * b * b));
+    STV_TRY(upload(ctx, &dsrc, src.data(), src.size()));
+    hipError_t e = launch_bsr_transpose_vals(ctx->stream, b, L.val, dsrc, L.val_t, L.nnzb);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dfree(dsrc);
+    if (e != hipSuccess) return fail(ctx, STV_EHIP, std::string("transpose failed: ") + hipGetErrorString(e));
+  }
+  return STV_OK;
+}
+
+int check_transposable(stv_ctx* ctx, int mode) {
+  STV_TRY(check_ctx(ctx, true, true));
+  if (!ctx->inv_full)
+    return fail(ctx, STV_ESTATE, "transposed solves need inverses built with STV_STORE_FULL");
+  if (mode != STV_LAST_WRITER)
+    return fail(ctx, STV_EINVAL, "transposed solves use the last-writer sweep only");
+  return ensure_transpose(ctx);
 }
 
 int check_mg(stv_ctx* ctx, const stv_mg_params* p) {
@@ -1299,6 +1353,94 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
         return finish(fail(ctx, STV_ENOCONV, "GMRES did not reach rtol within max_it steps" + inst_name(z)));
     }
   return finish(STV_OK);
+}
+
+int stv_vcycle_transposed(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p) {
+  if (!ctx) return STV_EINVAL;
+  if (!p) return fail(ctx, STV_EINVAL, "mg params NULL");
+  STV_TRY(check_transposable(ctx, p->mode));
+  ctx->transposed = 1;
+  const int rc = stv_vcycle(ctx, r, d, p);
+  ctx->transposed = 0;
+  return rc;
+}
+
+int stv_gmres_solve_transposed(stv_ctx* ctx, const double* bvec, double* x,
+                               const stv_gmres_params* p, stv_gmres_info* info) {
+  if (!ctx) return STV_EINVAL;
+  if (!p) return fail(ctx, STV_EINVAL, "params NULL");
+  STV_TRY(check_transposable(ctx, p->mg.mode));
+  ctx->transposed = 1;
+  const int rc = stv_gmres_solve(ctx, bvec, x, p, info);
+  ctx->transposed = 0;
+  return rc;
+}
+
+int stv_cell_contract(stv_ctx* ctx, int level, const double* lam, const double* x, int n_ref,
+                      const double* Kref, const int32_t* kptr, const int32_t* kidx,
+                      const double* kw, const double* tw, double* out) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (level < 0 || level >= ctx->n_levels || ctx->lv[level].n_cells == 0)
+    return fail(ctx, STV_EINVAL, "level out of range or without smoothed cells");
+  if (!lam || !x || !Kref || !kptr || !kidx || !kw || !tw || !out || n_ref < 1)
+    return fail(ctx, STV_EINVAL, "NULL argument or n_ref < 1");
+  const DevLevel& L = ctx->lv[level];
+  const int nls = L.n_ls;
+  if (kptr[0] != 0) return fail(ctx, STV_EINVAL, "kptr[0] must be 0");
+  for (int32_t c = 0; c < L.n_cells; ++c)
+    if (kptr[c + 1] < kptr[c]) return fail(ctx, STV_EINVAL, "kptr must be non-decreasing");
+  const int32_t ne = kptr[L.n_cells];
+  for (int32_t e = 0; e < ne; ++e)
+    if (kidx[e] < 0 || kidx[e] >= n_ref) return fail(ctx, STV_EINVAL, "kidx out of range");
+  double *dK = nullptr, *dw = nullptr, *dtw = nullptr;
+  int32_t *dp = nullptr, *di = nullptr;
+  auto cleanup = [&]() { dfree(dK); dfree(dw); dfree(dtw); dfree(dp); dfree(di); };
+  int rc = upload(ctx, &dK, Kref, (size_t)n_ref * nls * nls);
+  if (rc == STV_OK) rc = upload(ctx, &dp, kptr, (size_t)L.n_cells + 1);
+  if (rc == STV_OK) rc = upload(ctx, &di, kidx, (size_t)std::max(ne, 1));
+  if (rc == STV_OK) rc = upload(ctx, &dw, kw, (size_t)std::max(ne, 1));
+  if (rc == STV_OK) rc = upload(ctx, &dtw, tw, (size_t)ctx->b);
+  if (rc != STV_OK) { cleanup(); return rc; }
+  hipError_t e = launch_cell_contract(ctx->stream, ctx->b, L, lam, x, dK, dp, di, dw, dtw, out);
+  const hipError_t es = hipStreamSynchronize(ctx->stream);
+  cleanup();
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return fail(ctx, STV_EHIP, std::string("cell contraction failed: ") + hipGetErrorString(e));
+  return STV_OK;
+}
+
+int stv_cell_dot(stv_ctx* ctx, int level, const double* lam, int n, const int32_t* cells,
+                 const double* f, double* out) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (level < 0 || level >= ctx->n_levels || ctx->lv[level].n_cells == 0)
+    return fail(ctx, STV_EINVAL, "level out of range or without smoothed cells");
+  if (n < 0 || (n > 0 && (!lam || !cells || !f || !out))) return fail(ctx, STV_EINVAL, "bad arguments");
+  if (n == 0) return STV_OK;
+  const DevLevel& L = ctx->lv[level];
+  for (int k = 0; k < n; ++k)
+    if (cells[k] < 0 || cells[k] >= L.n_cells) return fail(ctx, STV_EINVAL, "cell out of range");
+  int32_t* dc = nullptr;
+  double* df = nullptr;
+  int rc = upload(ctx, &dc, cells, (size_t)n);
+  if (rc == STV_OK) rc = upload(ctx, &df, f, (size_t)n * L.n_ls * ctx->b);
+  if (rc != STV_OK) { dfree(dc); dfree(df); return rc; }
+  hipError_t e = launch_cell_dot(ctx->stream, ctx->b, L, lam, dc, n, df, out);
+  const hipError_t es = hipStreamSynchronize(ctx->stream);
+  dfree(dc);
+  dfree(df);
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return fail(ctx, STV_EHIP, std::string("cell dot failed: ") + hipGetErrorString(e));
+  return STV_OK;
+}
+
+int stv_dot(stv_ctx* ctx, const double* a, const double* bv, double* out) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (!a || !bv || !out) return fail(ctx, STV_EINVAL, "NULL argument");
+  STV_TRY(ensure_workspace(ctx, 1));
+  std::vector<double> v;
+  STV_TRY(dots_to_host(ctx, a, bv, ctx->ws_n, v));
+  for (int z = 0; z < ctx->n_inst; ++z) out[z] = v[(size_t)z];
+  return STV_OK;
 }
 
 int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out) {

@@ -59,6 +59,8 @@ struct DevLevel {
   std::vector<uint8_t> h_own_loc;
   int64_t n_cells_all = 0;        // cells of every member, the coarse ones included
   // launch shapes (chosen by the autotuner or set explicitly)
+  // transposed level matrix (built on first use by a transposed solve)
+  int32_t* rowptr_t = nullptr; int32_t* col_t = nullptr; double* val_t = nullptr;
   int spmv_rpw = 2;               // block rows per wavefront of the residual, 1..4
   int sweep_wgs = 0;              // workgroups of a persistent sweep (0: one wavefront per cell)
 };
@@ -124,6 +126,7 @@ struct stv_ctx {
   // V-cycle replayed from a captured HIP graph (STV_OPT_GRAPH): the graph
   // reads g_in and writes g_out; it is captured on cap_stream and replayed
   // on the caller's stream, and recaptured when its key changes
+  int transposed = 0;            // level operators act as J^T (adjoint solves)
   int use_graph = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -156,7 +159,19 @@ namespace stv {
 // ---- kernel launchers (each returns the hipError_t of the launch) ----
 // y = (r ? r : 0) + sx * (J x)
 hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
-                       const double* x, double* y, double sx);
+                       const double* x, double* y, double sx, bool transposed = false);
+hipError_t launch_bsr_transpose_vals(hipStream_t s, int b, const double* val, const int32_t* src,
+                                     double* val_t, int64_t nnzb);
+hipError_t launch_vanka_cells_t(hipStream_t s, int b, const DevLevel& L, const double* rho,
+                                double* d, double omega, int zero_init, int fp32);
+hipError_t launch_cell_contract(hipStream_t s, int b, const DevLevel& L, const double* lam,
+                                const double* x, const double* Kref, const int32_t* kptr,
+                                const int32_t* kidx, const double* kw, const double* tw,
+                                double* out);
+hipError_t launch_cell_dot(hipStream_t s, int b, const DevLevel& L, const double* lam,
+                           const int32_t* cells, int n, const double* f, double* out);
+hipError_t launch_dense_gemv_t(hipStream_t s, const CoarseDesc* desc, int cnt, int b,
+                               int64_t max_n0, const double* inv, const double* x, double* y);
 bool inverse_fits_regs(int b, int n_ls);
 hipError_t launch_build_posmap(hipStream_t s, const DevLevel& L);
 hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const double* rho,

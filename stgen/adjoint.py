@@ -176,3 +176,23 @@ def make_differentiation_problem(n_fine=(256, 64), n_levels=5, k=1, tau=0.01, se
     p.nu_cell = nu
     p.loss = outflow_loss_vector(mesh, k, tau)
     return p
+
+
+def add_cell_derivative(level, cell: int, dnu: float, refs, ref_ptr, ref_idx, ref_w, tw):
+    """Block values of the level matrix with cell's viscosity raised by dnu
+    (J is affine in nu_c: J + dnu (W_tau (x) K_c)); returns a new val array."""
+    val = np.array(level.val, copy=True)
+    K = sum(ref_w[e] * refs[ref_idx[e]] for e in range(ref_ptr[cell], ref_ptr[cell + 1]))
+    sd = level.cell_sdofs[cell]
+    rp, col = level.rowptr, level.col
+    W = np.diag(tw)
+    for a in range(sd.size):
+        r = sd[a]
+        cols = col[rp[r]:rp[r + 1]]
+        for bb in range(sd.size):
+            if K[a, bb] == 0.0:
+                continue
+            q = rp[r] + np.searchsorted(cols, sd[bb])
+            assert q < rp[r + 1] and col[q] == sd[bb]
+            val[q] += dnu * K[a, bb] * W
+    return val

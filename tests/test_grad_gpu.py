@@ -1,0 +1,197 @@
+"""Adjoint solves and the differentiable solve through the C ABI.
+
+* The transposed V-cycle and transposed FGMRES equal the oracle's Vanka-GMG
+  of J^T (local inverses recomputed from the transposed blocks).
+* The gradient of the outflow loss with respect to every cell's viscosity
+  and the inflow amplitude equals the oracle's adjoint gradient (direct
+  solves), FP64- and FP32-stored inverses, on small hierarchies and on the
+  256x64, 5-level, dG(1) workload.
+* Central finite differences (h = 1e-6, solves to 1e-13) on 20 random cells
+  of that workload agree with the gradient.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import log, relerr, to_dev, to_host
+from oracle import adjoint as oadj
+from oracle.smoother import spacetime_matrix
+from stgen import adjoint as gadj
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_2107_10561_amd as m
+    return m
+
+
+@functools.lru_cache(maxsize=None)
+def diff_problem(n, G):
+    return gadj.make_differentiation_problem(n, G, 1, 0.01, 3000)
+
+
+def adjoint_data(p):
+    from paper_2107_10561_amd.autograd import AdjointData
+    m = p.levels[-1].mesh
+    refs, ptr, idx, w = gadj.nu_derivative_refs(m)
+    F0, cells, Fc = gadj.inflow_rhs_parts(m, p.k, p.tau)
+    n, G = p.meta["n_fine"], p.meta["n_levels"]
+
+    def build(nu):
+        if np.array_equal(nu, p.nu_cell):
+            return p.levels
+        return gadj.make_differentiation_problem(n, G, p.k, p.tau, 3000, nu=nu).levels
+
+    return AdjointData(build, p.dim, p.k, refs, ptr, idx, w, gadj.time_weights(p.k, p.tau),
+                       F0, cells, Fc)
+
+
+def oracle_gradient(p, U=1.0):
+    m = p.levels[-1].mesh
+    L = p.levels[-1]
+    J = spacetime_matrix(L.rowptr, L.col, L.val, L.n_sdofs, p.b)
+    refs, ptr, idx, w = gadj.nu_derivative_refs(m)
+    F0, cells, Fc = gadj.inflow_rhs_parts(m, p.k, p.tau)
+    return oadj.loss_gradient(J, U * (p.rhs / p.meta["U"]), p.loss, U, p.nu_cell, m.cell_sdofs(),
+                              p.b, refs, ptr, idx, w, gadj.time_weights(p.k, p.tau), F0, cells, Fc)
+
+
+@pytest.mark.parametrize("shape", [((16, 4), 2), ((32, 8), 3)])
+def test_transposed_vcycle_and_fgmres(stv, shape):
+    p = diff_problem(*shape)
+    ol = oracle.build_inverses(oracle.prepare_levels(p.levels, p.b))
+    olt = oadj.transpose_levels(ol)
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    s.build_cell_inverses(full=True)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(ol[-1].n_st)
+    d = to_dev(np.zeros_like(r))
+    s.vcycle_transposed(to_dev(r), d, 2, 2, 0.7)
+    e = relerr(to_host(d), oracle.vcycle(olt, r, 2, 2, 0.7))
+    log(f"[adjoint] {shape} transposed V-cycle rel err {e:.2e}")
+    assert e <= 1e-11
+    cinv = oracle.coarse_inverse(olt[0])
+    xf, _ = oracle.fgmres(lambda v: olt[-1].J @ v, p.loss,
+                          lambda v: oracle.vcycle(olt, v, 2, 2, 0.7, coarse_inv=cinv),
+                          restart=30, fixed_iters=7)
+    x = to_dev(np.zeros_like(r))
+    s.gmres_solve_transposed(to_dev(p.loss), x, restart=30, fixed_iters=7)
+    e = relerr(to_host(x), xf)
+    log(f"[adjoint] {shape} transposed FGMRES(7 steps) rel err {e:.2e}")
+    assert e <= 1e-10
+    # tolerance mode: a true residual of J^T below 1e-8
+    x = to_dev(np.zeros_like(r))
+    info = s.gmres_solve_transposed(to_dev(p.loss), x, restart=30, rtol=1e-8)
+    xh = to_host(x)
+    true = np.linalg.norm(p.loss - ol[-1].J.T @ xh) / np.linalg.norm(p.loss)
+    assert info["converged"] and true <= 1e-8
+
+
+def test_transposed_needs_full_inverses(stv):
+    p = diff_problem((16, 4), 2)
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    s.build_cell_inverses(full=False)
+    x = to_dev(np.zeros(p.levels[-1].n_sdofs * p.b))
+    with pytest.raises(stv.StvError, match="STORE_FULL"):
+        s.gmres_solve_transposed(to_dev(p.loss), x)
+
+
+def _grad_gpu(stv, p, fp32, rtol, U=1.0):
+    import torch
+    from paper_2107_10561_amd.autograd import SolveOptions, SpaceTimeSolve
+    data = adjoint_data(p)
+    opts = SolveOptions(0, fp32=fp32, rtol=rtol)
+    nu = torch.tensor(p.nu_cell, dtype=torch.float64, requires_grad=True)
+    Ut = torch.tensor(U, dtype=torch.float64, requires_grad=True)
+    x = SpaceTimeSolve.apply(nu, Ut, data, opts)
+    q = torch.from_numpy(p.loss).to(x.device)
+    L = (q * x).sum()
+    L.backward()
+    return float(L), nu.grad.numpy().copy(), float(Ut.grad), opts
+
+
+def golden_gradient():
+    """Oracle values written by tests/golden/make_grad_golden.py."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "grad_256x64_dG1.txt")
+    vals, cells, g = {}, [], []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        a, b = line.split()
+        if a.isdigit():
+            cells.append(int(a))
+            g.append(float(b))
+        else:
+            vals[a] = float(b)
+    return vals, np.array(cells), np.array(g)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("shape", [((16, 4), 2), ((256, 64), 5)])
+def test_gradient_matches_oracle(stv, shape, fp32):
+    p = diff_problem(*shape)
+    L, g, gU, opts = _grad_gpu(stv, p, fp32, 1e-12)
+    if shape[0] == (256, 64):
+        vals, cells, gs = golden_gradient()
+        Lo, gUo, gmax = vals["loss"], vals["dL_dU"], vals["max_abs_grad"]
+        eg = np.abs(g[cells] - gs).max() / gmax
+        gmax_gpu = np.abs(g).max()
+        assert abs(gmax_gpu - gmax) <= 1e-8 * gmax
+    else:
+        Lo, go, gUo, _, _ = oracle_gradient(p)
+        eg = np.abs(g - go).max() / np.abs(go).max()
+    log(f"[grad] {shape} fp32={fp32}: L {L:.6e} (oracle {Lo:.6e}), max rel grad err {eg:.2e}, "
+        f"dL/dU {gU:.6e} (oracle {gUo:.6e}), forward iters {opts.last_info['forward']['iters']}, "
+        f"adjoint iters {opts.last_info['adjoint']['iters']}")
+    assert abs(L - Lo) <= 1e-9 * abs(Lo)
+    assert eg <= 1e-8
+    assert abs(gU - gUo) <= 1e-9 * abs(gUo)
+
+
+def test_finite_differences_on_20_cells(stv):
+    import torch
+    p = diff_problem((256, 64), 5)
+    L0, g, gU, _ = _grad_gpu(stv, p, False, 1e-12)
+    m = p.levels[-1].mesh
+    refs, ptr, idx, w = gadj.nu_derivative_refs(m)
+    tw = gadj.time_weights(p.k, p.tau)
+    F0, in_cells, Fc = gadj.inflow_rhs_parts(m, p.k, p.tau)
+    pos = {int(c): i for i, c in enumerate(in_cells)}
+    rng = np.random.default_rng(20)
+    # 20 random cells, and the 4 of largest sensitivity (most cells sit far
+    # upstream of the outflow and have tiny gradients)
+    cells = np.concatenate([rng.choice(m.n_cells, 20, replace=False), np.argsort(-np.abs(g))[:4]])
+    s = stv.Solver(0)
+    q = torch.from_numpy(p.loss).to("cuda:0")
+    h = 1e-6
+    fine = p.levels[-1]
+    for c in cells:
+        vals = []
+        for sgn in (1.0, -1.0):
+            lv = list(p.levels[:-1])
+            val = gadj.add_cell_derivative(fine, int(c), sgn * h, refs, ptr, idx, w, tw)
+            lv.append(dict(n_sdofs=fine.n_sdofs, rowptr=fine.rowptr, col=fine.col, val=val,
+                           cell_sdofs=fine.cell_sdofs, P=fine.P))
+            rhs = p.rhs.copy()
+            if int(c) in pos:     # b = U (F0 + sum nu_c F_c)
+                kk = pos[int(c)]
+                sd = fine.cell_sdofs[c].astype(np.int64)
+                for i in range(p.b):
+                    rhs[sd * p.b + i] += sgn * h * Fc[kk, :, i]
+            s.set_hierarchy(lv, p.dim, p.k)
+            s.build_cell_inverses()
+            x = to_dev(np.zeros_like(rhs))
+            s.gmres_solve(to_dev(rhs), x, restart=30, rtol=1e-13)
+            vals.append(float((q * x).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        log(f"[fd] cell {int(c)}: fd {fd:.8e} adjoint {g[c]:.8e}")
+        assert abs(fd - g[c]) <= 1e-6 * np.abs(g).max()
