@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--omega", type=float, default=0.7)
     ap.add_argument("--coarse-algo", default="auto", choices=["auto", "panels", "slabs"])
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-kron", action="store_true",
+                    help="residual from the stored blocks instead of the spatial factors")
     ap.add_argument("--no-graph-leg", action="store_true")
     ap.add_argument("--nu-sweep", action="store_true",
                     help="instead of the timing line: FGMRES iterations of the batched "
@@ -99,12 +101,13 @@ def sweep_bytes(L, b, inv_bytes, zero_init_fraction):
     return inv_bytes + idx + vec
 
 
-def residual_bytes(L, b):
-    """Algorithmic bytes of one level residual: blocks, columns, row pointers,
-    x, r and y once each."""
+def residual_bytes(L, b, kron=False):
+    """Algorithmic bytes of one level residual: blocks (or the two spatial
+    factor values per block), columns, row pointers, x, r and y once each."""
     nnzb = int(L.col.shape[0])
     n_st = L.n_sdofs * b
-    return nnzb * (b * b * 8 + 4) + (L.n_sdofs + 1) * 4 + 3 * n_st * 8
+    per_block = 2 * 8 if kron else b * b * 8
+    return nnzb * (per_block + 4) + (L.n_sdofs + 1) * 4 + 3 * n_st * 8
 
 
 def cpu_baseline(workload, nu1, nu2, omega):
@@ -236,6 +239,19 @@ def main():
     t_set = time.time() - t0
     G = s.n_levels
     members = packed_members(probs)
+    kron = not args.no_kron
+    if kron:
+        from stgen import fe
+        from stgen.problem import spatial_factors
+        t0 = time.time()
+        _, w, C, _ = fe.time_matrices(k)
+        tw = probs[0].tau * np.asarray(w, dtype=np.float64)
+        for g in range(G):
+            parts = [spatial_factors(L) for L, _ in members[g]]
+            s.set_kron_factors(g, np.concatenate([m_ for m_, _ in parts]),
+                               np.concatenate([a_ for _, a_ in parts]), np.asarray(C), tw)
+        print(f"[bench] spatial factors of every level in {time.time() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     rhs_h = np.concatenate([p.rhs for p in probs])
     rhs = torch.from_numpy(rhs_h).to("cuda:0")
     x = torch.zeros_like(rhs)
@@ -301,7 +317,7 @@ def main():
         return inv_b[g] + sum(sweep_bytes(L, b, 0, zi) for L, sm in members[g] if sm)
 
     def residual_bytes_packed(g):
-        return sum(residual_bytes(L, b) for L, _ in members[g])
+        return sum(residual_bytes(L, b, kron) for L, _ in members[g])
 
     def roofline(cls, bytes_of, kernel, traffic_key):
         """Aggregate over every launch of the kernel in the timed region (the
@@ -328,7 +344,9 @@ def main():
     roof_sweep = roofline("sweep", sweep_bytes_packed,
                           "Vanka cell sweep (k_vanka), all smoothed levels", "k_vanka")
     roof_res = roofline("residual", residual_bytes_packed,
-                        "block-sparse level residual (k_spmv), levels >= 1", "k_spmv")
+                        ("level residual from spatial factors (k_spmv_kron), levels >= 1" if kron
+                         else "block-sparse level residual (k_spmv_rows), levels >= 1"),
+                        "k_spmv_kron" if kron else "k_spmv")
     dominant = roof_sweep if stats["sweep"]["ms"] >= stats["residual"]["ms"] else roof_res
     s.set_timing(False)
 
@@ -407,6 +425,7 @@ def main():
         ("fp64_inverses" if primary_fp32 else "fp32_inverses"): other,
         "graph_replay": graph_leg,
         "launch_shapes": shapes,
+        "residual_from_spatial_factors": kron,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

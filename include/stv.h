@@ -294,6 +294,20 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
 #define STV_OPT_GRAPH 2
 int stv_set_option(stv_ctx* ctx, int option, int64_t value);
 
+/* Spatial factors of a level whose operator has time-independent
+ * coefficients (the Oseen linearisation): every block (i, l) of the level
+ * matrix is C[i][l] M(s, s') + delta_il tw[i] A(s, s') (C: (k+1)^2
+ * row-major, tw: k+1).  mval and aval hold M and A in the level's block
+ * pattern (one value per block, in the order of bsr_col; for a batch, the
+ * packed level's order).  The library checks on the device that the factors
+ * reproduce the stored blocks (to 1e-12 of the largest entry; otherwise
+ * STV_EINVAL) and from then on computes the level's residual from them,
+ * streaming two values per block instead of (k+1)^2; transposed solves keep
+ * using the blocks.  mval = aval = NULL drops the factors.  Host arrays,
+ * copied.  Synchronises. */
+int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const double* aval,
+                         const double* C, const double* tw);
+
 /* Launch shapes of the level kernels of one level: spmv_rows = block rows
  * per wavefront of the residual (1..4, default 2); sweep_wgs = workgroups
  * of the Vanka sweep, 0 (default) for one wavefront per cell, otherwise a

@@ -95,6 +95,7 @@ def _load():
         "stv_cell_contract": (I, [P, I, P, P, I, P, P, P, P, P, P]),
         "stv_cell_dot": (I, [P, I, P, I, P, P, P]),
         "stv_dot": (I, [P, P, P, P]),
+        "stv_set_kron_factors": (I, [P, I, P, P, P, P]),
         "stv_autotune": (I, [P, ctypes.POINTER(I), I]),
         "stv_kernel_stats": (I, [P, I, I, I64P, ctypes.POINTER(D)]),
     }
@@ -112,7 +113,8 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_gmres_solve", "stv_get_cell_inverse", "stv_level_info", "stv_set_timing",
             "stv_kernel_stats", "stv_set_option", "stv_set_batch", "stv_instance_layout",
             "stv_instance_info", "stv_set_launch", "stv_autotune", "stv_vcycle_transposed",
-            "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot")
+            "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot",
+            "stv_set_kron_factors")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2}
 
@@ -369,6 +371,19 @@ class Solver:
     def set_coarse_algorithm(self, name: str):
         """Dense inversion of the coarsest matrix: "auto", "panels" or "slabs"."""
         self._check(_lib.stv_set_option(self._h, 1, COARSE_ALGOS[name]))
+
+    def set_kron_factors(self, level: int, mval, aval, C, tw):
+        """Residual of `level` from its spatial factors (blocks = C[i,l] M +
+        delta_il tw[i] A); mval = aval = None drops them."""
+        if mval is None and aval is None:
+            self._check(_lib.stv_set_kron_factors(self._h, level, None, None, None, None))
+            return
+        mval = np.ascontiguousarray(mval, dtype=np.float64)
+        aval = np.ascontiguousarray(aval, dtype=np.float64)
+        C = np.ascontiguousarray(C, dtype=np.float64)
+        tw = np.ascontiguousarray(tw, dtype=np.float64)
+        self._check(_lib.stv_set_kron_factors(self._h, level, mval.ctypes.data, aval.ctypes.data,
+                                              C.ctypes.data, tw.ctypes.data))
 
     def set_launch(self, level: int, spmv_rows: int, sweep_wgs: int):
         """Launch shapes of one level's residual and sweep kernels."""

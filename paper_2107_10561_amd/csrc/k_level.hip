@@ -128,6 +128,148 @@ hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
   return hipErrorInvalidValue;
 }
 
+// Level residual from the spatial factors of an operator whose blocks are
+// C[i][l] M + delta_il tw[i] A (time-independent coefficients): per block only
+// the two scalars m = M(s, s') and a = A(s, s') are streamed.  Lane q_off of a
+// wavefront takes every 64th block of its RPW rows, forms the B outputs of the
+// block from the B entries of x at the block column, and the per-row sums are
+// folded across the wavefront as in the block kernel.
+struct KronCoef { double C[16]; double tw[4]; };
+
+template <int B, int RPW>
+__global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ mval,
+                                                   const double* __restrict__ aval,
+                                                   const double* __restrict__ r,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ y, int32_t n_rows,
+                                                   double sx, KronCoef K) {
+  constexpr int NV = RPW * B;
+  constexpr int NVP = NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : 32;
+  const int lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
+  if (row0 >= n_rows) return;  // uniform per wavefront
+  int32_t rp[RPW + 1];
+#pragma unroll
+  for (int t = 0; t <= RPW; ++t) rp[t] = rowptr[min(row0 + t, n_rows)];
+  double acc[NVP];
+#pragma unroll
+  for (int v = 0; v < NVP; ++v) acc[v] = 0.0;
+#pragma unroll 2
+  for (int32_t q = rp[0] + lane; q < rp[RPW]; q += 64) {
+    const int64_t c = col[q];
+    const double m = mval[q], a = aval[q];
+    double xl[B];
+#pragma unroll
+    for (int l = 0; l < B; ++l) xl[l] = x[c * B + l];
+    int rr = 0;
+#pragma unroll
+    for (int t = 1; t < RPW; ++t) rr += (q >= rp[t]) ? 1 : 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      double ci = 0.0;
+#pragma unroll
+      for (int l = 0; l < B; ++l) ci = fma(K.C[i * B + l], xl[l], ci);
+      const double v = fma(m, ci, a * K.tw[i] * xl[i]);
+#pragma unroll
+      for (int t = 0; t < RPW; ++t) acc[t * B + i] += (rr == t) ? v : 0.0;
+    }
+  }
+  const double sum = fold<NVP>(acc, lane);
+  constexpr int SPAN = 64 / NVP;
+  const int v = lane / SPAN;
+  if ((lane % SPAN) == 0 && v < NV) {
+    const int t = v / B, i = v - (v / B) * B;
+    const int row = row0 + t;
+    if (row < n_rows) {
+      const int64_t o = (int64_t)row * B + i;
+      y[o] = r ? fma(sx, sum, r[o]) : sx * sum;
+    }
+  }
+}
+
+template <int B>
+static hipError_t spmv_kron_b(hipStream_t s, const DevLevel& L, const double* r, const double* x,
+                              double* y, double sx) {
+  KronCoef K{};
+  for (int e = 0; e < B * B; ++e) K.C[e] = L.kron_C[e];
+  for (int e = 0; e < B; ++e) K.tw[e] = L.kron_tw[e];
+  const int rpw = L.spmv_rpw;
+  dim3 grid((L.n_s + 4 * rpw - 1) / (4 * rpw)), block(256);
+  switch (rpw) {
+    case 1: k_spmv_kron<B, 1><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 2: k_spmv_kron<B, 2><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 3: k_spmv_kron<B, 3><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 4: k_spmv_kron<B, 4><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_kron(hipStream_t s, int b, const DevLevel& L, const double* r,
+                            const double* x, double* y, double sx) {
+  switch (b) {
+    case 1: return spmv_kron_b<1>(s, L, r, x, y, sx);
+    case 2: return spmv_kron_b<2>(s, L, r, x, y, sx);
+    case 3: return spmv_kron_b<3>(s, L, r, x, y, sx);
+    case 4: return spmv_kron_b<4>(s, L, r, x, y, sx);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Largest deviation of the stored blocks from C m + delta tw a, and the
+// largest block entry: one (deviation, magnitude) pair per workgroup.
+template <int B>
+__global__ void __launch_bounds__(256) k_kron_check(const double* __restrict__ val,
+                                                    const double* __restrict__ mval,
+                                                    const double* __restrict__ aval,
+                                                    int64_t nnzb, KronCoef K,
+                                                    double* __restrict__ partial) {
+  __shared__ double sd[4], sm[4];
+  double dev = 0.0, mag = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzb;
+       q += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int l = 0; l < B; ++l) {
+        const double v = val[q * B * B + i * B + l];
+        const double rec = K.C[i * B + l] * mval[q] + (i == l ? K.tw[i] * aval[q] : 0.0);
+        dev = fmax(dev, fabs(v - rec));
+        mag = fmax(mag, fabs(v));
+      }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    dev = fmax(dev, __shfl_xor(dev, off, 64));
+    mag = fmax(mag, __shfl_xor(mag, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { sd[wv] = dev; sm[wv] = mag; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+    partial[2 * blockIdx.x + 1] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+  }
+}
+
+hipError_t launch_kron_check(hipStream_t s, int b, const DevLevel& L, const double* mval,
+                             const double* aval, const double* C, const double* tw,
+                             double* partial, int nblk) {
+  KronCoef K{};
+  for (int e = 0; e < b * b; ++e) K.C[e] = C[e];
+  for (int e = 0; e < b; ++e) K.tw[e] = tw[e];
+  switch (b) {
+    case 1: k_kron_check<1><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
+    case 2: k_kron_check<2><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
+    case 3: k_kron_check<3><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
+    case 4: k_kron_check<4><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // Values of the transposed level matrix: block qt of J^T is the transpose of
 // block src[qt] of J (the pattern of J^T is built on the host).
 template <int B>

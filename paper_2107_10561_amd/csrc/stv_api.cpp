@@ -95,6 +95,7 @@ void free_level(DevLevel& L) {
   dfree(L.inv_off); dfree(L.inv_store); dfree(L.posmap);
   dfree(L.rho); dfree(L.r); dfree(L.d); dfree(L.corr);
   dfree(L.rowptr_t); dfree(L.col_t); dfree(L.val_t);
+  dfree(L.kron_m); dfree(L.kron_a);
   L = DevLevel();
 }
 
@@ -264,18 +265,25 @@ int check_ctx(stv_ctx* ctx, bool need_hier, bool need_inv) {
 }
 
 // ---------------------------------------------------------------- level ops
-int residual(stv_ctx* ctx, int g, const double* r, const double* x, double* y) {
+// y = r + sx J_g x: from the spatial factors when the level has them (and
+// the operator is not transposed), else from the stored blocks.
+int level_apply(stv_ctx* ctx, int g, const double* r, const double* x, double* y, double sx) {
+  const DevLevel& L = ctx->lv[g];
   Timed t(ctx, KC_RESIDUAL, g);
-  STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], r, x, y, -1.0, ctx->transposed != 0));
+  if (L.kron_m && !ctx->transposed)
+    STV_HIP(launch_spmv_kron(ctx->stream, ctx->b, L, r, x, y, sx));
+  else
+    STV_HIP(launch_spmv(ctx->stream, ctx->b, L, r, x, y, sx, ctx->transposed != 0));
   t.done();
   return STV_OK;
 }
 
+int residual(stv_ctx* ctx, int g, const double* r, const double* x, double* y) {
+  return level_apply(ctx, g, r, x, y, -1.0);
+}
+
 int matvec(stv_ctx* ctx, int g, const double* x, double* y) {
-  Timed t(ctx, KC_RESIDUAL, g);
-  STV_HIP(launch_spmv(ctx->stream, ctx->b, ctx->lv[g], nullptr, x, y, 1.0, ctx->transposed != 0));
-  t.done();
-  return STV_OK;
+  return level_apply(ctx, g, nullptr, x, y, 1.0);
 }
 
 int cell_pass(stv_ctx* ctx, int g, const double* rho, double* d, double omega, int zero_init,
@@ -1564,7 +1572,10 @@ int stv_autotune(stv_ctx* ctx, int* choices, int cap) {
     for (int rpw = 1; rpw <= 4 && e == hipSuccess; ++rpw) {
       L.spmv_rpw = rpw;
       double ms = 0;
-      e = time_it([&]() { return launch_spmv(s, b, L, r, x, y, -1.0); }, ms);
+      e = time_it([&]() {
+        return L.kron_m ? launch_spmv_kron(s, b, L, r, x, y, -1.0)
+                        : launch_spmv(s, b, L, r, x, y, -1.0);
+      }, ms);
       if (ms < best) { best = ms; best_r = rpw; }
     }
     L.spmv_rpw = best_r;
@@ -1598,6 +1609,65 @@ int stv_autotune(stv_ctx* ctx, int* choices, int cap) {
       choices[2 * g] = ctx->lv[g].spmv_rpw;
       choices[2 * g + 1] = ctx->lv[g].sweep_wgs;
     }
+  return STV_OK;
+}
+
+int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const double* aval,
+                         const double* C, const double* tw) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (level < 0 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level out of range");
+  DevLevel& L = ctx->lv[level];
+  if (!mval && !aval) {   // drop the factors: back to the stored blocks
+    STV_HIP(hipStreamSynchronize(ctx->stream));
+    dfree(L.kron_m);
+    dfree(L.kron_a);
+    ++ctx->generation;
+    free_graph(ctx);
+    return STV_OK;
+  }
+  if (!mval || !aval || !C || !tw) return fail(ctx, STV_EINVAL, "NULL argument");
+  const int b = ctx->b;
+  for (int e = 0; e < b * b; ++e)
+    if (!std::isfinite(C[e])) return fail(ctx, STV_EINVAL, "C must be finite");
+  for (int e = 0; e < b; ++e)
+    if (!std::isfinite(tw[e])) return fail(ctx, STV_EINVAL, "tw must be finite");
+  STV_HIP(hipStreamSynchronize(ctx->stream));
+  double *dm = nullptr, *da = nullptr, *part = nullptr;
+  const int nblk = 1024;
+  auto drop = [&]() { dfree(dm); dfree(da); dfree(part); };
+  int rc = upload(ctx, &dm, mval, (size_t)L.nnzb);
+  if (rc == STV_OK) rc = upload(ctx, &da, aval, (size_t)L.nnzb);
+  if (rc == STV_OK) rc = dalloc(ctx, &part, (size_t)2 * nblk);
+  if (rc != STV_OK) { drop(); return rc; }
+  // the factors must reproduce the stored blocks
+  std::vector<double> hp((size_t)2 * nblk);
+  hipError_t e = launch_kron_check(ctx->stream, b, L, dm, da, C, tw, part, nblk);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(),
+                                          hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(part);
+  if (e != hipSuccess) {
+    drop();
+    return fail(ctx, STV_EHIP, std::string("factor check failed: ") + hipGetErrorString(e));
+  }
+  double dev = 0.0, mag = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    dev = std::max(dev, hp[(size_t)2 * i]);
+    mag = std::max(mag, hp[(size_t)2 * i + 1]);
+  }
+  if (!(dev <= 1e-12 * mag)) {
+    drop();
+    return fail(ctx, STV_EINVAL, "the factors do not reproduce the level's blocks (max deviation " +
+                                     std::to_string(dev) + " of " + std::to_string(mag) + ")");
+  }
+  dfree(L.kron_m);
+  dfree(L.kron_a);
+  L.kron_m = dm;
+  L.kron_a = da;
+  for (int i = 0; i < 16; ++i) L.kron_C[i] = i < b * b ? C[i] : 0.0;
+  for (int i = 0; i < 4; ++i) L.kron_tw[i] = i < b ? tw[i] : 0.0;
+  ++ctx->generation;
+  free_graph(ctx);
   return STV_OK;
 }
 

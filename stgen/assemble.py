@@ -229,3 +229,39 @@ def assemble_level(mesh: Mesh, k: int, tau: float, nu_cell, conv, chunk: int = 4
         if dropped[0]:
             raise RuntimeError(f"pattern '{pattern}' drops {dropped[0]} nonzero entries")
     return dict(rowptr=rowptr, col=col, val=val, cell_sdofs=csd)
+
+
+def assemble_spatial_factors(mesh: Mesh, nu_cell, conv, rowptr, col, chunk: int = 4096):
+    """Spatial factors of the level matrix in its block pattern: every block
+    (i, l) of the space-time matrix is C[i, l] M + delta_il tau w_i A, with M
+    the velocity mass and A the spatial Oseen operator of the same cells.
+    Returns (mval, aval), one value per block of the pattern (rowptr, col)."""
+    ref = RefData(mesh.dim)
+    const = level_constant_parts(ref, mesh.h)
+    Me = mass_operator(mesh, const)
+    csd = mesh.cell_sdofs()
+    colour = mesh.colours()
+    L = lib()
+    nls = mesh.n_ls
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    nnzb = int(rp[-1])
+    mval = np.zeros(nnzb)
+    aval = np.zeros(nnzb)
+    dropped = np.zeros(1, dtype=np.int64)
+    one, zero = np.ones(1), np.zeros(1)
+    Z = np.zeros((nls, nls))
+    for c0 in range(0, mesh.n_cells, chunk):
+        cells = np.arange(c0, min(mesh.n_cells, c0 + chunk))
+        Ae = np.ascontiguousarray(cell_operators(mesh, ref, const, nu_cell, conv, cells))
+        Zc = np.zeros_like(Ae)
+        # b = 1 scatter: C = 1, tau w = 0 gives M; C = 0, tau w = 1 gives A
+        L.stgen_scatter(nls, 1, csd.ctypes.data, c0, len(cells), colour.ctypes.data, 1 << mesh.dim,
+                        Zc.ctypes.data, Me.ctypes.data, one.ctypes.data, zero.ctypes.data,
+                        rp.ctypes.data, cl.ctypes.data, mval.ctypes.data, dropped.ctypes.data)
+        L.stgen_scatter(nls, 1, csd.ctypes.data, c0, len(cells), colour.ctypes.data, 1 << mesh.dim,
+                        Ae.ctypes.data, Z.ctypes.data, zero.ctypes.data, one.ctypes.data,
+                        rp.ctypes.data, cl.ctypes.data, aval.ctypes.data, dropped.ctypes.data)
+        if dropped[0]:
+            raise RuntimeError("the block pattern drops nonzero factor entries")
+    return mval, aval

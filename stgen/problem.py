@@ -84,6 +84,8 @@ class Level:
     val: np.ndarray           # (nnzb, b, b)
     cell_sdofs: np.ndarray    # (n_cells, n_ls)
     P: tuple | None = None    # (rowptr, col, val) fine x coarse spatial, None on level 0
+    nu_cell: np.ndarray | None = None   # viscosity per cell the level was assembled with
+    conv: object = None                  # convection field of the assembly
 
     @property
     def n_sdofs(self):
@@ -146,8 +148,14 @@ def make_hierarchy(dim, n_fine, n_levels, k, tau, nu, conv, ext=None, nu_cell_fi
         nu_c = nus[g] if nus[g] is not None else np.full(m.n_cells, float(nu))
         A = assemble_level(m, k, tau, nu_c, conv)
         P = prolongation(m, meshes[g - 1]) if g > 0 else None
-        levels.append(Level(m, A["rowptr"], A["col"], A["val"], A["cell_sdofs"], P))
+        levels.append(Level(m, A["rowptr"], A["col"], A["val"], A["cell_sdofs"], P, nu_c, conv))
     return levels
+
+
+def spatial_factors(level: Level):
+    """(mval, aval) of a level: its blocks are C[i, l] M + delta_il tau w_i A."""
+    from .assemble import assemble_spatial_factors
+    return assemble_spatial_factors(level.mesh, level.nu_cell, level.conv, level.rowptr, level.col)
 
 
 CONFIGS = {

@@ -1,0 +1,129 @@
+"""Level residual from spatial factors (blocks = C[i,l] M + delta_il tau w_i A)
+through the C ABI: it must reproduce the block residual and the oracle's
+V-cycle and FGMRES; factors that do not reproduce the stored blocks are
+rejected; transposed solves keep using the blocks."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import log, problem, relerr, to_dev, to_host
+from oracle import adjoint as oadj
+from stgen import fe
+from stgen.problem import make_problem, spatial_factors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_2107_10561_amd as m
+    return m
+
+
+def time_factors(p):
+    _, w, C, _ = fe.time_matrices(p.k)
+    return np.asarray(C, dtype=np.float64), p.tau * np.asarray(w, dtype=np.float64)
+
+
+def kron_solver(stv, p, full=False):
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    C, tw = time_factors(p)
+    for g, L in enumerate(p.levels):
+        m, a = spatial_factors(L)
+        s.set_kron_factors(g, m, a, C, tw)
+    s.build_cell_inverses(full=full)
+    return s
+
+
+@pytest.mark.parametrize("name", ["c1_2d_dg1", "2d_dg2", "3d_dg1"])
+def test_kron_residual_vcycle_gmres(stv, name):
+    p, ol = problem(name)
+    s = kron_solver(stv, p)
+    G = len(ol) - 1
+    rng = np.random.default_rng(12)
+    r, d = rng.standard_normal(ol[G].n_st), rng.standard_normal(ol[G].n_st)
+    for rows in (1, 2, 3, 4):
+        s.set_launch(G, rows, 0)
+        out = to_dev(np.zeros(ol[G].n_st))
+        s.residual(G, to_dev(r), to_dev(d), out)
+        ref = r - ol[G].J @ d
+        assert np.abs(to_host(out) - ref).max() <= 1e-13 * np.abs(ref).max()
+    dd = to_dev(np.zeros(ol[G].n_st))
+    s.vcycle(to_dev(r), dd, 2, 2, 0.7)
+    assert relerr(to_host(dd), oracle.vcycle(ol, r, 2, 2, 0.7)) <= 1e-11
+    cinv = oracle.coarse_inverse(ol[0])
+    xf, _ = oracle.fgmres(lambda v: ol[-1].J @ v, p.rhs,
+                          lambda v: oracle.vcycle(ol, v, 2, 2, 0.7, coarse_inv=cinv),
+                          restart=30, fixed_iters=6)
+    x = to_dev(np.zeros(ol[G].n_st))
+    s.gmres_solve(to_dev(p.rhs), x, restart=30, fixed_iters=6)
+    e = relerr(to_host(x), xf)
+    log(f"[kron] {name} fgmres(6) rel err {e:.2e}")
+    assert e <= 1e-10
+
+
+def test_kron_rejects_inconsistent_factors_and_can_be_dropped(stv):
+    p, ol = problem("c1_2d_dg1")
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    C, tw = time_factors(p)
+    m, a = spatial_factors(p.levels[-1])
+    bad = m.copy()
+    bad[len(bad) // 2] *= 1.001
+    with pytest.raises(stv.StvError, match="reproduce"):
+        s.set_kron_factors(1, bad, a, C, tw)
+    with pytest.raises(stv.StvError, match="reproduce"):
+        s.set_kron_factors(1, m, a, C[::-1].copy(), tw)
+    s.set_kron_factors(1, m, a, C, tw)
+    s.set_kron_factors(1, None, None, None, None)
+    s.build_cell_inverses()
+    rng = np.random.default_rng(13)
+    r, d = rng.standard_normal(ol[1].n_st), rng.standard_normal(ol[1].n_st)
+    out = to_dev(np.zeros(ol[1].n_st))
+    s.residual(1, to_dev(r), to_dev(d), out)
+    ref = r - ol[1].J @ d
+    assert np.abs(to_host(out) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_kron_batch(stv):
+    specs = [(2, (16, 4), 2, 1, 0.01, 1e-3, 71), (2, (32, 8), 3, 1, 0.01, 3e-3, 72)]
+    probs = [make_problem(*sp) for sp in specs]
+    s = stv.Solver(0)
+    s.set_batch([q.levels for q in probs], 2, 1)
+    C, tw = time_factors(probs[0])
+    D = s.n_levels
+    for g in range(D):
+        ms, as_ = [], []
+        for q in probs:
+            l = g - (D - len(q.levels))
+            if l >= 0:
+                m, a = spatial_factors(q.levels[l])
+                ms.append(m)
+                as_.append(a)
+        s.set_kron_factors(g, np.concatenate(ms), np.concatenate(as_), C, tw)
+    s.build_cell_inverses()
+    b = np.concatenate([q.rhs for q in probs])
+    x = to_dev(np.zeros_like(b))
+    s.gmres_solve(to_dev(b), x, restart=30, fixed_iters=5)
+    xh = to_host(x)
+    for i, q in enumerate(probs):
+        ol = oracle.build_inverses(oracle.prepare_levels(q.levels, q.b))
+        cinv = oracle.coarse_inverse(ol[0])
+        xf, _ = oracle.fgmres(lambda v: ol[-1].J @ v, q.rhs,
+                              lambda v: oracle.vcycle(ol, v, 2, 2, 0.7, coarse_inv=cinv),
+                              restart=30, fixed_iters=5)
+        _, o, n = s.instance_layout(i)
+        assert relerr(xh[o:o + n], xf) <= 1e-10
+
+
+def test_transposed_solve_ignores_factors(stv):
+    p, ol = problem("2d_dg2")
+    s = kron_solver(stv, p, full=True)
+    olt = oadj.transpose_levels(ol)
+    r = np.random.default_rng(14).standard_normal(ol[-1].n_st)
+    d = to_dev(np.zeros_like(r))
+    s.vcycle_transposed(to_dev(r), d, 2, 2, 0.7)
+    assert relerr(to_host(d), oracle.vcycle(olt, r, 2, 2, 0.7)) <= 1e-11
