@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--nu2", type=int, default=2)
     ap.add_argument("--omega", type=float, default=0.7)
     ap.add_argument("--coarse-algo", default="auto", choices=["auto", "panels", "slabs"])
+    ap.add_argument("--coarse-overlap", type=int, default=1, choices=[0, 1],
+                    help="coarse factorisation concurrent with the cell inverses (1) or before (0)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-kron", action="store_true",
                     help="residual from the stored blocks instead of the spatial factors")
@@ -231,6 +233,7 @@ def main():
     print(f"[bench] generated {desc} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     s = stv.Solver(0)
     s.set_coarse_algorithm(args.coarse_algo)
+    s.set_coarse_overlap(bool(args.coarse_overlap))
     t0 = time.time()
     if len(probs) == 1:
         s.set_hierarchy(probs[0].levels, dim, k)

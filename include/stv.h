@@ -280,8 +280,9 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
  *   STV_OPT_COARSE_ALGO: how the coarsest matrix is inverted by Gauss-Jordan
  *   elimination with partial pivoting: 0 = chosen by size (default),
  *   1 = one level of narrow panels, each updating the whole matrix,
- *   2 = slabs of 64 columns eliminated by narrow panels, then one rank-64
- *   update of the rest on the matrix cores.  Both give the same pivots.
+ *   2 = slabs of 64 (128 above order 5120) columns eliminated by narrow
+ *   panels, then one rank-64 (128) update of the rest on the matrix cores.
+ *   Both give the same pivots.
  * Errors: STV_EINVAL (unknown option or value). */
 #define STV_OPT_COARSE_ALGO 1
 /*   STV_OPT_GRAPH: 1 = the V-cycle (stv_vcycle and the preconditioner of
@@ -292,6 +293,10 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
  *   (class 7) instead of the kernels inside it.  0 = eager launches
  *   (default).  Results are identical in both modes. */
 #define STV_OPT_GRAPH 2
+/*   STV_OPT_COARSE_OVERLAP: 1 (default) = the coarse factorisations run on
+ *   an internal stream concurrently with the cell inverses; 0 = they run on
+ *   the caller's stream before the cell inverses.  Same results. */
+#define STV_OPT_COARSE_OVERLAP 3
 int stv_set_option(stv_ctx* ctx, int option, int64_t value);
 
 /* Spatial factors of a level whose operator has time-independent

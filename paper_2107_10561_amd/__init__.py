@@ -397,6 +397,10 @@ class Solver:
         self._check(_lib.stv_autotune(self._h, ch, cap))
         return {g: (ch[2 * g], ch[2 * g + 1]) for g in range(self.n_levels)}
 
+    def set_coarse_overlap(self, on: bool):
+        """Coarse factorisation concurrent with the cell inverses (default) or before them."""
+        self._check(_lib.stv_set_option(self._h, 3, int(bool(on))))
+
     def set_graph(self, on: bool):
         """Replay the V-cycle from a captured HIP graph (identical results)."""
         self._check(_lib.stv_set_option(self._h, 2, int(bool(on))))

@@ -139,21 +139,44 @@ __global__ void __launch_bounds__(TPB) k_gj_panel(double* __restrict__ pbuf, int
     if (tid == 0) rloc[t] = ok ? cand : -1;
     if (cand >= n) continue;  // uniform: no candidate row at all (singular, flagged)
     const int r = cand;
-    double pr[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) pr[c] = wrow[par][win][c];
-    const double pv = pr[t];
+    const double pv = wrow[par][win][t];
     const double ipiv = (pv != 0.0) ? 1.0 / pv : 0.0;
     const int dr = r - tid;
+    // pivot row: (src 0, factor -1/piv); other rows: (own value, factor a_it/piv)
+    if constexpr (NB >= 16 && RPT <= NB) {
+      // few rows, wide panel: the row factors stay in registers and the
+      // pivot-row entries are read from LDS one column at a time (broadcast)
+      double f[RPT];
+      unsigned isr = 0;
 #pragma unroll
-    for (int m = 0; m < RPT; ++m) {
-      const bool isr = (dr == TPB * m);
-      if (isr) umask |= 1u << m;
-      // pivot row: (src 0, factor -1/piv); other rows: (own value, factor a_it/piv)
-      const double f = isr ? -ipiv : P[m][t] * ipiv;
+      for (int m = 0; m < RPT; ++m) {
+        const bool is = (dr == TPB * m);
+        if (is) { umask |= 1u << m; isr |= 1u << m; }
+        f[m] = is ? -ipiv : P[m][t] * ipiv;
+      }
 #pragma unroll
-      for (int c = 0; c < NB; ++c)
-        P[m][c] = (c == t) ? (isr ? ipiv : -f) : fma(-f, pr[c], isr ? 0.0 : P[m][c]);
+      for (int c = 0; c < NB; ++c) {
+        const double prc = wrow[par][win][c];
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+          const bool is = (isr >> m) & 1u;
+          P[m][c] = (c == t) ? (is ? ipiv : -f[m]) : fma(-f[m], prc, is ? 0.0 : P[m][c]);
+        }
+      }
+    } else {
+      // the pivot row stays in registers
+      double pr[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) pr[c] = wrow[par][win][c];
+#pragma unroll
+      for (int m = 0; m < RPT; ++m) {
+        const bool is = (dr == TPB * m);
+        if (is) umask |= 1u << m;
+        const double f = is ? -ipiv : P[m][t] * ipiv;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          P[m][c] = (c == t) ? (is ? ipiv : -f) : fma(-f, pr[c], is ? 0.0 : P[m][c]);
+      }
     }
   }
   __syncthreads();
@@ -476,7 +499,7 @@ static const GjCfg kCfg2[3] = {{8, 512, 5, 64}, {8, 512, 10, 64}, {4, 768, 15, 1
 
 GjPlan gj_plan(int64_t n, int algo) {
   GjPlan p{};
-  p.algo = algo == 0 ? ((n > 1024) ? 2 : 1) : algo;
+  p.algo = algo == 0 ? ((n > 256) ? 2 : 1) : algo;
   const GjCfg* cfg = p.algo == 1 ? kCfg1 : kCfg2;
   p.cfg = 2;
   for (int c = 0; c < 3; ++c) {

@@ -877,7 +877,9 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   ctx->inv_full = full;
   const int b = ctx->b;
   hipStream_t s = ctx->stream;
-  hipStream_t side = ctx->side;
+  // the coarse factorisations run on the internal stream, overlapping the
+  // cell inverses, or on the caller's stream ahead of them
+  hipStream_t side = ctx->coarse_overlap ? ctx->side : ctx->stream;
   // ---- cell inverse storage (host-side offsets of every cell's stored rows)
   std::vector<uint8_t*> status((size_t)ctx->n_levels, nullptr);
   std::vector<double*> scratch((size_t)ctx->n_levels, nullptr);
@@ -994,15 +996,21 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   }
   // ---- launch: cell inverses on the caller's stream, coarse factorisations
   // on the internal stream (it starts after everything queued before it)
-  hipError_t e = hipEventRecord(ctx->ev_fork, s);
-  if (e == hipSuccess) e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
-  for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
-    if (ctx->lv[g].n_cells == 0) continue;
-    Timed t(ctx, KC_INVERSE, g);
-    e = launch_cell_inverses(s, b, ctx->lv[g], fp32, full, status[(size_t)g], scratch[(size_t)g],
-                             slots[(size_t)g]);
-    t.done();
+  hipError_t e = hipSuccess;
+  if (side != s) {
+    e = hipEventRecord(ctx->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
   }
+  auto cell_inverses = [&]() {
+    for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
+      if (ctx->lv[g].n_cells == 0) continue;
+      Timed t(ctx, KC_INVERSE, g);
+      e = launch_cell_inverses(s, b, ctx->lv[g], fp32, full, status[(size_t)g], scratch[(size_t)g],
+                               slots[(size_t)g]);
+      t.done();
+    }
+  };
+  if (side != s) cell_inverses();
   for (auto& G : groups) {
     if (e != hipSuccess) break;
     Timed t(ctx, KC_COARSE_FACTOR, 0, side);
@@ -1050,8 +1058,12 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
                               G.n0, ctx->coarse_inv);
     t.done();
   }
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, side);
-  if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
+  if (side == s) {
+    cell_inverses();
+  } else {
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
+  }
   std::vector<std::vector<uint8_t>> hs((size_t)ctx->n_levels);
   for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
     if (ctx->lv[g].n_cells == 0) continue;
@@ -1677,6 +1689,10 @@ int stv_set_option(stv_ctx* ctx, int option, int64_t value) {
     case STV_OPT_COARSE_ALGO:
       if (value < 0 || value > 2) return fail(ctx, STV_EINVAL, "coarse algorithm must be 0, 1 or 2");
       ctx->coarse_algo = (int)value;
+      return STV_OK;
+    case STV_OPT_COARSE_OVERLAP:
+      if (value < 0 || value > 1) return fail(ctx, STV_EINVAL, "overlap option must be 0 or 1");
+      ctx->coarse_overlap = (int)value;
       return STV_OK;
     case STV_OPT_GRAPH:
       if (value < 0 || value > 1) return fail(ctx, STV_EINVAL, "graph option must be 0 or 1");

@@ -125,6 +125,7 @@ struct stv_ctx {
   double* coarse_inv = nullptr;       // every member's inverse
   int64_t coarse_elems = 0;
   int coarse_algo = 0;          // STV_OPT_COARSE_ALGO
+  int coarse_overlap = 1;       // STV_OPT_COARSE_OVERLAP
   int64_t scal_segs = 0;        // instances the scalar buffers are sized for
   // V-cycle replayed from a captured HIP graph (STV_OPT_GRAPH): the graph
   // reads g_in and writes g_out; it is captured on cap_stream and replayed

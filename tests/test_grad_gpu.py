@@ -115,7 +115,7 @@ def _grad_gpu(stv, p, fp32, rtol, U=1.0):
     q = torch.from_numpy(p.loss).to(x.device)
     L = (q * x).sum()
     L.backward()
-    return float(L), nu.grad.numpy().copy(), float(Ut.grad), opts
+    return float(L.detach()), nu.grad.numpy().copy(), float(Ut.grad), opts
 
 
 def golden_gradient():

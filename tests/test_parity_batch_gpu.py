@@ -137,7 +137,7 @@ def test_batch_gmres_tolerance_mode(stv, name):
             f"true {true:.2e}")
         assert ii["converged"] and true <= 1e-8
         assert abs(ii["iters"] - io["iters"]) <= 1
-        assert abs(ii["true_relres"] - true) <= 1e-3 * true + 1e-15
+        assert abs(ii["true_relres"] - true) <= 1e-3 * true + 1e-14   # recomputing a residual near 1e-13 carries ~1e-15 of rounding
 
 
 def test_batch_equals_single_instances(stv):

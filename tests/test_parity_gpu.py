@@ -199,7 +199,7 @@ def test_gmres_tolerance_mode(stv, name):
     log(f"[gmres] {name} gpu iters {info['iters']} oracle {io['iters']} true relres {true:.2e}")
     assert info["converged"] and true <= 1e-8
     assert abs(info["iters"] - io["iters"]) <= 1
-    assert abs(info["true_relres"] - true) <= 1e-3 * true + 1e-15
+    assert abs(info["true_relres"] - true) <= 1e-3 * true + 1e-14   # recomputing a residual near 1e-13 carries ~1e-15 of rounding
 
 
 @pytest.mark.parametrize("name", ["c1_2d_dg1", "2d_dg2", "3d_dg1"])
