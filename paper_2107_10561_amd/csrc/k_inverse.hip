@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(((B * NLS + 15) / 16) * 64)
 __attribute__((amdgpu_waves_per_eu((((B * NLS + 15) / 16) + 3) / 4, 8))) k_inverse_mfma(
     const int32_t* __restrict__ posmap, const double* __restrict__ val,
     const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
-    const int64_t* __restrict__ inv_off, void* store, int fp32, uint8_t* status) {
+    const int64_t* __restrict__ inv_off, int ld, void* store, int fp32, uint8_t* status) {
   constexpr int N = B * NLS;
   constexpr int NT = (N + 15) / 16;
   constexpr int NP = 16 * NT;
@@ -251,7 +251,7 @@ __attribute__((amdgpu_waves_per_eu((((B * NLS + 15) / 16) + 3) / 4, 8))) k_inver
       if (p < N && j < N) {
         const int o = rowmap[p];
         if (o >= 0) {
-          const int64_t e = off + (int64_t)o * N + j;
+          const int64_t e = off + (int64_t)o * ld + j;
           if (fp32) ((float*)store)[e] = (float)acc[tj][v];
           else ((double*)store)[e] = acc[tj][v];
         }
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) k_inverse_global(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const int32_t* __restrict__ csd, int B, int NLS, int n_cells,
     const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
-    const int64_t* __restrict__ inv_off, void* store, int fp32, uint8_t* status,
+    const int64_t* __restrict__ inv_off, int ld, void* store, int fp32, uint8_t* status,
     double* gscratch) {
   extern __shared__ double sm[];
   __shared__ int sing;
@@ -349,8 +349,8 @@ __global__ void __launch_bounds__(256) k_inverse_global(
       const int o = rowmap[i];
       if (o < 0) continue;
       const double v = A[(int64_t)i * n + sigma[j]];
-      if (fp32) ((float*)store)[off + (int64_t)o * n + j] = (float)v;
-      else ((double*)store)[off + (int64_t)o * n + j] = v;
+      if (fp32) ((float*)store)[off + (int64_t)o * ld + j] = (float)v;
+      else ((double*)store)[off + (int64_t)o * ld + j] = v;
     }
     __syncthreads();
   }
@@ -365,7 +365,8 @@ template <int B, int NLS>
 static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full, uint8_t* status) {
   constexpr int NT = (B * NLS + 15) / 16;
   k_inverse_mfma<B, NLS><<<L.n_cells, NT * 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc,
-                                                       full, L.inv_off, L.inv_store, fp32, status);
+                                                       full, L.inv_off, L.inv_ld, L.inv_store, fp32,
+                                                       status);
   return hipGetLastError();
 }
 
@@ -390,7 +391,7 @@ hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp3
   const size_t shm = sizeof(double) * 3 * (size_t)n + sizeof(int) * 3 * (size_t)n;
   k_inverse_global<<<n_slots, 256, shm, s>>>(L.rowptr, L.col, L.val, L.cell_sdofs, b, L.n_ls,
                                              L.n_cells, L.own_ptr, L.own_loc, full, L.inv_off,
-                                             L.inv_store, fp32, status, gscratch);
+                                             L.inv_ld, L.inv_store, fp32, status, gscratch);
   return hipGetLastError();
 }
 

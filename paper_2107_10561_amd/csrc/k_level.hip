@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
                                               const int32_t* __restrict__ csd,
                                               const int32_t* __restrict__ own_ptr,
                                               const uint8_t* __restrict__ own_loc,
-                                              const int64_t* __restrict__ inv_off,
+                                              const int64_t* __restrict__ inv_off, int ld,
                                               const TS* __restrict__ store, double omega,
                                               int zero_init, int full, int n_cells) {
   constexpr int N = B * NLS;
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
           const int os = row / B;
           srow = own_loc[o0 + os] * B + (row - os * B);
         }
-        p[t] = row_dot<N, NC, TS>(A + (int64_t)srow * N, x, lane);
+        p[t] = row_dot<N, NC, TS>(A + (int64_t)srow * ld, x, lane);
       }
     }
     const double sum = fold<8>(p, lane);
@@ -386,12 +386,12 @@ static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, 
   if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
   if (fp32)
     k_vanka<B, NLS, float><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
-                                                L.inv_off, (const float*)L.inv_store, omega,
-                                                zero_init, full, L.n_cells);
+                                                L.inv_off, L.inv_ld, (const float*)L.inv_store,
+                                                omega, zero_init, full, L.n_cells);
   else
     k_vanka<B, NLS, double><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
-                                                 L.inv_off, (const double*)L.inv_store, omega,
-                                                 zero_init, full, L.n_cells);
+                                                 L.inv_off, L.inv_ld, (const double*)L.inv_store,
+                                                 omega, zero_init, full, L.n_cells);
   return hipGetLastError();
 }
 
@@ -427,7 +427,7 @@ __global__ void __launch_bounds__(256) k_vanka_t(const double* __restrict__ rho,
                                                 const int32_t* __restrict__ csd,
                                                 const int32_t* __restrict__ own_ptr,
                                                 const uint8_t* __restrict__ own_loc,
-                                                const int64_t* __restrict__ inv_off,
+                                                const int64_t* __restrict__ inv_off, int ld,
                                                 const TS* __restrict__ store, double omega,
                                                 int zero_init, int n_cells) {
   constexpr int N = B * NLS;
@@ -454,7 +454,7 @@ __global__ void __launch_bounds__(256) k_vanka_t(const double* __restrict__ rho,
       const int jn = (N - 64 * cj) < 64 ? (N - 64 * cj) : 64;
       for (int jl = 0; jl < jn; ++jl) {
         const double rj = __shfl(x[cj], jl, 64);
-        const TS* Ar = A + (int64_t)(64 * cj + jl) * N;
+        const TS* Ar = A + (int64_t)(64 * cj + jl) * ld;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const int o = lane + 64 * c;
@@ -485,12 +485,13 @@ static hipError_t vanka_t_bn(hipStream_t s, const DevLevel& L, const double* rho
   if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
   if (fp32)
     k_vanka_t<B, NLS, float><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
-                                                  L.inv_off, (const float*)L.inv_store, omega,
-                                                  zero_init, L.n_cells);
+                                                  L.inv_off, L.inv_ld, (const float*)L.inv_store,
+                                                  omega, zero_init, L.n_cells);
   else
     k_vanka_t<B, NLS, double><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
-                                                   L.inv_off, (const double*)L.inv_store, omega,
-                                                   zero_init, L.n_cells);
+                                                   L.inv_off, L.inv_ld,
+                                                   (const double*)L.inv_store, omega, zero_init,
+                                                   L.n_cells);
   return hipGetLastError();
 }
 
@@ -645,7 +646,7 @@ template <int B, typename TS>
 __global__ void __launch_bounds__(64) k_vanka_corr(const double* __restrict__ rho,
                                                   double* __restrict__ corr,
                                                   const int32_t* __restrict__ csd, int n_ls,
-                                                  const int64_t* __restrict__ inv_off,
+                                                  const int64_t* __restrict__ inv_off, int ld,
                                                   const TS* __restrict__ store, double omega) {
   extern __shared__ double sm[];
   const int n_loc = n_ls * B;
@@ -660,7 +661,7 @@ __global__ void __launch_bounds__(64) k_vanka_corr(const double* __restrict__ rh
   const TS* A = store + inv_off[T];
   for (int i = lane; i < n_loc; i += 64) {
     double acc = 0.0;
-    for (int j = 0; j < n_loc; ++j) acc = fma((double)A[(int64_t)i * n_loc + j], sm[j], acc);
+    for (int j = 0; j < n_loc; ++j) acc = fma((double)A[(int64_t)i * ld + j], sm[j], acc);
     corr[(int64_t)T * n_loc + i] = omega * acc;
   }
 }
@@ -687,11 +688,11 @@ hipError_t launch_vanka_cells_corr(hipStream_t s, int b, const DevLevel& L, cons
 #define STV_CORR(BB)                                                                        \
   if (fp32)                                                                                 \
     k_vanka_corr<BB, float><<<L.n_cells, 64, shm, s>>>(rho, L.corr, L.cell_sdofs, L.n_ls,   \
-                                                       L.inv_off, (const float*)L.inv_store, \
-                                                       omega);                              \
+                                                       L.inv_off, L.inv_ld,                 \
+                                                       (const float*)L.inv_store, omega);   \
   else                                                                                      \
     k_vanka_corr<BB, double><<<L.n_cells, 64, shm, s>>>(rho, L.corr, L.cell_sdofs, L.n_ls,  \
-                                                        L.inv_off,                          \
+                                                        L.inv_off, L.inv_ld,                \
                                                         (const double*)L.inv_store, omega);
   switch (b) {
     case 1: STV_CORR(1) break;

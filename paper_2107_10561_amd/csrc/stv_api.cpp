@@ -923,12 +923,15 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     DevLevel& L = ctx->lv[g];
     if (L.n_cells == 0) continue;
     const int n = L.n_ls * b;
+    // rows stored densely (padding each row to a 128-byte boundary was
+    // measured slower: the sweep reads whole cells as one contiguous stream)
+    L.inv_ld = n;
     std::vector<int64_t> off((size_t)L.n_cells);
     int64_t tot = 0;
     for (int32_t c = 0; c < L.n_cells; ++c) {
       off[(size_t)c] = tot;
       const int rows = full ? n : (L.h_own_ptr[(size_t)c + 1] - L.h_own_ptr[(size_t)c]) * b;
-      tot += (int64_t)rows * n;
+      tot += (int64_t)rows * L.inv_ld;
     }
     if ((rc = upload(ctx, &L.inv_off, off.data(), off.size())) != STV_OK) break;
     if (fp32) {
@@ -1472,11 +1475,12 @@ int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out) {
   const int b = ctx->b, nls = L.n_ls, n = nls * b;
   const int o0 = L.h_own_ptr[(size_t)cell], no = L.h_own_ptr[(size_t)cell + 1] - o0;
   const int R = ctx->inv_full ? n : no * b;
+  const int ld = L.inv_ld;
   std::vector<int64_t> off(1);
   STV_HIP(hipMemcpy(off.data(), L.inv_off + cell, sizeof(int64_t), hipMemcpyDeviceToHost));
-  std::vector<double> blk((size_t)R * n);
+  std::vector<double> blk((size_t)R * ld);
   if (ctx->inv_fp32) {
-    std::vector<float> f((size_t)R * n);
+    std::vector<float> f((size_t)R * ld);
     STV_HIP(hipMemcpy(f.data(), (const float*)L.inv_store + off[0], sizeof(float) * f.size(), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < f.size(); ++i) blk[i] = f[i];
   } else {
@@ -1491,7 +1495,7 @@ int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out) {
     const int row = l * nls + alpha;   // eq. (4.4) order
     for (int j = 0; j < n; ++j) {
       const int beta = j / b, lj = j % b;
-      out[(int64_t)row * n + lj * nls + beta] = blk[(size_t)o * n + j];   // stored row-major
+      out[(int64_t)row * n + lj * nls + beta] = blk[(size_t)o * ld + j];   // stored row-major
     }
   }
   return STV_OK;

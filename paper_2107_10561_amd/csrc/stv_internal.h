@@ -48,6 +48,7 @@ struct DevLevel {
   // stored inverses (levels >= 1)
   int64_t* inv_off = nullptr;     // [n_cells] element offset of each cell's block
   void* inv_store = nullptr;
+  int inv_ld = 0;                 // row stride of the stored rows (n_loc)
   int64_t inv_elems = 0;
   // work vectors (n_s*b each)
   double* rho = nullptr;
