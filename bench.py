@@ -27,9 +27,11 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_2d512x128_dG2.json")
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch from the counter record in profiles/, or None when
-    there is none for this workload or the kernel source changed since."""
+def measured_traffic(workload: str, kernel: str, launches_per_level):
+    """HBM bytes per launch from the counter record in profiles/ (bytes per
+    launch on each level), averaged over the given launches per level, or
+    None when there is no record for this workload and kernel, a level is
+    missing, or the kernel source changed since the counters were taken."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_RECORD))
@@ -44,7 +46,16 @@ def measured_traffic(workload: str, kernel: str):
         return None
     if sha != rec.get("kernel_source_sha256"):
         return None
-    return int(rec[kernel]["traffic_bytes_per_launch"])
+    per = rec[kernel]["bytes_per_launch_by_level"]
+    tot = n = 0
+    for g, cnt in launches_per_level.items():
+        if cnt == 0:
+            continue
+        if str(g) not in per:
+            return None
+        tot += cnt * per[str(g)]
+        n += cnt
+    return int(tot / n) if n else None
 
 
 def parse():
@@ -327,17 +338,19 @@ def main():
         population rocprofv3's per-kernel average covers) plus the finest level."""
         tb = tms = 0.0
         tn = 0
+        per_level = {}
         for g in range(1, G):
             n_g, ms_g = s.kernel_stats(cls, g)
             tb += n_g * bytes_of(g)
             tms += ms_g
             tn += n_g
+            per_level[g] = n_g
         n_f, ms_f = s.kernel_stats(cls, top)
         gbs = tb / (tms / 1e3) / 1e9 if tms > 0 else 0.0
         gbs_f = bytes_of(top) / (ms_f / n_f / 1e3) / 1e9 if n_f else 0.0
         return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(gbs / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(args.workload, traffic_key), kernel=kernel,
+                    traffic=measured_traffic(args.workload, traffic_key, per_level), kernel=kernel,
                     bytes_per_launch=int(tb / max(tn, 1)), avg_launch_ms=round(tms / max(tn, 1), 5),
                     launches=tn, finest_gbs=round(gbs_f, 1),
                     finest_frac=round(gbs_f / HBM_PEAK_GBS, 4),
