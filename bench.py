@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--nu1", type=int, default=2)
     ap.add_argument("--nu2", type=int, default=2)
     ap.add_argument("--omega", type=float, default=0.7)
-    ap.add_argument("--coarse-algo", default="auto", choices=["auto", "panels", "slabs"])
+    ap.add_argument("--coarse-algo", default="auto", choices=["auto", "panels", "slabs", "tournament"])
     ap.add_argument("--coarse-overlap", type=int, default=1, choices=[0, 1],
                     help="coarse factorisation concurrent with the cell inverses (1) or before (0)")
     ap.add_argument("--no-autotune", action="store_true")

@@ -278,11 +278,16 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
 
 /* Options (take effect at the next stv_build_cell_inverses):
  *   STV_OPT_COARSE_ALGO: how the coarsest matrix is inverted by Gauss-Jordan
- *   elimination with partial pivoting: 0 = chosen by size (default),
+ *   elimination with partial pivoting: 0 = chosen by size (default: 1 up
+ *   to order 256, 3 above),
  *   1 = one level of narrow panels, each updating the whole matrix,
  *   2 = slabs of 64 (128 above order 5120) columns eliminated by narrow
- *   panels, then one rank-64 (128) update of the rest on the matrix cores.
- *   Both give the same pivots.
+ *   panels, then one rank-64 (128) update of the rest on the matrix cores
+ *   (1 and 2 give the same pivots),
+ *   3 = the slabs of 2 with panels of 16 columns whose pivot rows are chosen
+ *   by a tournament: 64-row chunks propose rows by partial pivoting on their
+ *   own rows and the proposals are merged by partial pivoting up a tree
+ *   (the pivots can differ from 1 and 2; the inverse agrees to rounding).
  * Errors: STV_EINVAL (unknown option or value). */
 #define STV_OPT_COARSE_ALGO 1
 /*   STV_OPT_GRAPH: 1 = the V-cycle (stv_vcycle and the preconditioner of

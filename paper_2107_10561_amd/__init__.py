@@ -116,7 +116,7 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot",
             "stv_set_kron_factors")
 
-COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2}
+COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2, "tournament": 3}
 
 
 def library():
@@ -369,7 +369,8 @@ class Solver:
         return dict(n_sdofs=a.value, n_cells=b.value, n_loc=c.value, inverse_bytes=d.value)
 
     def set_coarse_algorithm(self, name: str):
-        """Dense inversion of the coarsest matrix: "auto", "panels" or "slabs"."""
+        """Dense inversion of the coarsest matrix: "auto", "panels", "slabs" or
+        "tournament"."""
         self._check(_lib.stv_set_option(self._h, 1, COARSE_ALGOS[name]))
 
     def set_kron_factors(self, level: int, mval, aval, C, tw):

@@ -491,6 +491,352 @@ static hipError_t gj_slab(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Slabs eliminated by panels whose pivot rows are chosen by a tournament
+// (tall-skinny pivoting in the manner of communication-avoiding LU): every
+// 64-row chunk proposes NB of its rows by partial pivoting on its own rows,
+// groups of proposals are merged, again by partial pivoting on the proposed
+// rows' panel values, up a tree, and the rows left at the root are the
+// panel's pivots R, in the root's pivot order.  The root's LU factors give
+// Z = Pb^-1 B'' for the pivot block Pb = S(R, panel) and B'' = S(R, :) with its
+// panel columns replaced by the identity; the panel's elimination is then one
+// block Gauss-Jordan step,
+//   S(R[s], c) <- Z(s, c),
+//   S(i, c)    <- [c outside the panel] S(i, c) - S(i, panel) Z(:, c)  (i not in R),
+// which equals NB single steps with pivots (R[t], panel column t).  Every
+// pivot decision runs inside one wavefront (DPP reductions, no workgroup
+// barrier), and one launch per panel applies the previous panel's step,
+// proposes the next panel's rows and, in the workgroup that arrives last,
+// merges the proposals and computes the next Z.
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Maximum over the 64 lanes of a wavefront (all lanes active), in every lane.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]: lane ^ 1
+  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]: lane ^ 2
+  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror: the other quad of 8
+  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror: the other half of 16
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+// Partial pivoting over rows held by the lanes of one wavefront (all 64
+// lanes active): lane l holds a row when `avail`, with panel values
+// w[0..NB).  Step t takes the available lane of largest |w[t]| (lowest lane
+// on ties) or, when no available lane has a positive |w[t]|, the lowest
+// available lane (bit t of `zero` set), and eliminates column t from the
+// other available lanes.  Lane t (< NB) returns in `mine` the lane taken at
+// step t (-1: none left).  The lane taken at step s returns step = s; with
+// LU it holds its multipliers in lmul[0..s) and its eliminated row in
+// w[s..NB) (the rows taken, in step order, are L U).
+template <int NB, bool LU>
+__device__ __forceinline__ void wave_select(double (&w)[NB], bool avail, int& mine,
+                                            unsigned& zero, double (&lmul)[NB], int& step) {
+  const int lane = threadIdx.x & 63;
+  mine = -1;
+  zero = 0;
+  step = -1;
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const double v = avail ? fabs(w[t]) : -1.0;
+    const double m = wave_max_f64(v);
+    const bool nz = m > 0.0;
+    int p;
+    if (nz) {
+      p = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(v == m));
+    } else {
+      zero |= 1u << t;
+      const uint64_t am = __builtin_amdgcn_ballot_w64(avail);
+      p = am ? (int)__builtin_ctzll(am) : -1;
+    }
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (lane == t) mine = p;
+    if (p < 0) continue;
+    if (lane == p) {
+      avail = false;
+      step = t;
+    }
+    if (nz) {
+      double pr[NB];
+#pragma unroll
+      for (int c = t; c < NB; ++c) pr[c] = readlane_f64(w[c], p);
+      const double f = w[t] * (1.0 / pr[t]);
+      if (LU) lmul[t] = f;
+      if (avail) {
+#pragma unroll
+        for (int c = t + 1; c < NB; ++c) w[c] = fma(-f, pr[c], w[c]);
+      }
+    }
+  }
+}
+
+// One launch of the tournament schedule on slab S (n x NO, row-major) of
+// every matrix z = blockIdx.z; 256 rows per workgroup, 16 wavefronts.
+// UPDATE: apply the step of panel q0 (pivots rpiv[j0+q0..], factor Zc),
+// then choose the pivots of panel q0+NB (if inside the slab); otherwise only
+// choose the pivots of panel q0.  The choice writes rpiv, used and Zn.
+template <int NB, int NO, bool UPDATE>
+__global__ void __launch_bounds__(1024) k_gj_tour(double* __restrict__ S, int64_t sS, int64_t n,
+                                                  int64_t j0, int q0, int* __restrict__ rpiv,
+                                                  uint8_t* __restrict__ used, int64_t sV,
+                                                  const double* __restrict__ Zc,
+                                                  double* __restrict__ Zn, int64_t sZ,
+                                                  int* __restrict__ cand, int64_t sC,
+                                                  unsigned* __restrict__ counter) {
+  constexpr int RW = 256, NW = 16, FAN = 64 / NB, MAXL = 64, NH = NO / 64, RB = NH == 1 ? 16 : 4;
+  static_assert(NB == 8 || NB == 16, "panel width");
+  static_assert(64 * NO <= RW * (2 * NB + 1), "candidate rows fit the panel buffers");
+  // the panel buffers (current panel of the workgroup's rows, next panel)
+  // hold the root's candidate rows once the merge has started
+  __shared__ double smem[RW * (2 * NB + 1)];
+  double(*Acur)[NB] = reinterpret_cast<double(*)[NB]>(smem);
+  double(*Anx)[NB + 1] = reinterpret_cast<double(*)[NB + 1]>(smem + RW * NB);
+  double* Brow = smem;
+  __shared__ int clist[4][NB];
+  __shared__ int tl[2][MAXL * NB];
+  __shared__ int rootg[64];
+  __shared__ double LUs[NB][NB + 1];
+  __shared__ int Ll[NB];
+  __shared__ unsigned s_last;
+  const int z = blockIdx.z;
+  S += z * sS;
+  rpiv += z * sV;
+  used += z * sV;
+  Zn += z * sZ;
+  cand += z * sC;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t r0 = (int64_t)blockIdx.x * RW;
+  const int qn = UPDATE ? q0 + NB : q0;     // panel whose pivots this launch chooses
+  double dummy[NB];
+  unsigned zf;
+  int step, mine;
+  if constexpr (UPDATE) {
+    Zc += z * sZ;
+    // this wavefront's rows wv + NW u; the loads of a batch are issued together
+    double old[RB][NH];
+    auto load_batch = [&](int u0) {
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int64_t i = r0 + wv + NW * (u0 + u);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const int c = lane + 64 * h;
+          old[u][h] = (i < n && !(c >= q0 && c < q0 + NB)) ? S[i * NO + c] : 0.0;
+        }
+      }
+    };
+    load_batch(0);
+    for (int e = tid; e < RW * NB; e += 1024) {
+      const int di = e / NB, t = e - di * NB;
+      const int64_t i = r0 + di;
+      Acur[di][t] = i < n ? S[i * NO + q0 + t] : 0.0;
+    }
+    double zc[NH][NB];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int t = 0; t < NB; ++t) zc[h][t] = Zc[t * NO + lane + 64 * h];
+    int rp[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) rp[t] = rpiv[j0 + q0 + t];
+    __syncthreads();
+#pragma unroll
+    for (int u0 = 0; u0 < 16; u0 += RB) {
+      if (u0) load_batch(u0);
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int di = wv + NW * (u0 + u);
+        const int64_t i = r0 + di;
+        if (i >= n) break;
+        int s = -1;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) s = (rp[t] == i) ? t : s;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const int c = lane + 64 * h;
+          double val;
+          if (s >= 0) {
+            val = Zc[(int64_t)s * NO + c];
+          } else {
+            double acc = old[u][h];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) acc = fma(-Acur[di][t], zc[h][t], acc);
+            val = acc;
+          }
+          S[i * NO + c] = val;
+          if (c >= qn && c < qn + NB) Anx[di][c - qn] = val;
+        }
+      }
+    }
+    if (qn >= NO) return;                   // last panel of the slab
+  } else {
+    for (int e = tid; e < RW * NB; e += 1024) {
+      const int di = e / NB, t = e - di * NB;
+      const int64_t i = r0 + di;
+      Anx[di][t] = i < n ? S[i * NO + qn + t] : 0.0;
+    }
+  }
+  __syncthreads();
+  // proposals of the four 64-row chunks, merged into one list of NB rows
+  if (wv < 4) {
+    const int di = 64 * wv + lane;
+    const int64_t i = r0 + di;
+    const bool av = i < n && !used[i];
+    double w[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) w[t] = av ? Anx[di][t] : 0.0;
+    wave_select<NB, false>(w, av, mine, zf, dummy, step);
+    if (lane < NB) clist[wv][lane] = mine >= 0 ? 64 * wv + mine : -1;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    const int li = lane / NB, sl = lane % NB;
+    const int di = li < 4 ? clist[li][sl] : -1;
+    const bool av = di >= 0;
+    double w[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) w[t] = av ? Anx[di][t] : 0.0;
+    wave_select<NB, false>(w, av, mine, zf, dummy, step);
+    const int rs = __shfl(di, mine >= 0 ? mine : 0, 64);
+    if (lane < NB) cand[(int64_t)blockIdx.x * NB + lane] = (mine >= 0 && rs >= 0) ? (int)(r0 + rs) : -1;
+  }
+  // the workgroup that arrives last merges every workgroup's list; one
+  // device-scope release (after the barrier that orders this workgroup's
+  // stores) and one acquire per workgroup
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const unsigned last = (atomicAdd(counter + z, 1u) == gridDim.x - 1) ? 1u : 0u;
+    if (last) {
+      __threadfence();
+      atomicExch(counter + z, 0u);
+    }
+    s_last = last;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  int m = (int)gridDim.x, cur = -1;        // cur < 0: lists in cand
+  while (m > FAN) {
+    const int nodes = (m + FAN - 1) / FAN, nxt = cur == 0 ? 1 : 0;
+    for (int j = wv; j < nodes; j += NW) {
+      const int li = j * FAN + lane / NB, sl = lane % NB;
+      int g = -1;
+      if (li < m) g = cur < 0 ? cand[(int64_t)li * NB + sl] : tl[cur][li * NB + sl];
+      double w[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) w[t] = g >= 0 ? S[(int64_t)g * NO + qn + t] : 0.0;
+      wave_select<NB, false>(w, g >= 0, mine, zf, dummy, step);
+      const int gs = __shfl(g, mine >= 0 ? mine : 0, 64);
+      if (lane < NB) tl[nxt][j * NB + lane] = mine >= 0 ? gs : -1;
+    }
+    __syncthreads();
+    cur = nxt;
+    m = nodes;
+  }
+  if (tid < 64) {
+    const int li = tid / NB;
+    rootg[tid] = li < m ? (cur < 0 ? cand[(int64_t)li * NB + tid % NB] : tl[cur][li * NB + tid % NB]) : -1;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    // the root: its pivot rows, their LU factors
+    const int g = rootg[lane];
+    double w[NB], lmul[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      w[t] = g >= 0 ? S[(int64_t)g * NO + qn + t] : 0.0;
+      lmul[t] = 0.0;
+    }
+    wave_select<NB, true>(w, g >= 0, mine, zf, lmul, step);
+    const int gs = __shfl(g, mine >= 0 ? mine : 0, 64);
+    if (lane < NB) {
+      const bool ok = mine >= 0 && !((zf >> lane) & 1u);
+      const int r = ok ? gs : -1;
+      Ll[lane] = ok ? mine : -1;
+      rpiv[j0 + qn + lane] = r;
+      if (r >= 0) used[r] = 1;
+    }
+    if (step >= 0) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) LUs[step][c] = c < step ? lmul[c] : w[c];
+    }
+  } else {
+    // meanwhile the other wavefronts stage the candidates' rows of the slab
+    for (int e = tid - 64; e < 64 * NO; e += 1024 - 64) {
+      const int l = e / NO, c = e - l * NO;
+      const int g = rootg[l];
+      Brow[e] = g >= 0 ? S[(int64_t)g * NO + c] : 0.0;
+    }
+  }
+  __syncthreads();
+  // Z = U^-1 L^-1 B'', one column per thread
+  if (tid < NO) {
+    const int c = tid;
+    const bool inp = c >= qn && c < qn + NB;
+    double y[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int l = Ll[s];
+      y[s] = inp ? ((c - qn == s) ? 1.0 : 0.0) : (l >= 0 ? Brow[l * NO + c] : 0.0);
+    }
+#pragma unroll
+    for (int s = 1; s < NB; ++s)
+#pragma unroll
+      for (int t = 0; t < s; ++t) y[s] = fma(-LUs[s][t], y[t], y[s]);
+#pragma unroll
+    for (int s = NB - 1; s >= 0; --s) {
+#pragma unroll
+      for (int t = s + 1; t < NB; ++t) y[s] = fma(-LUs[s][t], y[t], y[s]);
+      y[s] = y[s] / LUs[s][s];
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s) Zn[s * NO + c] = y[s];
+  }
+}
+
+template <int NB, int NO>
+static hipError_t gj_tour(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
+  double* sb[2] = {w.S, w.S + n * NO};
+  double* zb[2] = {w.Z, w.Z + NB * NO};
+  hipError_t e = load_panel(s, cnt, w.A, w.sA, n, n, 0, NO, sb[0], w.sS);
+  if (e != hipSuccess) return e;
+  const unsigned nwg = (unsigned)((n + 255) / 256), nt = (unsigned)(n / 64);
+  int cs = 0, cz = 0;
+  for (int64_t j0 = 0; j0 < n; j0 += NO, cs ^= 1) {
+    k_gj_tour<NB, NO, false><<<dim3(nwg, 1, cnt), 1024, 0, s>>>(
+        sb[cs], w.sS, n, j0, 0, w.rpiv, w.used, w.sV, nullptr, zb[cz], w.sZ, w.cand, w.sC,
+        w.counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int q0 = 0; q0 < NO; q0 += NB, cz ^= 1) {
+      k_gj_tour<NB, NO, true><<<dim3(nwg, 1, cnt), 1024, 0, s>>>(
+          sb[cs], w.sS, n, j0, q0, w.rpiv, w.used, w.sV, zb[cz], zb[cz ^ 1], w.sZ, w.cand, w.sC,
+          w.counter);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), 1, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, (int)j0, NO, w.rpiv, w.sV, w.B, w.sB);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_gj_slab_update<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, sb[cs ^ 1],
+        w.sS, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Panel configurations (panel width, threads, rows per thread, slab width);
 // the largest order each one holds is RPT * TPB.
 struct GjCfg { int nb, tpb, rpt, no; };
@@ -499,7 +845,17 @@ static const GjCfg kCfg2[3] = {{8, 512, 5, 64}, {8, 512, 10, 64}, {4, 768, 15, 1
 
 GjPlan gj_plan(int64_t n, int algo) {
   GjPlan p{};
-  p.algo = algo == 0 ? ((n > 256) ? 2 : 1) : algo;
+  p.algo = algo == 0 ? ((n > 256) ? 3 : 1) : algo;
+  if (p.algo == 3) {
+    // tournament panels of 16 in slabs of 64 (128 above order 5120); the
+    // merge tree holds up to 256 workgroup lists of 256 rows
+    p.cfg = n > 5120 ? 1 : 0;
+    p.nb = 16;
+    p.no = p.cfg ? 128 : 64;
+    p.pad = p.no;
+    p.max_n = 65536;
+    return p;
+  }
   const GjCfg* cfg = p.algo == 1 ? kCfg1 : kCfg2;
   p.cfg = 2;
   for (int c = 0; c < 3; ++c) {
@@ -524,6 +880,8 @@ hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n,
       default: return gj_blocked<15, 4, 768>(s, w, n, cnt);
     }
   }
+  if (p.algo == 3)
+    return p.cfg ? gj_tour<16, 128>(s, w, n, cnt) : gj_tour<16, 64>(s, w, n, cnt);
   switch (p.cfg) {
     case 0: return gj_slab<5, 8, 512, 64>(s, w, n, cnt);
     case 1: return gj_slab<10, 8, 512, 64>(s, w, n, cnt);

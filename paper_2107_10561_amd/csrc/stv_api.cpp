@@ -916,6 +916,7 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     for (auto& G : groups) {
       dfree(G.d_desc); dfree(G.w.A); dfree(G.w.rpiv); dfree(G.w.used); dfree(G.w.B);
       dfree(G.w.P); dfree(G.w.S); dfree(G.w.Bin); dfree(G.rinv);
+      dfree(G.w.cand); dfree(G.w.Z); dfree(G.w.counter);
     }
   };
   int rc = STV_OK;
@@ -985,6 +986,14 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (G.plan.no > 0 && ((rc = dalloc(ctx, &w.S, (size_t)(cnt * w.sS))) != STV_OK ||
                           (rc = dalloc(ctx, &w.Bin, (size_t)(cnt * w.sBin))) != STV_OK))
       break;
+    if (G.plan.algo == 3) {
+      w.sC = (np + 255) / 256 * G.plan.nb;
+      w.sZ = 2 * (int64_t)G.plan.nb * G.plan.no;
+      if ((rc = dalloc(ctx, &w.cand, (size_t)(cnt * w.sC))) != STV_OK ||
+          (rc = dalloc(ctx, &w.Z, (size_t)(cnt * w.sZ))) != STV_OK ||
+          (rc = dalloc(ctx, &w.counter, (size_t)cnt)) != STV_OK)
+        break;
+    }
   }
   // device descriptors of the members per level (inverse offsets now known)
   for (int g = 0; g < ctx->n_levels && rc == STV_OK; ++g) {
@@ -1000,6 +1009,7 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   // ---- launch: cell inverses on the caller's stream, coarse factorisations
   // on the internal stream (it starts after everything queued before it)
   hipError_t e = hipSuccess;
+  hipStream_t inv = s;
   if (side != s) {
     e = hipEventRecord(ctx->ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
@@ -1007,9 +1017,9 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   auto cell_inverses = [&]() {
     for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
       if (ctx->lv[g].n_cells == 0) continue;
-      Timed t(ctx, KC_INVERSE, g);
-      e = launch_cell_inverses(s, b, ctx->lv[g], fp32, full, status[(size_t)g], scratch[(size_t)g],
-                               slots[(size_t)g]);
+      Timed t(ctx, KC_INVERSE, g, inv);
+      e = launch_cell_inverses(inv, b, ctx->lv[g], fp32, full, status[(size_t)g],
+                               scratch[(size_t)g], slots[(size_t)g]);
       t.done();
     }
   };
@@ -1024,6 +1034,8 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (e == hipSuccess) e = launch_bsr_to_dense(side, b, G.d_desc, cnt, max_rows, G.w.A, G.w.sA, G.np);
     if (e == hipSuccess) e = launch_set_diag(side, G.d_desc, cnt, b, G.w.A, G.w.sA, G.np);
     if (e == hipSuccess) e = hipMemsetAsync(G.w.used, 0, (size_t)(cnt * G.w.sV), side);
+    if (e == hipSuccess && G.w.counter)
+      e = hipMemsetAsync(G.w.counter, 0, sizeof(unsigned) * (size_t)cnt, side);
     if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt);
     t.done();
   }
@@ -1691,7 +1703,7 @@ int stv_set_option(stv_ctx* ctx, int option, int64_t value) {
   if (!ctx) return STV_EINVAL;
   switch (option) {
     case STV_OPT_COARSE_ALGO:
-      if (value < 0 || value > 2) return fail(ctx, STV_EINVAL, "coarse algorithm must be 0, 1 or 2");
+      if (value < 0 || value > 3) return fail(ctx, STV_EINVAL, "coarse algorithm must be 0, 1, 2 or 3");
       ctx->coarse_algo = (int)value;
       return STV_OK;
     case STV_OPT_COARSE_OVERLAP:

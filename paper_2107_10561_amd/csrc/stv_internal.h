@@ -90,6 +90,11 @@ struct GjWork {
   double* P; int64_t sP;          // two panel buffers, 2 x n x nb
   double* S; int64_t sS;          // two slab buffers, 2 x n x no
   double* Bin; int64_t sBin;      // pivot rows of a slab, nb x no
+  // tournament schedule: candidate pivot rows of each 256-row group, the
+  // two panel right factors (2 x nb x no) and one arrival counter per matrix
+  int* cand; int64_t sC;
+  double* Z; int64_t sZ;
+  unsigned* counter;
 };
 
 // Results of the last solve for one instance.
@@ -201,8 +206,9 @@ hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 hipError_t launch_bsr_to_dense(hipStream_t s, int b, const CoarseDesc* desc, int cnt,
                                int32_t max_rows, double* A, int64_t sA, int64_t n);
 // Dense Gauss-Jordan plan: algo 1 = one level of panels (width nb), 2 = slabs
-// of no columns eliminated by panels of nb; the matrix is padded to a
-// multiple of pad; max_n is the largest supported order.
+// of no columns eliminated by panels of nb, 3 = slabs whose panels take
+// tournament-chosen pivot rows; the matrix is padded to a multiple of pad;
+// max_n is the largest supported order.
 struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; };
 GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */);
 hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt);

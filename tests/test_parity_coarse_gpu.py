@@ -1,6 +1,8 @@
 """Dense coarse-level inversion (the direct solve of Algorithm 4.1) through the
-C ABI, both elimination schedules, at orders that cover every panel
+C ABI, every elimination schedule, at orders that cover every panel
 configuration of the library (up to 8934 unknowns) and ragged padding.
+The tournament schedule may take other pivots than partial pivoting: it is
+held to the same residual and forward-error bounds.
 
 Expected values: SuperLU applied to the oracle's coarse matrix (a library
 routine on the same matrix), and the residual r - J d computed on the CPU."""
@@ -54,12 +56,12 @@ def solve_on_gpu(stv, p, algo, r):
 
 
 @pytest.mark.parametrize("name", list(COARSE))
-def test_coarse_inverse_both_schedules(stv, name):
+def test_coarse_inverse_every_schedule(stv, name):
     p, J, lu, cond = coarse_case(name)
     r = np.random.default_rng(21).standard_normal(J.shape[0])
     ref = lu.solve(r)
     out = {}
-    for algo in ("panels", "slabs"):
+    for algo in ("panels", "slabs", "tournament"):
         log(f"[coarse] {name} n={J.shape[0]} {algo}")
         d = solve_on_gpu(stv, p, algo, r)
         res = np.linalg.norm(r - J @ d) / np.linalg.norm(r)
