@@ -303,26 +303,18 @@ hipError_t launch_bsr_transpose_vals(hipStream_t s, int b, const double* val, co
 // workgroup, no LDS, no barriers): lane j holds rho_T[j] for the columns
 // j = lane + 64c of the cell-local order (alpha, l) -> alpha*B + l, gathered
 // straight from the level residual.  The stored inverse rows are row-major,
-// so each row is one contiguous, fully coalesced read; rows are processed 8 at
-// a time and their 64 partial sums are folded by a transpose-reduce after
-// which lanes 8t..8t+7 hold row t.  Last-writer form: only the rows of the
-// DoFs the cell owns are computed and written (d_j += omega c_j, or
-// = omega c_j for a zero initial iterate); every DoF has exactly one owner,
-// so the stores are disjoint (no atomics, deterministic).
-// Row r of the cell's stored block as this lane's partial product.
-template <int N, int NC, typename TS>
-__device__ __forceinline__ double row_dot(const TS* __restrict__ Ar, const double (&x)[NC],
-                                          int lane) {
-  double acc = 0.0;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const int j = lane + 64 * c;
-    if (j < N) acc = fma((double)Ar[j], x[c], acc);
-  }
-  return acc;
-}
-
-template <int B, int NLS, typename TS>
+// so each row is one contiguous, fully coalesced read.  Rows are taken G at
+// a time with every load of a group issued before the first is used
+// (indices clamped into the cell's block instead of branches, so that the
+// loads do not serialise), and the G partial sums are folded by one
+// transpose-reduce.  Last-writer form: only the rows of the DoFs the cell
+// owns are computed; row r of the cell ends in lane r % 64, which also
+// fetched the old iterate of that DoF at the start, and the cell's rows are
+// stored in one pass (d_j += omega c_j, or = omega c_j for a zero initial
+// iterate).  Every DoF has exactly one owner, so the stores are disjoint (no
+// atomics, deterministic).  FULL: the store keeps every row of J_T^-1 and the
+// owned ones are picked by their local index.
+template <int B, int NLS, typename TS, bool FULL>
 __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
                                               double* __restrict__ d,
                                               const int32_t* __restrict__ csd,
@@ -330,52 +322,105 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
                                               const uint8_t* __restrict__ own_loc,
                                               const int64_t* __restrict__ inv_off, int ld,
                                               const TS* __restrict__ store, double omega,
-                                              int zero_init, int full, int n_cells) {
+                                              int zero_init, int n_cells) {
   constexpr int N = B * NLS;
-  constexpr int NC = (N + 63) / 64;
+  constexpr int NC = (N + 63) / 64;        // 64-column chunks of a row
+  constexpr int NOC = (NLS + 63) / 64;     // 64-lane chunks of the owned DoFs
+  constexpr int RC = NC;                   // 64-lane chunks of the owned rows (R <= N)
+  constexpr int G = NC == 1 ? 16 : 8;      // rows per group
   const int lane = threadIdx.x & 63;
   // one cell per wavefront and step; a grid smaller than the cell count makes
   // the launch persistent (each wavefront strides over the cells)
-  for (int T = blockIdx.x * 4 + (threadIdx.x >> 6); T < n_cells; T += gridDim.x * 4) {
-  const int32_t* sd = csd + (int64_t)T * NLS;
-  const int o0 = own_ptr[T];
-  const int R = (own_ptr[T + 1] - o0) * B;
-  const TS* A = store + inv_off[T];
-  double x[NC];
+  // (the cell index is wave-uniform: its per-cell data sits in scalar registers)
+  const int T0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  for (int T = T0; T < n_cells; T += gridDim.x * 4) {
+    const int32_t* sd = csd + (int64_t)T * NLS;
+    const int o0 = own_ptr[T];
+    const int no = own_ptr[T + 1] - o0;
+    if (no <= 0) continue;
+    const int R = no * B;
+    const TS* A = store + inv_off[T];
+    double x[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const int j = lane + 64 * c;
-    x[c] = 0.0;
-    if (j < N) {
-      const int be = j / B;
-      x[c] = rho[(int64_t)sd[be] * B + (j - be * B)];
+    for (int c = 0; c < NC; ++c) {
+      const int j = lane + 64 * c;
+      const int jc = j < N ? j : N - 1;
+      const int be = jc / B;
+      const double v = rho[(int64_t)sd[be] * B + (jc - be * B)];
+      x[c] = j < N ? v : 0.0;
     }
-  }
-  // groups of 8 owned rows: 8 row reads in flight, then one fold (keeping
-  // more groups in flight was measured slower: it costs occupancy)
-  for (int r0 = 0; r0 < R; r0 += 8) {
-    double p[8];
+    // owned DoFs, lane = owned index: local index and spatial DoF
+    int ol[NOC], gs[NOC];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int row = r0 + t;
-      p[t] = 0.0;
-      if (row < R) {
-        int srow = row;
-        if (full) {
-          const int os = row / B;
-          srow = own_loc[o0 + os] * B + (row - os * B);
-        }
-        p[t] = row_dot<N, NC, TS>(A + (int64_t)srow * ld, x, lane);
+    for (int c = 0; c < NOC; ++c) {
+      const int k = lane + 64 * c;
+      ol[c] = own_loc[o0 + (k < no ? k : no - 1)];
+      gs[c] = sd[ol[c]];
+    }
+    // the rows this lane stores (r = lane + 64 rc): DoF index and old value
+    int64_t gi[RC];
+    double dold[RC], res[RC];
+#pragma unroll
+    for (int rc = 0; rc < RC; ++rc) {
+      const int r = lane + 64 * rc;
+      const int rcl = r < R ? r : R - 1;
+      const int os = rcl / B;
+      int g = __shfl(gs[0], os & 63, 64);
+      if constexpr (NOC > 1) {
+        const int g1 = __shfl(gs[NOC - 1], os & 63, 64);
+        g = os < 64 ? g : g1;
       }
+      gi[rc] = (int64_t)g * B + (rcl - os * B);
+      dold[rc] = zero_init ? 0.0 : d[gi[rc]];
+      res[rc] = 0.0;
     }
-    const double sum = fold<8>(p, lane);
-    const int row = r0 + (lane >> 3);
-    if ((lane & 7) == 0 && row < R) {
-      const int os = row / B;
-      const int64_t g = (int64_t)sd[own_loc[o0 + os]] * B + (row - os * B);
-      d[g] = zero_init ? omega * sum : fma(omega, sum, d[g]);
+    for (int r0 = 0; r0 < R; r0 += G) {
+      TS a[G][NC];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const int row = min(r0 + t, R - 1);
+        int srow = row;
+        if constexpr (FULL) {
+          const int os = row / B;
+          int l = __builtin_amdgcn_readlane(ol[0], os & 63);
+          if constexpr (NOC > 1) {
+            const int l1 = __builtin_amdgcn_readlane(ol[NOC - 1], os & 63);
+            l = os < 64 ? l : l1;
+          }
+          srow = l * B + (row - os * B);
+        }
+        // offsets inside the cell's block fit 32 bits: the loads address
+        // from the block's (wave-uniform) base
+        const unsigned ro = (unsigned)(srow * ld);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int j = lane + 64 * c;
+          a[t][c] = A[ro + (unsigned)(j < N ? j : N - 1)];
+        }
+      }
+      double p[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc = fma((double)a[t][c], x[c], acc);
+        p[t] = acc;
+      }
+      const double sum = fold<G>(p, lane);   // row r0 + t in lanes t * (64 / G) ..
+      // row r0 + t goes to lane (r0 + t) % 64 of chunk r0 / 64 (a group never
+      // straddles two chunks: G divides 64)
+      const int t = lane - (r0 & 63);
+      const double v = __shfl(sum, (t & (G - 1)) * (64 / G), 64);
+      const int rcg = r0 >> 6;
+#pragma unroll
+      for (int rc = 0; rc < RC; ++rc)
+        if (rc == rcg && t >= 0 && t < G) res[rc] = v;
     }
-  }
+#pragma unroll
+    for (int rc = 0; rc < RC; ++rc) {
+      const int r = lane + 64 * rc;
+      if (r < R) d[gi[rc]] = zero_init ? omega * res[rc] : fma(omega, res[rc], dold[rc]);
+    }
   }
 }
 
@@ -384,14 +429,18 @@ static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, 
                            double omega, int zero_init, int fp32, int full) {
   unsigned grid = (unsigned)((L.n_cells + 3) / 4);
   if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
-  if (fp32)
-    k_vanka<B, NLS, float><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
-                                                L.inv_off, L.inv_ld, (const float*)L.inv_store,
-                                                omega, zero_init, full, L.n_cells);
-  else
-    k_vanka<B, NLS, double><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
-                                                 L.inv_off, L.inv_ld, (const double*)L.inv_store,
-                                                 omega, zero_init, full, L.n_cells);
+#define STV_VANKA(TS, F)                                                                     \
+  k_vanka<B, NLS, TS, F><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,  \
+                                              L.inv_off, L.inv_ld, (const TS*)L.inv_store, \
+                                              omega, zero_init, L.n_cells)
+  if (fp32) {
+    if (full) STV_VANKA(float, true);
+    else STV_VANKA(float, false);
+  } else {
+    if (full) STV_VANKA(double, true);
+    else STV_VANKA(double, false);
+  }
+#undef STV_VANKA
   return hipGetLastError();
 }
 
