@@ -318,8 +318,9 @@ int stv_set_option(stv_ctx* ctx, int option, int64_t value);
 int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const double* aval,
                          const double* C, const double* tw);
 
-/* Launch shapes of the level kernels of one level: spmv_rows = block rows
- * per wavefront of the residual (1..4, default 2); sweep_wgs = workgroups
+/* Launch shapes of the level kernels of one level: spmv_rows = shape of the
+ * residual (1..4, default 2): with the blocks, block rows per wavefront;
+ * with spatial factors, 2^(spmv_rows+1) lanes per block row; sweep_wgs = workgroups
  * of the Vanka sweep, 0 (default) for one wavefront per cell, otherwise a
  * persistent launch of that many workgroups whose wavefronts stride over the
  * cells.  The residual's summation order depends on spmv_rows (results
@@ -327,13 +328,13 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
  * Errors: STV_ESTATE (no hierarchy), STV_EINVAL. */
 int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs);
 
-/* Autotuner: on every smoothed level, time each residual shape (1..4 rows
- * per wavefront) and each sweep shape (one wavefront per cell, or persistent
+/* Autotuner: on every smoothed level, time each residual shape (1..4) and
+ * each sweep shape (one wavefront per cell, or persistent
  * grids of 2, 4, 8, 16 workgroups per compute unit) on the device, five
  * launches each after one untimed launch, and keep the fastest.  Needs the
  * inverses (the sweep is timed with the stored ones); uses temporary device
  * vectors; the hierarchy's data are not modified.  If choices is non-NULL
- * it receives, for level g < cap/2, choices[2g] = rows per wavefront and
+ * it receives, for level g < cap/2, choices[2g] = residual shape and
  * choices[2g+1] = sweep workgroups.  Synchronises the stream. */
 int stv_autotune(stv_ctx* ctx, int* choices, int cap);
 

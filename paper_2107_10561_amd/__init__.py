@@ -392,7 +392,7 @@ class Solver:
 
     def autotune(self):
         """Time the launch shapes on the device and keep the fastest; returns
-        {level: (rows per wavefront, sweep workgroups)}."""
+        {level: (residual shape, sweep workgroups)}."""
         cap = 2 * self.n_levels
         ch = (ctypes.c_int * cap)()
         self._check(_lib.stv_autotune(self._h, ch, cap))

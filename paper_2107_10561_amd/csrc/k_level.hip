@@ -130,13 +130,16 @@ hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
 
 // Level residual from the spatial factors of an operator whose blocks are
 // C[i][l] M + delta_il tw[i] A (time-independent coefficients): per block only
-// the two scalars m = M(s, s') and a = A(s, s') are streamed.  Lane q_off of a
-// wavefront takes every 64th block of its RPW rows, forms the B outputs of the
-// block from the B entries of x at the block column, and the per-row sums are
-// folded across the wavefront as in the block kernel.
+// the two scalars m = M(s, s') and a = A(s, s') are streamed.  LPR lanes per
+// block row (64 / LPR rows per wavefront): lane `sub` of a row takes the
+// row's blocks sub, sub + LPR, ..., U of them per round, with every load of a
+// round issued before the first is used (indices clamped into the row, the
+// blocks past its end weighted by zero, instead of branches), and keeps only
+// the B partial sums of its own row; the row's lanes then add their sums
+// (butterfly over the LPR lanes).
 struct KronCoef { double C[16]; double tw[4]; };
 
-template <int B, int RPW>
+template <int B, int LPR>
 __global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col,
                                                    const double* __restrict__ mval,
@@ -145,63 +148,74 @@ __global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ r
                                                    const double* __restrict__ x,
                                                    double* __restrict__ y, int32_t n_rows,
                                                    double sx, KronCoef K) {
-  constexpr int NV = RPW * B;
-  constexpr int NVP = NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : 32;
-  const int lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
-  if (row0 >= n_rows) return;  // uniform per wavefront
-  int32_t rp[RPW + 1];
+  constexpr int RPWV = 64 / LPR;
+  constexpr int U = LPR >= 16 ? 2 : 4;
+  const int lane = threadIdx.x & 63, sub = lane % LPR;
+  const int row = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPWV + lane / LPR;
+  const bool live = row < n_rows;
+  const int rr = live ? row : n_rows - 1;
+  const int32_t q0 = rowptr[rr], q1 = rowptr[rr + 1];
+  double rv = 0.0;
+  if (r && live && sub < B) rv = r[(int64_t)rr * B + sub];
+  double acc[B];
 #pragma unroll
-  for (int t = 0; t <= RPW; ++t) rp[t] = rowptr[min(row0 + t, n_rows)];
-  double acc[NVP];
+  for (int i = 0; i < B; ++i) acc[i] = 0.0;
+  const int nit = (q1 - q0 + U * LPR - 1) / (U * LPR);
+  for (int it = 0; it < nit; ++it) {
+    const int32_t qb = q0 + it * U * LPR + sub;
+    int64_t c[U];
+    double m[U], a[U];
 #pragma unroll
-  for (int v = 0; v < NVP; ++v) acc[v] = 0.0;
-#pragma unroll 2
-  for (int32_t q = rp[0] + lane; q < rp[RPW]; q += 64) {
-    const int64_t c = col[q];
-    const double m = mval[q], a = aval[q];
-    double xl[B];
-#pragma unroll
-    for (int l = 0; l < B; ++l) xl[l] = x[c * B + l];
-    int rr = 0;
-#pragma unroll
-    for (int t = 1; t < RPW; ++t) rr += (q >= rp[t]) ? 1 : 0;
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-      double ci = 0.0;
-#pragma unroll
-      for (int l = 0; l < B; ++l) ci = fma(K.C[i * B + l], xl[l], ci);
-      const double v = fma(m, ci, a * K.tw[i] * xl[i]);
-#pragma unroll
-      for (int t = 0; t < RPW; ++t) acc[t * B + i] += (rr == t) ? v : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const int32_t q = qb + u * LPR;
+      const bool v = q < q1;
+      const int32_t qc = v ? q : q1 - 1;
+      c[u] = col[qc];
+      const double mm = mval[qc], aa = aval[qc];
+      m[u] = v ? mm : 0.0;
+      a[u] = v ? aa : 0.0;
     }
+    double xl[U][B];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int l = 0; l < B; ++l) xl[u][l] = x[c[u] * B + l];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        double ci = 0.0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) ci = fma(K.C[i * B + l], xl[u][l], ci);
+        acc[i] = fma(m[u], ci, fma(a[u] * K.tw[i], xl[u][i], acc[i]));
+      }
   }
-  const double sum = fold<NVP>(acc, lane);
-  constexpr int SPAN = 64 / NVP;
-  const int v = lane / SPAN;
-  if ((lane % SPAN) == 0 && v < NV) {
-    const int t = v / B, i = v - (v / B) * B;
-    const int row = row0 + t;
-    if (row < n_rows) {
-      const int64_t o = (int64_t)row * B + i;
-      y[o] = r ? fma(sx, sum, r[o]) : sx * sum;
-    }
+#pragma unroll
+  for (int off = LPR / 2; off >= 1; off >>= 1)
+#pragma unroll
+    for (int i = 0; i < B; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+  if (live && sub < B) {
+    double s = acc[0];
+#pragma unroll
+    for (int i = 1; i < B; ++i) s = (sub == i) ? acc[i] : s;
+    y[(int64_t)row * B + sub] = r ? fma(sx, s, rv) : sx * s;
   }
 }
 
+// residual shape s (1..4): 2^(s+1) lanes per block row
 template <int B>
 static hipError_t spmv_kron_b(hipStream_t s, const DevLevel& L, const double* r, const double* x,
                               double* y, double sx) {
   KronCoef K{};
   for (int e = 0; e < B * B; ++e) K.C[e] = L.kron_C[e];
   for (int e = 0; e < B; ++e) K.tw[e] = L.kron_tw[e];
-  const int rpw = L.spmv_rpw;
-  dim3 grid((L.n_s + 4 * rpw - 1) / (4 * rpw)), block(256);
-  switch (rpw) {
-    case 1: k_spmv_kron<B, 1><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 2: k_spmv_kron<B, 2><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 3: k_spmv_kron<B, 3><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+  const int lpr = 2 << L.spmv_rpw, rows_per_wg = 4 * (64 / lpr);
+  dim3 grid((L.n_s + rows_per_wg - 1) / rows_per_wg), block(256);
+  switch (lpr) {
     case 4: k_spmv_kron<B, 4><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 8: k_spmv_kron<B, 8><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 16: k_spmv_kron<B, 16><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 32: k_spmv_kron<B, 32><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -1,4 +1,4 @@
-"""Launch shapes of the level kernels (rows per wavefront of the residual,
+"""Launch shapes of the level kernels (the residual's shape,
 persistent sweep grids) and the autotuner that picks them: every shape must
 reproduce the oracle, and the sweep must not depend on its grid at all."""
 import numpy as np
