@@ -785,18 +785,38 @@ hipError_t launch_vanka_combine(hipStream_t s, int b, const DevLevel& L, double*
 // ---------------------------------------------------------------------------
 // Transfers: y[row*B + l] (+)= sum_e val[e] x[col[e]*B + l] for a spatial CSR
 // (identity in time).  Restriction uses the stored transpose of P, so both
-// directions are gathers (no atomics).
+// directions are gathers (no atomics).  The entries of a row are taken 8 at
+// a time with all their loads in flight (indices clamped into the row, the
+// entries past its end weighted by zero); the summation order is the row's.
 template <int B>
 __global__ void k_csr_time(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                            const double* __restrict__ val, const double* __restrict__ x,
                            double* __restrict__ y, int32_t n_rows, int accumulate) {
+  constexpr int U = 8;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n_rows * B) return;
   const int32_t row = (int32_t)(idx / B);
   const int l = (int)(idx - (int64_t)row * B);
+  const int32_t e0 = rp[row], e1 = rp[row + 1];
+  const double y0 = accumulate ? y[idx] : 0.0;
   double acc = 0.0;
-  for (int32_t e = rp[row]; e < rp[row + 1]; ++e) acc = fma(val[e], x[(int64_t)col[e] * B + l], acc);
-  y[idx] = accumulate ? y[idx] + acc : acc;
+  for (int32_t e = e0; e < e1; e += U) {
+    int64_t c[U];
+    double v[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e + u < e1;
+      const int32_t ec = ok ? e + u : e1 - 1;
+      c[u] = col[ec];
+      const double w = val[ec];
+      v[u] = ok ? w : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u] * B + l];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = fma(v[u], xv[u], acc);
+  }
+  y[idx] = accumulate ? y0 + acc : acc;
 }
 
 static hipError_t csr_time(hipStream_t s, int b, const int32_t* rp, const int32_t* col,
