@@ -7,6 +7,7 @@
 // batched hierarchy) is inverted by the same launches, each matrix and work
 // buffer at its own stride.
 #include "stv_internal.h"
+#include "wave.h"
 
 namespace stv {
 
@@ -508,29 +509,6 @@ static hipError_t gj_slab(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
 // barrier), and one launch per panel applies the previous panel's step,
 // proposes the next panel's rows and, in the workgroup that arrives last,
 // merges the proposals and computes the next Z.
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
-// Maximum over the 64 lanes of a wavefront (all lanes active), in every lane.
-__device__ __forceinline__ double wave_max_f64(double v) {
-  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]: lane ^ 1
-  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]: lane ^ 2
-  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror: the other quad of 8
-  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror: the other half of 16
-  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
-              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
-}
 
 // Partial pivoting over rows held by the lanes of one wavefront (all 64
 // lanes active): lane l holds a row when `avail`, with panel values

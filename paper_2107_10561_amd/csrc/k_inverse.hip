@@ -13,6 +13,7 @@
 // Cell-local order inside the kernel is (alpha, l) -> alpha*B + l, matching
 // the time-inner global layout.
 #include "stv_internal.h"
+#include "wave.h"
 
 namespace stv {
 
@@ -150,13 +151,18 @@ __attribute__((amdgpu_waves_per_eu((((B * NLS + 15) / 16) + 3) / 4, 8))) k_inver
               if (v > best) { best = v; bi = rho; }
             }
           }
-          double m = best;
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-          int cand = (best == m) ? bi : 0x7fffffff;
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off, 64));
-          int r = cand;
+          // the largest magnitude (DPP max), then the lowest row holding it:
+          // read from the single lane that has it, or a DPP min over ties
+          const double m = wave_max_f64(best);
+          const uint64_t tied = __builtin_amdgcn_ballot_w64(bi < NP && best == m);
+          int r;
+          if (tied == 0)
+            r = 0x7fffffff;
+          else if (NCH == 1 || (tied & (tied - 1)) == 0)
+            r = __builtin_amdgcn_readlane(bi, (int)__builtin_ctzll(tied));
+          else
+            r = wave_min_i32(best == m ? bi : 0x7fffffff);
+          r = __builtin_amdgcn_readfirstlane(r);
           if (r >= NP) {   // no finite candidate (NaN column): lowest unused row
             int u = 0x7fffffff;
 #pragma unroll

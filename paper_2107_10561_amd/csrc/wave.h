@@ -1,0 +1,50 @@
+// Wavefront reductions built from DPP lane permutations (gfx9 encodings)
+// and readlane: no LDS traffic, a few cycles per step.  Every lane of the
+// wavefront must be active when they are called.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace stv {
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = dpp_i32<CTRL>(__double2loint(v));
+  const int hi = dpp_i32<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Maximum over the 64 lanes, the same in every lane: within each row of 16
+// lanes by partner exchanges (lane ^ 1, lane ^ 2, the mirrored quad of 8,
+// the mirrored half of 16), then across the four rows by readlane.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+// Minimum over the 64 lanes, the same in every lane.
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, dpp_i32<0xB1>(v));
+  v = min(v, dpp_i32<0x4E>(v));
+  v = min(v, dpp_i32<0x141>(v));
+  v = min(v, dpp_i32<0x140>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+}  // namespace stv
