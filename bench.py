@@ -81,6 +81,14 @@ def parse():
     ap.add_argument("--nu-sweep", action="store_true",
                     help="instead of the timing line: FGMRES iterations of the batched "
                          "instances against viscosity, undamped and damped smoother")
+    ap.add_argument("--newton", action="store_true",
+                    help="instead of the Oseen solve: the linear solve of a Newton step of the "
+                         "Navier-Stokes system (256x64, 5 levels, dG(1), Jacobian at the iterate "
+                         "after one Newton step from rest: full time blocks)")
+    ap.add_argument("--gradient", action="store_true",
+                    help="instead of the solve: one gradient of the outflow loss with respect "
+                         "to every cell viscosity and the inflow amplitude per step (256x64, "
+                         "5 levels, dG(1), per-cell viscosity)")
     return ap.parse_args()
 
 
@@ -225,10 +233,235 @@ def nu_sweep(args):
                       "data": "synthetic"}), flush=True)
 
 
+def gradient_cpu_baseline(n_fine, G, reps=1):
+    """The oracle's gradient on a bounded sample of the differentiation
+    workload: forward and adjoint FGMRES(30) with the oracle's Vanka-GMG (of J
+    and of J^T) to 1e-8, then the cellwise contractions; one thread."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from oracle import adjoint as oadj
+    from stgen import adjoint as gadj
+    p = gadj.make_differentiation_problem(n_fine, G, 1, 0.01, 3000)
+    m = p.levels[-1].mesh
+    refs, ptr, idx, w = gadj.nu_derivative_refs(m)
+    tw = gadj.time_weights(p.k, p.tau)
+    F0, in_cells, Fc = gadj.inflow_rhs_parts(m, p.k, p.tau)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ol = oracle.build_inverses(oracle.prepare_levels(p.levels, p.b))
+            olt = oadj.transpose_levels(ol)
+            ci, cit = oracle.coarse_inverse(ol[0]), oracle.coarse_inverse(olt[0])
+            x, fi = oracle.fgmres(lambda v: ol[-1].J @ v, p.rhs,
+                                  lambda v: oracle.vcycle(ol, v, 2, 2, 0.7, coarse_inv=ci),
+                                  restart=30, rtol=1e-8)
+            lam, ai = oracle.fgmres(lambda v: olt[-1].J @ v, p.loss,
+                                    lambda v: oracle.vcycle(olt, v, 2, 2, 0.7, coarse_inv=cit),
+                                    restart=30, rtol=1e-8)
+            csd = m.cell_sdofs()
+            g = -oadj.cell_contraction(lam, x, csd, p.b, refs, ptr, idx, w, tw)
+            g[in_cells] += oadj.cell_dot(lam, in_cells, csd, p.b, Fc)
+        dt = (time.perf_counter() - t0) / reps
+    sweeps = (fi["iters"] + ai["iters"]) * 4 * sum(L.n_cells for L in p.levels[1:])
+    return dict(value=round(1.0 / dt, 4), unit="gradients/s", cores=1, kind="oracle",
+                cell_sweeps_per_s=round(sweeps / dt, 1),
+                sample=f"{n_fine[0]}x{n_fine[1]} cells, {G} levels, dG(1), same loss and "
+                       f"viscosity field law ({fi['iters']} + {ai['iters']} FGMRES iterations); "
+                       f"{dt:.1f} s per gradient, 1 thread")
+
+
+def gradient_bench(args):
+    """One step = the gradient of the outflow loss L = q . x with respect to
+    every cell viscosity and the inflow amplitude: the cell inverses (all
+    rows), FGMRES on J x = b, FGMRES on J^T lam = q with the stored inverses
+    read transposed, and the cellwise contractions, on the resident
+    hierarchy (assembly and upload of the operator are input, outside)."""
+    import torch
+
+    import paper_2107_10561_amd as stv
+    from stgen import adjoint as gadj
+    n_fine, G = (256, 64), 5
+    t0 = time.time()
+    p = gadj.make_differentiation_problem(n_fine, G, 1, 0.01, 3000)
+    m = p.levels[-1].mesh
+    refs, ptr, idx, w = gadj.nu_derivative_refs(m)
+    tw = gadj.time_weights(p.k, p.tau)
+    F0, in_cells, Fc = gadj.inflow_rhs_parts(m, p.k, p.tau)
+    print(f"[bench] generated the differentiation workload in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    dev = torch.device("cuda", 0)
+    b = torch.from_numpy(p.rhs).to(dev)
+    q = torch.from_numpy(p.loss).to(dev)
+    x = torch.zeros_like(b)
+    lam = torch.zeros_like(b)
+    nc = m.n_cells
+    con = torch.empty(nc, dtype=torch.float64, device=dev)
+    fdot = torch.empty(len(in_cells), dtype=torch.float64, device=dev)
+    fcf = Fc.reshape(len(in_cells), -1)
+    cells_smoothed = sum(L.n_cells for L in p.levels[1:])
+
+    def step(fp32):
+        s.build_cell_inverses(fp32=fp32, full=True)
+        fi = s.gmres_solve(b, x, restart=30, max_it=1000, rtol=1e-8)
+        ai = s.gmres_solve_transposed(q, lam, restart=30, max_it=1000, rtol=1e-8)
+        s.cell_contract(G - 1, lam, x, refs, ptr, idx, w, tw, con)
+        s.cell_dot(G - 1, lam, in_cells, fcf, fdot)
+        return fi, ai
+
+    def leg(fp32):
+        for _ in range(args.warmup):
+            step(fp32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sweeps = 0
+        for _ in range(args.steps):
+            fi, ai = step(fp32)
+            sweeps += (fi["iters"] + ai["iters"]) * cells_smoothed * (args.nu1 + args.nu2)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g = -con.cpu().numpy()
+        g[in_cells] += fdot.cpu().numpy()
+        return dict(ms_per_step=round(1e3 * el / args.steps, 3),
+                    gradients_per_s=round(args.steps / el, 3),
+                    cell_sweeps_per_s=round(sweeps / el, 1), forward_iters=fi["iters"],
+                    adjoint_iters=ai["iters"], forward_relres=fi["true_relres"],
+                    adjoint_relres=ai["true_relres"], max_abs_grad=float(np.abs(g).max()),
+                    loss=float((q * x).sum()))
+
+    r64 = leg(False)
+    r32 = None if args.no_fp32 else leg(True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = gradient_cpu_baseline((128, 32), 4)
+    print(json.dumps({
+        "metric": "gradient of the outflow loss w.r.t. every cell viscosity and the inflow "
+                  "amplitude (forward + adjoint Vanka-GMG-FGMRES to 1e-8)",
+        "value": r64["gradients_per_s"], "unit": "gradients/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2d channel 256x64 Q2/P1disc x dG(1), 5 levels, per-cell "
+                               "viscosity 1e-3 exp(0.3 z), tau=0.01, outflow-flux loss",
+                   "cells_finest": nc, "levels": G, "parallelism": "single GPU"},
+        "fp64": r64, "fp32_inverses": r32, "cpu_baseline": cpu}), flush=True)
+
+
+def newton_system(n_fine, G):
+    """The Newton problem, its data and the iterate after one Newton step
+    from rest (solved directly on the host: input generation)."""
+    import scipy.sparse.linalg as sla
+
+    from oracle.smoother import spacetime_matrix
+    from stgen.newton import NewtonProblem
+    P = NewtonProblem(2, n_fine, G, 1, 0.01, 1e-3)
+    F = P.data(0.0, np.zeros(P.fine.mesh.n_sdofs))
+    u = np.zeros(P.fine.mesh.n_sdofs * P.b)
+    L = P.hierarchy(u)[-1]
+    J0 = spacetime_matrix(L["rowptr"], L["col"], L["val"], L["n_sdofs"], P.b)
+    u = u - sla.spsolve(J0.tocsc(), P.residual(u, F))
+    return P, F, u
+
+
+def newton_cpu_baseline(n_fine, G):
+    """The oracle's Vanka-GMG FGMRES(30) on the Newton Jacobian of a bounded
+    sample (cell inverses, coarse inverse and the solve to 1e-8), one thread."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    P, F, u = newton_system(n_fine, G)
+    H = P.hierarchy(u)
+    R = P.residual(u, F)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ol = oracle.build_inverses(oracle.prepare_levels(H, P.b))
+        ci = oracle.coarse_inverse(ol[0])
+        _, info = oracle.fgmres(lambda v: ol[-1].J @ v, -R,
+                                lambda v: oracle.vcycle(ol, v, 2, 2, 0.7, coarse_inv=ci),
+                                restart=30, rtol=1e-8)
+        dt = time.perf_counter() - t0
+    sweeps = info["iters"] * 4 * sum(int(np.asarray(L["cell_sdofs"]).shape[0]) for L in H[1:])
+    return dict(value=round(sweeps / dt, 1), unit="cell-sweeps/s", cores=1, kind="oracle",
+                sample=f"{n_fine[0]}x{n_fine[1]} cells, {G} levels, dG(1), Newton Jacobian at "
+                       f"the same kind of iterate ({info['iters']} FGMRES iterations); "
+                       f"{dt:.1f} s per solve, 1 thread")
+
+
+def newton_bench(args):
+    """One step = the linear solve of a Newton step: all cell inverses and the
+    coarse inverse of the Jacobian hierarchy J(u) (full time blocks: the
+    convection term is integrated exactly in time at a time-dependent
+    iterate), then FGMRES(30) + V(2,2) on J(u) du = -R(u) to 1e-8."""
+    import torch
+
+    import paper_2107_10561_amd as stv
+    n_fine, G = (256, 64), 5
+    t0 = time.time()
+    P, F, u = newton_system(n_fine, G)
+    H = P.hierarchy(u)
+    R = P.residual(u, F)
+    print(f"[bench] Newton system at the first iterate in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    s = stv.Solver(0)
+    s.set_hierarchy(H, 2, 1)
+    rhs = torch.from_numpy(-R).to("cuda:0")
+    du = torch.zeros_like(rhs)
+    cells = sum(int(np.asarray(L["cell_sdofs"]).shape[0]) for L in H[1:])
+
+    def leg(fp32):
+        for _ in range(args.warmup):
+            s.build_cell_inverses(fp32=fp32)
+            s.gmres_solve(rhs, du, restart=30, max_it=1000, rtol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sweeps = 0
+        for _ in range(args.steps):
+            s.build_cell_inverses(fp32=fp32)
+            info = s.gmres_solve(rhs, du, restart=30, max_it=1000, rtol=1e-8)
+            sweeps += info["iters"] * cells * (args.nu1 + args.nu2)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        r1 = P.residual(u + du.cpu().numpy(), F)
+        return dict(ms_per_step=round(1e3 * el / args.steps, 3),
+                    cell_sweeps_per_s=round(sweeps / el, 1), iters=info["iters"],
+                    true_relres=info["true_relres"],
+                    newton_residual_before=float(np.linalg.norm(R) / np.linalg.norm(F)),
+                    newton_residual_after=float(np.linalg.norm(r1) / np.linalg.norm(F)))
+
+    r64 = leg(False)
+    r32 = None if args.no_fp32 else leg(True)
+    cpu = None if args.no_cpu_baseline else newton_cpu_baseline((128, 32), 4)
+    print(json.dumps({
+        "metric": "Newton-step linear solve: GMG-GMRES time to rel. residual 1e-8; Vanka "
+                  "cell-sweeps/s", "value": r64["cell_sweeps_per_s"], "unit": "cell-sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2d channel 256x64 Q2/P1disc x dG(1), 5 levels, Navier-Stokes "
+                               "Newton Jacobian, nu=1e-3, tau=0.01, parabolic inflow ramp",
+                   "cells_finest": n_fine[0] * n_fine[1], "levels": G,
+                   "parallelism": "single GPU"},
+        "fp64": r64, "fp32_inverses": r32, "cpu_baseline": cpu}), flush=True)
+
+
 def main():
     args = parse()
+    if args.newton:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        newton_bench(args)
+        return
     if args.nu_sweep:
         nu_sweep(args)
+        return
+    if args.gradient:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        gradient_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "

@@ -2,6 +2,7 @@
 // cell sweep and the grid transfers.  Vectors are FP64 and time-inner
 // (x[s*B + l], B = k+1 temporal DoFs per spatial DoF).
 #include "stv_internal.h"
+#include "wave.h"
 
 namespace stv {
 
@@ -481,9 +482,12 @@ hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const dou
 // Vanka sweep of the transposed operator J^T.  Its local inverse is
 // (J_T^T)^-1 = (J_T^-1)^T, the stored full inverse read transposed: with the
 // residual rho_T of J^T in lane j = lane + 64c, the correction
-// c_o = sum_j (J_T^-1)[j][o] rho_j is accumulated row by row (each stored row
-// one coalesced read, rho_j broadcast from its lane); the owner rule and the
-// update are those of the forward sweep.  Needs every stored row.
+// c_o = sum_j (J_T^-1)[j][o] rho_j of local DoF o = lane + 64c accumulates in
+// lane o, stored row j after row j (each row one coalesced read, rho_j
+// broadcast by readlane), 8 rows per round with all their loads in flight.
+// The owner rule and the update are those of the forward sweep: lane o
+// learns whether the cell owns its DoF from the cell's owned list, fetches
+// the DoF's old value at the start and stores once.  Needs every stored row.
 template <int B, int NLS, typename TS>
 __global__ void __launch_bounds__(256) k_vanka_t(const double* __restrict__ rho,
                                                 double* __restrict__ d,
@@ -495,49 +499,87 @@ __global__ void __launch_bounds__(256) k_vanka_t(const double* __restrict__ rho,
                                                 int zero_init, int n_cells) {
   constexpr int N = B * NLS;
   constexpr int NC = (N + 63) / 64;
+  constexpr int NOC = (NLS + 63) / 64;
+  constexpr int U = 8;
   const int lane = threadIdx.x & 63;
-  for (int T = blockIdx.x * 4 + (threadIdx.x >> 6); T < n_cells; T += gridDim.x * 4) {
+  const int T0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  for (int T = T0; T < n_cells; T += gridDim.x * 4) {
     const int32_t* sd = csd + (int64_t)T * NLS;
     const int o0 = own_ptr[T];
     const int no = own_ptr[T + 1] - o0;
+    if (no <= 0) continue;
     const TS* A = store + inv_off[T];
-    double x[NC], acc[NC];
+    double x[NC], acc[NC], dold[NC];
+    int64_t gi[NC];
+    bool own[NC];
+    int ol[NOC];
+#pragma unroll
+    for (int c = 0; c < NOC; ++c) {
+      const int k = lane + 64 * c;
+      ol[c] = own_loc[o0 + (k < no ? k : no - 1)];
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int j = lane + 64 * c;
-      x[c] = 0.0;
+      const int jc = j < N ? j : N - 1;
+      const int be = jc / B;
+      const int64_t g = (int64_t)sd[be] * B + (jc - be * B);
+      const double v = rho[g];
+      x[c] = j < N ? v : 0.0;
       acc[c] = 0.0;
-      if (j < N) {
-        const int be = j / B;
-        x[c] = rho[(int64_t)sd[be] * B + (j - be * B)];
+      gi[c] = g;
+      own[c] = false;
+    }
+    // ownership of this lane's DoFs: compare their spatial index with the
+    // cell's owned list (broadcast entry by entry)
+    for (int k = 0; k < no; ++k) {
+      int a = __builtin_amdgcn_readlane(ol[0], k & 63);
+      if constexpr (NOC > 1) {
+        const int a1 = __builtin_amdgcn_readlane(ol[NOC - 1], k & 63);
+        a = k < 64 ? a : a1;
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int o = lane + 64 * c;
+        own[c] = own[c] || (o < N && o / B == a);
       }
     }
 #pragma unroll
-    for (int cj = 0; cj < NC; ++cj) {
-      const int jn = (N - 64 * cj) < 64 ? (N - 64 * cj) : 64;
-      for (int jl = 0; jl < jn; ++jl) {
-        const double rj = __shfl(x[cj], jl, 64);
-        const TS* Ar = A + (int64_t)(64 * cj + jl) * ld;
+    for (int c = 0; c < NC; ++c) {
+      const double v = d[gi[c]];
+      dold[c] = zero_init ? 0.0 : v;
+    }
+#pragma unroll 1
+    for (int j0 = 0; j0 < N; j0 += U) {
+      TS a[U][NC];
+      double rj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u;
+        const int jr = j < N ? j : N - 1;
+        const unsigned ro = (unsigned)(jr * ld);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const int o = lane + 64 * c;
-          if (o < N) acc[c] = fma((double)Ar[o], rj, acc[c]);
+          a[u][c] = A[ro + (unsigned)(o < N ? o : N - 1)];
         }
-      }
-    }
-    for (int os = 0; os < no; ++os) {
-      const int alpha = own_loc[o0 + os];
+        // rho_j from its lane (chunk j / 64, uniform)
+        double r = readlane_f64(x[0], jr & 63);
 #pragma unroll
-      for (int l = 0; l < B; ++l) {
-        const int o = alpha * B + l;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (o == lane + 64 * c) {
-            const int64_t g = (int64_t)sd[alpha] * B + l;
-            d[g] = zero_init ? omega * acc[c] : fma(omega, acc[c], d[g]);
-          }
+        for (int c = 1; c < NC; ++c) {
+          const double rc = readlane_f64(x[c], jr & 63);
+          r = (jr >> 6) == c ? rc : r;
+        }
+        rj[u] = j < N ? r : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = fma((double)a[u][c], rj[u], acc[c]);
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (own[c]) d[gi[c]] = zero_init ? omega * acc[c] : fma(omega, acc[c], dold[c]);
   }
 }
 
