@@ -266,6 +266,257 @@ __attribute__((amdgpu_waves_per_eu((((B * NLS + 15) / 16) + 3) / 4, 8))) k_inver
   }
 }
 
+// Stores row r of the block (r uniform) into dst[0 .. 16 NT): the lanes of
+// group r & 3 hold it in tile row r >> 4, register (r >> 2) & 3, one value
+// per tile column.  Each case stores from its own registers, so no
+// accumulator is ever selected by a run-time index (the empty asm statement
+// ending each case keeps the compiler from merging the cases into one store
+// of a run-time-indexed element, which would move the block to scratch).
+template <int NT>
+__device__ __forceinline__ void store_row(const stv_d4 (&acc)[NT][NT], int r, double* dst, int lr,
+                                          int lc) {
+  if (lr != (r & 3)) return;
+  switch (r >> 2) {
+#define STV_ROW_CASE(S)                                                                     \
+  case S:                                                                                   \
+    if constexpr (S < 4 * NT) {                                                             \
+      _Pragma("unroll") for (int tj = 0; tj < NT; ++tj) dst[16 * tj + lc] = acc[S >> 2][tj][S & 3]; \
+      asm volatile("; row case %0" ::"n"(S));                                               \
+    }                                                                                       \
+    break;
+    STV_ROW_CASE(0) STV_ROW_CASE(1) STV_ROW_CASE(2) STV_ROW_CASE(3)
+    STV_ROW_CASE(4) STV_ROW_CASE(5) STV_ROW_CASE(6) STV_ROW_CASE(7)
+    STV_ROW_CASE(8) STV_ROW_CASE(9) STV_ROW_CASE(10) STV_ROW_CASE(11)
+    STV_ROW_CASE(12) STV_ROW_CASE(13) STV_ROW_CASE(14) STV_ROW_CASE(15)
+#undef STV_ROW_CASE
+    default: break;
+  }
+}
+
+// Pivot of one column with one candidate row per lane: the unused row of
+// largest magnitude, the lowest such row on ties; -1 when no unused row holds
+// a finite value.  Non-negative doubles order as their bit patterns, so the
+// high words are compared first (a DPP max of 32-bit keys) and the low words
+// only among the lanes that tie there.
+__device__ __forceinline__ int pivot_lane(double x, bool cand) {
+  const double ax = fabs(x);
+  const unsigned hi = (unsigned)__double2hiint(ax);
+  const unsigned key = (cand && ax == ax) ? hi + 1u : 0u;   // NaN and used rows: 0
+  const unsigned kmax = wave_max_u32(key);
+  if (kmax == 0u) return -1;
+  uint64_t tied = __builtin_amdgcn_ballot_w64(key == kmax);
+  if (tied & (tied - 1)) {
+    const unsigned lo = (unsigned)__double2loint(ax);
+    const unsigned lmax = wave_max_u32(key == kmax ? lo : 0u);
+    tied = __builtin_amdgcn_ballot_w64(key == kmax && lo == lmax);
+  }
+  return (int)__builtin_ctzll(tied);
+}
+
+// The same Gauss-Jordan inversion with one wavefront per cell, for orders up
+// to 64: the whole identity-padded block (NT x NT tiles) sits in this
+// wavefront's accumulators, so no step needs a workgroup barrier.  Per panel
+// of 4 columns:
+//  - the panel moves through LDS into one row per lane; its four pivots are
+//    chosen by pivot_lane and the pivot row is broadcast by readlane;
+//  - the four pivot rows as they were before the panel go to LDS; the panel
+//    columns take their eliminated values directly and see B = 0;
+//  - the rank-4 update A += W B is one MFMA per tile, the panel's own tile
+//    column first so that the next panel can start while the rest run.
+// The in-place result is permuted as in k_inverse_mfma.
+template <int B, int NLS>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ val,
+               const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
+               const int64_t* __restrict__ inv_off, int ld, void* store, int fp32,
+               uint8_t* status) {
+  constexpr int N = B * NLS;
+  constexpr int NT = (N + 15) / 16;
+  constexpr int NP = 16 * NT;
+  static_assert(NP <= 64, "one wavefront holds at most 64 rows");
+  __shared__ int spos[NLS * NLS];
+  __shared__ double panel[NP][4];
+  __shared__ double brow[4][NP];
+  __shared__ int rpiv[NP];
+  __shared__ int rinv[NP];
+  __shared__ int rowmap[NP];
+  const int lane = threadIdx.x;
+  const int lr = lane >> 4;
+  const int lc = lane & 15;
+  const int T = blockIdx.x;
+
+  // J_T: the cell's block positions through LDS, then every value load at
+  // once (indices clamped into the block, the padding and absent blocks
+  // selected afterwards)
+  {
+    constexpr int NPOS = NLS * NLS;
+    const int32_t* pos = posmap + (int64_t)T * NPOS;
+    int32_t q[(NPOS + 63) / 64];
+#pragma unroll
+    for (int i = 0; i < (NPOS + 63) / 64; ++i) {
+      const int e = lane + 64 * i;
+      q[i] = pos[e < NPOS ? e : NPOS - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < (NPOS + 63) / 64; ++i)
+      if (lane + 64 * i < NPOS) spos[lane + 64 * i] = q[i];
+  }
+  wave_lds_sync();
+  stv_d4 acc[NT][NT];
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * ti + 4 * v + lr;
+      const int rc = row < N ? row : N - 1;
+      const int ra = rc / B;
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const int col = 16 * tj + lc;
+        const int cc = col < N ? col : N - 1;
+        const int be = cc / B;
+        const int32_t q = spos[ra * NLS + be];
+        const double x =
+            val[(int64_t)(q > 0 ? q : 0) * (B * B) + (rc - ra * B) * B + (cc - be * B)];
+        // bitwise predicates and a value select: no branch for the load to
+        // sink into
+        const bool inb = (row < N) & (col < N);
+        const bool keep = inb & (q >= 0);
+        const double pad = ((!inb) & (row == col)) ? 1.0 : 0.0;
+        acc[ti][tj][v] = keep ? x : pad;
+      }
+    }
+  }
+
+  bool used = lane >= NP;   // this lane's row has been a pivot row
+  int mypiv = 0;            // lane p: pivot row of column p
+  bool sing = false;
+  const int prow = lane < NP ? lane : NP - 1;
+#pragma unroll
+  for (int tc = 0; tc < NT; ++tc) {
+#pragma unroll 1
+    for (int q4 = 0; q4 < 4; ++q4) {
+      const int c0 = 4 * q4;
+      const bool pcol = (unsigned)(lc - c0) < 4u;   // lane holds a panel column
+      // panel columns -> LDS, read back one row per lane
+      wave_lds_sync();
+      if (pcol) {
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) panel[16 * ti + 4 * v + lr][lc - c0] = acc[ti][tc][v];
+      }
+      wave_lds_sync();
+      double pv[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) pv[c] = panel[prow][c];
+      int rk[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        int r = pivot_lane(pv[t], !used);
+        if (r < 0) {   // no finite candidate (NaN column): lowest unused row
+          r = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(!used));
+          sing = true;
+        }
+        r = __builtin_amdgcn_readfirstlane(r);
+        double pr[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pr[c] = readlane_f64(pv[c], r);
+        const double piv = pr[t];
+        if (!(piv != 0.0)) sing = true;
+        const double ipiv = (piv != 0.0) ? 1.0 / piv : 0.0;
+        // pivot row: pr * ipiv (ipiv in column t); other rows: pv - f pr
+        // (-f in column t), both as fma(-g, pr, pv') with pv' = 0 in the
+        // pivot row
+        const bool me = lane == r;
+        const double g = me ? -ipiv : pv[t] * ipiv;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pv[c] = (c == t) ? -g : fma(-g, pr[c], me ? 0.0 : pv[c]);
+        used = used || me;
+        if (lane == 16 * tc + c0 + t) mypiv = r;
+        rk[t] = r;
+      }
+      // the pivot rows as they were before the panel
+#pragma unroll 1
+      for (int k = 0; k < 4; ++k) {
+        const int r = k == 0 ? rk[0] : k == 1 ? rk[1] : k == 2 ? rk[2] : rk[3];
+        store_row<NT>(acc, r, &brow[k][0], lr, lc);
+      }
+      if (lane < NP) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) panel[lane][c] = pv[c];
+      }
+      wave_lds_sync();
+      // W = (E - I)(:, pivot rows) and B in the operand layouts of the MFMA;
+      // the panel columns take the eliminated values and see B = 0
+      const int rsel = lr == 0 ? rk[0] : lr == 1 ? rk[1] : lr == 2 ? rk[2] : rk[3];
+      double a[NT], b[NT];
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        a[ti] = panel[16 * ti + lc][lr] - ((16 * ti + lc == rsel) ? 1.0 : 0.0);
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const double bv = brow[lr][16 * tj + lc];
+        b[tj] = (tj == tc && pcol) ? 0.0 : bv;
+      }
+      if (pcol) {
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[ti][tc][v] = panel[16 * ti + 4 * v + lr][lc - c0];
+      }
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        acc[ti][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tc], acc[ti][tc], 0, 0, 0);
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        if (tj == tc) continue;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+      }
+    }
+  }
+
+  // row of the inverse held by in-place row rho, owned rows, and the store
+  wave_lds_sync();
+  if (lane < NP) {
+    rpiv[lane] = mypiv;
+    rinv[mypiv] = lane;
+    rowmap[lane] = (full && lane < N) ? lane : -1;
+  }
+  wave_lds_sync();
+  if (!full) {
+    const int o0 = own_ptr[T], no = own_ptr[T + 1] - o0;
+    for (int e = lane; e < no * B; e += 64) {
+      const int os = e / B;
+      rowmap[own_loc[o0 + os] * B + (e - os * B)] = e;
+    }
+  }
+  if (lane == 0) status[T] = (uint8_t)sing;
+  wave_lds_sync();
+  const int64_t off = inv_off[T];
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) {
+    const int j = rpiv[16 * tj + lc];
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = rinv[16 * ti + 4 * v + lr];
+        if (p < N && j < N) {
+          const int o = rowmap[p];
+          if (o >= 0) {
+            const int64_t e = off + (int64_t)o * ld + j;
+            if (fp32) ((float*)store)[e] = (float)acc[ti][tj][v];
+            else ((double*)store)[e] = acc[ti][tj][v];
+          }
+        }
+      }
+    }
+  }
+}
+
 // Fallback for blocks too large for registers (n > 256): the same
 // elimination on a global scratch copy, one persistent workgroup per slot.
 __global__ void __launch_bounds__(256) k_inverse_global(
@@ -370,10 +621,16 @@ bool inverse_fits_regs(int b, int n_ls) {
 template <int B, int NLS>
 static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full, uint8_t* status) {
   constexpr int NT = (B * NLS + 15) / 16;
-  k_inverse_mfma<B, NLS><<<L.n_cells, NT * 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc,
+  if constexpr (NT <= 4) {
+    k_inverse_wave<B, NLS><<<L.n_cells, 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc, full,
+                                                   L.inv_off, L.inv_ld, L.inv_store, fp32, status);
+    return hipGetLastError();
+  } else {
+    k_inverse_mfma<B, NLS><<<L.n_cells, NT * 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc,
                                                        full, L.inv_off, L.inv_ld, L.inv_store, fp32,
-                                                       status);
-  return hipGetLastError();
+                                                         status);
+    return hipGetLastError();
+  }
 }
 
 hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,

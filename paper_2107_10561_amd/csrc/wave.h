@@ -47,4 +47,27 @@ __device__ __forceinline__ int wave_min_i32(int v) {
              min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
+// Maximum of unsigned 32-bit values over the 64 lanes, the same in every
+// lane (partner exchanges inside rows of 16, then readlane across rows).
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)dpp_i32<0xB1>((int)v));
+  v = max(v, (unsigned)dpp_i32<0x4E>((int)v));
+  v = max(v, (unsigned)dpp_i32<0x141>((int)v));
+  v = max(v, (unsigned)dpp_i32<0x140>((int)v));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// Orders the LDS accesses of one wavefront for the compiler: a store by one
+// lane before the call is seen by loads of any lane after it (a wavefront's
+// LDS instructions are processed in issue order, so no wait is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 }  // namespace stv
