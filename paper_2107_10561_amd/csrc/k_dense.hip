@@ -220,19 +220,19 @@ static hipError_t load_panel(hipStream_t s, int cnt, const double* A, int64_t sA
   return hipGetLastError();
 }
 
-// Pivot rows rpiv[p0..p0+nb) of A (n x n) before an update: Bbuf (nb x n).
+// Pivot rows rpiv[p0..p0+nb) of A (n x n) before an update: Bbuf (nb x n);
+// row t of the copy is blockIdx.y, so every load of the copy is independent.
 __global__ void k_gj_gather_rows(const double* __restrict__ A, int64_t sA, int64_t n, int p0,
-                                 int nb, const int* __restrict__ rpiv, int64_t sV,
+                                 const int* __restrict__ rpiv, int64_t sV,
                                  double* __restrict__ Bbuf, int64_t sB) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  const int t = blockIdx.y;
   A += blockIdx.z * sA;
   rpiv += blockIdx.z * sV;
   Bbuf += blockIdx.z * sB;
-  for (int t = 0; t < nb; ++t) {
-    const int r = rpiv[p0 + t];
-    Bbuf[(int64_t)t * n + j] = r >= 0 ? A[(int64_t)r * n + j] : 0.0;
-  }
+  const int r = rpiv[p0 + t];
+  Bbuf[(int64_t)t * n + j] = r >= 0 ? A[(int64_t)r * n + j] : 0.0;
 }
 
 // A(i, j) += sum_t (P(i, t) - [i == rpiv[p0+t]]) * Bbuf(t, j) for j outside the
@@ -480,8 +480,8 @@ static hipError_t gj_slab(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), 1, cnt), 256, 0, s>>>(
-        w.A, w.sA, n, (int)j0, NO, w.rpiv, w.sV, w.B, w.sB);
+    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, (int)j0, w.rpiv, w.sV, w.B, w.sB);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_gj_slab_update<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
@@ -804,8 +804,8 @@ static hipError_t gj_tour(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
           w.counter);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), 1, cnt), 256, 0, s>>>(
-        w.A, w.sA, n, (int)j0, NO, w.rpiv, w.sV, w.B, w.sB);
+    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, (int)j0, w.rpiv, w.sV, w.B, w.sB);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_gj_slab_update<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
         w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, sb[cs ^ 1],
@@ -894,7 +894,53 @@ __global__ void k_gj_unpermute(const double* __restrict__ S, int64_t sA, int64_t
   if (i >= n0 || j >= n0) return;
   const int* rp = rpiv + blockIdx.z * sV;
   const int* ri = rinv + blockIdx.z * sV;
-  out[D.inv_off + i * n0 + j] = S[blockIdx.z * sA + (int64_t)rp[i] * n + ri[j]];
+  const int r = rp[i], c = ri[j];   // -1 only in a record the verdict rejects
+  out[D.inv_off + i * n0 + j] =
+      (r >= 0 && c >= 0) ? S[blockIdx.z * sA + (int64_t)r * n + c] : __builtin_nan("");
+}
+
+// One workgroup per member: rinv <- -1, then rinv[rpiv[p]] = p for every
+// valid entry; a duplicate row, an entry outside [0, n) or a padding row
+// taken by a real column sets the member's verdict.
+__global__ void __launch_bounds__(1024) k_gj_invert_perm(const int* __restrict__ rpiv, int64_t sV,
+                                                         int64_t n,
+                                                         const CoarseDesc* __restrict__ desc,
+                                                         int b, int* __restrict__ rinv,
+                                                         int* __restrict__ verdict) {
+  __shared__ int bad;
+  const int z = blockIdx.x;
+  const int64_t n0 = (int64_t)desc[z].n_s * b;
+  const int* rp = rpiv + z * sV;
+  int* ri = rinv + z * sV;
+  if (threadIdx.x == 0) bad = 0;
+  for (int64_t p = threadIdx.x; p < n; p += blockDim.x) ri[p] = -1;
+  __syncthreads();
+  for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
+    const int r = rp[p];
+    bool ok = r >= 0 && r < n && !(p < n0 && r >= n0);
+    if (ok) ok = atomicCAS(&ri[r], -1, (int)p) == -1;
+    if (!ok) atomicOr(&bad, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) verdict[z] = bad;
+}
+
+hipError_t launch_gj_invert_perm(hipStream_t s, const int* rpiv, int64_t sV, int64_t n,
+                                 const CoarseDesc* desc, int cnt, int b, int* rinv,
+                                 int* verdict) {
+  k_gj_invert_perm<<<(unsigned)cnt, 1024, 0, s>>>(rpiv, sV, n, desc, b, rinv, verdict);
+  return hipGetLastError();
+}
+
+__global__ void k_first_flag(const uint8_t* __restrict__ flag, int64_t n, int* out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && flag[c]) atomicMin(out, (int)c);
+}
+
+hipError_t launch_first_flag(hipStream_t s, const uint8_t* flag, int64_t n, int* out) {
+  if (n <= 0) return hipSuccess;
+  k_first_flag<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(flag, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t sA, int64_t n,

@@ -74,6 +74,19 @@ void free_graph(stv_ctx* ctx) {
   dfree(ctx->g_out);
 }
 
+void free_coarse_groups(stv_ctx* ctx) {
+  for (auto& G : ctx->cgroups) {
+    dfree(G.d_desc); dfree(G.w.A); dfree(G.w.rpiv); dfree(G.w.used); dfree(G.w.B);
+    dfree(G.w.P); dfree(G.w.S); dfree(G.w.Bin); dfree(G.rinv);
+    dfree(G.w.cand); dfree(G.w.Z); dfree(G.w.counter);
+  }
+  ctx->cgroups.clear();
+  ctx->cgroups_algo = -1;
+  dfree(ctx->coarse_inv);
+  ctx->coarse_elems = 0;
+}
+
+// Every stored inverse and the whole inverse-build workspace.
 void free_inverses(stv_ctx* ctx) {
   ++ctx->generation;
   free_graph(ctx);
@@ -81,9 +94,16 @@ void free_inverses(stv_ctx* ctx) {
     dfree(ctx->lv[g].inv_off);
     dfree(ctx->lv[g].inv_store);
     ctx->lv[g].inv_elems = 0;
+    dfree(ctx->inv_status[g]);
+    dfree(ctx->inv_scratch[g]);
+    ctx->inv_slots[g] = 0;
   }
-  dfree(ctx->coarse_inv);
-  ctx->coarse_elems = 0;
+  ctx->inv_layout = ctx->inv_type = -1;
+  free_coarse_groups(ctx);
+  dfree(ctx->inv_report);
+  if (ctx->h_report) (void)hipHostFree(ctx->h_report);
+  ctx->h_report = nullptr;
+  ctx->n_report = 0;
   ctx->have_inv = false;
 }
 
@@ -863,38 +883,11 @@ int stv_set_batch(stv_ctx* ctx, int n_inst, int dim, int k, const int* n_levels,
   return setup_packed(ctx, n_inst, dim, k, n_levels, levels);
 }
 
-int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_cell) {
-  STV_TRY(check_ctx(ctx, true, false));
-  if (bad_level) *bad_level = -1;
-  if (bad_cell) *bad_cell = -1;
-  const int fp32 = storage & STV_F32;
-  const int full = (storage & STV_STORE_FULL) ? 1 : 0;
-  if (storage & ~(STV_F32 | STV_STORE_FULL)) return fail(ctx, STV_EINVAL, "unknown storage flags");
-  STV_HIP(hipSetDevice(ctx->device));
-  STV_HIP(hipStreamSynchronize(ctx->stream));
-  free_inverses(ctx);
-  ctx->inv_fp32 = fp32;
-  ctx->inv_full = full;
+// Coarse members grouped by order (one batched elimination per group), their
+// buffers, the coarse inverse store and the member descriptors.
+static int make_coarse_groups(stv_ctx* ctx) {
   const int b = ctx->b;
-  hipStream_t s = ctx->stream;
-  // the coarse factorisations run on the internal stream, overlapping the
-  // cell inverses, or on the caller's stream ahead of them
-  hipStream_t side = ctx->coarse_overlap ? ctx->side : ctx->stream;
-  // ---- cell inverse storage (host-side offsets of every cell's stored rows)
-  std::vector<uint8_t*> status((size_t)ctx->n_levels, nullptr);
-  std::vector<double*> scratch((size_t)ctx->n_levels, nullptr);
-  std::vector<int> slots((size_t)ctx->n_levels, 0);
-  // ---- coarse members grouped by order: one batched elimination per group
-  struct Member { int g; int idx; int64_t n0; };
-  struct Group {
-    int64_t n0 = 0, np = 0;
-    GjPlan plan{};
-    std::vector<Member> mem;
-    CoarseDesc* d_desc = nullptr;
-    GjWork w{};
-    int* rinv = nullptr;
-  };
-  std::vector<Group> groups;
+  std::vector<CoarseGroup>& groups = ctx->cgroups;
   int64_t coarse_total = 0;
   for (int g = 0; g < ctx->n_levels; ++g)
     for (size_t q = 0; q < ctx->h_coarse[g].size(); ++q) {
@@ -908,20 +901,65 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
         groups.emplace_back();
         groups.back().n0 = n0;
       }
-      groups[gi].mem.push_back({g, (int)q, n0});
+      groups[gi].lev.push_back(g);
+      groups[gi].idx.push_back((int)q);
     }
-  auto cleanup = [&]() {
-    for (auto& p : status) dfree(p);
-    for (auto& p : scratch) dfree(p);
-    for (auto& G : groups) {
-      dfree(G.d_desc); dfree(G.w.A); dfree(G.w.rpiv); dfree(G.w.used); dfree(G.w.B);
-      dfree(G.w.P); dfree(G.w.S); dfree(G.w.Bin); dfree(G.rinv);
-      dfree(G.w.cand); dfree(G.w.Z); dfree(G.w.counter);
+  ctx->coarse_elems = coarse_total;
+  STV_TRY(dalloc(ctx, &ctx->coarse_inv, (size_t)coarse_total));
+  for (auto& G : groups) {
+    G.plan = gj_plan(G.n0, ctx->coarse_algo);
+    G.np = (G.n0 + G.plan.pad - 1) / G.plan.pad * G.plan.pad;
+    if (G.np > G.plan.max_n)
+      return fail(ctx, STV_EINVAL, "coarse level larger than " + std::to_string(G.plan.max_n) + " unknowns");
+    const int64_t cnt = (int64_t)G.lev.size(), np = G.np;
+    const int64_t nbo = std::max(G.plan.nb, G.plan.no);
+    GjWork& w = G.w;
+    w = GjWork{};
+    w.sA = np * np;
+    w.sV = np;
+    w.sB = nbo * np;
+    w.sP = 2 * G.plan.nb * np;
+    w.sS = 2 * (int64_t)G.plan.no * np;
+    w.sBin = (int64_t)G.plan.nb * G.plan.no;
+    std::vector<CoarseDesc> hd;
+    for (size_t m = 0; m < G.lev.size(); ++m) hd.push_back(ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]]);
+    STV_TRY(upload(ctx, &G.d_desc, hd.data(), hd.size()));
+    STV_TRY(dalloc(ctx, &w.A, (size_t)(cnt * w.sA)));
+    STV_TRY(dalloc(ctx, &w.rpiv, (size_t)(cnt * w.sV)));
+    STV_TRY(dalloc(ctx, &w.used, (size_t)(cnt * w.sV)));
+    STV_TRY(dalloc(ctx, &w.B, (size_t)(cnt * w.sB)));
+    STV_TRY(dalloc(ctx, &w.P, (size_t)(cnt * w.sP)));
+    STV_TRY(dalloc(ctx, &G.rinv, (size_t)(cnt * w.sV)));
+    if (G.plan.no > 0) {
+      STV_TRY(dalloc(ctx, &w.S, (size_t)(cnt * w.sS)));
+      STV_TRY(dalloc(ctx, &w.Bin, (size_t)(cnt * w.sBin)));
     }
-  };
-  int rc = STV_OK;
-  for (int g = 0; g < ctx->n_levels && rc == STV_OK; ++g) {
+    if (G.plan.algo == 3) {
+      w.sC = (np + 255) / 256 * G.plan.nb;
+      w.sZ = 2 * (int64_t)G.plan.nb * G.plan.no;
+      STV_TRY(dalloc(ctx, &w.cand, (size_t)(cnt * w.sC)));
+      STV_TRY(dalloc(ctx, &w.Z, (size_t)(cnt * w.sZ)));
+      STV_TRY(dalloc(ctx, &w.counter, (size_t)cnt));
+    }
+  }
+  // device descriptors of the members per level (inverse offsets now known)
+  for (int g = 0; g < ctx->n_levels; ++g) {
+    dfree(ctx->d_coarse[g]);
+    if (!ctx->h_coarse[g].empty())
+      STV_TRY(upload(ctx, &ctx->d_coarse[g], ctx->h_coarse[g].data(), ctx->h_coarse[g].size()));
+  }
+  return STV_OK;
+}
+
+// Stores of every cell's inverse rows for a layout (all rows or the owned
+// rows) and element type: per-level row offsets and the store itself.
+static int make_inverse_stores(stv_ctx* ctx, int fp32, int full) {
+  const int b = ctx->b;
+  for (int g = 0; g < ctx->n_levels; ++g) {
     DevLevel& L = ctx->lv[g];
+    dfree(L.inv_off);
+    dfree(L.inv_store);
+    L.inv_elems = 0;
     if (L.n_cells == 0) continue;
     const int n = L.n_ls * b;
     // rows stored densely (padding each row to a 128-byte boundary was
@@ -934,102 +972,125 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
       const int rows = full ? n : (L.h_own_ptr[(size_t)c + 1] - L.h_own_ptr[(size_t)c]) * b;
       tot += (int64_t)rows * L.inv_ld;
     }
-    if ((rc = upload(ctx, &L.inv_off, off.data(), off.size())) != STV_OK) break;
+    STV_TRY(upload(ctx, &L.inv_off, off.data(), off.size()));
     if (fp32) {
       float* p = nullptr;
-      rc = dalloc(ctx, &p, (size_t)tot);
+      STV_TRY(dalloc(ctx, &p, (size_t)tot));
       L.inv_store = p;
     } else {
       double* p = nullptr;
-      rc = dalloc(ctx, &p, (size_t)tot);
+      STV_TRY(dalloc(ctx, &p, (size_t)tot));
       L.inv_store = p;
     }
-    if (rc != STV_OK) break;
     L.inv_elems = tot;
-    if ((rc = dalloc(ctx, &status[(size_t)g], (size_t)L.n_cells)) != STV_OK) break;
-    if (!inverse_fits_regs(b, L.n_ls)) {
-      slots[(size_t)g] = std::min<int>(L.n_cells, 1024);
-      rc = dalloc(ctx, &scratch[(size_t)g], (size_t)slots[(size_t)g] * n * n);
-    }
   }
-  if (rc == STV_OK) {
-    ctx->coarse_elems = coarse_total;
-    rc = dalloc(ctx, &ctx->coarse_inv, (size_t)coarse_total);
-  }
-  for (auto& G : groups) {
-    if (rc != STV_OK) break;
-    G.plan = gj_plan(G.n0, ctx->coarse_algo);
-    G.np = (G.n0 + G.plan.pad - 1) / G.plan.pad * G.plan.pad;
-    if (G.np > G.plan.max_n) {
-      rc = fail(ctx, STV_EINVAL, "coarse level larger than " + std::to_string(G.plan.max_n) + " unknowns");
-      break;
+  return STV_OK;
+}
+
+int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_cell) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (bad_level) *bad_level = -1;
+  if (bad_cell) *bad_cell = -1;
+  const int fp32 = storage & STV_F32;
+  const int full = (storage & STV_STORE_FULL) ? 1 : 0;
+  if (storage & ~(STV_F32 | STV_STORE_FULL)) return fail(ctx, STV_EINVAL, "unknown storage flags");
+  STV_HIP(hipSetDevice(ctx->device));
+  STV_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->side) STV_HIP(hipStreamSynchronize(ctx->side));
+  ctx->have_inv = false;
+  const int b = ctx->b;
+  hipStream_t s = ctx->stream;
+  // the coarse factorisations run on the internal stream, overlapping the
+  // cell inverses, or on the caller's stream ahead of them
+  hipStream_t side = ctx->coarse_overlap ? ctx->side : ctx->stream;
+
+  // ---- workspace: made on the first build of a hierarchy and whenever the
+  // layout, the element type or the coarse algorithm changes; a captured
+  // V-cycle is dropped only when a buffer it reads moved
+  int rc = STV_OK;
+  bool moved = false;
+  if (ctx->inv_layout != full || ctx->inv_type != fp32) {
+    ctx->inv_layout = ctx->inv_type = -1;
+    rc = make_inverse_stores(ctx, fp32, full);
+    if (rc == STV_OK) {
+      ctx->inv_layout = full;
+      ctx->inv_type = fp32;
     }
-    const int64_t cnt = (int64_t)G.mem.size(), np = G.np;
-    const int64_t nbo = std::max(G.plan.nb, G.plan.no);
-    GjWork& w = G.w;
-    w.sA = np * np;
-    w.sV = np;
-    w.sB = nbo * np;
-    w.sP = 2 * G.plan.nb * np;
-    w.sS = 2 * (int64_t)G.plan.no * np;
-    w.sBin = (int64_t)G.plan.nb * G.plan.no;
-    std::vector<CoarseDesc> hd;
-    for (const Member& m : G.mem) hd.push_back(ctx->h_coarse[m.g][(size_t)m.idx]);
-    if ((rc = upload(ctx, &G.d_desc, hd.data(), hd.size())) != STV_OK ||
-        (rc = dalloc(ctx, &w.A, (size_t)(cnt * w.sA))) != STV_OK ||
-        (rc = dalloc(ctx, &w.rpiv, (size_t)(cnt * w.sV))) != STV_OK ||
-        (rc = dalloc(ctx, &w.used, (size_t)(cnt * w.sV))) != STV_OK ||
-        (rc = dalloc(ctx, &w.B, (size_t)(cnt * w.sB))) != STV_OK ||
-        (rc = dalloc(ctx, &w.P, (size_t)(cnt * w.sP))) != STV_OK ||
-        (rc = dalloc(ctx, &G.rinv, (size_t)(cnt * w.sV))) != STV_OK)
-      break;
-    if (G.plan.no > 0 && ((rc = dalloc(ctx, &w.S, (size_t)(cnt * w.sS))) != STV_OK ||
-                          (rc = dalloc(ctx, &w.Bin, (size_t)(cnt * w.sBin))) != STV_OK))
-      break;
-    if (G.plan.algo == 3) {
-      w.sC = (np + 255) / 256 * G.plan.nb;
-      w.sZ = 2 * (int64_t)G.plan.nb * G.plan.no;
-      if ((rc = dalloc(ctx, &w.cand, (size_t)(cnt * w.sC))) != STV_OK ||
-          (rc = dalloc(ctx, &w.Z, (size_t)(cnt * w.sZ))) != STV_OK ||
-          (rc = dalloc(ctx, &w.counter, (size_t)cnt)) != STV_OK)
-        break;
-    }
+    moved = true;
   }
-  // device descriptors of the members per level (inverse offsets now known)
   for (int g = 0; g < ctx->n_levels && rc == STV_OK; ++g) {
-    dfree(ctx->d_coarse[g]);
-    if (!ctx->h_coarse[g].empty())
-      rc = upload(ctx, &ctx->d_coarse[g], ctx->h_coarse[g].data(), ctx->h_coarse[g].size());
+    const DevLevel& L = ctx->lv[g];
+    if (L.n_cells == 0 || ctx->inv_status[g]) continue;
+    rc = dalloc(ctx, &ctx->inv_status[g], (size_t)L.n_cells);
+    if (rc == STV_OK && !inverse_fits_regs(b, L.n_ls)) {
+      ctx->inv_slots[g] = std::min<int>(L.n_cells, 1024);
+      rc = dalloc(ctx, &ctx->inv_scratch[g], (size_t)ctx->inv_slots[g] * L.n_ls * b * L.n_ls * b);
+    }
+  }
+  if (rc == STV_OK && ctx->cgroups_algo != ctx->coarse_algo) {
+    free_coarse_groups(ctx);
+    rc = make_coarse_groups(ctx);
+    if (rc == STV_OK) ctx->cgroups_algo = ctx->coarse_algo;
+    moved = true;
+  }
+  int members = 0;
+  for (const auto& G : ctx->cgroups) members += (int)G.lev.size();
+  const int nrep = ctx->n_levels + members;
+  if (rc == STV_OK && ctx->n_report != nrep) {
+    dfree(ctx->inv_report);
+    if (ctx->h_report) (void)hipHostFree(ctx->h_report);
+    ctx->h_report = nullptr;
+    ctx->n_report = 0;
+    rc = dalloc(ctx, &ctx->inv_report, (size_t)nrep);
+    if (rc == STV_OK &&
+        hipHostMalloc((void**)&ctx->h_report, sizeof(int) * (size_t)nrep, hipHostMallocDefault) !=
+            hipSuccess) {
+      ctx->h_report = nullptr;
+      rc = fail(ctx, STV_ENOMEM, "pinned host allocation of the build report failed");
+    }
+    if (rc == STV_OK) ctx->n_report = nrep;
   }
   if (rc != STV_OK) {
-    cleanup();
     free_inverses(ctx);
     return rc;
   }
+  if (moved) {
+    ++ctx->generation;
+    free_graph(ctx);
+  }
+  ctx->inv_fp32 = fp32;
+  ctx->inv_full = full;
+
   // ---- launch: cell inverses on the caller's stream, coarse factorisations
-  // on the internal stream (it starts after everything queued before it)
-  hipError_t e = hipSuccess;
+  // on the internal stream (it starts after everything queued before it);
+  // the report starts at 0x7f7f7f7f ("no flagged cell") per level
+  int* rep = ctx->inv_report;
+  hipError_t e = hipMemsetAsync(rep, 0x7f, sizeof(int) * (size_t)nrep, s);
   hipStream_t inv = s;
-  if (side != s) {
+  if (e == hipSuccess && side != s) {
     e = hipEventRecord(ctx->ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
   }
   auto cell_inverses = [&]() {
     for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
-      if (ctx->lv[g].n_cells == 0) continue;
+      const DevLevel& L = ctx->lv[g];
+      if (L.n_cells == 0) continue;
       Timed t(ctx, KC_INVERSE, g, inv);
-      e = launch_cell_inverses(inv, b, ctx->lv[g], fp32, full, status[(size_t)g],
-                               scratch[(size_t)g], slots[(size_t)g]);
+      e = launch_cell_inverses(inv, b, L, fp32, full, ctx->inv_status[g], ctx->inv_scratch[g],
+                               ctx->inv_slots[g]);
+      if (e == hipSuccess) e = launch_first_flag(inv, ctx->inv_status[g], L.n_cells, rep + g);
       t.done();
     }
   };
   if (side != s) cell_inverses();
-  for (auto& G : groups) {
+  int mbase = ctx->n_levels;
+  for (auto& G : ctx->cgroups) {
     if (e != hipSuccess) break;
     Timed t(ctx, KC_COARSE_FACTOR, 0, side);
-    const int cnt = (int)G.mem.size();
+    const int cnt = (int)G.lev.size();
     int32_t max_rows = 0;
-    for (const Member& m : G.mem) max_rows = std::max(max_rows, ctx->h_coarse[m.g][(size_t)m.idx].n_s);
+    for (size_t m = 0; m < G.lev.size(); ++m)
+      max_rows = std::max(max_rows, ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]].n_s);
     e = launch_fill(side, G.w.A, cnt * G.w.sA, 0.0);
     if (e == hipSuccess) e = launch_bsr_to_dense(side, b, G.d_desc, cnt, max_rows, G.w.A, G.w.sA, G.np);
     if (e == hipSuccess) e = launch_set_diag(side, G.d_desc, cnt, b, G.w.A, G.w.sA, G.np);
@@ -1037,41 +1098,15 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (e == hipSuccess && G.w.counter)
       e = hipMemsetAsync(G.w.counter, 0, sizeof(unsigned) * (size_t)cnt, side);
     if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt);
-    t.done();
-  }
-  // pivot records -> inverse permutations (host), then the unpermuted inverses
-  bool coarse_singular = false;
-  int sing_level = -1;
-  std::vector<std::vector<int>> rinvs(groups.size());
-  for (size_t gi = 0; gi < groups.size() && e == hipSuccess && !coarse_singular; ++gi) {
-    Group& G = groups[gi];
-    const int cnt = (int)G.mem.size();
-    std::vector<int> hp((size_t)(cnt * G.w.sV));
-    e = hipMemcpyAsync(hp.data(), G.w.rpiv, sizeof(int) * hp.size(), hipMemcpyDeviceToHost, side);
-    if (e == hipSuccess) e = hipStreamSynchronize(side);
-    if (e != hipSuccess) break;
-    std::vector<int>& rv = rinvs[gi];
-    rv.assign(hp.size(), -1);
-    for (int z = 0; z < cnt && !coarse_singular; ++z) {
-      const int* pz = hp.data() + (size_t)z * G.w.sV;
-      int* rz = rv.data() + (size_t)z * G.w.sV;
-      for (int64_t p = 0; p < G.np; ++p) {
-        const int r = pz[p];
-        if (r < 0 || r >= G.np || rz[r] >= 0) { coarse_singular = true; break; }
-        rz[r] = (int)p;
-      }
-      // the real block must pivot within itself (the padding is an identity)
-      for (int64_t p = 0; p < G.n0 && !coarse_singular; ++p)
-        if (pz[p] >= G.n0) coarse_singular = true;
-      if (coarse_singular) sing_level = G.mem[(size_t)z].g;
-    }
-    if (coarse_singular) break;
-    Timed t(ctx, KC_COARSE_FACTOR, 0, side);
-    e = hipMemcpyAsync(G.rinv, rv.data(), sizeof(int) * rv.size(), hipMemcpyHostToDevice, side);
+    // pivot records -> inverse permutations and verdicts, then the
+    // unpermuted inverses
     if (e == hipSuccess)
-      e = launch_gj_unpermute(side, G.w.A, G.w.sA, G.np, G.w.rpiv, G.rinv, G.w.sV, G.d_desc, cnt, b,
-                              G.n0, ctx->coarse_inv);
+      e = launch_gj_invert_perm(side, G.w.rpiv, G.w.sV, G.np, G.d_desc, cnt, b, G.rinv, rep + mbase);
+    if (e == hipSuccess)
+      e = launch_gj_unpermute(side, G.w.A, G.w.sA, G.np, G.w.rpiv, G.rinv, G.w.sV, G.d_desc, cnt,
+                              b, G.n0, ctx->coarse_inv);
     t.done();
+    mbase += cnt;
   }
   if (side == s) {
     cell_inverses();
@@ -1079,39 +1114,36 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
   }
-  std::vector<std::vector<uint8_t>> hs((size_t)ctx->n_levels);
-  for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
-    if (ctx->lv[g].n_cells == 0) continue;
-    hs[(size_t)g].resize((size_t)ctx->lv[g].n_cells);
-    e = hipMemcpyAsync(hs[(size_t)g].data(), status[(size_t)g], hs[(size_t)g].size(),
-                       hipMemcpyDeviceToHost, s);
-  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->h_report, rep, sizeof(int) * (size_t)nrep, hipMemcpyDeviceToHost, s);
   {
-    // both streams drain before any buffer is released, on every path (the
-    // host permutations outlive their copies)
+    // both streams drain on every path
     const hipError_t e1 = hipStreamSynchronize(s);
     const hipError_t e2 = hipStreamSynchronize(side);
     if (e == hipSuccess) e = (e1 != hipSuccess) ? e1 : e2;
   }
-  cleanup();
   if (e != hipSuccess) {
     free_inverses(ctx);
     return fail(ctx, STV_EHIP, std::string("inverse build failed: ") + hipGetErrorString(e));
   }
+  const int none = 0x7f7f7f7f;
   for (int g = 1; g < ctx->n_levels; ++g)
-    for (int32_t c = 0; c < (int32_t)hs[(size_t)g].size(); ++c)
-      if (hs[(size_t)g][(size_t)c]) {
-        if (bad_level) *bad_level = g;
-        if (bad_cell) *bad_cell = c;
-        free_inverses(ctx);
+    if (ctx->lv[g].n_cells > 0 && ctx->h_report[g] != none) {
+      if (bad_level) *bad_level = g;
+      if (bad_cell) *bad_cell = ctx->h_report[g];
+      return fail(ctx, STV_ESINGULAR, "zero pivot in J_T of level " + std::to_string(g) +
+                                          " cell " + std::to_string(ctx->h_report[g]));
+    }
+  mbase = ctx->n_levels;
+  for (const auto& G : ctx->cgroups) {
+    for (size_t m = 0; m < G.lev.size(); ++m)
+      if (ctx->h_report[mbase + (int)m] != 0) {
+        if (bad_level) *bad_level = G.lev[m];
+        if (bad_cell) *bad_cell = -1;
         return fail(ctx, STV_ESINGULAR,
-                    "zero pivot in J_T of level " + std::to_string(g) + " cell " + std::to_string(c));
+                    "zero pivot in a coarse matrix (level " + std::to_string(G.lev[m]) + ")");
       }
-  if (coarse_singular) {
-    if (bad_level) *bad_level = sing_level;
-    if (bad_cell) *bad_cell = -1;
-    free_inverses(ctx);
-    return fail(ctx, STV_ESINGULAR, "zero pivot in a coarse matrix (level " + std::to_string(sing_level) + ")");
+    mbase += (int)G.lev.size();
   }
   ctx->have_inv = true;
   return STV_OK;

@@ -97,6 +97,24 @@ struct GjWork {
   unsigned* counter;
 };
 
+// Dense Gauss-Jordan plan: algo 1 = one level of panels (width nb), 2 = slabs
+// of no columns eliminated by panels of nb, 3 = slabs whose panels take
+// tournament-chosen pivot rows; the matrix is padded to a multiple of pad;
+// max_n is the largest supported order.
+struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; };
+
+// The coarse members of one order, eliminated by one batched Gauss-Jordan:
+// members (packed level, index in that level), their device descriptors,
+// the elimination buffers and the inverse pivot permutations.
+struct CoarseGroup {
+  int64_t n0 = 0, np = 0;
+  GjPlan plan{};
+  std::vector<int> lev, idx;
+  CoarseDesc* d_desc = nullptr;
+  GjWork w{};
+  int* rinv = nullptr;
+};
+
 // Results of the last solve for one instance.
 struct InstInfo { int iters = 0, restarts = 0, converged = 0; double relres = 0.0; };
 
@@ -130,6 +148,20 @@ struct stv_ctx {
   int64_t coarse_max_n0[stv::kMaxLevels] = {};
   double* coarse_inv = nullptr;       // every member's inverse
   int64_t coarse_elems = 0;
+  // inverse-build workspace, kept between builds of one hierarchy: the
+  // store layout it was made for (full rows or owned rows, element type),
+  // per-level cell statuses and scratch, the coarse groups (for the coarse
+  // algorithm in cgroups_algo) and the report block (first flagged cell per
+  // level, then one verdict per coarse member) with its pinned host mirror
+  int inv_layout = -1, inv_type = -1;
+  uint8_t* inv_status[stv::kMaxLevels] = {};
+  double* inv_scratch[stv::kMaxLevels] = {};
+  int inv_slots[stv::kMaxLevels] = {};
+  std::vector<stv::CoarseGroup> cgroups;
+  int cgroups_algo = -1;
+  int* inv_report = nullptr;
+  int* h_report = nullptr;
+  int n_report = 0;
   int coarse_algo = 0;          // STV_OPT_COARSE_ALGO
   int coarse_overlap = 1;       // STV_OPT_COARSE_OVERLAP
   int64_t scal_segs = 0;        // instances the scalar buffers are sized for
@@ -205,15 +237,19 @@ hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 // dense coarse level
 hipError_t launch_bsr_to_dense(hipStream_t s, int b, const CoarseDesc* desc, int cnt,
                                int32_t max_rows, double* A, int64_t sA, int64_t n);
-// Dense Gauss-Jordan plan: algo 1 = one level of panels (width nb), 2 = slabs
-// of no columns eliminated by panels of nb, 3 = slabs whose panels take
-// tournament-chosen pivot rows; the matrix is padded to a multiple of pad;
-// max_n is the largest supported order.
-struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; };
 GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */);
 hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt);
 hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b, double* A,
                            int64_t sA, int64_t n);
+// rinv = the inverse of every member's pivot record rpiv (order n, real
+// order n0 from desc); verdict[z] = 0 when member z's record is a
+// permutation whose real columns pivot on real rows, else 1.
+hipError_t launch_gj_invert_perm(hipStream_t s, const int* rpiv, int64_t sV, int64_t n,
+                                 const CoarseDesc* desc, int cnt, int b, int* rinv,
+                                 int* verdict);
+// out[0] = the lowest index c < n with flag[c] != 0 (out[0] keeps its value
+// when it is lower or no flag is set)
+hipError_t launch_first_flag(hipStream_t s, const uint8_t* flag, int64_t n, int* out);
 hipError_t launch_gj_unpermute(hipStream_t s, const double* S, int64_t sA, int64_t n,
                                const int* rpiv, const int* rinv, int64_t sV,
                                const CoarseDesc* desc, int cnt, int b, int64_t max_n0,
