@@ -346,6 +346,16 @@ int stv_autotune(stv_ctx* ctx, int* choices, int cap);
  * apply, 4 = Krylov vector kernels, 5 = cell inverse build, 6 = coarse
  * factorisation, 7 = V-cycle graph replay.  Synchronises the stream. */
 int stv_set_timing(stv_ctx* ctx, int on);
+
+/* Restricts the recording to the kernel classes whose bit (1 << class) is
+ * set in class_mask and to the levels whose bit (1 << level) is set in
+ * level_mask (default: all of both; launches not tied to a level count as
+ * level 0).  Launches of the sweep, residual, transfer and coarse-apply
+ * classes are timed by the kernel's own start and end stamps
+ * (hipExtLaunchKernel events), the other classes by event records around
+ * them.  Synchronises the stream.  Errors: STV_EINVAL (a class bit beyond
+ * the last class). */
+int stv_set_timing_filter(stv_ctx* ctx, unsigned class_mask, unsigned level_mask);
 int stv_kernel_stats(stv_ctx* ctx, int kernel_class, int level, int64_t* launches,
                      double* total_ms);
 

@@ -85,6 +85,7 @@ def _load():
         "stv_get_cell_inverse": (I, [P, I, I, P]),
         "stv_level_info": (I, [P, I, I64P, I64P, I64P, I64P]),
         "stv_set_timing": (I, [P, I]),
+        "stv_set_timing_filter": (I, [P, ctypes.c_uint, ctypes.c_uint]),
         "stv_set_option": (I, [P, I, ctypes.c_int64]),
         "stv_set_batch": (I, [P, I, I, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.POINTER(_Level))]),
         "stv_instance_layout": (I, [P, I, ctypes.POINTER(I), I64P, I64P]),
@@ -114,7 +115,7 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_kernel_stats", "stv_set_option", "stv_set_batch", "stv_instance_layout",
             "stv_instance_info", "stv_set_launch", "stv_autotune", "stv_vcycle_transposed",
             "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot",
-            "stv_set_kron_factors")
+            "stv_set_kron_factors", "stv_set_timing_filter")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2, "tournament": 3}
 
@@ -406,7 +407,13 @@ class Solver:
         """Replay the V-cycle from a captured HIP graph (identical results)."""
         self._check(_lib.stv_set_option(self._h, 2, int(bool(on))))
 
-    def set_timing(self, on: bool):
+    def set_timing(self, on: bool, classes=None, levels=None):
+        """Per-kernel timing on or off; classes (names of KERNEL_CLASSES) and
+        levels (indices) restrict what is recorded (None: all)."""
+        cmask = (1 << len(KERNEL_CLASSES)) - 1 if classes is None else \
+            sum(1 << KERNEL_CLASSES[c] for c in classes)
+        lmask = 0xFFFFFFFF if levels is None else sum(1 << g for g in levels)
+        self._check(_lib.stv_set_timing_filter(self._h, cmask, lmask))
         self._check(_lib.stv_set_timing(self._h, int(on)))
 
     def kernel_stats(self, name: str, level: int = -1):

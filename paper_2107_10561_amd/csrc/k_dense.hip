@@ -996,7 +996,7 @@ hipError_t launch_dense_gemv_t(hipStream_t s, const CoarseDesc* desc, int cnt, i
                                int64_t max_n0, const double* inv, const double* x, double* y) {
   if (cnt < 1) return hipSuccess;
   dim3 grid((unsigned)((max_n0 + 255) / 256), 1, (unsigned)cnt);
-  k_dense_gemv_t<<<grid, 256, 0, s>>>(desc, b, inv, x, y);
+  launch(k_dense_gemv_t, dim3(grid), dim3(256), 0, s, desc, b, inv, x, y);
   return hipGetLastError();
 }
 
@@ -1004,7 +1004,7 @@ hipError_t launch_dense_gemv(hipStream_t s, const CoarseDesc* desc, int cnt, int
                              int64_t max_n0, const double* inv, const double* x, double* y) {
   if (cnt < 1) return hipSuccess;
   dim3 grid((unsigned)((max_n0 + 3) / 4), 1, (unsigned)cnt);
-  k_dense_gemv<<<grid, 256, 0, s>>>(desc, b, inv, x, y);
+  launch(k_dense_gemv, dim3(grid), dim3(256), 0, s, desc, b, inv, x, y);
   return hipGetLastError();
 }
 

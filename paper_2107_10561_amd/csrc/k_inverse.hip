@@ -293,26 +293,6 @@ __device__ __forceinline__ void store_row(const stv_d4 (&acc)[NT][NT], int r, do
   }
 }
 
-// Pivot of one column with one candidate row per lane: the unused row of
-// largest magnitude, the lowest such row on ties; -1 when no unused row holds
-// a finite value.  Non-negative doubles order as their bit patterns, so the
-// high words are compared first (a DPP max of 32-bit keys) and the low words
-// only among the lanes that tie there.
-__device__ __forceinline__ int pivot_lane(double x, bool cand) {
-  const double ax = fabs(x);
-  const unsigned hi = (unsigned)__double2hiint(ax);
-  const unsigned key = (cand && ax == ax) ? hi + 1u : 0u;   // NaN and used rows: 0
-  const unsigned kmax = wave_max_u32(key);
-  if (kmax == 0u) return -1;
-  uint64_t tied = __builtin_amdgcn_ballot_w64(key == kmax);
-  if (tied & (tied - 1)) {
-    const unsigned lo = (unsigned)__double2loint(ax);
-    const unsigned lmax = wave_max_u32(key == kmax ? lo : 0u);
-    tied = __builtin_amdgcn_ballot_w64(key == kmax && lo == lmax);
-  }
-  return (int)__builtin_ctzll(tied);
-}
-
 // The same Gauss-Jordan inversion with one wavefront per cell, for orders up
 // to 64: the whole identity-padded block (NT x NT tiles) sits in this
 // wavefront's accumulators, so no step needs a workgroup barrier.  Per panel

@@ -109,10 +109,10 @@ static hipError_t spmv_b(hipStream_t s, const DevLevel& L, bool tr, const double
   if (!rp || !cl || !vl) return hipErrorInvalidValue;
   dim3 grid((L.n_s + 4 * rpw - 1) / (4 * rpw)), block(256);
   switch (rpw) {
-    case 1: k_spmv_rows<B, 1><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
-    case 2: k_spmv_rows<B, 2><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
-    case 3: k_spmv_rows<B, 3><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
-    case 4: k_spmv_rows<B, 4><<<grid, block, 0, s>>>(rp, cl, vl, r, x, y, L.n_s, sx); break;
+    case 1: launch(k_spmv_rows<B, 1>, dim3(grid), dim3(block), 0, s, rp, cl, vl, r, x, y, L.n_s, sx); break;
+    case 2: launch(k_spmv_rows<B, 2>, dim3(grid), dim3(block), 0, s, rp, cl, vl, r, x, y, L.n_s, sx); break;
+    case 3: launch(k_spmv_rows<B, 3>, dim3(grid), dim3(block), 0, s, rp, cl, vl, r, x, y, L.n_s, sx); break;
+    case 4: launch(k_spmv_rows<B, 4>, dim3(grid), dim3(block), 0, s, rp, cl, vl, r, x, y, L.n_s, sx); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -213,10 +213,10 @@ static hipError_t spmv_kron_b(hipStream_t s, const DevLevel& L, const double* r,
   const int lpr = 2 << L.spmv_rpw, rows_per_wg = 4 * (64 / lpr);
   dim3 grid((L.n_s + rows_per_wg - 1) / rows_per_wg), block(256);
   switch (lpr) {
-    case 4: k_spmv_kron<B, 4><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 8: k_spmv_kron<B, 8><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 16: k_spmv_kron<B, 16><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 32: k_spmv_kron<B, 32><<<grid, block, 0, s>>>(L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 4: launch(k_spmv_kron<B, 4>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 8: launch(k_spmv_kron<B, 8>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 16: launch(k_spmv_kron<B, 16>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+    case 32: launch(k_spmv_kron<B, 32>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -445,7 +445,7 @@ static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, 
   unsigned grid = (unsigned)((L.n_cells + 3) / 4);
   if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
 #define STV_VANKA(TS, F)                                                                     \
-  k_vanka<B, NLS, TS, F><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,  \
+  launch(k_vanka<B, NLS, TS, F>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,  \
                                               L.inv_off, L.inv_ld, (const TS*)L.inv_store, \
                                               omega, zero_init, L.n_cells)
   if (fp32) {
@@ -589,11 +589,11 @@ static hipError_t vanka_t_bn(hipStream_t s, const DevLevel& L, const double* rho
   unsigned grid = (unsigned)((L.n_cells + 3) / 4);
   if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
   if (fp32)
-    k_vanka_t<B, NLS, float><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
+    launch(k_vanka_t<B, NLS, float>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
                                                   L.inv_off, L.inv_ld, (const float*)L.inv_store,
                                                   omega, zero_init, L.n_cells);
   else
-    k_vanka_t<B, NLS, double><<<grid, 256, 0, s>>>(rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
+    launch(k_vanka_t<B, NLS, double>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,
                                                    L.inv_off, L.inv_ld,
                                                    (const double*)L.inv_store, omega, zero_init,
                                                    L.n_cells);
@@ -867,10 +867,10 @@ static hipError_t csr_time(hipStream_t s, int b, const int32_t* rp, const int32_
   const int64_t n = (int64_t)n_rows * b;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
   switch (b) {
-    case 1: k_csr_time<1><<<grid, block, 0, s>>>(rp, col, val, x, y, n_rows, acc); break;
-    case 2: k_csr_time<2><<<grid, block, 0, s>>>(rp, col, val, x, y, n_rows, acc); break;
-    case 3: k_csr_time<3><<<grid, block, 0, s>>>(rp, col, val, x, y, n_rows, acc); break;
-    case 4: k_csr_time<4><<<grid, block, 0, s>>>(rp, col, val, x, y, n_rows, acc); break;
+    case 1: launch(k_csr_time<1>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
+    case 2: launch(k_csr_time<2>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
+    case 3: launch(k_csr_time<3>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
+    case 4: launch(k_csr_time<4>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -16,6 +16,8 @@
 
 using namespace stv;
 
+thread_local stv::LaunchEvents stv::g_launch_events;
+
 namespace {
 
 std::string g_create_err;
@@ -156,26 +158,51 @@ hipEvent_t get_event(stv_ctx* ctx) {
   return e;
 }
 
+// Times one kernel class on one level while timing is on and the class is
+// selected.  A scope holding exactly one launch made through stv::launch
+// (one_launch) has that kernel stamp its own start and end; any other scope
+// is bracketed by event records on its stream.
 struct Timed {
   stv_ctx* ctx;
   int cls;
   int level;
   hipStream_t st;
-  hipEvent_t a = nullptr;
-  Timed(stv_ctx* c, int k, int g = 0, hipStream_t on = nullptr)
+  bool stamp = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(stv_ctx* c, int k, int g = 0, hipStream_t on = nullptr, bool one_launch = false)
       : ctx(c), cls(k), level(g), st(on ? on : c->stream) {
-    if (ctx->timing) {
-      a = get_event(ctx);
+    if (!ctx->timing || !((ctx->timing_mask >> cls) & 1u) || !((ctx->timing_levels >> level) & 1u))
+      return;
+    a = get_event(ctx);
+    if (one_launch) {
+      b = get_event(ctx);
+      g_launch_events = LaunchEvents{a, b};
+      stamp = true;
+    } else {
       (void)hipEventRecord(a, st);
     }
   }
   void done() {
-    if (ctx->timing && a) {
-      hipEvent_t b = get_event(ctx);
+    if (!a) return;
+    if (stamp) {
+      // the pair counts only when the launch took it
+      const bool taken = g_launch_events.start != a;
+      g_launch_events = LaunchEvents{};
+      if (taken) {
+        ctx->pending.push_back({a, b, cls, level});
+      } else {
+        ctx->pool.push_back(a);
+        ctx->pool.push_back(b);
+      }
+    } else {
+      b = get_event(ctx);
       (void)hipEventRecord(b, st);
       ctx->pending.push_back({a, b, cls, level});
-      a = nullptr;
     }
+    a = b = nullptr;
+  }
+  ~Timed() {
+    if (a && g_launch_events.start == a) g_launch_events = LaunchEvents{};
   }
 };
 
@@ -289,7 +316,7 @@ int check_ctx(stv_ctx* ctx, bool need_hier, bool need_inv) {
 // the operator is not transposed), else from the stored blocks.
 int level_apply(stv_ctx* ctx, int g, const double* r, const double* x, double* y, double sx) {
   const DevLevel& L = ctx->lv[g];
-  Timed t(ctx, KC_RESIDUAL, g);
+  Timed t(ctx, KC_RESIDUAL, g, nullptr, true);
   if (L.kron_m && !ctx->transposed)
     STV_HIP(launch_spmv_kron(ctx->stream, ctx->b, L, r, x, y, sx));
   else
@@ -311,13 +338,13 @@ int cell_pass(stv_ctx* ctx, int g, const double* rho, double* d, double omega, i
   DevLevel& L = ctx->lv[g];
   const int b = ctx->b;
   if (ctx->transposed) {
-    Timed t(ctx, KC_SWEEP, g);
+    Timed t(ctx, KC_SWEEP, g, nullptr, true);
     STV_HIP(launch_vanka_cells_t(ctx->stream, b, L, rho, d, omega, zero_init, ctx->inv_fp32));
     t.done();
     return STV_OK;
   }
   if (mode == STV_LAST_WRITER) {
-    Timed t(ctx, KC_SWEEP, g);
+    Timed t(ctx, KC_SWEEP, g, nullptr, true);
     STV_HIP(launch_vanka_cells(ctx->stream, b, L, rho, d, omega, zero_init, ctx->inv_fp32,
                                ctx->inv_full));
     t.done();
@@ -358,7 +385,7 @@ int sweeps(stv_ctx* ctx, int g, const double* r, double* d, int n, double omega,
 int coarse_apply(stv_ctx* ctx, int g, const double* r, double* d) {
   const int cnt = (int)ctx->h_coarse[g].size();
   if (cnt == 0) return STV_OK;
-  Timed t(ctx, KC_COARSE, g);
+  Timed t(ctx, KC_COARSE, g, nullptr, true);
   if (ctx->transposed)
     STV_HIP(launch_dense_gemv_t(ctx->stream, ctx->d_coarse[g], cnt, ctx->b, ctx->coarse_max_n0[g],
                                 ctx->coarse_inv, r, d));
@@ -384,13 +411,13 @@ int vcycle_level(stv_ctx* ctx, int g, const double* r, double* d, const stv_mg_p
   STV_TRY(coarse_apply(ctx, g, r, d));
   STV_TRY(residual(ctx, g, r, d, L.rho));
   {
-    Timed t(ctx, KC_TRANSFER, g);
+    Timed t(ctx, KC_TRANSFER, g, nullptr, true);
     STV_HIP(launch_restrict(ctx->stream, b, L, L.rho, C.r));
     t.done();
   }
   STV_TRY(vcycle_level(ctx, g - 1, C.r, C.d, p));
   {
-    Timed t(ctx, KC_TRANSFER, g);
+    Timed t(ctx, KC_TRANSFER, g, nullptr, true);
     STV_HIP(launch_prolongate_add(ctx->stream, b, L, C.d, d));
     t.done();
   }
@@ -1171,7 +1198,7 @@ int stv_vanka_sweep(stv_ctx* ctx, int level, const double* r, double* d, int n_s
 int stv_restrict(stv_ctx* ctx, int level, const double* rho, double* r_c) {
   STV_TRY(check_ctx(ctx, true, false));
   if (level < 1 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level must be in [1, n_levels)");
-  Timed t(ctx, KC_TRANSFER);
+  Timed t(ctx, KC_TRANSFER, 0, nullptr, true);
   STV_HIP(launch_restrict(ctx->stream, ctx->b, ctx->lv[level], rho, r_c));
   t.done();
   return STV_OK;
@@ -1180,7 +1207,7 @@ int stv_restrict(stv_ctx* ctx, int level, const double* rho, double* r_c) {
 int stv_prolongate_add(stv_ctx* ctx, int level, const double* d_c, double* d) {
   STV_TRY(check_ctx(ctx, true, false));
   if (level < 1 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level must be in [1, n_levels)");
-  Timed t(ctx, KC_TRANSFER);
+  Timed t(ctx, KC_TRANSFER, 0, nullptr, true);
   STV_HIP(launch_prolongate_add(ctx->stream, ctx->b, ctx->lv[level], d_c, d));
   t.done();
   return STV_OK;
@@ -1758,6 +1785,16 @@ int stv_set_timing(stv_ctx* ctx, int on) {
   ctx->timing = on != 0;
   for (int c = 0; c < KC_COUNT; ++c)
     for (int g = 0; g < kMaxLevels; ++g) { ctx->launches[c][g] = 0; ctx->total_ms[c][g] = 0.0; }
+  return STV_OK;
+}
+
+int stv_set_timing_filter(stv_ctx* ctx, unsigned class_mask, unsigned level_mask) {
+  if (!ctx) return STV_EINVAL;
+  if (class_mask >> KC_COUNT) return fail(ctx, STV_EINVAL, "unknown kernel class in the mask");
+  STV_HIP(hipStreamSynchronize(ctx->stream));
+  resolve_timers(ctx);
+  ctx->timing_mask = class_mask;
+  ctx->timing_levels = level_mask;
   return STV_OK;
 }
 

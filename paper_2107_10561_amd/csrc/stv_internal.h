@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <string>
@@ -115,6 +116,21 @@ struct CoarseGroup {
   int* rinv = nullptr;
 };
 
+// Start and stop events for the next kernel launched through stv::launch:
+// hipExtLaunchKernel stamps them at the kernel's own start and end, so a
+// timed launch needs no marker packets around it.  The launch clears them.
+struct LaunchEvents { hipEvent_t start = nullptr, stop = nullptr; };
+extern thread_local LaunchEvents g_launch_events;
+
+template <typename... P, typename... A>
+inline void launch(void (*kernel)(P...), dim3 grid, dim3 block, uint32_t shm, hipStream_t s,
+                   A... args) {
+  const LaunchEvents ev = g_launch_events;
+  g_launch_events = LaunchEvents{};
+  hipExtLaunchKernelGGL(kernel, grid, block, shm, s, ev.start, ev.stop, 0u,
+                        static_cast<P>(args)...);
+}
+
 // Results of the last solve for one instance.
 struct InstInfo { int iters = 0, restarts = 0, converged = 0; double relres = 0.0; };
 
@@ -190,6 +206,8 @@ struct stv_ctx {
   int64_t ws_n = 0;
   // timing
   bool timing = false;
+  unsigned timing_mask = ~0u;     // kernel classes recorded while timing is on
+  unsigned timing_levels = ~0u;   // levels recorded while timing is on
   std::vector<stv::TimerPair> pending;
   std::vector<hipEvent_t> pool;
   int64_t launches[stv::KC_COUNT][stv::kMaxLevels] = {};

@@ -61,6 +61,26 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   return max(max(a, b), max(c, d));
 }
 
+// Pivot of one column with one candidate row per lane: the unused row of
+// largest magnitude, the lowest such row on ties; -1 when no unused row holds
+// a finite value.  Non-negative doubles order as their bit patterns, so the
+// high words are compared first (a DPP max of 32-bit keys) and the low words
+// only among the lanes that tie there.
+__device__ __forceinline__ int pivot_lane(double x, bool cand) {
+  const double ax = fabs(x);
+  const unsigned hi = (unsigned)__double2hiint(ax);
+  const unsigned key = (cand && ax == ax) ? hi + 1u : 0u;   // NaN and used rows: 0
+  const unsigned kmax = wave_max_u32(key);
+  if (kmax == 0u) return -1;
+  uint64_t tied = __builtin_amdgcn_ballot_w64(key == kmax);
+  if (tied & (tied - 1)) {
+    const unsigned lo = (unsigned)__double2loint(ax);
+    const unsigned lmax = wave_max_u32(key == kmax ? lo : 0u);
+    tied = __builtin_amdgcn_ballot_w64(key == kmax && lo == lmax);
+  }
+  return (int)__builtin_ctzll(tied);
+}
+
 // Orders the LDS accesses of one wavefront for the compiler: a store by one
 // lane before the call is seen by loads of any lane after it (a wavefront's
 // LDS instructions are processed in issue order, so no wait is needed).
