@@ -550,7 +550,7 @@ __device__ __forceinline__ void wave_select(double (&w)[NB], bool avail, int& mi
       double pr[NB];
 #pragma unroll
       for (int c = t; c < NB; ++c) pr[c] = readlane_f64(w[c], p);
-      const double f = w[t] * (1.0 / pr[t]);
+      const double f = w[t] * recip_f64(pr[t]);
       if (LU) lmul[t] = f;
       if (avail) {
 #pragma unroll

@@ -81,6 +81,17 @@ __device__ __forceinline__ int pivot_lane(double x, bool cand) {
   return (int)__builtin_ctzll(tied);
 }
 
+// 1 / x for a normal, nonzero x: the hardware reciprocal refined by two
+// Newton steps (r <- r + r (1 - x r)), within an ulp or so of the rounded
+// quotient; five dependent operations instead of the IEEE division sequence.
+__device__ __forceinline__ double recip_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Orders the LDS accesses of one wavefront for the compiler: a store by one
 // lane before the call is seen by loads of any lane after it (a wavefront's
 // LDS instructions are processed in issue order, so no wait is needed).
