@@ -183,9 +183,13 @@ int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info);
  * cell's DoFs, Section 4.2) on levels >= 1, invert it by Gauss-Jordan
  * elimination with partial pivoting in FP64 and store it (Section 4.3);
  * factor the coarsest matrix densely (its explicit inverse) in FP64.
- * storage = STV_F64 or STV_F32, optionally | STV_STORE_FULL.  Synchronises
- * the stream.  On a zero pivot returns STV_ESINGULAR and, if non-NULL, sets
- * *bad_level and *bad_cell (bad_cell = -1 for the coarse matrix).
+ * storage = STV_F64 or STV_F32, optionally | STV_STORE_FULL.  The stores
+ * and the build's work buffers are owned by the context and kept between
+ * builds of one hierarchy (remade when the storage flags or the coarse
+ * algorithm change; a changed hierarchy frees them).  Synchronises the
+ * stream.  On a zero pivot returns STV_ESINGULAR and, if non-NULL, sets
+ * *bad_level and *bad_cell (bad_cell = -1 for the coarse matrix); the
+ * inverses are then unusable until the next successful build.
  * Errors: STV_ESTATE (no hierarchy), STV_EINVAL, STV_ENOMEM, STV_EHIP. */
 int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_cell);
 
