@@ -323,8 +323,9 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
                          const double* C, const double* tw);
 
 /* Launch shapes of the level kernels of one level: spmv_rows = shape of the
- * residual (1..4, default 2): with the blocks, block rows per wavefront;
- * with spatial factors, 2^(spmv_rows+1) lanes per block row; sweep_wgs = workgroups
+ * residual (1..6, default 2): with the blocks, block rows per wavefront (5
+ * and 6 act as 4); with spatial factors, (lanes per block row, blocks per
+ * lane and round) = (4,4), (8,3), (8,4), (16,2), (16,4), (32,2); sweep_wgs = workgroups
  * of the Vanka sweep, 0 (default) for one wavefront per cell, otherwise a
  * persistent launch of that many workgroups whose wavefronts stride over the
  * cells.  The residual's summation order depends on spmv_rows (results
@@ -332,7 +333,8 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
  * Errors: STV_ESTATE (no hierarchy), STV_EINVAL. */
 int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs);
 
-/* Autotuner: on every smoothed level, time each residual shape (1..4) and
+/* Autotuner: on every smoothed level, time each residual shape (1..4 with
+ * the blocks, 1..6 with spatial factors) and
  * each sweep shape (one wavefront per cell, or persistent
  * grids of 2, 4, 8, 16 workgroups per compute unit) on the device, five
  * launches each after one untimed launch, and keep the fastest.  Needs the

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) k_spmv_rows(const int32_t* __restrict__ r
 template <int B>
 static hipError_t spmv_b(hipStream_t s, const DevLevel& L, bool tr, const double* r,
                          const double* x, double* y, double sx) {
-  const int rpw = L.spmv_rpw;
+  const int rpw = L.spmv_rpw < 4 ? L.spmv_rpw : 4;
   const int32_t* rp = tr ? L.rowptr_t : L.rowptr;
   const int32_t* cl = tr ? L.col_t : L.col;
   const double* vl = tr ? L.val_t : L.val;
@@ -131,26 +131,25 @@ hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
 
 // Level residual from the spatial factors of an operator whose blocks are
 // C[i][l] M + delta_il tw[i] A (time-independent coefficients): per block only
-// the two scalars m = M(s, s') and a = A(s, s') are streamed.  LPR lanes per
-// block row (64 / LPR rows per wavefront): lane `sub` of a row takes the
-// row's blocks sub, sub + LPR, ..., U of them per round, with every load of a
-// round issued before the first is used (indices clamped into the row, the
-// blocks past its end weighted by zero, instead of branches), and keeps only
-// the B partial sums of its own row; the row's lanes then add their sums
-// (butterfly over the LPR lanes).
+// the two scalars m = M(s, s') and a = A(s, s') are streamed, as one 16-byte
+// pair.  LPR lanes per block row (64 / LPR rows per wavefront): lane `sub` of
+// a row takes the row's blocks sub, sub + LPR, ..., U of them per round, with
+// every load of a round issued before the first is used (indices clamped
+// into the row, the blocks past its end weighted by zero, instead of
+// branches), and keeps only the B partial sums of its own row; the row's
+// lanes then add their sums (butterfly over the LPR lanes).  LPR x U slots
+// per round are matched to the typical row length by the autotuner.
 struct KronCoef { double C[16]; double tw[4]; };
 
-template <int B, int LPR>
+template <int B, int LPR, int U>
 __global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col,
-                                                   const double* __restrict__ mval,
-                                                   const double* __restrict__ aval,
+                                                   const double2* __restrict__ ma,
                                                    const double* __restrict__ r,
                                                    const double* __restrict__ x,
                                                    double* __restrict__ y, int32_t n_rows,
                                                    double sx, KronCoef K) {
   constexpr int RPWV = 64 / LPR;
-  constexpr int U = LPR >= 16 ? 2 : 4;
   const int lane = threadIdx.x & 63, sub = lane % LPR;
   const int row = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPWV + lane / LPR;
   const bool live = row < n_rows;
@@ -172,9 +171,9 @@ __global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ r
       const bool v = q < q1;
       const int32_t qc = v ? q : q1 - 1;
       c[u] = col[qc];
-      const double mm = mval[qc], aa = aval[qc];
-      m[u] = v ? mm : 0.0;
-      a[u] = v ? aa : 0.0;
+      const double2 f = ma[qc];
+      m[u] = v ? f.x : 0.0;
+      a[u] = v ? f.y : 0.0;
     }
     double xl[U][B];
 #pragma unroll
@@ -203,22 +202,35 @@ __global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ r
   }
 }
 
-// residual shape s (1..4): 2^(s+1) lanes per block row
+// residual shapes from the factors: (lanes per block row, blocks per lane and round)
+static constexpr int kKronShapes = 6;
+static constexpr int kKronLpr[kKronShapes] = {4, 8, 8, 16, 16, 32};
+static constexpr int kKronU[kKronShapes] = {4, 3, 4, 2, 4, 2};
+
+int residual_shapes(const DevLevel& L) { return L.kron_ma ? kKronShapes : 4; }
+
 template <int B>
 static hipError_t spmv_kron_b(hipStream_t s, const DevLevel& L, const double* r, const double* x,
                               double* y, double sx) {
   KronCoef K{};
   for (int e = 0; e < B * B; ++e) K.C[e] = L.kron_C[e];
   for (int e = 0; e < B; ++e) K.tw[e] = L.kron_tw[e];
-  const int lpr = 2 << L.spmv_rpw, rows_per_wg = 4 * (64 / lpr);
+  const int sh = L.spmv_rpw - 1;
+  if (sh < 0 || sh >= kKronShapes) return hipErrorInvalidValue;
+  const int lpr = kKronLpr[sh], rows_per_wg = 4 * (64 / lpr);
   dim3 grid((L.n_s + rows_per_wg - 1) / rows_per_wg), block(256);
-  switch (lpr) {
-    case 4: launch(k_spmv_kron<B, 4>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 8: launch(k_spmv_kron<B, 8>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 16: launch(k_spmv_kron<B, 16>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
-    case 32: launch(k_spmv_kron<B, 32>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, L.kron_m, L.kron_a, r, x, y, L.n_s, sx, K); break;
+  const double2* ma = (const double2*)L.kron_ma;
+#define STV_KRON(S, LP, UU)                                                                  \
+  case S:                                                                                   \
+    launch(k_spmv_kron<B, LP, UU>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, ma, r, x, \
+           y, L.n_s, sx, K);                                                                \
+    break;
+  switch (sh) {
+    STV_KRON(0, 4, 4) STV_KRON(1, 8, 3) STV_KRON(2, 8, 4)
+    STV_KRON(3, 16, 2) STV_KRON(4, 16, 4) STV_KRON(5, 32, 2)
     default: return hipErrorInvalidValue;
   }
+#undef STV_KRON
   return hipGetLastError();
 }
 
@@ -237,8 +249,7 @@ hipError_t launch_spmv_kron(hipStream_t s, int b, const DevLevel& L, const doubl
 // largest block entry: one (deviation, magnitude) pair per workgroup.
 template <int B>
 __global__ void __launch_bounds__(256) k_kron_check(const double* __restrict__ val,
-                                                    const double* __restrict__ mval,
-                                                    const double* __restrict__ aval,
+                                                    const double2* __restrict__ ma,
                                                     int64_t nnzb, KronCoef K,
                                                     double* __restrict__ partial) {
   __shared__ double sd[4], sm[4];
@@ -250,7 +261,8 @@ __global__ void __launch_bounds__(256) k_kron_check(const double* __restrict__ v
 #pragma unroll
       for (int l = 0; l < B; ++l) {
         const double v = val[q * B * B + i * B + l];
-        const double rec = K.C[i * B + l] * mval[q] + (i == l ? K.tw[i] * aval[q] : 0.0);
+        const double2 f = ma[q];
+        const double rec = K.C[i * B + l] * f.x + (i == l ? K.tw[i] * f.y : 0.0);
         dev = fmax(dev, fabs(v - rec));
         mag = fmax(mag, fabs(v));
       }
@@ -269,17 +281,17 @@ __global__ void __launch_bounds__(256) k_kron_check(const double* __restrict__ v
   }
 }
 
-hipError_t launch_kron_check(hipStream_t s, int b, const DevLevel& L, const double* mval,
-                             const double* aval, const double* C, const double* tw,
-                             double* partial, int nblk) {
+hipError_t launch_kron_check(hipStream_t s, int b, const DevLevel& L, const double* ma_,
+                             const double* C, const double* tw, double* partial, int nblk) {
+  const double2* ma = (const double2*)ma_;
   KronCoef K{};
   for (int e = 0; e < b * b; ++e) K.C[e] = C[e];
   for (int e = 0; e < b; ++e) K.tw[e] = tw[e];
   switch (b) {
-    case 1: k_kron_check<1><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
-    case 2: k_kron_check<2><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
-    case 3: k_kron_check<3><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
-    case 4: k_kron_check<4><<<nblk, 256, 0, s>>>(L.val, mval, aval, L.nnzb, K, partial); break;
+    case 1: k_kron_check<1><<<nblk, 256, 0, s>>>(L.val, ma, L.nnzb, K, partial); break;
+    case 2: k_kron_check<2><<<nblk, 256, 0, s>>>(L.val, ma, L.nnzb, K, partial); break;
+    case 3: k_kron_check<3><<<nblk, 256, 0, s>>>(L.val, ma, L.nnzb, K, partial); break;
+    case 4: k_kron_check<4><<<nblk, 256, 0, s>>>(L.val, ma, L.nnzb, K, partial); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

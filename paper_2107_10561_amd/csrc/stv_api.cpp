@@ -117,7 +117,7 @@ void free_level(DevLevel& L) {
   dfree(L.inv_off); dfree(L.inv_store); dfree(L.posmap);
   dfree(L.rho); dfree(L.r); dfree(L.d); dfree(L.corr);
   dfree(L.rowptr_t); dfree(L.col_t); dfree(L.val_t);
-  dfree(L.kron_m); dfree(L.kron_a);
+  dfree(L.kron_ma);
   L = DevLevel();
 }
 
@@ -317,7 +317,7 @@ int check_ctx(stv_ctx* ctx, bool need_hier, bool need_inv) {
 int level_apply(stv_ctx* ctx, int g, const double* r, const double* x, double* y, double sx) {
   const DevLevel& L = ctx->lv[g];
   Timed t(ctx, KC_RESIDUAL, g, nullptr, true);
-  if (L.kron_m && !ctx->transposed)
+  if (L.kron_ma && !ctx->transposed)
     STV_HIP(launch_spmv_kron(ctx->stream, ctx->b, L, r, x, y, sx));
   else
     STV_HIP(launch_spmv(ctx->stream, ctx->b, L, r, x, y, sx, ctx->transposed != 0));
@@ -1610,7 +1610,7 @@ int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info) {
 int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs) {
   STV_TRY(check_ctx(ctx, true, false));
   if (level < 0 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level out of range");
-  if (spmv_rows < 1 || spmv_rows > 4) return fail(ctx, STV_EINVAL, "spmv_rows must be in [1, 4]");
+  if (spmv_rows < 1 || spmv_rows > 6) return fail(ctx, STV_EINVAL, "spmv_rows must be in [1, 6]");
   if (sweep_wgs < 0) return fail(ctx, STV_EINVAL, "sweep_wgs must be >= 0");
   STV_HIP(hipStreamSynchronize(ctx->stream));
   ctx->lv[level].spmv_rpw = spmv_rows;
@@ -1656,11 +1656,11 @@ int stv_autotune(stv_ctx* ctx, int* choices, int cap) {
     if (L.n_cells == 0) continue;
     int best_r = L.spmv_rpw;
     double best = 1e30;
-    for (int rpw = 1; rpw <= 4 && e == hipSuccess; ++rpw) {
+    for (int rpw = 1; rpw <= residual_shapes(L) && e == hipSuccess; ++rpw) {
       L.spmv_rpw = rpw;
       double ms = 0;
       e = time_it([&]() {
-        return L.kron_m ? launch_spmv_kron(s, b, L, r, x, y, -1.0)
+        return L.kron_ma ? launch_spmv_kron(s, b, L, r, x, y, -1.0)
                         : launch_spmv(s, b, L, r, x, y, -1.0);
       }, ms);
       if (ms < best) { best = ms; best_r = rpw; }
@@ -1706,8 +1706,7 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
   DevLevel& L = ctx->lv[level];
   if (!mval && !aval) {   // drop the factors: back to the stored blocks
     STV_HIP(hipStreamSynchronize(ctx->stream));
-    dfree(L.kron_m);
-    dfree(L.kron_a);
+    dfree(L.kron_ma);
     ++ctx->generation;
     free_graph(ctx);
     return STV_OK;
@@ -1719,16 +1718,20 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
   for (int e = 0; e < b; ++e)
     if (!std::isfinite(tw[e])) return fail(ctx, STV_EINVAL, "tw must be finite");
   STV_HIP(hipStreamSynchronize(ctx->stream));
-  double *dm = nullptr, *da = nullptr, *part = nullptr;
+  double *dma = nullptr, *part = nullptr;
   const int nblk = 1024;
-  auto drop = [&]() { dfree(dm); dfree(da); dfree(part); };
-  int rc = upload(ctx, &dm, mval, (size_t)L.nnzb);
-  if (rc == STV_OK) rc = upload(ctx, &da, aval, (size_t)L.nnzb);
+  auto drop = [&]() { dfree(dma); dfree(part); };
+  std::vector<double> hma((size_t)2 * L.nnzb);
+  for (int64_t q = 0; q < L.nnzb; ++q) {
+    hma[(size_t)(2 * q)] = mval[q];
+    hma[(size_t)(2 * q + 1)] = aval[q];
+  }
+  int rc = upload(ctx, &dma, hma.data(), hma.size());
   if (rc == STV_OK) rc = dalloc(ctx, &part, (size_t)2 * nblk);
   if (rc != STV_OK) { drop(); return rc; }
   // the factors must reproduce the stored blocks
   std::vector<double> hp((size_t)2 * nblk);
-  hipError_t e = launch_kron_check(ctx->stream, b, L, dm, da, C, tw, part, nblk);
+  hipError_t e = launch_kron_check(ctx->stream, b, L, dma, C, tw, part, nblk);
   if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(),
                                           hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -1747,10 +1750,8 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
     return fail(ctx, STV_EINVAL, "the factors do not reproduce the level's blocks (max deviation " +
                                      std::to_string(dev) + " of " + std::to_string(mag) + ")");
   }
-  dfree(L.kron_m);
-  dfree(L.kron_a);
-  L.kron_m = dm;
-  L.kron_a = da;
+  dfree(L.kron_ma);
+  L.kron_ma = dma;
   for (int i = 0; i < 16; ++i) L.kron_C[i] = i < b * b ? C[i] : 0.0;
   for (int i = 0; i < 4; ++i) L.kron_tw[i] = i < b ? tw[i] : 0.0;
   ++ctx->generation;

@@ -64,9 +64,9 @@ struct DevLevel {
   // transposed level matrix (built on first use by a transposed solve)
   int32_t* rowptr_t = nullptr; int32_t* col_t = nullptr; double* val_t = nullptr;
   // spatial factors (optional): blocks = C[i][l] M + delta_il tw[i] A
-  double* kron_m = nullptr; double* kron_a = nullptr;
+  double* kron_ma = nullptr;      // spatial factors (m, a), interleaved per block
   double kron_C[16] = {}, kron_tw[4] = {};
-  int spmv_rpw = 2;               // block rows per wavefront of the residual, 1..4
+  int spmv_rpw = 2;               // residual shape: 1..4 (blocks), 1..6 (factors)
   int sweep_wgs = 0;              // workgroups of a persistent sweep (0: one wavefront per cell)
 };
 
@@ -222,9 +222,10 @@ hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
                        const double* x, double* y, double sx, bool transposed = false);
 hipError_t launch_spmv_kron(hipStream_t s, int b, const DevLevel& L, const double* r,
                             const double* x, double* y, double sx);
-hipError_t launch_kron_check(hipStream_t s, int b, const DevLevel& L, const double* mval,
-                             const double* aval, const double* C, const double* tw,
-                             double* partial, int nblk);
+hipError_t launch_kron_check(hipStream_t s, int b, const DevLevel& L, const double* ma,
+                             const double* C, const double* tw, double* partial, int nblk);
+// residual shapes available for a level (factors: lanes per row x blocks per lane)
+int residual_shapes(const DevLevel& L);
 hipError_t launch_bsr_transpose_vals(hipStream_t s, int b, const double* val, const int32_t* src,
                                      double* val_t, int64_t nnzb);
 hipError_t launch_vanka_cells_t(hipStream_t s, int b, const DevLevel& L, const double* rho,
