@@ -881,6 +881,84 @@ hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b
   return hipGetLastError();
 }
 
+// Dense diagonal block of a time-decoupled coarse member (kdesc[z]):
+// B[(a, s), (c, s')] = T[a][c] m + delta_ac a for every block (s, s') of the
+// member's spatial pattern, rows and columns ordered a * n_s + s; one
+// workgroup per spatial row.
+__global__ void k_kron_block_dense(const KronBlockDesc* __restrict__ kdesc,
+                                   double* __restrict__ A, int64_t sA, int64_t n) {
+  const KronBlockDesc D = kdesc[blockIdx.z];
+  const int32_t row = blockIdx.x;
+  if (row >= D.n_s) return;
+  double* Az = A + blockIdx.z * sA;
+  const int32_t gr = D.row_off + row;
+  for (int32_t q = D.rowptr[gr] + threadIdx.x; q < D.rowptr[gr + 1]; q += blockDim.x) {
+    const int64_t c = D.col[q] - D.row_off;
+    const double m = D.ma[2 * (int64_t)q], a = D.ma[2 * (int64_t)q + 1];
+    for (int i = 0; i < D.nt; ++i)
+      for (int l = 0; l < D.nt; ++l)
+        Az[((int64_t)i * D.n_s + row) * n + (int64_t)l * D.n_s + c] =
+            D.t[2 * i + l] * m + (i == l ? a : 0.0);
+  }
+}
+
+hipError_t launch_kron_block_dense(hipStream_t s, const KronBlockDesc* kdesc, int cnt,
+                                   int32_t max_rows, double* A, int64_t sA, int64_t n) {
+  dim3 grid((unsigned)max_rows, 1, (unsigned)cnt);
+  k_kron_block_dense<<<grid, 64, 0, s>>>(kdesc, A, sA, n);
+  return hipGetLastError();
+}
+
+// Member z's inverse from its blocks' inverses (rec[z]); thread (s', s)
+// forms the b x b entries of spatial pair (s, s').
+template <int B>
+__global__ void __launch_bounds__(256) k_kron_recombine(const KronRecomb* __restrict__ rec,
+                                                        double* __restrict__ out) {
+  const KronRecomb* R = rec + blockIdx.z;
+  const int32_t n_s = R->n_s;
+  const int32_t sp = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int32_t s = (int32_t)blockIdx.y;
+  if (s >= n_s || sp >= n_s) return;
+  double acc[B][B];
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int l = 0; l < B; ++l) acc[i][l] = 0.0;
+  for (int p = 0; p < R->nblk; ++p) {
+    const int sz = R->sz[p], f = R->first[p];
+    const int64_t ord = (int64_t)sz * n_s;
+    const double* bi = R->binv[p];
+    for (int a = 0; a < sz; ++a)
+      for (int c = 0; c < sz; ++c) {
+        const double v = bi[((int64_t)a * n_s + s) * ord + (int64_t)c * n_s + sp];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          const double vi = R->V[i * B + f + a] * v;
+#pragma unroll
+          for (int l = 0; l < B; ++l) acc[i][l] = fma(vi, R->W[(f + c) * B + l], acc[i][l]);
+        }
+      }
+  }
+  const int64_t n0 = (int64_t)n_s * B;
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int l = 0; l < B; ++l)
+      out[R->inv_off + ((int64_t)s * B + i) * n0 + (int64_t)sp * B + l] = acc[i][l];
+}
+
+hipError_t launch_kron_recombine(hipStream_t s, int b, const KronRecomb* rec, int cnt,
+                                 int32_t max_ns, double* out) {
+  dim3 grid((unsigned)((max_ns + 255) / 256), (unsigned)max_ns, (unsigned)cnt);
+  switch (b) {
+    case 2: k_kron_recombine<2><<<grid, 256, 0, s>>>(rec, out); break;
+    case 3: k_kron_recombine<3><<<grid, 256, 0, s>>>(rec, out); break;
+    case 4: k_kron_recombine<4><<<grid, 256, 0, s>>>(rec, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // Member z's inverse (n0 x n0, row-major, at desc.inv_off of out):
 // out(i, j) = S(rpiv[i], rinv[j]) from the in-place result S (order n).
 __global__ void k_gj_unpermute(const double* __restrict__ S, int64_t sA, int64_t n,

@@ -6,6 +6,7 @@
 // and triangular solves of GMRES, and control flow.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -81,8 +82,11 @@ void free_coarse_groups(stv_ctx* ctx) {
     dfree(G.d_desc); dfree(G.w.A); dfree(G.w.rpiv); dfree(G.w.used); dfree(G.w.B);
     dfree(G.w.P); dfree(G.w.S); dfree(G.w.Bin); dfree(G.rinv);
     dfree(G.w.cand); dfree(G.w.Z); dfree(G.w.counter);
+    dfree(G.d_kdesc); dfree(G.binv);
   }
   ctx->cgroups.clear();
+  ctx->h_krec.clear();
+  dfree(ctx->d_krec);
   ctx->cgroups_algo = -1;
   dfree(ctx->coarse_inv);
   ctx->coarse_elems = 0;
@@ -910,11 +914,232 @@ int stv_set_batch(stv_ctx* ctx, int n_inst, int dim, int k, const int* n_levels,
   return setup_packed(ctx, n_inst, dim, k, n_levels, levels);
 }
 
+// Real block diagonalisation of the time matrix K = D^-1 C (D = diag(tw),
+// b <= 4) of an operator C (x) M + D (x) A: K = V T V^-1 with T block
+// diagonal, a 1 x 1 block per real eigenvalue and [[al, be], [-be, al]] per
+// pair al +- i be (columns Re v, Im v of V).  Then
+//   (C (x) M + D (x) A)^-1 = (V (x) I) blockdiag_p(T_p (x) M + I (x) A)^-1 (W (x) I)
+// with W = V^-1 D^-1, so each block is inverted on its own.  Eigenvalues are
+// the roots of the characteristic polynomial (Newton's identities for the
+// coefficients, Durand-Kerner iterations for the roots), eigenvectors null
+// vectors of K - lambda I by complete pivoting.  Returns false (use the
+// whole matrix) when there would be a single block, when K V = V T fails to
+// working accuracy, or when V is ill-conditioned.
+struct TimeSplit {
+  int nblk = 0;
+  int sz[4] = {}, first[4] = {};
+  double t[4][4] = {};   // per block, 2 x 2 row-major
+  double V[16] = {}, W[16] = {};
+};
+
+static bool time_split(const double* C, const double* tw, int b, TimeSplit& out) {
+  typedef std::complex<double> cd;
+  if (b < 2 || b > 4) return false;
+  double K[16];
+  double kmax = 0.0;
+  for (int i = 0; i < b; ++i) {
+    if (!(tw[i] != 0.0)) return false;
+    for (int l = 0; l < b; ++l) {
+      K[i * b + l] = C[i * b + l] / tw[i];
+      kmax = std::max(kmax, std::fabs(K[i * b + l]));
+    }
+  }
+  if (!(kmax > 0.0) || !std::isfinite(kmax)) return false;
+  // characteristic polynomial lambda^b + c[1] lambda^(b-1) + ... + c[b]
+  double P[16], Q[16], ptr[5] = {}, c[5] = {1.0};
+  for (int e = 0; e < b * b; ++e) P[e] = K[e];
+  for (int k = 1; k <= b; ++k) {
+    double tr = 0.0;
+    for (int i = 0; i < b; ++i) tr += P[i * b + i];
+    ptr[k] = tr;
+    for (int i = 0; i < b; ++i)
+      for (int l = 0; l < b; ++l) {
+        double acc = 0.0;
+        for (int j = 0; j < b; ++j) acc += P[i * b + j] * K[j * b + l];
+        Q[i * b + l] = acc;
+      }
+    for (int e = 0; e < b * b; ++e) P[e] = Q[e];
+  }
+  for (int k = 1; k <= b; ++k) {
+    double acc = ptr[k];
+    for (int j = 1; j < k; ++j) acc += c[j] * ptr[k - j];
+    c[k] = -acc / k;
+  }
+  auto poly = [&](cd z) {
+    cd v = 1.0;
+    for (int k = 1; k <= b; ++k) v = v * z + c[k];
+    return v;
+  };
+  cd z[4];
+  const cd seed(0.4, 0.9);
+  cd pw = 1.0;
+  for (int k = 0; k < b; ++k) { pw *= seed; z[k] = pw * kmax; }
+  for (int it = 0; it < 500; ++it) {
+    double delta = 0.0;
+    for (int k = 0; k < b; ++k) {
+      cd den = 1.0;
+      for (int j = 0; j < b; ++j)
+        if (j != k) den *= (z[k] - z[j]);
+      if (std::abs(den) == 0.0) return false;
+      const cd step = poly(z[k]) / den;
+      z[k] -= step;
+      delta = std::max(delta, std::abs(step));
+    }
+    if (delta <= 1e-15 * kmax) break;
+  }
+  // eigenvector of each root: null vector of K - lambda I
+  auto null_vector = [&](cd lam, cd* v) {
+    cd M[16];
+    int cperm[4];
+    for (int i = 0; i < b; ++i) {
+      cperm[i] = i;
+      for (int l = 0; l < b; ++l) M[i * b + l] = cd(K[i * b + l]) - (i == l ? lam : cd(0.0));
+    }
+    for (int k = 0; k < b - 1; ++k) {
+      int pr = k, pc = k;
+      double best = -1.0;
+      for (int i = k; i < b; ++i)
+        for (int l = k; l < b; ++l)
+          if (std::abs(M[i * b + l]) > best) { best = std::abs(M[i * b + l]); pr = i; pc = l; }
+      if (!(best > 0.0)) return false;
+      for (int l = 0; l < b; ++l) std::swap(M[k * b + l], M[pr * b + l]);
+      for (int i = 0; i < b; ++i) std::swap(M[i * b + k], M[i * b + pc]);
+      std::swap(cperm[k], cperm[pc]);
+      for (int i = k + 1; i < b; ++i) {
+        const cd f = M[i * b + k] / M[k * b + k];
+        for (int l = k; l < b; ++l) M[i * b + l] -= f * M[k * b + l];
+      }
+    }
+    cd y[4];
+    y[b - 1] = 1.0;
+    for (int k = b - 2; k >= 0; --k) {
+      cd acc = 0.0;
+      for (int l = k + 1; l < b; ++l) acc += M[k * b + l] * y[l];
+      y[k] = -acc / M[k * b + k];
+    }
+    double mx = 0.0;
+    for (int k = 0; k < b; ++k) mx = std::max(mx, std::abs(y[k]));
+    for (int k = 0; k < b; ++k) v[cperm[k]] = y[k] / mx;
+    return true;
+  };
+  const double tol_im = 1e-9 * kmax;
+  TimeSplit S;
+  int col = 0;
+  double T[16] = {};
+  // real eigenvalues first, then one representative per pair
+  for (int pass = 0; pass < 2; ++pass)
+    for (int k = 0; k < b; ++k) {
+      const bool real = std::fabs(z[k].imag()) <= tol_im;
+      if ((pass == 0) != real) continue;
+      if (!real && z[k].imag() < 0.0) continue;
+      cd v[4];
+      if (!null_vector(real ? cd(z[k].real(), 0.0) : z[k], v)) return false;
+      if (S.nblk >= 4) return false;
+      S.first[S.nblk] = col;
+      if (real) {
+        if (col + 1 > b) return false;
+        for (int i = 0; i < b; ++i) S.V[i * b + col] = v[i].real();
+        T[col * b + col] = z[k].real();
+        S.sz[S.nblk] = 1;
+        S.t[S.nblk][0] = z[k].real();
+        col += 1;
+      } else {
+        if (col + 2 > b) return false;
+        const double al = z[k].real(), be = z[k].imag();
+        for (int i = 0; i < b; ++i) {
+          S.V[i * b + col] = v[i].real();
+          S.V[i * b + col + 1] = v[i].imag();
+        }
+        T[col * b + col] = al; T[col * b + col + 1] = be;
+        T[(col + 1) * b + col] = -be; T[(col + 1) * b + col + 1] = al;
+        S.sz[S.nblk] = 2;
+        S.t[S.nblk][0] = al; S.t[S.nblk][1] = be; S.t[S.nblk][2] = -be; S.t[S.nblk][3] = al;
+        col += 2;
+      }
+      ++S.nblk;
+    }
+  if (col != b || S.nblk < 2) return false;
+  // K V = V T to working accuracy
+  double dev = 0.0;
+  for (int i = 0; i < b; ++i)
+    for (int l = 0; l < b; ++l) {
+      double kv = 0.0, vt = 0.0;
+      for (int j = 0; j < b; ++j) {
+        kv += K[i * b + j] * S.V[j * b + l];
+        vt += S.V[i * b + j] * T[j * b + l];
+      }
+      dev = std::max(dev, std::fabs(kv - vt));
+    }
+  if (!(dev <= 1e-10 * kmax)) return false;
+  // W = V^-1 D^-1 (Gauss-Jordan with partial pivoting), conditioning check
+  double A[16], I[16];
+  for (int e = 0; e < b * b; ++e) { A[e] = S.V[e]; I[e] = 0.0; }
+  for (int i = 0; i < b; ++i) I[i * b + i] = 1.0;
+  double vnorm = 0.0;
+  for (int i = 0; i < b; ++i) {
+    double rs = 0.0;
+    for (int l = 0; l < b; ++l) rs += std::fabs(S.V[i * b + l]);
+    vnorm = std::max(vnorm, rs);
+  }
+  for (int k = 0; k < b; ++k) {
+    int pr = k;
+    for (int i = k + 1; i < b; ++i)
+      if (std::fabs(A[i * b + k]) > std::fabs(A[pr * b + k])) pr = i;
+    if (!(std::fabs(A[pr * b + k]) > 0.0)) return false;
+    for (int l = 0; l < b; ++l) { std::swap(A[k * b + l], A[pr * b + l]); std::swap(I[k * b + l], I[pr * b + l]); }
+    const double ip = 1.0 / A[k * b + k];
+    for (int l = 0; l < b; ++l) { A[k * b + l] *= ip; I[k * b + l] *= ip; }
+    for (int i = 0; i < b; ++i)
+      if (i != k) {
+        const double f = A[i * b + k];
+        for (int l = 0; l < b; ++l) { A[i * b + l] -= f * A[k * b + l]; I[i * b + l] -= f * I[k * b + l]; }
+      }
+  }
+  double inorm = 0.0;
+  for (int i = 0; i < b; ++i) {
+    double rs = 0.0;
+    for (int l = 0; l < b; ++l) rs += std::fabs(I[i * b + l]);
+    inorm = std::max(inorm, rs);
+  }
+  if (!(vnorm * inorm <= 1e8)) return false;
+  for (int c2 = 0; c2 < b; ++c2)
+    for (int l = 0; l < b; ++l) S.W[c2 * b + l] = I[c2 * b + l] / tw[l];
+  out = S;
+  return true;
+}
+
 // Coarse members grouped by order (one batched elimination per group), their
-// buffers, the coarse inverse store and the member descriptors.
+// buffers, the coarse inverse store and the member descriptors.  A member on
+// a level with spatial factors whose time matrix splits (time_split) is
+// inverted block by block: its blocks join groups of their own order and
+// the member's inverse is recombined from theirs.
 static int make_coarse_groups(stv_ctx* ctx) {
   const int b = ctx->b;
   std::vector<CoarseGroup>& groups = ctx->cgroups;
+  ctx->h_krec.clear();
+  // split of each level's time matrix (levels with spatial factors)
+  std::vector<TimeSplit> split((size_t)ctx->n_levels);
+  std::vector<bool> has_split((size_t)ctx->n_levels, false);
+  for (int g = 0; g < ctx->n_levels; ++g)
+    if (ctx->lv[g].kron_ma && !ctx->h_coarse[g].empty())
+      has_split[(size_t)g] = time_split(ctx->lv[g].kron_C, ctx->lv[g].kron_tw, b, split[(size_t)g]);
+  // whole members: one group per order; blocks of time-decoupled members:
+  // one group, each block padded with the identity to the largest order
+  // (the blocks then share every launch of one elimination chain)
+  auto group_of = [&](int64_t order, bool kron) -> CoarseGroup& {
+    for (auto& G : groups)
+      if (G.kron == kron && (kron || G.n0 == order)) {
+        G.n0 = std::max(G.n0, order);
+        return G;
+      }
+    groups.emplace_back();
+    groups.back().n0 = order;
+    groups.back().kron = kron;
+    return groups.back();
+  };
+  // block slots of the time-decoupled members: (group index, slot in group)
+  struct BlockRef { size_t gi; size_t slot; };
+  std::vector<std::vector<BlockRef>> mblocks;
   int64_t coarse_total = 0;
   for (int g = 0; g < ctx->n_levels; ++g)
     for (size_t q = 0; q < ctx->h_coarse[g].size(); ++q) {
@@ -922,18 +1147,37 @@ static int make_coarse_groups(stv_ctx* ctx) {
       const int64_t n0 = (int64_t)c.n_s * b;
       c.inv_off = coarse_total;
       coarse_total += n0 * n0;
-      size_t gi = 0;
-      while (gi < groups.size() && groups[gi].n0 != n0) ++gi;
-      if (gi == groups.size()) {
-        groups.emplace_back();
-        groups.back().n0 = n0;
+      if (!has_split[(size_t)g]) {
+        CoarseGroup& G = group_of(n0, false);
+        G.lev.push_back(g);
+        G.idx.push_back((int)q);
+        continue;
       }
-      groups[gi].lev.push_back(g);
-      groups[gi].idx.push_back((int)q);
+      const TimeSplit& S = split[(size_t)g];
+      KronRecomb R{};
+      R.nblk = S.nblk;
+      R.n_s = c.n_s;
+      R.inv_off = c.inv_off;
+      for (int e = 0; e < 16; ++e) { R.V[e] = S.V[e]; R.W[e] = S.W[e]; }
+      std::vector<BlockRef> refs;
+      for (int p = 0; p < S.nblk; ++p) {
+        R.sz[p] = S.sz[p];
+        R.first[p] = S.first[p];
+        CoarseGroup& G = group_of((int64_t)S.sz[p] * c.n_s, true);
+        G.lev.push_back(g);
+        G.idx.push_back((int)q);
+        G.part.push_back(p);
+        refs.push_back({(size_t)(&G - groups.data()), G.lev.size() - 1});
+      }
+      mblocks.push_back(refs);
+      ctx->h_krec.push_back(R);
     }
   ctx->coarse_elems = coarse_total;
   STV_TRY(dalloc(ctx, &ctx->coarse_inv, (size_t)coarse_total));
-  for (auto& G : groups) {
+  // per group: plan, descriptors, buffers
+  std::vector<std::vector<int64_t>> boff(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    CoarseGroup& G = groups[gi];
     G.plan = gj_plan(G.n0, ctx->coarse_algo);
     G.np = (G.n0 + G.plan.pad - 1) / G.plan.pad * G.plan.pad;
     if (G.np > G.plan.max_n)
@@ -949,7 +1193,38 @@ static int make_coarse_groups(stv_ctx* ctx) {
     w.sS = 2 * (int64_t)G.plan.no * np;
     w.sBin = (int64_t)G.plan.nb * G.plan.no;
     std::vector<CoarseDesc> hd;
-    for (size_t m = 0; m < G.lev.size(); ++m) hd.push_back(ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]]);
+    if (!G.kron) {
+      for (size_t m = 0; m < G.lev.size(); ++m) hd.push_back(ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]]);
+    } else {
+      // blocks: order n0 each, inverses packed in binv
+      std::vector<KronBlockDesc> kd;
+      int64_t off = 0;
+      for (size_t m = 0; m < G.lev.size(); ++m) {
+        const CoarseDesc& c = ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]];
+        const TimeSplit& S = split[(size_t)G.lev[m]];
+        const int nt = S.sz[G.part[m]];
+        const int64_t order = (int64_t)nt * c.n_s;
+        CoarseDesc cb = c;
+        cb.n_s = (int32_t)order;
+        cb.inv_off = off;
+        boff[gi].push_back(off);
+        off += order * order;
+        hd.push_back(cb);
+        const DevLevel& L = ctx->lv[G.lev[m]];
+        KronBlockDesc k{};
+        k.rowptr = L.rowptr;
+        k.col = L.col;
+        k.ma = L.kron_ma;
+        k.row_off = c.row_off;
+        k.n_s = c.n_s;
+        k.nt = nt;
+        kd.push_back(k);
+      }
+      STV_TRY(dalloc(ctx, &G.binv, (size_t)off));
+      for (size_t m = 0; m < G.lev.size(); ++m)
+        for (int e = 0; e < 4; ++e) kd[m].t[e] = split[(size_t)G.lev[m]].t[G.part[m]][e];
+      STV_TRY(upload(ctx, &G.d_kdesc, kd.data(), kd.size()));
+    }
     STV_TRY(upload(ctx, &G.d_desc, hd.data(), hd.size()));
     STV_TRY(dalloc(ctx, &w.A, (size_t)(cnt * w.sA)));
     STV_TRY(dalloc(ctx, &w.rpiv, (size_t)(cnt * w.sV)));
@@ -969,6 +1244,19 @@ static int make_coarse_groups(stv_ctx* ctx) {
       STV_TRY(dalloc(ctx, &w.counter, (size_t)cnt));
     }
   }
+  // recombination descriptors: the device addresses of every block inverse
+  for (size_t k = 0; k < ctx->h_krec.size(); ++k) {
+    KronRecomb& R = ctx->h_krec[k];
+    for (int p = 0; p < R.nblk; ++p) {
+      const BlockRef& br = mblocks[k][(size_t)p];
+      R.binv[p] = groups[br.gi].binv + boff[br.gi][br.slot];
+    }
+  }
+  if (!ctx->h_krec.empty()) {
+    dfree(ctx->d_krec);
+    STV_TRY(upload(ctx, &ctx->d_krec, ctx->h_krec.data(), ctx->h_krec.size()));
+  }
+  ctx->krec_b = b;
   // device descriptors of the members per level (inverse offsets now known)
   for (int g = 0; g < ctx->n_levels; ++g) {
     dfree(ctx->d_coarse[g]);
@@ -1113,27 +1401,39 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   int mbase = ctx->n_levels;
   for (auto& G : ctx->cgroups) {
     if (e != hipSuccess) break;
+    const int gb = G.kron ? 1 : b;   // a block's descriptor holds its order in n_s
     Timed t(ctx, KC_COARSE_FACTOR, 0, side);
     const int cnt = (int)G.lev.size();
     int32_t max_rows = 0;
     for (size_t m = 0; m < G.lev.size(); ++m)
       max_rows = std::max(max_rows, ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]].n_s);
     e = launch_fill(side, G.w.A, cnt * G.w.sA, 0.0);
-    if (e == hipSuccess) e = launch_bsr_to_dense(side, b, G.d_desc, cnt, max_rows, G.w.A, G.w.sA, G.np);
-    if (e == hipSuccess) e = launch_set_diag(side, G.d_desc, cnt, b, G.w.A, G.w.sA, G.np);
+    if (e == hipSuccess)
+      e = G.kron ? launch_kron_block_dense(side, G.d_kdesc, cnt, max_rows, G.w.A, G.w.sA, G.np)
+                 : launch_bsr_to_dense(side, b, G.d_desc, cnt, max_rows, G.w.A, G.w.sA, G.np);
+    if (e == hipSuccess) e = launch_set_diag(side, G.d_desc, cnt, gb, G.w.A, G.w.sA, G.np);
     if (e == hipSuccess) e = hipMemsetAsync(G.w.used, 0, (size_t)(cnt * G.w.sV), side);
     if (e == hipSuccess && G.w.counter)
       e = hipMemsetAsync(G.w.counter, 0, sizeof(unsigned) * (size_t)cnt, side);
     if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt);
     // pivot records -> inverse permutations and verdicts, then the
-    // unpermuted inverses
+    // unpermuted inverses (a block's into the group's block store)
     if (e == hipSuccess)
-      e = launch_gj_invert_perm(side, G.w.rpiv, G.w.sV, G.np, G.d_desc, cnt, b, G.rinv, rep + mbase);
+      e = launch_gj_invert_perm(side, G.w.rpiv, G.w.sV, G.np, G.d_desc, cnt, gb, G.rinv,
+                                rep + mbase);
     if (e == hipSuccess)
       e = launch_gj_unpermute(side, G.w.A, G.w.sA, G.np, G.w.rpiv, G.rinv, G.w.sV, G.d_desc, cnt,
-                              b, G.n0, ctx->coarse_inv);
+                              gb, G.n0, G.kron ? G.binv : ctx->coarse_inv);
     t.done();
     mbase += cnt;
+  }
+  if (e == hipSuccess && !ctx->h_krec.empty()) {
+    Timed t(ctx, KC_COARSE_FACTOR, 0, side);
+    int32_t max_ns = 0;
+    for (const auto& R : ctx->h_krec) max_ns = std::max(max_ns, R.n_s);
+    e = launch_kron_recombine(side, b, ctx->d_krec, (int)ctx->h_krec.size(), max_ns,
+                              ctx->coarse_inv);
+    t.done();
   }
   if (side == s) {
     cell_inverses();
@@ -1707,6 +2007,7 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
   if (!mval && !aval) {   // drop the factors: back to the stored blocks
     STV_HIP(hipStreamSynchronize(ctx->stream));
     dfree(L.kron_ma);
+    ctx->cgroups_algo = -1;   // the coarse groups may refer to the factors
     ++ctx->generation;
     free_graph(ctx);
     return STV_OK;
@@ -1752,6 +2053,7 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
   }
   dfree(L.kron_ma);
   L.kron_ma = dma;
+  ctx->cgroups_algo = -1;   // the coarse groups are regrouped at the next build
   for (int i = 0; i < 16; ++i) L.kron_C[i] = i < b * b ? C[i] : 0.0;
   for (int i = 0; i < 4; ++i) L.kron_tw[i] = i < b ? tw[i] : 0.0;
   ++ctx->generation;

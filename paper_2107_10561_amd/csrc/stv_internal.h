@@ -104,6 +104,29 @@ struct GjWork {
 // max_n is the largest supported order.
 struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; };
 
+// One diagonal block of a coarse member's time-decoupled operator, built
+// from the member's spatial factors: B[(a, s), (c, s')] = T[a][c] M(s, s') +
+// delta_ac A(s, s') for a, c < nt (nt = 1 or 2 time components), rows and
+// columns ordered a * n_s + s.
+struct KronBlockDesc {
+  const int32_t* rowptr; const int32_t* col; const double* ma;
+  int32_t row_off, n_s;
+  int nt;
+  double t[4];
+};
+
+// Recombination of a member's inverse from its blocks' inverses:
+//   J^-1[(s, i), (s', l)] = sum_p sum_{a, c in block p} V[i][a] Binv_p[(a, s), (c, s')] W[c][l]
+// (time-inner rows s * b + i of the member's n0 x n0 inverse at inv_off).
+struct KronRecomb {
+  const double* binv[4];
+  int nblk;
+  int sz[4], first[4];
+  int32_t n_s;
+  int64_t inv_off;
+  double V[16], W[16];
+};
+
 // The coarse members of one order, eliminated by one batched Gauss-Jordan:
 // members (packed level, index in that level), their device descriptors,
 // the elimination buffers and the inverse pivot permutations.
@@ -114,6 +137,14 @@ struct CoarseGroup {
   CoarseDesc* d_desc = nullptr;
   GjWork w{};
   int* rinv = nullptr;
+  // blocks of time-decoupled members instead of whole members, each padded
+  // with the identity to the group's order n0: their descriptors (desc then
+  // holds n_s = block order, b = 1, and the offset of the block's inverse in
+  // binv)
+  bool kron = false;
+  std::vector<int> part;          // kron: which block of its member each slot is
+  KronBlockDesc* d_kdesc = nullptr;
+  double* binv = nullptr;
 };
 
 // Start and stop events for the next kernel launched through stv::launch:
@@ -175,6 +206,11 @@ struct stv_ctx {
   int inv_slots[stv::kMaxLevels] = {};
   std::vector<stv::CoarseGroup> cgroups;
   int cgroups_algo = -1;
+  // coarse members inverted through time decoupling, recombined after the
+  // block eliminations (device descriptors, one per member)
+  std::vector<stv::KronRecomb> h_krec;
+  stv::KronRecomb* d_krec = nullptr;
+  int krec_b = 0;
   int* inv_report = nullptr;
   int* h_report = nullptr;
   int n_report = 0;
@@ -260,6 +296,12 @@ GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */);
 hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt);
 hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b, double* A,
                            int64_t sA, int64_t n);
+// dense blocks of time-decoupled coarse members (member z: kdesc[z])
+hipError_t launch_kron_block_dense(hipStream_t s, const KronBlockDesc* kdesc, int cnt,
+                                   int32_t max_rows, double* A, int64_t sA, int64_t n);
+// every member's inverse from its blocks' inverses
+hipError_t launch_kron_recombine(hipStream_t s, int b, const KronRecomb* rec, int cnt,
+                                 int32_t max_ns, double* out);
 // rinv = the inverse of every member's pivot record rpiv (order n, real
 // order n0 from desc); verdict[z] = 0 when member z's record is a
 // permutation whose real columns pivot on real rows, else 1.
