@@ -404,7 +404,7 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
         for (int c = 0; c < 4; ++c) pr[c] = readlane_f64(pv[c], r);
         const double piv = pr[t];
         if (!(piv != 0.0)) sing = true;
-        const double ipiv = (piv != 0.0) ? 1.0 / piv : 0.0;
+        const double ipiv = (piv != 0.0) ? recip_f64(piv) : 0.0;
         // pivot row: pr * ipiv (ipiv in column t); other rows: pv - f pr
         // (-f in column t), both as fma(-g, pr, pv') with pv' = 0 in the
         // pivot row
