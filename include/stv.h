@@ -292,6 +292,12 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
  *   by a tournament: 64-row chunks propose rows by partial pivoting on their
  *   own rows and the proposals are merged by partial pivoting up a tree
  *   (the pivots can differ from 1 and 2; the inverse agrees to rounding).
+ *   With spatial factors on the coarsest level (stv_set_kron_factors) the
+ *   coarse inverse is assembled from the diagonal blocks of the operator in
+ *   the real Jordan basis of its time matrix, each built as the real form
+ *   of a complex matrix of order n_s; with 3 (and 0 above order 256) the
+ *   tournament takes complex pivots there (16 per panel of 32 real
+ *   columns), with 1 and 2 the real schedules run on the same real forms.
  * Errors: STV_EINVAL (unknown option or value). */
 #define STV_OPT_COARSE_ALGO 1
 /*   STV_OPT_GRAPH: 1 = the V-cycle (stv_vcycle and the preconditioner of

@@ -13,6 +13,17 @@ namespace stv {
 
 typedef double stv_d4 __attribute__((ext_vector_type(4)));
 
+#ifndef STV_CHAIN_PRIO
+#define STV_CHAIN_PRIO 3
+#endif
+
+// The kernels of the dense elimination chain run beside the cell-inverse
+// kernels of the same build and are latency bound: their wavefronts take
+// the higher issue priority on the SIMDs they share.
+__device__ __forceinline__ void chain_priority() {
+  if (STV_CHAIN_PRIO > 0) __builtin_amdgcn_s_setprio(STV_CHAIN_PRIO);
+}
+
 // Dense copy of member z's rows of its level matrix (columns shifted by the
 // member's first row; the blocks of a member couple only its own rows).
 template <int B>
@@ -225,6 +236,7 @@ static hipError_t load_panel(hipStream_t s, int cnt, const double* A, int64_t sA
 __global__ void k_gj_gather_rows(const double* __restrict__ A, int64_t sA, int64_t n, int p0,
                                  const int* __restrict__ rpiv, int64_t sV,
                                  double* __restrict__ Bbuf, int64_t sB) {
+  chain_priority();
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int t = blockIdx.y;
@@ -380,6 +392,7 @@ __global__ void __launch_bounds__(256) k_gj_slab_update(double* __restrict__ A, 
                                                         double* __restrict__ pnext, int64_t sP,
                                                         int nbn) {
   constexpr int KC = 32;
+  chain_priority();
   A += blockIdx.z * sA;
   rp += blockIdx.z * sV;
   Sb += blockIdx.z * sS;
@@ -574,6 +587,7 @@ __global__ void __launch_bounds__(1024) k_gj_tour(double* __restrict__ S, int64_
                                                   int* __restrict__ cand, int64_t sC,
                                                   unsigned* __restrict__ counter) {
   constexpr int RW = 256, NW = 16, FAN = 64 / NB, MAXL = 64, NH = NO / 64, RB = NH == 1 ? 16 : 4;
+  chain_priority();
   static_assert(NB == 8 || NB == 16, "panel width");
   static_assert(64 * NO <= RW * (2 * NB + 1), "candidate rows fit the panel buffers");
   // the panel buffers (current panel of the workgroup's rows, next panel)
@@ -815,20 +829,377 @@ static hipError_t gj_tour(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
   return hipSuccess;
 }
 
+// Complex partial pivoting on a wavefront, as wave_select: lane l holds the
+// complex row (wr[t], wi[t]), t < NB; the magnitude of a candidate is
+// |Re| + |Im|; the multipliers are w[t] / p[t] with the complex quotient.
+// With LU the lane taken at step s holds its multipliers in w[0..s) (column
+// t of a lane is not read again once step t has eliminated it) and its
+// eliminated row in w[s..NB).
+template <int NB, bool LU>
+__device__ __forceinline__ void wave_select_cx(double (&wr)[NB], double (&wi)[NB], bool avail,
+                                               int& mine, unsigned& zero, int& step) {
+  const int lane = threadIdx.x & 63;
+  mine = -1;
+  zero = 0;
+  step = -1;
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const double v = avail ? fabs(wr[t]) + fabs(wi[t]) : -1.0;
+    const double m = wave_max_f64(v);
+    const bool nz = m > 0.0;
+    int p;
+    if (nz) {
+      p = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(v == m));
+    } else {
+      zero |= 1u << t;
+      const uint64_t am = __builtin_amdgcn_ballot_w64(avail);
+      p = am ? (int)__builtin_ctzll(am) : -1;
+    }
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (lane == t) mine = p;
+    if (p < 0) continue;
+    if (lane == p) {
+      avail = false;
+      step = t;
+    }
+    if (nz) {
+      double pr[NB], pi[NB];
+#pragma unroll
+      for (int c = t; c < NB; ++c) {
+        pr[c] = readlane_f64(wr[c], p);
+        pi[c] = readlane_f64(wi[c], p);
+      }
+      const double d = recip_f64(fma(pr[t], pr[t], pi[t] * pi[t]));
+      const double fr = fma(wr[t], pr[t], wi[t] * pi[t]) * d;
+      const double fi = fma(wi[t], pr[t], -wr[t] * pi[t]) * d;
+      if (avail) {
+#pragma unroll
+        for (int c = t + 1; c < NB; ++c) {
+          wr[c] = fma(-fr, pr[c], fma(fi, pi[c], wr[c]));
+          wi[c] = fma(-fr, pi[c], fma(-fi, pr[c], wi[c]));
+        }
+        if (LU) {
+          wr[t] = fr;
+          wi[t] = fi;
+        }
+      }
+    }
+  }
+}
+
+// The tournament schedule of k_gj_tour on the real form of complex matrices
+// (complex row i = real rows 2i, 2i+1; see GjPlan::pair): the pivots are
+// complex, 16 per panel of 32 real columns, chosen by complex partial
+// pivoting (wave_select_cx) on each workgroup's rows and up a merge tree of
+// the workgroups' proposals; the panel step is the complex block step
+//   Z = P^-1 B'' (P = pivot rows x panel columns, B'' = pivot rows with the
+//   panel columns replaced by the identity), pivot rows <- Z, other rows
+//   <- row - (row's panel entries) Z,
+// written back in real form.  Complex values are read from the even real
+// row of a pair (Re x, -Im x) and both rows are written, so the pair keeps
+// its structure exactly.  64 complex rows per workgroup (one chunk), four
+// wavefronts: a workgroup needs one wavefront slot per SIMD, so it is
+// placed next to the cell-inverse kernels that run concurrently instead of
+// waiting for a whole compute unit to drain.  Z is stored complex,
+// [16][NO / 2] pairs (re, im).  rpiv receives real rows (2r at real column
+// 2t, 2r + 1 at 2t + 1); used flags both rows.
+template <int NO, bool UPDATE>
+__global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int64_t sS, int64_t n,
+                                                     int64_t j0, int q0, int* __restrict__ rpiv,
+                                                     uint8_t* __restrict__ used, int64_t sV,
+                                                     const double* __restrict__ Zc,
+                                                     double* __restrict__ Zn, int64_t sZ,
+                                                     int* __restrict__ cand, int64_t sC,
+                                                     unsigned* __restrict__ counter) {
+  constexpr int NB = 16, RC = 64, NW = 4, NT = 64 * NW, FAN = 64 / NB, MAXL = 128;
+  chain_priority();
+  constexpr int NOC = NO / 2;                  // complex columns of the slab
+  constexpr int LPR = NOC < 64 ? NOC : 64;     // lanes per row in the panel step
+  constexpr int RPP = 64 / LPR;                // rows per wavefront and pass
+  constexpr int NH = NOC / LPR;                // complex columns per lane
+  constexpr int PASSES = RC / (NW * RPP);
+  constexpr int NSM = RC * (2 * NB + 1) > 64 * NOC ? RC * (2 * NB + 1) : 64 * NOC;
+  __shared__ double2 smem[NSM];
+  double2(*Acur)[NB] = reinterpret_cast<double2(*)[NB]>(smem);
+  double2(*Anx)[NB + 1] = reinterpret_cast<double2(*)[NB + 1]>(smem + RC * NB);
+  double2* Brow = smem;
+  __shared__ int tl[2][MAXL * NB];
+  __shared__ int rootg[64];
+  __shared__ double2 LUs[NB][NB + 1];
+  __shared__ int Ll[NB];
+  __shared__ unsigned s_last;
+  const int z = blockIdx.z;
+  S += z * sS;
+  rpiv += z * sV;
+  used += z * sV;
+  Zn += z * sZ;
+  cand += z * sC;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t c0 = (int64_t)blockIdx.x * RC, nc = n / 2;
+  const int qn = UPDATE ? q0 + 2 * NB : q0;    // real column of the panel chosen here
+  const int q0c = q0 / 2, qnc = qn / 2;
+  // complex value of entry (complex row ic, complex column cc)
+  auto cval = [&](int64_t ic, int cc) {
+    const double2 r = *reinterpret_cast<const double2*>(&S[2 * ic * NO + 2 * cc]);
+    return make_double2(r.x, -r.y);
+  };
+  unsigned zf;
+  int step, mine;
+  if constexpr (UPDATE) {
+    Zc += z * sZ;
+    const double2* Z2 = reinterpret_cast<const double2*>(Zc);
+    const int cl = lane % LPR, rl = lane / LPR;
+    // this thread's rows and their old values (zero in the panel's columns)
+    double2 old[PASSES][NH];
+#pragma unroll
+    for (int u = 0; u < PASSES; ++u) {
+      const int64_t ic = c0 + rl + RPP * (wv + NW * u);
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const int cc = cl + LPR * h;
+        old[u][h] = (ic < nc && !(cc >= q0c && cc < q0c + NB)) ? cval(ic, cc) : make_double2(0.0, 0.0);
+      }
+    }
+    for (int e = tid; e < RC * NB; e += NT) {
+      const int dx = e / NB, t = e - dx * NB;
+      const int64_t ic = c0 + dx;
+      Acur[dx][t] = ic < nc ? cval(ic, q0c + t) : make_double2(0.0, 0.0);
+    }
+    double zr[NH][NB], zi[NH][NB];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const double2 v = Z2[t * NOC + cl + LPR * h];
+        zr[h][t] = v.x;
+        zi[h][t] = v.y;
+      }
+    int rp[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) rp[t] = rpiv[j0 + q0 + 2 * t] >> 1;   // -1 stays -1
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PASSES; ++u) {
+      const int dx = rl + RPP * (wv + NW * u);
+      const int64_t ic = c0 + dx;
+      if (ic >= nc) continue;
+      int s = -1;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) s = (rp[t] == ic) ? t : s;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const int cc = cl + LPR * h;
+        double vr, vi;
+        if (s >= 0) {
+          const double2 v = Z2[s * NOC + cc];
+          vr = v.x;
+          vi = v.y;
+        } else {
+          vr = old[u][h].x;
+          vi = old[u][h].y;
+#pragma unroll
+          for (int t = 0; t < NB; ++t) {
+            const double2 a = Acur[dx][t];
+            vr = fma(-a.x, zr[h][t], fma(a.y, zi[h][t], vr));
+            vi = fma(-a.x, zi[h][t], fma(-a.y, zr[h][t], vi));
+          }
+        }
+        *reinterpret_cast<double2*>(&S[2 * ic * NO + 2 * cc]) = make_double2(vr, -vi);
+        *reinterpret_cast<double2*>(&S[(2 * ic + 1) * NO + 2 * cc]) = make_double2(vi, vr);
+        if (cc >= qnc && cc < qnc + NB) Anx[dx][cc - qnc] = make_double2(vr, vi);
+      }
+    }
+    if (qn >= NO) return;                      // last panel of the slab
+  } else {
+    for (int e = tid; e < RC * NB; e += NT) {
+      const int dx = e / NB, t = e - dx * NB;
+      const int64_t ic = c0 + dx;
+      Anx[dx][t] = ic < nc ? cval(ic, qnc + t) : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  // the workgroup's proposal: NB rows by partial pivoting on its rows
+  if (wv == 0) {
+    const int64_t ic = c0 + lane;
+    const bool av = ic < nc && !used[2 * ic];
+    double wr[NB], wi[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const double2 v = av ? Anx[lane][t] : make_double2(0.0, 0.0);
+      wr[t] = v.x;
+      wi[t] = v.y;
+    }
+    wave_select_cx<NB, false>(wr, wi, av, mine, zf, step);
+    if (lane < NB) cand[(int64_t)blockIdx.x * NB + lane] = mine >= 0 ? (int)(c0 + mine) : -1;
+  }
+  // the workgroup that arrives last merges every workgroup's list
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const unsigned last = (atomicAdd(counter + z, 1u) == gridDim.x - 1) ? 1u : 0u;
+    if (last) {
+      __threadfence();
+      atomicExch(counter + z, 0u);
+    }
+    s_last = last;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  int m = (int)gridDim.x, cur = -1;           // cur < 0: lists in cand
+  while (m > FAN) {
+    const int nodes = (m + FAN - 1) / FAN, nxt = cur == 0 ? 1 : 0;
+    for (int j = wv; j < nodes; j += NW) {
+      const int lx = j * FAN + lane / NB, sl = lane % NB;
+      int g = -1;
+      if (lx < m) g = cur < 0 ? cand[(int64_t)lx * NB + sl] : tl[cur][lx * NB + sl];
+      double wr[NB], wi[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const double2 v = g >= 0 ? cval(g, qnc + t) : make_double2(0.0, 0.0);
+        wr[t] = v.x;
+        wi[t] = v.y;
+      }
+      wave_select_cx<NB, false>(wr, wi, g >= 0, mine, zf, step);
+      const int gs = __shfl(g, mine >= 0 ? mine : 0, 64);
+      if (lane < NB) tl[nxt][j * NB + lane] = mine >= 0 ? gs : -1;
+    }
+    __syncthreads();
+    cur = nxt;
+    m = nodes;
+  }
+  if (tid < 64) {
+    const int lx = tid / NB;
+    rootg[tid] = lx < m ? (cur < 0 ? cand[(int64_t)lx * NB + tid % NB] : tl[cur][lx * NB + tid % NB]) : -1;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    // the root: its pivot rows, their complex LU factors
+    const int g = rootg[lane];
+    double wr[NB], wi[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const double2 v = g >= 0 ? cval(g, qnc + t) : make_double2(0.0, 0.0);
+      wr[t] = v.x;
+      wi[t] = v.y;
+    }
+    wave_select_cx<NB, true>(wr, wi, g >= 0, mine, zf, step);
+    const int gs = __shfl(g, mine >= 0 ? mine : 0, 64);
+    if (lane < NB) {
+      const bool ok = mine >= 0 && !((zf >> lane) & 1u);
+      const int r = ok ? gs : -1;
+      Ll[lane] = ok ? mine : -1;
+      rpiv[j0 + qn + 2 * lane] = ok ? 2 * r : -1;
+      rpiv[j0 + qn + 2 * lane + 1] = ok ? 2 * r + 1 : -1;
+      if (ok) {
+        used[2 * (int64_t)r] = 1;
+        used[2 * (int64_t)r + 1] = 1;
+      }
+    }
+    if (step >= 0) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) LUs[step][c] = make_double2(wr[c], wi[c]);
+    }
+  } else {
+    // meanwhile the other wavefronts stage the candidates' complex rows
+    for (int e = tid - 64; e < 64 * NOC; e += NT - 64) {
+      const int l = e / NOC, cc = e - l * NOC;
+      const int g = rootg[l];
+      Brow[e] = g >= 0 ? cval(g, cc) : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  // Z = U^-1 L^-1 B'', one complex column per thread
+  if (tid < NOC) {
+    const int cc = tid;
+    const bool inp = cc >= qnc && cc < qnc + NB;
+    double yr[NB], yi[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int l = Ll[s];
+      const double2 v = inp ? make_double2((cc - qnc == s) ? 1.0 : 0.0, 0.0)
+                            : (l >= 0 ? Brow[l * NOC + cc] : make_double2(0.0, 0.0));
+      yr[s] = v.x;
+      yi[s] = v.y;
+    }
+#pragma unroll
+    for (int s = 1; s < NB; ++s)
+#pragma unroll
+      for (int t = 0; t < s; ++t) {
+        const double2 f = LUs[s][t];
+        yr[s] = fma(-f.x, yr[t], fma(f.y, yi[t], yr[s]));
+        yi[s] = fma(-f.x, yi[t], fma(-f.y, yr[t], yi[s]));
+      }
+#pragma unroll
+    for (int s = NB - 1; s >= 0; --s) {
+#pragma unroll
+      for (int t = s + 1; t < NB; ++t) {
+        const double2 f = LUs[s][t];
+        yr[s] = fma(-f.x, yr[t], fma(f.y, yi[t], yr[s]));
+        yi[s] = fma(-f.x, yi[t], fma(-f.y, yr[t], yi[s]));
+      }
+      const double2 u = LUs[s][s];
+      const double d = 1.0 / fma(u.x, u.x, u.y * u.y);
+      const double qr = fma(yr[s], u.x, yi[s] * u.y) * d;
+      const double qi = fma(yi[s], u.x, -yr[s] * u.y) * d;
+      yr[s] = qr;
+      yi[s] = qi;
+    }
+    double2* Z2 = reinterpret_cast<double2*>(Zn);
+#pragma unroll
+    for (int s = 0; s < NB; ++s) Z2[s * NOC + cc] = make_double2(yr[s], yi[s]);
+  }
+}
+
+template <int NO>
+static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
+  constexpr int NBR = 32;                      // real columns per panel
+  double* sb[2] = {w.S, w.S + n * NO};
+  double* zb[2] = {w.Z, w.Z + NBR * NO};
+  hipError_t e = load_panel(s, cnt, w.A, w.sA, n, n, 0, NO, sb[0], w.sS);
+  if (e != hipSuccess) return e;
+  // 128 real rows per workgroup; the proposals fit the candidate buffer
+  // (w.sC = 32 per 256 real rows) and the merge tree (at most 512 lists)
+  const unsigned nwg = (unsigned)((n + 127) / 128), nt = (unsigned)(n / 64);
+  int cs = 0, cz = 0;
+  for (int64_t j0 = 0; j0 < n; j0 += NO, cs ^= 1) {
+    k_gj_tour_cx<NO, false><<<dim3(nwg, 1, cnt), 256, 0, s>>>(
+        sb[cs], w.sS, n, j0, 0, w.rpiv, w.used, w.sV, nullptr, zb[cz], w.sZ, w.cand, w.sC,
+        w.counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int q0 = 0; q0 < NO; q0 += NBR, cz ^= 1) {
+      k_gj_tour_cx<NO, true><<<dim3(nwg, 1, cnt), 256, 0, s>>>(
+          sb[cs], w.sS, n, j0, q0, w.rpiv, w.used, w.sV, zb[cz], zb[cz ^ 1], w.sZ, w.cand, w.sC,
+          w.counter);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, (int)j0, w.rpiv, w.sV, w.B, w.sB);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_gj_slab_update<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, sb[cs ^ 1],
+        w.sS, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Panel configurations (panel width, threads, rows per thread, slab width);
 // the largest order each one holds is RPT * TPB.
 struct GjCfg { int nb, tpb, rpt, no; };
 static const GjCfg kCfg1[3] = {{12, 512, 5, 0}, {8, 512, 10, 0}, {4, 768, 15, 0}};
 static const GjCfg kCfg2[3] = {{8, 512, 5, 64}, {8, 512, 10, 64}, {4, 768, 15, 128}};
 
-GjPlan gj_plan(int64_t n, int algo) {
+GjPlan gj_plan(int64_t n, int algo, bool pair) {
   GjPlan p{};
   p.algo = algo == 0 ? ((n > 256) ? 3 : 1) : algo;
   if (p.algo == 3) {
-    // tournament panels of 16 in slabs of 64 (128 above order 5120); the
-    // merge tree holds up to 256 workgroup lists of 256 rows
+    // tournament panels of 16 (16 complex pivots, 32 real columns, for the
+    // real form of a complex matrix) in slabs of 64 (128 above order 5120);
+    // the merge tree holds up to 256 workgroup lists of 256 real rows
     p.cfg = n > 5120 ? 1 : 0;
-    p.nb = 16;
+    p.pair = pair;
+    p.nb = pair ? 32 : 16;
     p.no = p.cfg ? 128 : 64;
     p.pad = p.no;
     p.max_n = 65536;
@@ -850,7 +1221,8 @@ GjPlan gj_plan(int64_t n, int algo) {
 // cnt matrices of order n (a multiple of plan.pad, at most plan.max_n) at
 // the strides of w.
 hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt) {
-  if (n > p.max_n || n % p.pad || cnt < 1) return hipErrorInvalidValue;
+  if (n > p.max_n || n % p.pad || cnt < 1 || (p.pair && (p.algo != 3 || n % 2)))
+    return hipErrorInvalidValue;
   if (p.algo == 1) {
     switch (p.cfg) {
       case 0: return gj_blocked<5, 12, 512>(s, w, n, cnt);
@@ -858,6 +1230,8 @@ hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n,
       default: return gj_blocked<15, 4, 768>(s, w, n, cnt);
     }
   }
+  if (p.algo == 3 && p.pair)
+    return p.cfg ? gj_tour_cx<128>(s, w, n, cnt) : gj_tour_cx<64>(s, w, n, cnt);
   if (p.algo == 3)
     return p.cfg ? gj_tour<16, 128>(s, w, n, cnt) : gj_tour<16, 64>(s, w, n, cnt);
   switch (p.cfg) {
@@ -881,10 +1255,10 @@ hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b
   return hipGetLastError();
 }
 
-// Dense diagonal block of a time-decoupled coarse member (kdesc[z]):
-// B[(a, s), (c, s')] = T[a][c] m + delta_ac a for every block (s, s') of the
-// member's spatial pattern, rows and columns ordered a * n_s + s; one
-// workgroup per spatial row.
+// Dense diagonal block of a time-decoupled coarse member (kdesc[z]) in real
+// form: B[2s + a, 2s' + c] = T[a][c] m + delta_ac a (a, c < 2) for every
+// block (s, s') of the member's spatial pattern; one workgroup per spatial
+// row, two 16-byte stores per block.
 __global__ void k_kron_block_dense(const KronBlockDesc* __restrict__ kdesc,
                                    double* __restrict__ A, int64_t sA, int64_t n) {
   const KronBlockDesc D = kdesc[blockIdx.z];
@@ -895,10 +1269,10 @@ __global__ void k_kron_block_dense(const KronBlockDesc* __restrict__ kdesc,
   for (int32_t q = D.rowptr[gr] + threadIdx.x; q < D.rowptr[gr + 1]; q += blockDim.x) {
     const int64_t c = D.col[q] - D.row_off;
     const double m = D.ma[2 * (int64_t)q], a = D.ma[2 * (int64_t)q + 1];
-    for (int i = 0; i < D.nt; ++i)
-      for (int l = 0; l < D.nt; ++l)
-        Az[((int64_t)i * D.n_s + row) * n + (int64_t)l * D.n_s + c] =
-            D.t[2 * i + l] * m + (i == l ? a : 0.0);
+    *reinterpret_cast<double2*>(&Az[2 * (int64_t)row * n + 2 * c]) =
+        make_double2(fma(D.t[0], m, a), D.t[1] * m);
+    *reinterpret_cast<double2*>(&Az[(2 * (int64_t)row + 1) * n + 2 * c]) =
+        make_double2(D.t[2] * m, fma(D.t[3], m, a));
   }
 }
 
@@ -926,11 +1300,11 @@ __global__ void __launch_bounds__(256) k_kron_recombine(const KronRecomb* __rest
     for (int l = 0; l < B; ++l) acc[i][l] = 0.0;
   for (int p = 0; p < R->nblk; ++p) {
     const int sz = R->sz[p], f = R->first[p];
-    const int64_t ord = (int64_t)sz * n_s;
+    const int64_t ord = 2 * (int64_t)n_s;
     const double* bi = R->binv[p];
     for (int a = 0; a < sz; ++a)
       for (int c = 0; c < sz; ++c) {
-        const double v = bi[((int64_t)a * n_s + s) * ord + (int64_t)c * n_s + sp];
+        const double v = bi[(2 * (int64_t)s + a) * ord + 2 * (int64_t)sp + c];
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           const double vi = R->V[i * B + f + a] * v;

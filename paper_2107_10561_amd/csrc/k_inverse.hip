@@ -305,11 +305,11 @@ __device__ __forceinline__ void store_row(const stv_d4 (&acc)[NT][NT], int r, do
 //    column first so that the next panel can start while the rest run.
 // The in-place result is permuted as in k_inverse_mfma.
 template <int B, int NLS>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ val,
                const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
                const int64_t* __restrict__ inv_off, int ld, void* store, int fp32,
-               uint8_t* status) {
+               uint8_t* status, int n_cells) {
   constexpr int N = B * NLS;
   constexpr int NT = (N + 15) / 16;
   constexpr int NP = 16 * NT;
@@ -320,176 +320,184 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
   __shared__ int rpiv[NP];
   __shared__ int rinv[NP];
   __shared__ int rowmap[NP];
-  const int lane = threadIdx.x;
-  const int lr = lane >> 4;
-  const int lc = lane & 15;
-  const int T = blockIdx.x;
+  // grid-stride over the cells: a capped grid leaves room on every SIMD
+  // for the kernels of a concurrent stream
+  for (int T = blockIdx.x; T < n_cells; T += gridDim.x) {
+    wave_lds_sync();   // the previous cell's LDS reads come first
+    // the lane index passes through an empty asm statement each cell, so the
+    // per-lane index arithmetic stays inside the loop instead of being
+    // hoisted and held in registers across it
+    int lane = (int)threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    const int lr = lane >> 4;
+    const int lc = lane & 15;
 
-  // J_T: the cell's block positions through LDS, then every value load at
-  // once (indices clamped into the block, the padding and absent blocks
-  // selected afterwards)
-  {
-    constexpr int NPOS = NLS * NLS;
-    const int32_t* pos = posmap + (int64_t)T * NPOS;
-    int32_t q[(NPOS + 63) / 64];
+    // J_T: the cell's block positions through LDS, then every value load at
+    // once (indices clamped into the block, the padding and absent blocks
+    // selected afterwards)
+    {
+      constexpr int NPOS = NLS * NLS;
+      const int32_t* pos = posmap + (int64_t)T * NPOS;
+      int32_t q[(NPOS + 63) / 64];
 #pragma unroll
-    for (int i = 0; i < (NPOS + 63) / 64; ++i) {
-      const int e = lane + 64 * i;
-      q[i] = pos[e < NPOS ? e : NPOS - 1];
+      for (int i = 0; i < (NPOS + 63) / 64; ++i) {
+        const int e = lane + 64 * i;
+        q[i] = pos[e < NPOS ? e : NPOS - 1];
+      }
+#pragma unroll
+      for (int i = 0; i < (NPOS + 63) / 64; ++i)
+        if (lane + 64 * i < NPOS) spos[lane + 64 * i] = q[i];
     }
-#pragma unroll
-    for (int i = 0; i < (NPOS + 63) / 64; ++i)
-      if (lane + 64 * i < NPOS) spos[lane + 64 * i] = q[i];
-  }
-  wave_lds_sync();
-  stv_d4 acc[NT][NT];
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 16 * ti + 4 * v + lr;
-      const int rc = row < N ? row : N - 1;
-      const int ra = rc / B;
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj) {
-        const int col = 16 * tj + lc;
-        const int cc = col < N ? col : N - 1;
-        const int be = cc / B;
-        const int32_t q = spos[ra * NLS + be];
-        const double x =
-            val[(int64_t)(q > 0 ? q : 0) * (B * B) + (rc - ra * B) * B + (cc - be * B)];
-        // bitwise predicates and a value select: no branch for the load to
-        // sink into
-        const bool inb = (row < N) & (col < N);
-        const bool keep = inb & (q >= 0);
-        const double pad = ((!inb) & (row == col)) ? 1.0 : 0.0;
-        acc[ti][tj][v] = keep ? x : pad;
-      }
-    }
-  }
-
-  bool used = lane >= NP;   // this lane's row has been a pivot row
-  int mypiv = 0;            // lane p: pivot row of column p
-  bool sing = false;
-  const int prow = lane < NP ? lane : NP - 1;
-#pragma unroll
-  for (int tc = 0; tc < NT; ++tc) {
-#pragma unroll 1
-    for (int q4 = 0; q4 < 4; ++q4) {
-      const int c0 = 4 * q4;
-      const bool pcol = (unsigned)(lc - c0) < 4u;   // lane holds a panel column
-      // panel columns -> LDS, read back one row per lane
-      wave_lds_sync();
-      if (pcol) {
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) panel[16 * ti + 4 * v + lr][lc - c0] = acc[ti][tc][v];
-      }
-      wave_lds_sync();
-      double pv[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) pv[c] = panel[prow][c];
-      int rk[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        int r = pivot_lane(pv[t], !used);
-        if (r < 0) {   // no finite candidate (NaN column): lowest unused row
-          r = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(!used));
-          sing = true;
-        }
-        r = __builtin_amdgcn_readfirstlane(r);
-        double pr[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) pr[c] = readlane_f64(pv[c], r);
-        const double piv = pr[t];
-        if (!(piv != 0.0)) sing = true;
-        const double ipiv = (piv != 0.0) ? recip_f64(piv) : 0.0;
-        // pivot row: pr * ipiv (ipiv in column t); other rows: pv - f pr
-        // (-f in column t), both as fma(-g, pr, pv') with pv' = 0 in the
-        // pivot row
-        const bool me = lane == r;
-        const double g = me ? -ipiv : pv[t] * ipiv;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) pv[c] = (c == t) ? -g : fma(-g, pr[c], me ? 0.0 : pv[c]);
-        used = used || me;
-        if (lane == 16 * tc + c0 + t) mypiv = r;
-        rk[t] = r;
-      }
-      // the pivot rows as they were before the panel
-#pragma unroll 1
-      for (int k = 0; k < 4; ++k) {
-        const int r = k == 0 ? rk[0] : k == 1 ? rk[1] : k == 2 ? rk[2] : rk[3];
-        store_row<NT>(acc, r, &brow[k][0], lr, lc);
-      }
-      if (lane < NP) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) panel[lane][c] = pv[c];
-      }
-      wave_lds_sync();
-      // W = (E - I)(:, pivot rows) and B in the operand layouts of the MFMA;
-      // the panel columns take the eliminated values and see B = 0
-      const int rsel = lr == 0 ? rk[0] : lr == 1 ? rk[1] : lr == 2 ? rk[2] : rk[3];
-      double a[NT], b[NT];
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        a[ti] = panel[16 * ti + lc][lr] - ((16 * ti + lc == rsel) ? 1.0 : 0.0);
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj) {
-        const double bv = brow[lr][16 * tj + lc];
-        b[tj] = (tj == tc && pcol) ? 0.0 : bv;
-      }
-      if (pcol) {
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[ti][tc][v] = panel[16 * ti + 4 * v + lr][lc - c0];
-      }
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        acc[ti][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tc], acc[ti][tc], 0, 0, 0);
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj) {
-        if (tj == tc) continue;
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
-      }
-    }
-  }
-
-  // row of the inverse held by in-place row rho, owned rows, and the store
-  wave_lds_sync();
-  if (lane < NP) {
-    rpiv[lane] = mypiv;
-    rinv[mypiv] = lane;
-    rowmap[lane] = (full && lane < N) ? lane : -1;
-  }
-  wave_lds_sync();
-  if (!full) {
-    const int o0 = own_ptr[T], no = own_ptr[T + 1] - o0;
-    for (int e = lane; e < no * B; e += 64) {
-      const int os = e / B;
-      rowmap[own_loc[o0 + os] * B + (e - os * B)] = e;
-    }
-  }
-  if (lane == 0) status[T] = (uint8_t)sing;
-  wave_lds_sync();
-  const int64_t off = inv_off[T];
-#pragma unroll
-  for (int tj = 0; tj < NT; ++tj) {
-    const int j = rpiv[16 * tj + lc];
+    wave_lds_sync();
+    stv_d4 acc[NT][NT];
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int p = rinv[16 * ti + 4 * v + lr];
-        if (p < N && j < N) {
-          const int o = rowmap[p];
-          if (o >= 0) {
-            const int64_t e = off + (int64_t)o * ld + j;
-            if (fp32) ((float*)store)[e] = (float)acc[ti][tj][v];
-            else ((double*)store)[e] = acc[ti][tj][v];
+        const int row = 16 * ti + 4 * v + lr;
+        const int rc = row < N ? row : N - 1;
+        const int ra = rc / B;
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+          const int col = 16 * tj + lc;
+          const int cc = col < N ? col : N - 1;
+          const int be = cc / B;
+          const int32_t q = spos[ra * NLS + be];
+          const double x =
+              val[(int64_t)(q > 0 ? q : 0) * (B * B) + (rc - ra * B) * B + (cc - be * B)];
+          // bitwise predicates and a value select: no branch for the load to
+          // sink into
+          const bool inb = (row < N) & (col < N);
+          const bool keep = inb & (q >= 0);
+          const double pad = ((!inb) & (row == col)) ? 1.0 : 0.0;
+          acc[ti][tj][v] = keep ? x : pad;
+        }
+      }
+    }
+
+    bool used = lane >= NP;   // this lane's row has been a pivot row
+    int mypiv = 0;            // lane p: pivot row of column p
+    bool sing = false;
+    const int prow = lane < NP ? lane : NP - 1;
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) {
+#pragma unroll 1
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int c0 = 4 * q4;
+        const bool pcol = (unsigned)(lc - c0) < 4u;   // lane holds a panel column
+        // panel columns -> LDS, read back one row per lane
+        wave_lds_sync();
+        if (pcol) {
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) panel[16 * ti + 4 * v + lr][lc - c0] = acc[ti][tc][v];
+        }
+        wave_lds_sync();
+        double pv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pv[c] = panel[prow][c];
+        int rk[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          int r = pivot_lane(pv[t], !used);
+          if (r < 0) {   // no finite candidate (NaN column): lowest unused row
+            r = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(!used));
+            sing = true;
+          }
+          r = __builtin_amdgcn_readfirstlane(r);
+          double pr[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) pr[c] = readlane_f64(pv[c], r);
+          const double piv = pr[t];
+          if (!(piv != 0.0)) sing = true;
+          const double ipiv = (piv != 0.0) ? recip_f64(piv) : 0.0;
+          // pivot row: pr * ipiv (ipiv in column t); other rows: pv - f pr
+          // (-f in column t), both as fma(-g, pr, pv') with pv' = 0 in the
+          // pivot row
+          const bool me = lane == r;
+          const double g = me ? -ipiv : pv[t] * ipiv;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) pv[c] = (c == t) ? -g : fma(-g, pr[c], me ? 0.0 : pv[c]);
+          used = used || me;
+          if (lane == 16 * tc + c0 + t) mypiv = r;
+          rk[t] = r;
+        }
+        // the pivot rows as they were before the panel
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+          const int r = k == 0 ? rk[0] : k == 1 ? rk[1] : k == 2 ? rk[2] : rk[3];
+          store_row<NT>(acc, r, &brow[k][0], lr, lc);
+        }
+        if (lane < NP) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) panel[lane][c] = pv[c];
+        }
+        wave_lds_sync();
+        // W = (E - I)(:, pivot rows) and B in the operand layouts of the MFMA;
+        // the panel columns take the eliminated values and see B = 0
+        const int rsel = lr == 0 ? rk[0] : lr == 1 ? rk[1] : lr == 2 ? rk[2] : rk[3];
+        double a[NT], b[NT];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+          a[ti] = panel[16 * ti + lc][lr] - ((16 * ti + lc == rsel) ? 1.0 : 0.0);
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+          const double bv = brow[lr][16 * tj + lc];
+          b[tj] = (tj == tc && pcol) ? 0.0 : bv;
+        }
+        if (pcol) {
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[ti][tc][v] = panel[16 * ti + 4 * v + lr][lc - c0];
+        }
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+          acc[ti][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tc], acc[ti][tc], 0, 0, 0);
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+          if (tj == tc) continue;
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+            acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+        }
+      }
+    }
+
+    // row of the inverse held by in-place row rho, owned rows, and the store
+    wave_lds_sync();
+    if (lane < NP) {
+      rpiv[lane] = mypiv;
+      rinv[mypiv] = lane;
+      rowmap[lane] = (full && lane < N) ? lane : -1;
+    }
+    wave_lds_sync();
+    if (!full) {
+      const int o0 = own_ptr[T], no = own_ptr[T + 1] - o0;
+      for (int e = lane; e < no * B; e += 64) {
+        const int os = e / B;
+        rowmap[own_loc[o0 + os] * B + (e - os * B)] = e;
+      }
+    }
+    if (lane == 0) status[T] = (uint8_t)sing;
+    wave_lds_sync();
+    const int64_t off = inv_off[T];
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+      const int j = rpiv[16 * tj + lc];
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = rinv[16 * ti + 4 * v + lr];
+          if (p < N && j < N) {
+            const int o = rowmap[p];
+            if (o >= 0) {
+              const int64_t e = off + (int64_t)o * ld + j;
+              if (fp32) ((float*)store)[e] = (float)acc[ti][tj][v];
+              else ((double*)store)[e] = acc[ti][tj][v];
+            }
           }
         }
       }
@@ -598,12 +606,32 @@ bool inverse_fits_regs(int b, int n_ls) {
 }
 
 
+// Wavefronts per compute unit of kernel f that leave `reserve` VGPRs free
+// on each of the four SIMDs (a SIMD holds 512 per lane, allocated in
+// granules of 8); 0 when the kernel's register count is not available.
+template <typename K>
+static int waves_leaving(K f, int reserve) {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(f)) != hipSuccess) return 0;
+  const int regs = (a.numRegs + 7) / 8 * 8;
+  if (regs <= 0 || regs > 512) return 0;
+  const int per_simd = std::min(8, (512 - reserve) / regs);
+  return per_simd > 0 ? 4 * per_simd : 0;
+}
+
 template <int B, int NLS>
-static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full, uint8_t* status) {
+static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full, uint8_t* status,
+                           int n_cu, int reserve) {
   constexpr int NT = (B * NLS + 15) / 16;
   if constexpr (NT <= 4) {
-    k_inverse_wave<B, NLS><<<L.n_cells, 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc, full,
-                                                   L.inv_off, L.inv_ld, L.inv_store, fp32, status);
+    int grid = L.n_cells;
+    if (n_cu > 0 && reserve > 0) {
+      static const int per_cu = waves_leaving(k_inverse_wave<B, NLS>, reserve);
+      if (per_cu > 0) grid = std::min(grid, n_cu * per_cu);
+    }
+    k_inverse_wave<B, NLS><<<grid, 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc, full,
+                                               L.inv_off, L.inv_ld, L.inv_store, fp32, status,
+                                               L.n_cells);
     return hipGetLastError();
   } else {
     k_inverse_mfma<B, NLS><<<L.n_cells, NT * 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc,
@@ -614,19 +642,20 @@ static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full,
 }
 
 hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,
-                                uint8_t* status, double* gscratch, int n_slots) {
+                                uint8_t* status, double* gscratch, int n_slots, int n_cu,
+                                int reserve) {
   if (L.n_ls == 21) {
     switch (b) {
-      case 1: return inv_mfma<1, 21>(s, L, fp32, full, status);
-      case 2: return inv_mfma<2, 21>(s, L, fp32, full, status);
-      case 3: return inv_mfma<3, 21>(s, L, fp32, full, status);
-      case 4: return inv_mfma<4, 21>(s, L, fp32, full, status);
+      case 1: return inv_mfma<1, 21>(s, L, fp32, full, status, n_cu, reserve);
+      case 2: return inv_mfma<2, 21>(s, L, fp32, full, status, n_cu, reserve);
+      case 3: return inv_mfma<3, 21>(s, L, fp32, full, status, n_cu, reserve);
+      case 4: return inv_mfma<4, 21>(s, L, fp32, full, status, n_cu, reserve);
     }
   } else if (L.n_ls == 85) {
     switch (b) {
-      case 1: return inv_mfma<1, 85>(s, L, fp32, full, status);
-      case 2: return inv_mfma<2, 85>(s, L, fp32, full, status);
-      case 3: return inv_mfma<3, 85>(s, L, fp32, full, status);
+      case 1: return inv_mfma<1, 85>(s, L, fp32, full, status, n_cu, reserve);
+      case 2: return inv_mfma<2, 85>(s, L, fp32, full, status, n_cu, reserve);
+      case 3: return inv_mfma<3, 85>(s, L, fp32, full, status, n_cu, reserve);
       default: break;
     }
   }

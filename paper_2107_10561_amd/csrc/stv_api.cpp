@@ -15,6 +15,12 @@
 
 #include "stv_internal.h"
 
+// registers per lane that the dense elimination chain's largest kernel
+// needs on a SIMD (its workgroups run beside the cell inverses)
+#ifndef STV_CHAIN_VGPRS
+#define STV_CHAIN_VGPRS 168
+#endif
+
 using namespace stv;
 
 thread_local stv::LaunchEvents stv::g_launch_events;
@@ -923,8 +929,10 @@ int stv_set_batch(stv_ctx* ctx, int n_inst, int dim, int k, const int* n_levels,
 // the roots of the characteristic polynomial (Newton's identities for the
 // coefficients, Durand-Kerner iterations for the roots), eigenvectors null
 // vectors of K - lambda I by complete pivoting.  Returns false (use the
-// whole matrix) when there would be a single block, when K V = V T fails to
-// working accuracy, or when V is ill-conditioned.
+// whole matrix) when there would be a single real block, when K V = V T
+// fails to working accuracy, or when V is ill-conditioned.  A single pair
+// (dG(1)) is kept: its block is the real form of a complex matrix of order
+// n_s, eliminated with complex pivots in half the panels.
 struct TimeSplit {
   int nblk = 0;
   int sz[4] = {}, first[4] = {};
@@ -1058,7 +1066,7 @@ static bool time_split(const double* C, const double* tw, int b, TimeSplit& out)
       }
       ++S.nblk;
     }
-  if (col != b || S.nblk < 2) return false;
+  if (col != b || (S.nblk < 2 && S.sz[0] != 2)) return false;
   // K V = V T to working accuracy
   double dev = 0.0;
   for (int i = 0; i < b; ++i)
@@ -1111,8 +1119,11 @@ static bool time_split(const double* C, const double* tw, int b, TimeSplit& out)
 // Coarse members grouped by order (one batched elimination per group), their
 // buffers, the coarse inverse store and the member descriptors.  A member on
 // a level with spatial factors whose time matrix splits (time_split) is
-// inverted block by block: its blocks join groups of their own order and
-// the member's inverse is recombined from theirs.
+// inverted block by block: every block is built in real form of order 2 n_s
+// (a pair is the real form of a complex matrix, a real eigenvalue two
+// uncoupled copies), the blocks join one group per order, eliminated with
+// complex pivots by the tournament, and the member's inverse is recombined
+// from theirs.
 static int make_coarse_groups(stv_ctx* ctx) {
   const int b = ctx->b;
   std::vector<CoarseGroup>& groups = ctx->cgroups;
@@ -1128,10 +1139,7 @@ static int make_coarse_groups(stv_ctx* ctx) {
   // (the blocks then share every launch of one elimination chain)
   auto group_of = [&](int64_t order, bool kron) -> CoarseGroup& {
     for (auto& G : groups)
-      if (G.kron == kron && (kron || G.n0 == order)) {
-        G.n0 = std::max(G.n0, order);
-        return G;
-      }
+      if (G.kron == kron && G.n0 == order) return G;
     groups.emplace_back();
     groups.back().n0 = order;
     groups.back().kron = kron;
@@ -1163,7 +1171,7 @@ static int make_coarse_groups(stv_ctx* ctx) {
       for (int p = 0; p < S.nblk; ++p) {
         R.sz[p] = S.sz[p];
         R.first[p] = S.first[p];
-        CoarseGroup& G = group_of((int64_t)S.sz[p] * c.n_s, true);
+        CoarseGroup& G = group_of(2 * (int64_t)c.n_s, true);
         G.lev.push_back(g);
         G.idx.push_back((int)q);
         G.part.push_back(p);
@@ -1178,7 +1186,7 @@ static int make_coarse_groups(stv_ctx* ctx) {
   std::vector<std::vector<int64_t>> boff(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     CoarseGroup& G = groups[gi];
-    G.plan = gj_plan(G.n0, ctx->coarse_algo);
+    G.plan = gj_plan(G.n0, ctx->coarse_algo, G.kron);
     G.np = (G.n0 + G.plan.pad - 1) / G.plan.pad * G.plan.pad;
     if (G.np > G.plan.max_n)
       return fail(ctx, STV_EINVAL, "coarse level larger than " + std::to_string(G.plan.max_n) + " unknowns");
@@ -1196,14 +1204,12 @@ static int make_coarse_groups(stv_ctx* ctx) {
     if (!G.kron) {
       for (size_t m = 0; m < G.lev.size(); ++m) hd.push_back(ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]]);
     } else {
-      // blocks: order n0 each, inverses packed in binv
+      // blocks in real form (order 2 n_s each), inverses packed in binv
       std::vector<KronBlockDesc> kd;
       int64_t off = 0;
       for (size_t m = 0; m < G.lev.size(); ++m) {
         const CoarseDesc& c = ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]];
-        const TimeSplit& S = split[(size_t)G.lev[m]];
-        const int nt = S.sz[G.part[m]];
-        const int64_t order = (int64_t)nt * c.n_s;
+        const int64_t order = 2 * (int64_t)c.n_s;
         CoarseDesc cb = c;
         cb.n_s = (int32_t)order;
         cb.inv_off = off;
@@ -1217,12 +1223,17 @@ static int make_coarse_groups(stv_ctx* ctx) {
         k.ma = L.kron_ma;
         k.row_off = c.row_off;
         k.n_s = c.n_s;
-        k.nt = nt;
+        // a real eigenvalue: two uncoupled copies (T = lambda I)
+        const TimeSplit& S = split[(size_t)G.lev[m]];
+        const int p = G.part[m];
+        const bool pair = S.sz[p] == 2;
+        k.t[0] = S.t[p][0];
+        k.t[1] = pair ? S.t[p][1] : 0.0;
+        k.t[2] = pair ? S.t[p][2] : 0.0;
+        k.t[3] = pair ? S.t[p][3] : S.t[p][0];
         kd.push_back(k);
       }
       STV_TRY(dalloc(ctx, &G.binv, (size_t)off));
-      for (size_t m = 0; m < G.lev.size(); ++m)
-        for (int e = 0; e < 4; ++e) kd[m].t[e] = split[(size_t)G.lev[m]].t[G.part[m]][e];
       STV_TRY(upload(ctx, &G.d_kdesc, kd.data(), kd.size()));
     }
     STV_TRY(upload(ctx, &G.d_desc, hd.data(), hd.size()));
@@ -1386,13 +1397,23 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     e = hipEventRecord(ctx->ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
   }
+  // while the coarse factorisations run beside them, the one-wavefront cell
+  // inverses leave STV_CHAIN_VGPRS registers free on every SIMD: the
+  // elimination chain's latency-bound workgroups then start at once instead
+  // of waiting for the inverse kernel to drain whole compute units
+  int n_cu = 0;
+  if (STV_CHAIN_VGPRS > 0 && side != s && !ctx->cgroups.empty()) {
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+        hipSuccess)
+      n_cu = 0;
+  }
   auto cell_inverses = [&]() {
     for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
       const DevLevel& L = ctx->lv[g];
       if (L.n_cells == 0) continue;
       Timed t(ctx, KC_INVERSE, g, inv);
       e = launch_cell_inverses(inv, b, L, fp32, full, ctx->inv_status[g], ctx->inv_scratch[g],
-                               ctx->inv_slots[g]);
+                               ctx->inv_slots[g], n_cu, STV_CHAIN_VGPRS);
       if (e == hipSuccess) e = launch_first_flag(inv, ctx->inv_status[g], L.n_cells, rep + g);
       t.done();
     }

@@ -101,23 +101,29 @@ struct GjWork {
 // Dense Gauss-Jordan plan: algo 1 = one level of panels (width nb), 2 = slabs
 // of no columns eliminated by panels of nb, 3 = slabs whose panels take
 // tournament-chosen pivot rows; the matrix is padded to a multiple of pad;
-// max_n is the largest supported order.
-struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; };
+// max_n is the largest supported order.  pair (algo 3 only): the matrix is
+// the real form of a complex matrix (entry x of complex row i, column j at
+// real rows 2i, 2i+1 and columns 2j, 2j+1 as [[Re x, -Im x], [Im x, Re x]])
+// and the tournament chooses complex pivots, nb / 2 per panel of nb real
+// columns.
+struct GjPlan { int algo, cfg, nb, no, pad; int64_t max_n; bool pair; };
 
 // One diagonal block of a coarse member's time-decoupled operator, built
-// from the member's spatial factors: B[(a, s), (c, s')] = T[a][c] M(s, s') +
-// delta_ac A(s, s') for a, c < nt (nt = 1 or 2 time components), rows and
-// columns ordered a * n_s + s.
+// from the member's spatial factors in the real form of a complex matrix:
+// B[2s + a, 2s' + c] = T[a][c] M(s, s') + delta_ac A(s, s') (a, c < 2).  A
+// complex pair al +- i be has T = [[al, be], [-be, al]], the real form of the
+// complex matrix al M + A - i be M; a real eigenvalue lambda has T = lambda I
+// (two uncoupled copies of lambda M + A).
 struct KronBlockDesc {
   const int32_t* rowptr; const int32_t* col; const double* ma;
   int32_t row_off, n_s;
-  int nt;
   double t[4];
 };
 
 // Recombination of a member's inverse from its blocks' inverses:
-//   J^-1[(s, i), (s', l)] = sum_p sum_{a, c in block p} V[i][a] Binv_p[(a, s), (c, s')] W[c][l]
-// (time-inner rows s * b + i of the member's n0 x n0 inverse at inv_off).
+//   J^-1[(s, i), (s', l)] = sum_p sum_{a, c in block p} V[i][a] Binv_p[2s + a, 2s' + c] W[c][l]
+// (Binv_p of order 2 n_s; time-inner rows s * b + i of the member's n0 x n0
+// inverse at inv_off).
 struct KronRecomb {
   const double* binv[4];
   int nblk;
@@ -281,8 +287,13 @@ hipError_t launch_vanka_cells(hipStream_t s, int b, const DevLevel& L, const dou
 hipError_t launch_vanka_cells_corr(hipStream_t s, int b, const DevLevel& L, const double* rho,
                                    double omega, int fp32);
 hipError_t launch_vanka_combine(hipStream_t s, int b, const DevLevel& L, double* d, int pou);
+// n_cu > 0 and reserve > 0 cap the grid of the one-wavefront inverse kernel
+// (it strides over the cells) at the wavefronts per compute unit that leave
+// `reserve` VGPRs free on every SIMD, so that the kernels of a concurrent
+// stream find room beside it.
 hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,
-                                uint8_t* status, double* gscratch, int n_slots);
+                                uint8_t* status, double* gscratch, int n_slots, int n_cu,
+                                int reserve);
 hipError_t launch_restrict(hipStream_t s, int b, const DevLevel& L, const double* rho,
                            double* r_c);
 hipError_t launch_prolongate_add(hipStream_t s, int b, const DevLevel& L, const double* d_c,
@@ -292,7 +303,7 @@ hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 // dense coarse level
 hipError_t launch_bsr_to_dense(hipStream_t s, int b, const CoarseDesc* desc, int cnt,
                                int32_t max_rows, double* A, int64_t sA, int64_t n);
-GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */);
+GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */, bool pair);
 hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt);
 hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b, double* A,
                            int64_t sA, int64_t n);

@@ -133,11 +133,10 @@ def test_transposed_solve_ignores_factors(stv):
 def test_time_decoupled_coarse_inverse(stv, name):
     """With spatial factors on the coarsest level the coarse inverse is built
     from the diagonal blocks of the operator in the real Jordan basis of the
-    time matrix D^-1 C (dG(2): one real eigenvalue and one complex pair, two
-    independent eliminations of orders n_s and 2 n_s); dG(1) has a single
-    pair and keeps the whole-matrix elimination.  Both must reproduce the
-    oracle's dense inverse, with and without the factors on the coarsest
-    level."""
+    time matrix D^-1 C (dG(2): one real eigenvalue and one complex pair;
+    dG(1): a single pair), each block in real form of order 2 n_s and
+    eliminated with complex pivots.  Both must reproduce the oracle's dense
+    inverse, with and without the factors on the coarsest level."""
     p, ol = problem(name)
     s = kron_solver(stv, p)
     rng = np.random.default_rng(21)
