@@ -304,12 +304,15 @@ __device__ __forceinline__ void store_row(const stv_d4 (&acc)[NT][NT], int r, do
 //  - the rank-4 update A += W B is one MFMA per tile, the panel's own tile
 //    column first so that the next panel can start while the rest run.
 // The in-place result is permuted as in k_inverse_mfma.
-template <int B, int NLS>
+// DEC: the cell matrix is Q = M_T (x) T + A_T (x) I of the level's
+// CellSplit, gathered from the spatial factors (val = (m, a) per block
+// position), and the store takes its time-decoupled owned rows.
+template <int B, int NLS, bool DEC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ val,
                const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
                const int64_t* __restrict__ inv_off, int ld, void* store, int fp32,
-               uint8_t* status, int n_cells) {
+               uint8_t* status, int n_cells, CellSplit sp) {
   constexpr int N = B * NLS;
   constexpr int NT = (N + 15) / 16;
   constexpr int NP = 16 * NT;
@@ -320,6 +323,25 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
   __shared__ int rpiv[NP];
   __shared__ int rinv[NP];
   __shared__ int rowmap[NP];
+  // DEC: T[a][c] and the first stored column of the inverse entries with
+  // row component a and column component c (-1: not stored)
+  __shared__ double tco[B * B];
+  __shared__ int cmap[B * B];
+  if constexpr (DEC) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int e = 0; e < B * B; ++e) {
+        tco[e] = sp.T[e];
+        cmap[e] = -1;
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (p >= sp.nblk) break;
+        const int f = sp.first[p];
+        for (int a = 0; a < sp.sz[p]; ++a) cmap[f * B + f + a] = sp.off[p] + a * NLS;
+      }
+    }
+  }
   // grid-stride over the cells: a capped grid leaves room on every SIMD
   // for the kernels of a concurrent stream
   for (int T = blockIdx.x; T < n_cells; T += gridDim.x) {
@@ -363,8 +385,14 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
           const int cc = col < N ? col : N - 1;
           const int be = cc / B;
           const int32_t q = spos[ra * NLS + be];
-          const double x =
-              val[(int64_t)(q > 0 ? q : 0) * (B * B) + (rc - ra * B) * B + (cc - be * B)];
+          double x;
+          if constexpr (DEC) {
+            const double2 ma = *reinterpret_cast<const double2*>(&val[2 * (int64_t)(q > 0 ? q : 0)]);
+            const int ar = rc - ra * B, ac = cc - be * B;
+            x = fma(tco[ar * B + ac], ma.x, ar == ac ? ma.y : 0.0);
+          } else {
+            x = val[(int64_t)(q > 0 ? q : 0) * (B * B) + (rc - ra * B) * B + (cc - be * B)];
+          }
           // bitwise predicates and a value select: no branch for the load to
           // sink into
           const bool inb = (row < N) & (col < N);
@@ -477,7 +505,7 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
       const int o0 = own_ptr[T], no = own_ptr[T + 1] - o0;
       for (int e = lane; e < no * B; e += 64) {
         const int os = e / B;
-        rowmap[own_loc[o0 + os] * B + (e - os * B)] = e;
+        rowmap[own_loc[o0 + os] * B + (e - os * B)] = DEC ? os : e;
       }
     }
     if (lane == 0) status[T] = (uint8_t)sing;
@@ -493,8 +521,13 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
           const int p = rinv[16 * ti + 4 * v + lr];
           if (p < N && j < N) {
             const int o = rowmap[p];
-            if (o >= 0) {
-              const int64_t e = off + (int64_t)o * ld + j;
+            int col = j;
+            if constexpr (DEC) {
+              const int be = j / B, base = cmap[(j - be * B) * B + p % B];
+              col = base >= 0 ? base + be : -1;
+            }
+            if (o >= 0 && col >= 0) {
+              const int64_t e = off + (int64_t)o * ld + col;
               if (fp32) ((float*)store)[e] = (float)acc[ti][tj][v];
               else ((double*)store)[e] = acc[ti][tj][v];
             }
@@ -625,13 +658,24 @@ static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full,
   constexpr int NT = (B * NLS + 15) / 16;
   if constexpr (NT <= 4) {
     int grid = L.n_cells;
+    if (L.dec) {
+      if (!L.kron_ma || L.split.b != B) return hipErrorInvalidValue;
+      if (n_cu > 0 && reserve > 0) {
+        static const int per_cu = waves_leaving(k_inverse_wave<B, NLS, true>, reserve);
+        if (per_cu > 0) grid = std::min(grid, n_cu * per_cu);
+      }
+      k_inverse_wave<B, NLS, true><<<grid, 64, 0, s>>>(L.posmap, L.kron_ma, L.own_ptr, L.own_loc,
+                                                       full, L.inv_off, L.inv_ld, L.inv_store,
+                                                       fp32, status, L.n_cells, L.split);
+      return hipGetLastError();
+    }
     if (n_cu > 0 && reserve > 0) {
-      static const int per_cu = waves_leaving(k_inverse_wave<B, NLS>, reserve);
+      static const int per_cu = waves_leaving(k_inverse_wave<B, NLS, false>, reserve);
       if (per_cu > 0) grid = std::min(grid, n_cu * per_cu);
     }
-    k_inverse_wave<B, NLS><<<grid, 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc, full,
-                                               L.inv_off, L.inv_ld, L.inv_store, fp32, status,
-                                               L.n_cells);
+    k_inverse_wave<B, NLS, false><<<grid, 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc, full,
+                                                      L.inv_off, L.inv_ld, L.inv_store, fp32,
+                                                      status, L.n_cells, CellSplit{});
     return hipGetLastError();
   } else {
     k_inverse_mfma<B, NLS><<<L.n_cells, NT * 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc,

@@ -451,11 +451,155 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vanka cell sweep on time-decoupled inverses (CellSplit, last-writer form):
+//   d_T <- d_T + omega (I (x) V) Q^-1 (I (x) W) rho_T   on the owned rows.
+// One 64-lane wavefront per cell (B * NLS <= 64).  Lane j gathers rho_T[j]
+// (local order alpha * B + l) and forms u = (I (x) W) rho_T in the same
+// order (the B values of a spatial DoF by shuffles).  Lane j then takes the
+// multipliers of stored column j: in block p (first time component f) at
+// spatial DoF s, column j multiplies u[s, f] into output f; in the second
+// half of a pair block (the imaginary part of the complex inverse) it
+// multiplies -u[s, f + 1] into output f and u[s, f] into output f + 1, and
+// in the first half u[s, f + 1] into output f + 1 as well: the real form of
+// the complex product.  Each stored row (one owned spatial DoF) is one
+// coalesced read and gives B per-lane products; 16 / BP rows at a time are
+// folded by one transpose-reduce, and the lane of DoF (k, i) combines the
+// B outputs of row k with row i of V.  Stores as in k_vanka.
+template <int B, int NLS, typename TS>
+__global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rho,
+                                                  double* __restrict__ d,
+                                                  const int32_t* __restrict__ csd,
+                                                  const int32_t* __restrict__ own_ptr,
+                                                  const uint8_t* __restrict__ own_loc,
+                                                  const int64_t* __restrict__ inv_off, int ld,
+                                                  const TS* __restrict__ store, double omega,
+                                                  int zero_init, int n_cells, CellSplit sp) {
+  constexpr int N = B * NLS;
+  static_assert(N <= 64 && NLS <= 64, "one wavefront per cell");
+  constexpr int BP = B <= 2 ? 2 : 4;       // outputs per stored row, padded to a power of two
+  constexpr int GN = 16 / BP;              // stored rows per transpose-reduce
+  constexpr int GL = 2 * GN;               // stored rows loaded together
+  const int lane = threadIdx.x & 63;
+  const int jl = lane < N ? lane : N - 1;
+  const int al = jl / B, cl = jl - al * B;   // spatial DoF and time component of lane j
+  // W[cl][.], and V[i][.] for the output row r = lane (component i = lane % B)
+  const int il = lane % B;
+  double wl[B], vl[B];
+#pragma unroll
+  for (int l = 0; l < B; ++l) {
+    double w = sp.W[l], v = sp.V[l];
+#pragma unroll
+    for (int c = 1; c < B; ++c) {
+      w = cl == c ? sp.W[c * B + l] : w;
+      v = il == c ? sp.V[c * B + l] : v;
+    }
+    wl[l] = w;
+    vl[l] = v;
+  }
+  // stored column j: source lanes of u and the multipliers per output
+  int srca = 0, srcb = 0;
+  double ca[B], cb[B];
+#pragma unroll
+  for (int o = 0; o < B; ++o) ca[o] = cb[o] = 0.0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (p >= sp.nblk) break;
+    const int o0 = sp.off[p], sz = sp.sz[p], f = sp.first[p];
+    const int rel = lane - o0;
+    if (rel >= 0 && rel < sz * NLS) {
+      const bool im = rel >= NLS;
+      const int s = im ? rel - NLS : rel;
+      srca = s * B + f;
+      srcb = s * B + f + (sz == 2 ? 1 : 0);
+#pragma unroll
+      for (int o = 0; o < B; ++o) {
+        if (sz == 1) {
+          ca[o] = o == f ? 1.0 : 0.0;
+        } else if (!im) {
+          ca[o] = o == f ? 1.0 : 0.0;
+          cb[o] = o == f + 1 ? 1.0 : 0.0;
+        } else {
+          cb[o] = o == f ? -1.0 : 0.0;
+          ca[o] = o == f + 1 ? 1.0 : 0.0;
+        }
+      }
+    }
+  }
+  const int T0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  for (int T = T0; T < n_cells; T += gridDim.x * 4) {
+    const int32_t* sd = csd + (int64_t)T * NLS;
+    const int o0 = own_ptr[T];
+    const int no = own_ptr[T + 1] - o0;
+    if (no <= 0) continue;
+    const int R = no * B;
+    const TS* A = store + inv_off[T];
+    const double xv = rho[(int64_t)sd[al] * B + cl];
+    const double x = lane < N ? xv : 0.0;
+    double u = 0.0;
+#pragma unroll
+    for (int l = 0; l < B; ++l) u = fma(wl[l], __shfl(x, al * B + l, 64), u);
+    const double ua = __shfl(u, srca, 64), ub = __shfl(u, srcb, 64);
+    double m[B];
+#pragma unroll
+    for (int o = 0; o < B; ++o) m[o] = fma(ca[o], ua, cb[o] * ub);
+    // the owned DoF of each stored row (lane = owned index), the row this
+    // lane stores (r = lane = k * B + i), its global index and old value
+    const int ok = lane < no ? lane : no - 1;
+    const int gs = sd[own_loc[o0 + ok]];
+    const int rl = lane < R ? lane : R - 1;
+    const int kl = rl / B;
+    const int64_t gi = (int64_t)__shfl(gs, kl, 64) * B + (rl - kl * B);
+    const double dold = zero_init ? 0.0 : d[gi];
+    double res = 0.0;
+    for (int k0 = 0; k0 < no; k0 += GL) {
+      TS a[GL];
+#pragma unroll
+      for (int t = 0; t < GL; ++t) {
+        const int row = min(k0 + t, no - 1);
+        a[t] = A[(unsigned)(row * ld + jl)];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double pp[16];
+#pragma unroll
+        for (int t = 0; t < GN; ++t)
+#pragma unroll
+          for (int o = 0; o < BP; ++o) pp[t * BP + o] = o < B ? (double)a[h * GN + t] * m[o] : 0.0;
+        const double sum = fold<16>(pp, lane);   // value t * BP + o in lanes 4 (t * BP + o) ..
+        const int kb = k0 + h * GN;
+        const int kk = kl - kb;                  // this lane's row within the group
+        const int kc = kk < 0 ? 0 : (kk >= GN ? GN - 1 : kk);
+        double val = 0.0;
+#pragma unroll
+        for (int o = 0; o < B; ++o) val = fma(vl[o], __shfl(sum, 4 * (kc * BP + o), 64), val);
+        if (kk >= 0 && kk < GN) res = val;
+      }
+    }
+    if (lane < R) d[gi] = zero_init ? omega * res : fma(omega, res, dold);
+  }
+}
+
 template <int B, int NLS>
 static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, double* d,
                            double omega, int zero_init, int fp32, int full) {
   unsigned grid = (unsigned)((L.n_cells + 3) / 4);
   if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
+  if constexpr (B * NLS <= 64) {
+    if (L.dec) {
+      if (full || L.split.b != B) return hipErrorInvalidValue;
+      if (fp32)
+        launch(k_vanka_dec<B, NLS, float>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
+               L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const float*)L.inv_store, omega,
+               zero_init, L.n_cells, L.split);
+      else
+        launch(k_vanka_dec<B, NLS, double>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
+               L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const double*)L.inv_store, omega,
+               zero_init, L.n_cells, L.split);
+      return hipGetLastError();
+    }
+  }
+  if (L.dec) return hipErrorInvalidValue;
 #define STV_VANKA(TS, F)                                                                     \
   launch(k_vanka<B, NLS, TS, F>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs, L.own_ptr, L.own_loc,  \
                                               L.inv_off, L.inv_ld, (const TS*)L.inv_store, \

@@ -937,6 +937,7 @@ struct TimeSplit {
   int nblk = 0;
   int sz[4] = {}, first[4] = {};
   double t[4][4] = {};   // per block, 2 x 2 row-major
+  double T[16] = {};     // the whole b x b block diagonal T, row-major
   double V[16] = {}, W[16] = {};
 };
 
@@ -1079,6 +1080,7 @@ static bool time_split(const double* C, const double* tw, int b, TimeSplit& out)
       dev = std::max(dev, std::fabs(kv - vt));
     }
   if (!(dev <= 1e-10 * kmax)) return false;
+  for (int e = 0; e < b * b; ++e) S.T[e] = T[e];
   // W = V^-1 D^-1 (Gauss-Jordan with partial pivoting), conditioning check
   double A[16], I[16];
   for (int e = 0; e < b * b; ++e) { A[e] = S.V[e]; I[e] = 0.0; }
@@ -1288,6 +1290,31 @@ static int make_inverse_stores(stv_ctx* ctx, int fp32, int full) {
     L.inv_elems = 0;
     if (L.n_cells == 0) continue;
     const int n = L.n_ls * b;
+    // with spatial factors, the owned-row layout of a level whose cell
+    // problems fit one wavefront stores the time-decoupled inverse: one row
+    // of n values per owned spatial DoF instead of b rows (CellSplit)
+    L.dec = 0;
+    TimeSplit S;
+    if (!full && L.kron_ma && n <= 64 && inverse_fits_regs(b, L.n_ls) &&
+        time_split(L.kron_C, L.kron_tw, b, S)) {
+      CellSplit& c = L.split;
+      c = CellSplit{};
+      c.b = b;
+      c.nblk = S.nblk;
+      int o = 0;
+      for (int p = 0; p < S.nblk; ++p) {
+        c.sz[p] = S.sz[p];
+        c.first[p] = S.first[p];
+        c.off[p] = o;
+        o += S.sz[p] * L.n_ls;
+      }
+      for (int e = 0; e < 16; ++e) {
+        c.T[e] = S.T[e];
+        c.V[e] = S.V[e];
+        c.W[e] = S.W[e];
+      }
+      L.dec = 1;
+    }
     // rows stored densely (padding each row to a 128-byte boundary was
     // measured slower: the sweep reads whole cells as one contiguous stream)
     L.inv_ld = n;
@@ -1295,7 +1322,8 @@ static int make_inverse_stores(stv_ctx* ctx, int fp32, int full) {
     int64_t tot = 0;
     for (int32_t c = 0; c < L.n_cells; ++c) {
       off[(size_t)c] = tot;
-      const int rows = full ? n : (L.h_own_ptr[(size_t)c + 1] - L.h_own_ptr[(size_t)c]) * b;
+      const int no = L.h_own_ptr[(size_t)c + 1] - L.h_own_ptr[(size_t)c];
+      const int rows = full ? n : L.dec ? no : no * b;
       tot += (int64_t)rows * L.inv_ld;
     }
     STV_TRY(upload(ctx, &L.inv_off, off.data(), off.size()));
@@ -1866,7 +1894,7 @@ int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out) {
   if (!out) return fail(ctx, STV_EINVAL, "out is NULL");
   const int b = ctx->b, nls = L.n_ls, n = nls * b;
   const int o0 = L.h_own_ptr[(size_t)cell], no = L.h_own_ptr[(size_t)cell + 1] - o0;
-  const int R = ctx->inv_full ? n : no * b;
+  const int R = ctx->inv_full ? n : L.dec ? no : no * b;
   const int ld = L.inv_ld;
   std::vector<int64_t> off(1);
   STV_HIP(hipMemcpy(off.data(), L.inv_off + cell, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -1879,6 +1907,40 @@ int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out) {
     STV_HIP(hipMemcpy(blk.data(), (const double*)L.inv_store + off[0], sizeof(double) * blk.size(), hipMemcpyDeviceToHost));
   }
   for (int64_t e = 0; e < (int64_t)n * n; ++e) out[e] = NAN;
+  if (L.dec) {
+    // J_T^-1[(alpha, i), (beta, l)] = sum_{a, c} V[i][a] Q^-1[(alpha, a), (beta, c)] W[c][l]
+    // with Q^-1 from the stored time-decoupled row of alpha
+    const CellSplit& S = L.split;
+    std::vector<double> q((size_t)b * b);
+    for (int os = 0; os < no; ++os) {
+      const int alpha = L.h_own_loc[(size_t)(o0 + os)];
+      const double* row = &blk[(size_t)os * ld];
+      for (int beta = 0; beta < nls; ++beta) {
+        std::fill(q.begin(), q.end(), 0.0);   // Q^-1[(alpha, a), (beta, c)]
+        for (int p = 0; p < S.nblk; ++p) {
+          const int f = S.first[p];
+          const double re = row[S.off[p] + beta];
+          if (S.sz[p] == 1) {
+            q[(size_t)f * b + f] = re;
+          } else {
+            const double im = row[S.off[p] + nls + beta];
+            q[(size_t)f * b + f] = re;
+            q[(size_t)f * b + f + 1] = -im;
+            q[(size_t)(f + 1) * b + f] = im;
+            q[(size_t)(f + 1) * b + f + 1] = re;
+          }
+        }
+        for (int i = 0; i < b; ++i)
+          for (int l = 0; l < b; ++l) {
+            double acc = 0.0;
+            for (int a = 0; a < b; ++a)
+              for (int c = 0; c < b; ++c) acc += S.V[i * b + a] * q[(size_t)a * b + c] * S.W[c * b + l];
+            out[(int64_t)(i * nls + alpha) * n + l * nls + beta] = acc;   // eq. (4.4) order
+          }
+      }
+    }
+    return STV_OK;
+  }
   // stored row index -> internal local index (alpha*b + l)
   for (int o = 0; o < R; ++o) {
     int alpha, l;
@@ -2029,6 +2091,7 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
     STV_HIP(hipStreamSynchronize(ctx->stream));
     dfree(L.kron_ma);
     ctx->cgroups_algo = -1;   // the coarse groups may refer to the factors
+    ctx->inv_layout = -1;     // and the cell-inverse layout of the level
     ++ctx->generation;
     free_graph(ctx);
     return STV_OK;
@@ -2075,6 +2138,7 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
   dfree(L.kron_ma);
   L.kron_ma = dma;
   ctx->cgroups_algo = -1;   // the coarse groups are regrouped at the next build
+  ctx->inv_layout = -1;     // the cell inverses may be stored time-decoupled
   for (int i = 0; i < 16; ++i) L.kron_C[i] = i < b * b ? C[i] : 0.0;
   for (int i = 0; i < 4; ++i) L.kron_tw[i] = i < b ? tw[i] : 0.0;
   ++ctx->generation;

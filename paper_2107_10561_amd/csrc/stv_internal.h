@@ -23,6 +23,23 @@ enum KernelClass {
   KC_GRAPH, KC_COUNT
 };
 
+// Time decoupling of the cell problems of a level with spatial factors
+// (cell matrix J_T = M_T (x) C + A_T (x) D, spatial index outer, D =
+// diag(tw)): with D^-1 C = V T V^-1 (T real block diagonal, blocks of order
+// sz[p] starting at time component first[p]),
+//   J_T^-1 = (I (x) V) Q^-1 (I (x) W),  Q = M_T (x) T + A_T (x) I,  W = V^-1 D^-1.
+// Q couples time components only inside a block; its inverse is stored per
+// owned spatial DoF a as one row of B * n_loc values: for each block p, at
+// columns off[p] + s (s < n_loc), Q^-1[(a, f), (s, f)] (f = first[p]), and
+// for a pair also, at off[p] + n_loc + s, Q^-1[(a, f + 1), (s, f)] (the real
+// and imaginary parts of the inverse of the complex block).  T, V, W are
+// b x b, row-major.
+struct CellSplit {
+  int b, nblk;
+  int sz[4], first[4], off[4];
+  double T[16], V[16], W[16];
+};
+
 // Device arrays of one level.
 struct DevLevel {
   int32_t n_s = 0, n_cells = 0, n_ls = 0;
@@ -65,6 +82,8 @@ struct DevLevel {
   int32_t* rowptr_t = nullptr; int32_t* col_t = nullptr; double* val_t = nullptr;
   // spatial factors (optional): blocks = C[i][l] M + delta_il tw[i] A
   double* kron_ma = nullptr;      // spatial factors (m, a), interleaved per block
+  int dec = 0;                    // the inverse store holds time-decoupled rows (CellSplit)
+  CellSplit split{};
   double kron_C[16] = {}, kron_tw[4] = {};
   int spmv_rpw = 2;               // residual shape: 1..4 (blocks), 1..6 (factors)
   int sweep_wgs = 0;              // workgroups of a persistent sweep (0: one wavefront per cell)
