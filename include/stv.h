@@ -342,7 +342,7 @@ int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs);
 /* Autotuner: on every smoothed level, time each residual shape (1..4 with
  * the blocks, 1..6 with spatial factors) and
  * each sweep shape (one wavefront per cell, or persistent
- * grids of 2, 4, 8, 16 workgroups per compute unit) on the device, five
+ * grids of 2, 4, 8, 16, 32 workgroups per compute unit) on the device, five
  * launches each after one untimed launch, and keep the fastest.  Needs the
  * inverses (the sweep is timed with the stored ones); uses temporary device
  * vectors; the hierarchy's data are not modified.  If choices is non-NULL

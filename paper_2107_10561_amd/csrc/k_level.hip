@@ -12,6 +12,43 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Partner value for lane ^ M inside a row of 16 lanes (M <= 8): DPP lane
+// permutations (xor 1, xor 2 as quad permutations, xor 8 as a rotation of the
+// row by 8) and, for xor 4, a swizzle in bit-mask mode.
+template <int M>
+__device__ __forceinline__ double xor_f64(double v) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8, "inside a row");
+  if constexpr (M == 1) return dpp_f64<0xB1>(v);          // quad_perm [1,0,3,2]
+  if constexpr (M == 2) return dpp_f64<0x4E>(v);          // quad_perm [2,3,0,1]
+  if constexpr (M == 8) return dpp_f64<0x128>(v);         // row_ror:8
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x101F);   // xor 4
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x101F);
+  return __hiloint2double(hi, lo);
+}
+
+// x, y <- the lanes with bit M clear keep x and receive y's values of the
+// partner lanes (lane ^ M) in y, and vice versa: one v_permlane{16,32}_swap
+// per 32-bit half (M = 16: odd rows of x with even rows of y; M = 32: upper
+// half of x with lower half of y).  Afterwards x + y is, in every lane, its
+// own kept value plus its partner's sent one.
+template <int M>
+__device__ __forceinline__ void swap_halves(double& x, double& y) {
+  static_assert(M == 16 || M == 32, "across rows");
+  const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+  const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+  if constexpr (M == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    x = __hiloint2double((int)h[0], (int)l[0]);
+    y = __hiloint2double((int)h[1], (int)l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    x = __hiloint2double((int)h[0], (int)l[0]);
+    y = __hiloint2double((int)h[1], (int)l[1]);
+  }
+}
+
 // Transpose-reduce: NV (a power of two, 2..64) per-lane partial sums are
 // summed over the wavefront; afterwards the lanes L with L / (64 / NV) == v
 // hold the total of value v.  Each halving step exchanges half of the values
@@ -36,6 +73,47 @@ __device__ __forceinline__ double fold(double (&p)[NV], int lane) {
   double u = p[0];
 #pragma unroll
   for (int m = 32 / NV; m >= 1; m >>= 1) u += __shfl_xor(u, m, 64);
+  return u;
+}
+
+// The same transpose-reduce with the exchanges done without LDS: across
+// rows by lane-half swaps, inside a row by DPP and swizzle.  Every sum takes
+// the same two operands as in fold, so the results are identical.
+template <int CNT, int M, int NV>
+__device__ __forceinline__ void fold_swap_level(double (&p)[NV], int lane) {
+  if constexpr (CNT > 1) {
+    if constexpr (M >= 16) {
+#pragma unroll
+      for (int t = 0; t < CNT / 2; ++t) {
+        double x = p[t], y = p[t + CNT / 2];
+        swap_halves<M>(x, y);
+        p[t] = x + y;
+      }
+    } else {
+      const bool hi = lane & M;
+#pragma unroll
+      for (int t = 0; t < CNT / 2; ++t) {
+        const double keep = hi ? p[t + CNT / 2] : p[t];
+        const double send = hi ? p[t] : p[t + CNT / 2];
+        p[t] = keep + xor_f64<M>(send);
+      }
+    }
+    fold_swap_level<CNT / 2, M / 2, NV>(p, lane);
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ double fold_swap(double (&p)[NV], int lane) {
+  static_assert(NV >= 4, "the final exchanges stay inside a row");
+  fold_swap_level<NV, 32, NV>(p, lane);
+  double u = p[0];
+#pragma unroll
+  for (int m = 32 / NV; m >= 1; m >>= 1) {
+    if (m == 8) u += xor_f64<8>(u);
+    else if (m == 4) u += xor_f64<4>(u);
+    else if (m == 2) u += xor_f64<2>(u);
+    else u += xor_f64<1>(u);
+  }
   return u;
 }
 
@@ -462,7 +540,8 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
 // half of a pair block (the imaginary part of the complex inverse) it
 // multiplies -u[s, f + 1] into output f and u[s, f] into output f + 1, and
 // in the first half u[s, f + 1] into output f + 1 as well: the real form of
-// the complex product.  Each stored row (one owned spatial DoF) is one
+// the complex product (the lane's constants come from the level's table,
+// made with the store).  Each stored row (one owned spatial DoF) is one
 // coalesced read and gives B per-lane products; 16 / BP rows at a time are
 // folded by one transpose-reduce, and the lane of DoF (k, i) combines the
 // B outputs of row k with row i of V.  Stores as in k_vanka.
@@ -474,67 +553,65 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
                                                   const uint8_t* __restrict__ own_loc,
                                                   const int64_t* __restrict__ inv_off, int ld,
                                                   const TS* __restrict__ store, double omega,
-                                                  int zero_init, int n_cells, CellSplit sp) {
+                                                  int zero_init, int n_cells,
+                                                  const double* __restrict__ tab,
+                                                  const int32_t* __restrict__ code) {
   constexpr int N = B * NLS;
   static_assert(N <= 64 && NLS <= 64, "one wavefront per cell");
   constexpr int BP = B <= 2 ? 2 : 4;       // outputs per stored row, padded to a power of two
   constexpr int GN = 16 / BP;              // stored rows per transpose-reduce
-  constexpr int GL = 2 * GN;               // stored rows loaded together
+  // stored rows loaded together: an interior cell owns about n_loc / 2
+  // spatial DoFs, so one round of loads usually covers the cell (every load
+  // in flight at once; each transpose-reduce waits only for its own rows)
+#ifndef STV_DEC_FPR
+#define STV_DEC_FPR (B == 2 ? 2 : 3)
+#endif
+  constexpr int GL = STV_DEC_FPR * GN;
   const int lane = threadIdx.x & 63;
   const int jl = lane < N ? lane : N - 1;
   const int al = jl / B, cl = jl - al * B;   // spatial DoF and time component of lane j
-  // W[cl][.], and V[i][.] for the output row r = lane (component i = lane % B)
-  const int il = lane % B;
-  double wl[B], vl[B];
+  // per-lane constants of the level: W[cl][.], V[lane % B][.], the source
+  // lanes of u and the multipliers of stored column j = lane
+  double wl[B], vl[B], ca[B], cb[B];
 #pragma unroll
   for (int l = 0; l < B; ++l) {
-    double w = sp.W[l], v = sp.V[l];
-#pragma unroll
-    for (int c = 1; c < B; ++c) {
-      w = cl == c ? sp.W[c * B + l] : w;
-      v = il == c ? sp.V[c * B + l] : v;
-    }
-    wl[l] = w;
-    vl[l] = v;
+    wl[l] = tab[l * 64 + lane];
+    vl[l] = tab[(B + l) * 64 + lane];
   }
-  // stored column j: source lanes of u and the multipliers per output
-  int srca = 0, srcb = 0;
-  double ca[B], cb[B];
+  const int cd = code[lane];
+  const int srca = cd & 63, srcb = (cd >> 6) & 63;
 #pragma unroll
-  for (int o = 0; o < B; ++o) ca[o] = cb[o] = 0.0;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    if (p >= sp.nblk) break;
-    const int o0 = sp.off[p], sz = sp.sz[p], f = sp.first[p];
-    const int rel = lane - o0;
-    if (rel >= 0 && rel < sz * NLS) {
-      const bool im = rel >= NLS;
-      const int s = im ? rel - NLS : rel;
-      srca = s * B + f;
-      srcb = s * B + f + (sz == 2 ? 1 : 0);
-#pragma unroll
-      for (int o = 0; o < B; ++o) {
-        if (sz == 1) {
-          ca[o] = o == f ? 1.0 : 0.0;
-        } else if (!im) {
-          ca[o] = o == f ? 1.0 : 0.0;
-          cb[o] = o == f + 1 ? 1.0 : 0.0;
-        } else {
-          cb[o] = o == f ? -1.0 : 0.0;
-          ca[o] = o == f + 1 ? 1.0 : 0.0;
-        }
-      }
-    }
+  for (int o = 0; o < B; ++o) {
+    const int ea = (cd >> (12 + 2 * o)) & 3, eb = (cd >> (12 + 2 * B + 2 * o)) & 3;
+    ca[o] = ea == 1 ? 1.0 : (ea == 3 ? -1.0 : 0.0);
+    cb[o] = eb == 1 ? 1.0 : (eb == 3 ? -1.0 : 0.0);
   }
-  const int T0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  for (int T = T0; T < n_cells; T += gridDim.x * 4) {
-    const int32_t* sd = csd + (int64_t)T * NLS;
-    const int o0 = own_ptr[T];
-    const int no = own_ptr[T + 1] - o0;
+  // the cell's offsets and its DoF list are fetched one cell ahead (a
+  // persistent grid strides over the cells), so that a cell starts with its
+  // row loads and its gather instead of a chain of dependent loads
+  const int stride = gridDim.x * 4;
+  int T = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  int o0n = 0, nxn = 0, sdn = 0;
+  int64_t offn = 0;
+  if (T < n_cells) {
+    o0n = own_ptr[T];
+    nxn = own_ptr[T + 1];
+    offn = inv_off[T];
+    sdn = csd[(int64_t)T * NLS + al];
+  }
+  for (; T < n_cells; T += stride) {
+    const int o0 = o0n, no = nxn - o0n, sdv = sdn;
+    const TS* A = store + offn;
+    const int Tn = T + stride;
+    if (Tn < n_cells) {
+      o0n = own_ptr[Tn];
+      nxn = own_ptr[Tn + 1];
+      offn = inv_off[Tn];
+      sdn = csd[(int64_t)Tn * NLS + al];
+    }
     if (no <= 0) continue;
     const int R = no * B;
-    const TS* A = store + inv_off[T];
-    const double xv = rho[(int64_t)sd[al] * B + cl];
+    const double xv = rho[(int64_t)sdv * B + cl];
     const double x = lane < N ? xv : 0.0;
     double u = 0.0;
 #pragma unroll
@@ -543,10 +620,11 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
     double m[B];
 #pragma unroll
     for (int o = 0; o < B; ++o) m[o] = fma(ca[o], ua, cb[o] * ub);
-    // the owned DoF of each stored row (lane = owned index), the row this
-    // lane stores (r = lane = k * B + i), its global index and old value
+    // the owned DoF of each stored row (lane = owned index; its spatial
+    // index from the lanes of its local DoF), the row this lane stores
+    // (r = lane = k * B + i), its global index and old value
     const int ok = lane < no ? lane : no - 1;
-    const int gs = sd[own_loc[o0 + ok]];
+    const int gs = __shfl(sdv, own_loc[o0 + ok] * B, 64);
     const int rl = lane < R ? lane : R - 1;
     const int kl = rl / B;
     const int64_t gi = (int64_t)__shfl(gs, kl, 64) * B + (rl - kl * B);
@@ -560,13 +638,13 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
         a[t] = A[(unsigned)(row * ld + jl)];
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < GL / GN; ++h) {
         double pp[16];
 #pragma unroll
         for (int t = 0; t < GN; ++t)
 #pragma unroll
           for (int o = 0; o < BP; ++o) pp[t * BP + o] = o < B ? (double)a[h * GN + t] * m[o] : 0.0;
-        const double sum = fold<16>(pp, lane);   // value t * BP + o in lanes 4 (t * BP + o) ..
+        const double sum = fold_swap<16>(pp, lane);   // value t * BP + o in lanes 4 (t * BP + o) ..
         const int kb = k0 + h * GN;
         const int kk = kl - kb;                  // this lane's row within the group
         const int kc = kk < 0 ? 0 : (kk >= GN ? GN - 1 : kk);
@@ -587,15 +665,15 @@ static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, 
   if (L.sweep_wgs > 0 && (unsigned)L.sweep_wgs < grid) grid = (unsigned)L.sweep_wgs;
   if constexpr (B * NLS <= 64) {
     if (L.dec) {
-      if (full || L.split.b != B) return hipErrorInvalidValue;
+      if (full || L.split.b != B || !L.dec_tab || !L.dec_code) return hipErrorInvalidValue;
       if (fp32)
         launch(k_vanka_dec<B, NLS, float>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
                L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const float*)L.inv_store, omega,
-               zero_init, L.n_cells, L.split);
+               zero_init, L.n_cells, (const double*)L.dec_tab, (const int32_t*)L.dec_code);
       else
         launch(k_vanka_dec<B, NLS, double>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
                L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const double*)L.inv_store, omega,
-               zero_init, L.n_cells, L.split);
+               zero_init, L.n_cells, (const double*)L.dec_tab, (const int32_t*)L.dec_code);
       return hipGetLastError();
     }
   }

@@ -105,6 +105,9 @@ void free_inverses(stv_ctx* ctx) {
   for (int g = 0; g < kMaxLevels; ++g) {
     dfree(ctx->lv[g].inv_off);
     dfree(ctx->lv[g].inv_store);
+    dfree(ctx->lv[g].dec_tab);
+    dfree(ctx->lv[g].dec_code);
+    ctx->lv[g].dec = 0;
     ctx->lv[g].inv_elems = 0;
     dfree(ctx->inv_status[g]);
     dfree(ctx->inv_scratch[g]);
@@ -124,7 +127,7 @@ void free_level(DevLevel& L) {
   dfree(L.own_ptr); dfree(L.own_loc); dfree(L.inc_ptr); dfree(L.inc_cell); dfree(L.inc_loc);
   dfree(L.P_rowptr); dfree(L.P_col); dfree(L.P_val);
   dfree(L.Pt_rowptr); dfree(L.Pt_col); dfree(L.Pt_val);
-  dfree(L.inv_off); dfree(L.inv_store); dfree(L.posmap);
+  dfree(L.inv_off); dfree(L.inv_store); dfree(L.posmap); dfree(L.dec_tab); dfree(L.dec_code);
   dfree(L.rho); dfree(L.r); dfree(L.d); dfree(L.corr);
   dfree(L.rowptr_t); dfree(L.col_t); dfree(L.val_t);
   dfree(L.kron_ma);
@@ -1287,7 +1290,10 @@ static int make_inverse_stores(stv_ctx* ctx, int fp32, int full) {
     DevLevel& L = ctx->lv[g];
     dfree(L.inv_off);
     dfree(L.inv_store);
+    dfree(L.dec_tab);
+    dfree(L.dec_code);
     L.inv_elems = 0;
+    L.dec = 0;
     if (L.n_cells == 0) continue;
     const int n = L.n_ls * b;
     // with spatial factors, the owned-row layout of a level whose cell
@@ -1313,6 +1319,40 @@ static int make_inverse_stores(stv_ctx* ctx, int fp32, int full) {
         c.V[e] = S.V[e];
         c.W[e] = S.W[e];
       }
+      // the sweep's per-lane constants (stored column j = lane)
+      std::vector<double> tab((size_t)2 * b * 64);
+      std::vector<int32_t> code(64, 0);
+      auto enc = [](int v) { return v == 1 ? 1 : v == -1 ? 3 : 0; };
+      for (int lane = 0; lane < 64; ++lane) {
+        const int jl = std::min(lane, n - 1), cl = jl % b, il = lane % b;
+        for (int l = 0; l < b; ++l) {
+          tab[(size_t)l * 64 + lane] = S.W[cl * b + l];
+          tab[(size_t)(b + l) * 64 + lane] = S.V[il * b + l];
+        }
+        int srca = 0, srcb = 0, ca[4] = {}, cb[4] = {};
+        for (int p = 0; p < S.nblk; ++p) {
+          const int rel = lane - c.off[p], sz = S.sz[p], f = S.first[p];
+          if (rel < 0 || rel >= sz * L.n_ls) continue;
+          const bool im = rel >= L.n_ls;
+          const int sp = im ? rel - L.n_ls : rel;
+          srca = sp * b + f;
+          srcb = sp * b + f + (sz == 2 ? 1 : 0);
+          if (sz == 1) {
+            ca[f] = 1;
+          } else if (!im) {
+            ca[f] = 1;
+            cb[f + 1] = 1;
+          } else {
+            cb[f] = -1;
+            ca[f + 1] = 1;
+          }
+        }
+        int w = srca | (srcb << 6);
+        for (int o = 0; o < b; ++o) w |= (enc(ca[o]) << (12 + 2 * o)) | (enc(cb[o]) << (12 + 2 * b + 2 * o));
+        code[(size_t)lane] = w;
+      }
+      STV_TRY(upload(ctx, &L.dec_tab, tab.data(), tab.size()));
+      STV_TRY(upload(ctx, &L.dec_code, code.data(), code.size()));
       L.dec = 1;
     }
     // rows stored densely (padding each row to a 128-byte boundary was
@@ -2054,8 +2094,8 @@ int stv_autotune(stv_ctx* ctx, int* choices, int cap) {
     int cu = 256;
     (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
     const int full_grid = (L.n_cells + 3) / 4;
-    const int cand[5] = {0, 2 * cu, 4 * cu, 8 * cu, 16 * cu};
-    for (int c = 0; c < 5 && e == hipSuccess; ++c) {
+    const int cand[6] = {0, 2 * cu, 4 * cu, 8 * cu, 16 * cu, 32 * cu};
+    for (int c = 0; c < 6 && e == hipSuccess; ++c) {
       if (c > 0 && cand[c] >= full_grid) break;
       L.sweep_wgs = cand[c];
       double ms = 0;

@@ -84,6 +84,12 @@ struct DevLevel {
   double* kron_ma = nullptr;      // spatial factors (m, a), interleaved per block
   int dec = 0;                    // the inverse store holds time-decoupled rows (CellSplit)
   CellSplit split{};
+  // per lane j of the decoupled sweep: W[j % B][.] and V[j % B][.] (2B x 64,
+  // row-major), and a code word: source lanes of u (bits 0-5, 6-11) and the
+  // multipliers (2 bits per output: 0 = 0, 1 = +1, 3 = -1; from bit 12 for
+  // the first source, from bit 12 + 2B for the second)
+  double* dec_tab = nullptr;
+  int32_t* dec_code = nullptr;
   double kron_C[16] = {}, kron_tw[4] = {};
   int spmv_rpw = 2;               // residual shape: 1..4 (blocks), 1..6 (factors)
   int sweep_wgs = 0;              // workgroups of a persistent sweep (0: one wavefront per cell)

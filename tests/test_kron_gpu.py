@@ -182,7 +182,16 @@ def test_time_decoupled_cell_inverses_and_sweeps(stv, name):
     d0 = rng.standard_normal(ol[g].n_st)
     dd = to_dev(d0)
     s.vanka_sweep(g, to_dev(r), dd, 1, 0.7)
-    e1 = relerr(to_host(dd), oracle.vanka_sweep(ol[g], r, d0, 0.7))
+    d1 = to_host(dd)
+    e1 = relerr(d1, oracle.vanka_sweep(ol[g], r, d0, 0.7))
+    # persistent grids (each wavefront strides over several cells, fetching
+    # the next cell's offsets ahead): bitwise the same result
+    for w in (1, 3, 64):
+        s.set_launch(g, 2, w)
+        dd = to_dev(d0)
+        s.vanka_sweep(g, to_dev(r), dd, 1, 0.7)
+        assert np.array_equal(to_host(dd), d1), w
+    s.set_launch(g, 2, 0)
     z = np.zeros(ol[g].n_st)
     ref2 = oracle.vanka_sweep(ol[g], r, oracle.vanka_sweep(ol[g], r, z, 0.7), 0.7)
     errs = []
