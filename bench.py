@@ -597,7 +597,12 @@ def main():
 
     kname_res = ("level residual from spatial factors (k_spmv_kron)" if kron
                  else "block-sparse level residual (k_spmv_rows)")
-    roof_sweep = roofline("sweep", sweep_bytes_packed, "Vanka cell sweep (k_vanka)", "k_vanka")
+    # with spatial factors the library stores the owned rows of 2d cell
+    # problems (n_loc = 21, B <= 3) time-decoupled and sweeps with k_vanka_dec
+    dec = kron and dim == 2 and 2 <= b <= 3
+    roof_sweep = (roofline("sweep", sweep_bytes_packed,
+                           "Vanka cell sweep on time-decoupled inverses (k_vanka_dec)", "k_vanka_dec")
+                  if dec else roofline("sweep", sweep_bytes_packed, "Vanka cell sweep (k_vanka)", "k_vanka"))
     roof_res = roofline("residual", residual_bytes_packed, kname_res,
                         "k_spmv_kron" if kron else "k_spmv")
     dominant = roof_sweep if stats["sweep"]["ms"] >= stats["residual"]["ms"] else roof_res
