@@ -209,3 +209,38 @@ def test_time_decoupled_cell_inverses_and_sweeps(stv, name):
     log(f"[kron] {name} decoupled sweeps rel err: one {e1:.2e}, two fp64 {errs[0]:.2e}, "
         f"two fp32 {errs[1]:.2e}")
     assert e1 <= 1e-12 and errs[0] <= 1e-12 and errs[1] <= 1e-5
+
+
+def test_store_layout_follows_the_build(stv):
+    """The inverse store keeps the layout of the build that made it: factors
+    set after a build leave the plain owned-row store in use until the next
+    build, which stores the time-decoupled rows; dropping the factors and
+    rebuilding returns to the plain store.  Every state sweeps like the
+    oracle."""
+    p, ol = problem("2d_dg2")
+    g = len(ol) - 1
+    rng = np.random.default_rng(41)
+    r, d0 = rng.standard_normal(ol[g].n_st), rng.standard_normal(ol[g].n_st)
+    ref = oracle.vanka_sweep(ol[g], r, d0, 0.7)
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    s.build_cell_inverses()
+    plain = s.level_info(g)["inverse_bytes"]
+    C, tw = time_factors(p)
+    for lv, Lv in enumerate(p.levels):
+        m, a = spatial_factors(Lv)
+        s.set_kron_factors(lv, m, a, C, tw)
+    sizes = []
+    for step in ("factors set, old store", "rebuilt", "dropped, rebuilt"):
+        if step == "rebuilt":
+            s.build_cell_inverses()
+        if step == "dropped, rebuilt":
+            for lv in range(len(p.levels)):
+                s.set_kron_factors(lv, None, None, None, None)
+            s.build_cell_inverses()
+        sizes.append(s.level_info(g)["inverse_bytes"])
+        dd = to_dev(d0)
+        s.vanka_sweep(g, to_dev(r), dd, 1, 0.7)
+        assert relerr(to_host(dd), ref) <= 1e-12, step
+    assert sizes[0] == plain and sizes[2] == plain
+    assert sizes[1] * p.b == plain     # one row per owned spatial DoF instead of k+1
