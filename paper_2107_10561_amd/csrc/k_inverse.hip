@@ -304,15 +304,18 @@ __device__ __forceinline__ void store_row(const stv_d4 (&acc)[NT][NT], int r, do
 //  - the rank-4 update A += W B is one MFMA per tile, the panel's own tile
 //    column first so that the next panel can start while the rest run.
 // The in-place result is permuted as in k_inverse_mfma.
-// DEC: the cell matrix is Q = M_T (x) T + A_T (x) I of the level's
-// CellSplit, gathered from the spatial factors (val = (m, a) per block
-// position), and the store takes its time-decoupled owned rows.
+// DEC: the cell matrix is Q = M_T (x) T + A_T (x) I of the CellSplit sp,
+// gathered from the spatial factors (val = (m, a) per block position), and
+// the store takes its time-decoupled owned rows (sp describes one diagonal
+// block of a level's split: B = its order in time).  keep_status: a cell's
+// status is only raised, so that the launches of several blocks combine.
+
 template <int B, int NLS, bool DEC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ val,
                const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
                const int64_t* __restrict__ inv_off, int ld, void* store, int fp32,
-               uint8_t* status, int n_cells, CellSplit sp) {
+               uint8_t* status, int n_cells, CellSplit sp, int keep_status) {
   constexpr int N = B * NLS;
   constexpr int NT = (N + 15) / 16;
   constexpr int NP = 16 * NT;
@@ -508,7 +511,7 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
         rowmap[own_loc[o0 + os] * B + (e - os * B)] = DEC ? os : e;
       }
     }
-    if (lane == 0) status[T] = (uint8_t)sing;
+    if (lane == 0 && (!keep_status || sing)) status[T] = (uint8_t)sing;
     wave_lds_sync();
     const int64_t off = inv_off[T];
 #pragma unroll
@@ -660,14 +663,45 @@ static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full,
     int grid = L.n_cells;
     if (L.dec) {
       if (!L.kron_ma || L.split.b != B) return hipErrorInvalidValue;
-      if (n_cu > 0 && reserve > 0) {
-        static const int per_cu = waves_leaving(k_inverse_wave<B, NLS, true>, reserve);
-        if (per_cu > 0) grid = std::min(grid, n_cu * per_cu);
+      // one launch per diagonal block of the split: the real block of a
+      // real eigenvalue (order n_loc) or the real form of a pair (2 n_loc)
+      if constexpr (2 * NLS <= 64) {
+        for (int p = 0; p < L.split.nblk; ++p) {
+          const int sz = L.split.sz[p], f = L.split.first[p];
+          CellSplit one{};
+          one.b = sz;
+          one.nblk = 1;
+          one.sz[0] = sz;
+          one.first[0] = 0;
+          one.off[0] = L.split.off[p];
+          for (int a = 0; a < sz; ++a)
+            for (int c = 0; c < sz; ++c) one.T[a * sz + c] = L.split.T[(f + a) * B + f + c];
+          int g = L.n_cells;
+          if (sz == 1) {
+            if (n_cu > 0 && reserve > 0) {
+              static const int per_cu = waves_leaving(k_inverse_wave<1, NLS, true>, reserve);
+              if (per_cu > 0) g = std::min(g, n_cu * per_cu);
+            }
+            k_inverse_wave<1, NLS, true><<<g, 64, 0, s>>>(L.posmap, L.kron_ma, L.own_ptr,
+                                                          L.own_loc, full, L.inv_off, L.inv_ld,
+                                                          L.inv_store, fp32, status, L.n_cells,
+                                                          one, p > 0);
+          } else {
+            if (n_cu > 0 && reserve > 0) {
+              static const int per_cu = waves_leaving(k_inverse_wave<2, NLS, true>, reserve);
+              if (per_cu > 0) g = std::min(g, n_cu * per_cu);
+            }
+            k_inverse_wave<2, NLS, true><<<g, 64, 0, s>>>(L.posmap, L.kron_ma, L.own_ptr,
+                                                          L.own_loc, full, L.inv_off, L.inv_ld,
+                                                          L.inv_store, fp32, status, L.n_cells,
+                                                          one, p > 0);
+          }
+          const hipError_t e = hipGetLastError();
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
       }
-      k_inverse_wave<B, NLS, true><<<grid, 64, 0, s>>>(L.posmap, L.kron_ma, L.own_ptr, L.own_loc,
-                                                       full, L.inv_off, L.inv_ld, L.inv_store,
-                                                       fp32, status, L.n_cells, L.split);
-      return hipGetLastError();
+      return hipErrorInvalidValue;
     }
     if (n_cu > 0 && reserve > 0) {
       static const int per_cu = waves_leaving(k_inverse_wave<B, NLS, false>, reserve);
@@ -675,7 +709,7 @@ static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full,
     }
     k_inverse_wave<B, NLS, false><<<grid, 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc, full,
                                                       L.inv_off, L.inv_ld, L.inv_store, fp32,
-                                                      status, L.n_cells, CellSplit{});
+                                                      status, L.n_cells, CellSplit{}, 0);
     return hipGetLastError();
   } else {
     k_inverse_mfma<B, NLS><<<L.n_cells, NT * 64, 0, s>>>(L.posmap, L.val, L.own_ptr, L.own_loc,
