@@ -1059,26 +1059,30 @@ hipError_t launch_vanka_combine(hipStream_t s, int b, const DevLevel& L, double*
 }
 
 // ---------------------------------------------------------------------------
-// Transfers: y[row*B + l] (+)= sum_e val[e] x[col[e]*B + l] for a spatial CSR
-// (identity in time).  Restriction uses the stored transpose of P, so both
-// directions are gathers (no atomics).  The entries of a row are taken 8 at
-// a time with all their loads in flight (indices clamped into the row, the
-// entries past its end weighted by zero); the summation order is the row's.
+// Transfers: y (+)= (P (x) I_B) x for a spatial CSR matrix P (identity in
+// time).  Restriction uses the stored transpose of P, so both directions are
+// gathers (no atomics).  One thread per spatial row and all B time levels: the
+// row's column indices and values are read once for the B levels (four
+// entries at a time, every load in flight), the B entries of x at a column
+// are adjacent, and the row's B outputs are stored together; per level the
+// entries are summed in row order.
 template <int B>
-__global__ void k_csr_time(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                           const double* __restrict__ val, const double* __restrict__ x,
-                           double* __restrict__ y, int32_t n_rows, int accumulate) {
-  constexpr int U = 8;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n_rows * B) return;
-  const int32_t row = (int32_t)(idx / B);
-  const int l = (int)(idx - (int64_t)row * B);
+__global__ void __launch_bounds__(256) k_csr_rows(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y, int32_t n_rows,
+                                                  int accumulate) {
+  constexpr int U = 4;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n_rows) return;
   const int32_t e0 = rp[row], e1 = rp[row + 1];
-  const double y0 = accumulate ? y[idx] : 0.0;
-  double acc = 0.0;
+  double acc[B];
+#pragma unroll
+  for (int l = 0; l < B; ++l) acc[l] = 0.0;
   for (int32_t e = e0; e < e1; e += U) {
     int64_t c[U];
-    double v[U], xv[U];
+    double v[U], xv[U][B];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = e + u < e1;
@@ -1088,23 +1092,28 @@ __global__ void k_csr_time(const int32_t* __restrict__ rp, const int32_t* __rest
       v[u] = ok ? w : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = x[c[u] * B + l];
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc = fma(v[u], xv[u], acc);
+      for (int l = 0; l < B; ++l) xv[u][l] = x[c[u] * B + l];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int l = 0; l < B; ++l) acc[l] = fma(v[u], xv[u][l], acc[l]);
   }
-  y[idx] = accumulate ? y0 + acc : acc;
+  double* yr = y + row * B;
+#pragma unroll
+  for (int l = 0; l < B; ++l) yr[l] = accumulate ? yr[l] + acc[l] : acc[l];
 }
 
 static hipError_t csr_time(hipStream_t s, int b, const int32_t* rp, const int32_t* col,
                            const double* val, const double* x, double* y, int32_t n_rows,
                            int acc) {
-  const int64_t n = (int64_t)n_rows * b;
-  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  dim3 grid((unsigned)(((int64_t)n_rows + 255) / 256)), block(256);
   switch (b) {
-    case 1: launch(k_csr_time<1>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
-    case 2: launch(k_csr_time<2>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
-    case 3: launch(k_csr_time<3>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
-    case 4: launch(k_csr_time<4>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
+    case 1: launch(k_csr_rows<1>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
+    case 2: launch(k_csr_rows<2>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
+    case 3: launch(k_csr_rows<3>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
+    case 4: launch(k_csr_rows<4>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
