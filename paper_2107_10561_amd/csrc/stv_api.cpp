@@ -587,13 +587,17 @@ int ensure_scalars(stv_ctx* ctx, int64_t S) {
   if (ctx->scal_segs >= S && ctx->scal) return STV_OK;
   dfree(ctx->scal);
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
-  ctx->hscal = nullptr;
+  if (ctx->hstep) (void)hipHostFree(ctx->hstep);
+  ctx->hscal = ctx->hstep = nullptr;
   ctx->scal_segs = 0;
   const ScalLayout lay{S};
   STV_TRY(dalloc(ctx, &ctx->scal, (size_t)lay.total()));
   if (hipHostMalloc((void**)&ctx->hscal, sizeof(double) * lay.total(), hipHostMallocDefault) !=
-      hipSuccess) {
-    ctx->hscal = nullptr;
+          hipSuccess ||
+      hipHostMalloc((void**)&ctx->hstep, sizeof(double) * (lay.nrm() + S), hipHostMallocDefault) !=
+          hipSuccess) {
+    if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+    ctx->hscal = ctx->hstep = nullptr;
     return fail(ctx, STV_ENOMEM, "pinned allocation of the scalar buffer failed");
   }
   ctx->scal_segs = S;
@@ -856,7 +860,9 @@ int stv_create(stv_ctx** out, int device, void* hip_stream) {
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_step[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_step[1], hipEventDisableTiming) != hipSuccess) {
     g_create_err = "creation of the internal stream/events failed";
     delete ctx;
     return STV_EHIP;
@@ -867,6 +873,8 @@ int stv_create(stv_ctx** out, int device, void* hip_stream) {
     (void)hipStreamDestroy(ctx->side);
     (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_join);
+    (void)hipEventDestroy(ctx->ev_step[0]);
+    (void)hipEventDestroy(ctx->ev_step[1]);
     delete ctx;
     return STV_ENOMEM;
   }
@@ -881,6 +889,7 @@ void stv_destroy(stv_ctx* ctx) {
   free_hierarchy(ctx);
   dfree(ctx->scal);
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+  if (ctx->hstep) (void)hipHostFree(ctx->hstep);
   for (auto& t : ctx->pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->side) {
@@ -893,6 +902,8 @@ void stv_destroy(stv_ctx* ctx) {
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  for (auto e : ctx->ev_step)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -1737,8 +1748,17 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
       STV_HIP(launch_scale_by_norm(s, ctx->rt, ctx->scal + lay.aux(), 1, ctx->V, sg));
       t.done();
     }
-    int jmax = 0;
-    for (int j = 0; j < m && any_cycle(); ++j) {
+    // The device work of Arnoldi step j (preconditioner, product, CGS2,
+    // normalisation) needs only v_j, which the device computed itself; the
+    // host needs the step's coefficients only for the rotations and the
+    // stopping test.  So step j + 1 is enqueued before step j's coefficients
+    // are awaited, unless step j may end the cycle: then the host waits
+    // first (a step enqueued but not taken only costs time, the iterate is
+    // formed from the steps taken).  Each step's coefficients go to their
+    // own pinned buffer (two in turn).
+    int jmax = 0, enq = 0;
+    double* hbuf[2] = {hs, ctx->hstep};
+    auto enqueue = [&](int j) -> int {
       double* vj = ctx->V + (int64_t)j * n;
       double* zj = ctx->Z + (int64_t)j * n;
       STV_TRY(precond_apply(ctx, vj, zj, p->mg));
@@ -1753,8 +1773,37 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
         STV_HIP(launch_scale_by_norm(s, ctx->w, ctx->scal + lay.nrm(), 1, ctx->V + (int64_t)(j + 1) * n, sg));
         t.done();
       }
-      STV_HIP(hipMemcpyAsync(hs, ctx->scal, sizeof(double) * (lay.nrm() + S), hipMemcpyDeviceToHost, s));
-      STV_HIP(hipStreamSynchronize(s));
+      STV_HIP(hipMemcpyAsync(hbuf[j & 1], ctx->scal, sizeof(double) * (lay.nrm() + S),
+                             hipMemcpyDeviceToHost, s));
+      STV_HIP(hipEventRecord(ctx->ev_step[j & 1], s));
+      return STV_OK;
+    };
+    // whether some cycling instance may need a step after step j: a fixed
+    // count not reached, or an estimate after step j (the current residual
+    // |g_j| times the last step's reduction |s_{j-1}|) above three times the
+    // target
+    auto may_continue = [&](int j) {
+      for (const auto& I : in) {
+        if (!I.cyc) continue;
+        if (I.iters + 1 >= budget) continue;
+        if (p->fixed_iters > 0) return true;
+        const double cur = std::fabs(I.gv[(size_t)j]);
+        const double rate = j > 0 ? std::fabs(I.sn[(size_t)j - 1]) : 1.0;
+        if (!(cur * rate <= 3.0 * I.target)) return true;
+      }
+      return false;
+    };
+    for (int j = 0; j < m && any_cycle(); ++j) {
+      if (enq == j) {
+        STV_TRY(enqueue(j));
+        ++enq;
+      }
+      if (enq == j + 1 && j + 1 < m && may_continue(j)) {
+        STV_TRY(enqueue(j + 1));
+        ++enq;
+      }
+      STV_HIP(hipEventSynchronize(ctx->ev_step[j & 1]));
+      const double* hj = hbuf[j & 1];
       jmax = j + 1;
       double hist = 0.0;
       bool any = false;
@@ -1762,12 +1811,13 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
         Inst& I = in[(size_t)z];
         if (!I.cyc) continue;
         auto Hij = [&](int i, int jj) -> double& { return I.H[(size_t)i * m + jj]; };
-        for (int i = 0; i <= j; ++i) Hij(i, j) = hs[lay.h1(z) + i] + hs[lay.h2(z) + i];
-        const double hn = std::sqrt(hs[lay.nrm() + z]);
+        for (int i = 0; i <= j; ++i) Hij(i, j) = hj[lay.h1(z) + i] + hj[lay.h2(z) + i];
+        const double hn = std::sqrt(hj[lay.nrm() + z]);
         Hij(j + 1, j) = hn;
         for (int i = 0; i <= j + 1; ++i)
           if (!std::isfinite(Hij(i, j))) {
             I.beta = NAN;
+            (void)hipStreamSynchronize(s);
             return finish(fail(ctx, STV_ENUMERIC, "NaN/Inf in the Arnoldi process at step " +
                                                       std::to_string(I.iters) + inst_name(z)));
           }

@@ -205,6 +205,7 @@ struct stv_ctx {
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;     // internal stream: coarse factorisation overlaps the cell inverses
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_step[2] = {nullptr, nullptr};   // Arnoldi coefficients of a step reached the host
   std::string err;
   int n_levels = 0, dim = 0, k = 0, b = 0;
   stv::DevLevel lv[stv::kMaxLevels];
@@ -269,6 +270,7 @@ struct stv_ctx {
   double* partial = nullptr;    // kDotBlocks x 8
   double* scal = nullptr;       // device scalars
   double* hscal = nullptr;      // pinned host mirror
+  double* hstep = nullptr;      // pinned: the coefficients of the next Arnoldi step (look-ahead)
   int ws_restart = 0;
   int64_t ws_n = 0;
   // timing

@@ -184,6 +184,35 @@ def test_gmres_fixed_iterations(stv, name):
     assert e <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["c1_2d_dg1", "2d_dg2"])
+@pytest.mark.parametrize("mode", ["fixed", "tolerance"])
+def test_gmres_restarted(stv, name, mode):
+    """FGMRES(3): the cycles restart from the true residual.  The device
+    work of a step is enqueued before the previous step's coefficients reach
+    the host; the steps a cycle takes, the restarts and the iterate must be
+    those of the oracle's FGMRES(3)."""
+    p, ol = problem(name)
+    s = solver(stv, name)
+    cinv = oracle.coarse_inverse(ol[0])
+    A = lambda v: ol[-1].J @ v
+    M = lambda v: oracle.vcycle(ol, v, 2, 2, 0.7, coarse_inv=cinv)
+    x = to_dev(np.zeros(ol[-1].n_st))
+    if mode == "fixed":
+        xf, _ = oracle.fgmres(A, p.rhs, M, restart=3, fixed_iters=8)
+        info = s.gmres_solve(to_dev(p.rhs), x, restart=3, fixed_iters=8)
+        e = relerr(to_host(x), xf)
+        log(f"[gmres-restart] {name} fixed 8 rel err {e:.3e} restarts {info['restarts']}")
+        assert info["iters"] == 8 and e <= 1e-10
+    else:
+        xo, io = oracle.fgmres(A, p.rhs, M, restart=3, rtol=1e-8)
+        info = s.gmres_solve(to_dev(p.rhs), x, restart=3, rtol=1e-8)
+        xg = to_host(x)
+        true = np.linalg.norm(p.rhs - ol[-1].J @ xg) / np.linalg.norm(p.rhs)
+        log(f"[gmres-restart] {name} gpu iters {info['iters']} oracle {io['iters']} relres {true:.2e}")
+        assert info["converged"] and true <= 1e-8
+        assert abs(info["iters"] - io["iters"]) <= 1
+
+
 @pytest.mark.parametrize("name", ALL)
 def test_gmres_tolerance_mode(stv, name):
     p, ol = problem(name)
