@@ -183,6 +183,14 @@ int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info);
  * cell's DoFs, Section 4.2) on levels >= 1, invert it by Gauss-Jordan
  * elimination with partial pivoting in FP64 and store it (Section 4.3);
  * factor the coarsest matrix densely (its explicit inverse) in FP64.
+ * With spatial factors on a level (stv_set_kron_factors) whose cell problems
+ * fit one wavefront (n_ls = 21, k + 1 <= 3) and the owned-rows layout, the
+ * level's inverses are stored time-decoupled: with D^-1 C = V T V^-1 (real
+ * Jordan form), J_T^-1 = (I (x) V) Q^-1 (I (x) W), Q = M_T (x) T + A_T (x) I,
+ * W = V^-1 D^-1, and Q^-1 is block diagonal in time, so one row of
+ * (k+1)*n_ls values per owned spatial DoF is kept instead of k+1 rows (the
+ * sweep applies the same J_T^-1).  The layout is fixed by the build that
+ * made the store.
  * storage = STV_F64 or STV_F32, optionally | STV_STORE_FULL.  The stores
  * and the build's work buffers are owned by the context and kept between
  * builds of one hierarchy (remade when the storage flags or the coarse
@@ -272,7 +280,9 @@ int stv_dot(stv_ctx* ctx, const double* a, const double* b, double* out);
 /* Copy the stored inverse of cell `cell` on `level` (>= 1) into the host array
  * out[n_loc*n_loc], row-major in the cell-local order of eq. (4.4)
  * (time-major: index l*n_ls + alpha), converted to FP64.  Rows not stored
- * (the default owned-rows storage) are written as NaN.  Synchronises. */
+ * (the default owned-rows storage) are written as NaN.  A time-decoupled
+ * store (see stv_build_cell_inverses) is expanded on the host to the same
+ * rows of J_T^-1.  Synchronises. */
 int stv_get_cell_inverse(stv_ctx* ctx, int level, int cell, double* out);
 
 /* Sizes of a level: spatial DoFs, cells, local DoFs per cell (n_loc), stored
