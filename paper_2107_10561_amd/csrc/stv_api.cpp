@@ -1704,8 +1704,14 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
       I.done = true;
     }
   }
-  STV_TRY(residual(ctx, G, bvec, x, ctx->rt));
-  STV_TRY(dots_to_host(ctx, ctx->rt, ctx->rt, n, v2));
+  if (p->use_x0) {
+    STV_TRY(residual(ctx, G, bvec, x, ctx->rt));
+    STV_TRY(dots_to_host(ctx, ctx->rt, ctx->rt, n, v2));
+  } else {
+    // x = 0: the initial residual is b itself (b - J 0 = b exactly) and its
+    // squared norms are those just reduced
+    STV_HIP(hipMemcpyAsync(ctx->rt, bvec, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+  }
   double hmax = 0.0;
   for (int z = 0; z < S; ++z) {
     Inst& I = in[(size_t)z];
