@@ -17,6 +17,13 @@ Functions and what pins them (tests marked "not gpu"):
   vanka_sweep                       - pinned: one cell, omega = 1 -> exact solve;
                                       disjoint cells -> exact solve; a hand-derived
                                       two-cell overwrite example
+  vanka_sweep(pressure_rows=...)    - the eq. (4.5) ablation (r_0 with zeroed pressure
+                                      rows): pinned to break the fixed point and the
+                                      one-cell exact solve, and to agree with the full-r
+                                      sweep when r has zero pressure rows
+  coarse_inverse                    - pinned: a hand-inverted 3x3 that needs pivoting
+                                      and has a non-symmetric inverse; two-sided
+                                      inverse of the coarse Oseen matrix
   vcycle                            - pinned: one level = direct solve; no smoothing
                                       = coarse-grid correction P J_c^-1 P^T r;
                                       linearity in r
@@ -24,6 +31,10 @@ Functions and what pins them (tests marked "not gpu"):
                                       scipy's GMRES residual history; minimal
                                       residual over the explicit Krylov space;
                                       restart >= n converges in <= n steps
+  The assembled operators these functions read come from the seeded
+  generator (stgen), pinned separately: closed-form element and time
+  matrices, patch tests, and manufactured-solution convergence rates
+  (velocity L2 order 3, pressure L2 order 2) on three nested meshes.
   The cell loop order and the "last update wins" reading (owner = highest
   cell index) are readings of the paper, not fixed by it: parity unpinned by
   the paper for that choice; the hand-derived example pins the implementation

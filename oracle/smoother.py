@@ -101,14 +101,21 @@ def residual(J, r, d):
     return r - J @ d
 
 
-def vanka_sweep(L: OracleLevel, r, d, omega: float):
+def vanka_sweep(L: OracleLevel, r, d, omega: float, pressure_rows=None):
     """One Jacobi-type sweep of S_T(d, r) = d_T + omega J_T^-1 (r - J d)_T.
 
     The global residual is computed once from the pre-sweep iterate; the
     cells are then visited in index order and each one overwrites its DoFs
     with d_old + omega J_T^-1 rho_T, so a DoF shared by several cells keeps
     the value written by the last cell of the loop.
+
+    pressure_rows (ablation of eq. (4.5), not the default reading): a boolean
+    mask of the level's pressure DoFs; when given, the residual is formed
+    from r_0, the right-hand side with its pressure rows set to zero, as
+    eq. (4.5)-(4.6) print it.  The default uses the full r.
     """
+    if pressure_rows is not None:
+        r = np.where(pressure_rows, 0.0, r)
     rho = residual(L.J, r, d)
     d_old = d
     d_new = d.copy()

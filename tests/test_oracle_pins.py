@@ -193,3 +193,72 @@ def test_block_extraction_matches_csr_extraction(c1):
     for T in (0, 17, L.n_cells - 1):
         a = oracle.extract_cell_matrix_blocks(L.rowptr, L.col, L.val, p.b, L.cell_sdofs[T])
         np.testing.assert_array_equal(a, oracle.extract_cell_matrix(ol[-1].J, ol[-1].dofs[T]))
+
+
+def test_coarse_inverse_hand_worked_3x3():
+    """A 3x3 matrix whose (0, 0) entry is zero (pivoting needed) and whose
+    inverse is not symmetric (a transposed result fails), inverted by hand:
+    A = [[0,1,2],[1,0,3],[4,-3,8]], det A = -2,
+    A^-1 = adj(A)/det = [[-9/2, 7, -3/2], [-2, 4, -1], [3/2, -2, 1/2]]."""
+    A = np.array([[0., 1, 2], [1, 0, 3], [4, -3, 8]])
+    L0 = OracleLevel(sp.csr_matrix(A), np.zeros((0, 3), dtype=np.int64), 3, None)
+    inv = oracle.coarse_inverse(L0)
+    np.testing.assert_allclose(inv, [[-4.5, 7, -1.5], [-2, 4, -1], [1.5, -2, 0.5]], atol=1e-14)
+
+
+def test_coarse_inverse_is_two_sided_inverse(c1):
+    """On the coarsest space-time Oseen matrix of the small channel: the dense
+    inverse times J_0 is the identity from both sides."""
+    _, ol = c1
+    J0 = ol[0].J.toarray()
+    inv = oracle.coarse_inverse(ol[0])
+    cond = np.linalg.cond(J0, 1)
+    n = J0.shape[0]
+    assert np.abs(inv @ J0 - np.eye(n)).max() <= 1e-14 * cond
+    assert np.abs(J0 @ inv - np.eye(n)).max() <= 1e-14 * cond
+    r = np.random.default_rng(9).standard_normal(n)
+    np.testing.assert_allclose(oracle.vcycle(ol[:1], r, 2, 2, 0.7, coarse_inv=inv),
+                               np.linalg.solve(J0, r), rtol=0, atol=1e-12 * np.abs(inv @ r).max())
+
+
+def _pressure_rows(p, g):
+    """Space-time DoFs of level g that belong to pressure modes (spatial DoFs
+    after the dim * N_v velocity DoFs of the numbering)."""
+    m = p.levels[g].mesh
+    sdof_is_p = np.arange(m.n_sdofs) >= m.dim * m.n_vnodes
+    return np.repeat(sdof_is_p, p.b)
+
+
+def test_zero_pressure_residual_breaks_consistency():
+    """Ablation of eq. (4.5): with r_0 (pressure rows of r set to zero) the exact
+    solution of J x = r is not a fixed point of the sweep, and the one-cell sweep
+    with omega = 1 no longer solves exactly; with the full r (the reading used
+    everywhere else) both hold.  This is why the full r is used."""
+    p = make_problem(2, (1, 1), 1, 1, 0.01, 1e-3, 7)
+    ol = oracle.prepare_levels(p.levels, p.b)
+    oracle.build_inverses(ol, first_level=0)
+    L = ol[0]
+    pr = _pressure_rows(p, 0)
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal(L.n_st)
+    x = np.linalg.solve(L.J.toarray(), r)
+    d0 = rng.standard_normal(L.n_st)
+    full = oracle.vanka_sweep(L, r, d0, 1.0)
+    zero = oracle.vanka_sweep(L, r, d0, 1.0, pressure_rows=pr)
+    np.testing.assert_allclose(full, x, atol=1e-12 * np.abs(x).max())
+    assert np.abs(zero - x).max() > 1e-3 * np.abs(x).max()
+    # on a multi-cell level: x is a fixed point only with the full r
+    p2 = make_problem(2, (4, 2), 1, 1, 0.01, 1e-3, 8)
+    o2 = oracle.prepare_levels(p2.levels, p2.b)
+    oracle.build_inverses(o2, first_level=0)
+    L2 = o2[0]
+    r2 = rng.standard_normal(L2.n_st)
+    x2 = spla.spsolve(L2.J.tocsc(), r2)
+    np.testing.assert_allclose(oracle.vanka_sweep(L2, r2, x2, 0.7), x2,
+                               atol=1e-12 * np.abs(x2).max())
+    moved = oracle.vanka_sweep(L2, r2, x2, 0.7, pressure_rows=_pressure_rows(p2, 0))
+    assert np.abs(moved - x2).max() > 1e-3 * np.abs(x2).max()
+    # a right-hand side with zero pressure rows makes the two readings agree
+    r3 = np.where(_pressure_rows(p2, 0), 0.0, r2)
+    np.testing.assert_array_equal(oracle.vanka_sweep(L2, r3, x2, 0.7),
+                                  oracle.vanka_sweep(L2, r3, x2, 0.7, pressure_rows=_pressure_rows(p2, 0)))
