@@ -352,15 +352,17 @@ def gradient_bench(args):
 def newton_system(n_fine, G):
     """The Newton problem, its data and the iterate after one Newton step
     from rest (solved directly on the host: input generation)."""
+    import scipy.sparse as sps
     import scipy.sparse.linalg as sla
 
-    from oracle.smoother import spacetime_matrix
     from stgen.newton import NewtonProblem
     P = NewtonProblem(2, n_fine, G, 1, 0.01, 1e-3)
     F = P.data(0.0, np.zeros(P.fine.mesh.n_sdofs))
     u = np.zeros(P.fine.mesh.n_sdofs * P.b)
     L = P.hierarchy(u)[-1]
-    J0 = spacetime_matrix(L["rowptr"], L["col"], L["val"], L["n_sdofs"], P.b)
+    n = L["n_sdofs"] * P.b
+    J0 = sps.bsr_matrix((np.asarray(L["val"]).reshape(-1, P.b, P.b), L["col"], L["rowptr"]),
+                        shape=(n, n))
     u = u - sla.spsolve(J0.tocsc(), P.residual(u, F))
     return P, F, u
 

@@ -201,8 +201,12 @@ int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info);
  * Errors: STV_ESTATE (no hierarchy), STV_EINVAL, STV_ENOMEM, STV_EHIP. */
 int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_cell);
 
-/* out = r - J_level d.  r may be NULL (then out = -J d).  Device pointers,
- * N_s*(k+1) doubles each; out must not alias r or d. */
+/* out = r - J_level d: the level residual that Algorithm 4.1 restricts to the
+ * next coarser level and that every smoothing step of eq. (4.6) starts from.
+ * r may be NULL (then out = -J d).  Device pointers, N_s*(k+1) doubles each,
+ * time-inner; out must not alias r or d.  Asynchronous on the context's
+ * stream.  Errors: STV_ESTATE (no hierarchy), STV_EINVAL (level out of range
+ * or NULL d/out). */
 int stv_residual(stv_ctx* ctx, int level, const double* r, const double* d, double* out);
 
 /* n_sweeps damped Vanka sweeps on level >= 1, in place on d:
@@ -233,7 +237,11 @@ int stv_coarse_solve(stv_ctx* ctx, const double* r, double* d);
 int stv_vcycle(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p);
 
 /* Solve J x = b on the finest level by right-preconditioned flexible GMRES
- * (x = x0 + Z y with z_j = MG(v_j)), FP64 throughout.  A cycle ends when the
+ * (x = x0 + Z y with z_j = MG(v_j)), FP64 throughout: the linear solver of
+ * every Newton step of Section 3 (its Newton linear system), preconditioned
+ * by the V-cycle of Algorithm 4.1 (Section 4.1); the paper's robustness study
+ * (Section 5.3) caps it at 1000 steps, which is max_it's usual value.  The
+ * restart length is the caller's (the paper gives none).  A cycle ends when the
  * rotated residual estimate reaches rtol ||b|| or after `restart` steps; the
  * iterate is updated and the true residual decides convergence.  b and x are
  * device vectors.  Synchronises the stream.  Returns STV_ENOCONV (x holds the

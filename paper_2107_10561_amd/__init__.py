@@ -330,6 +330,17 @@ class Solver:
             self._check(rc)
         return info
 
+    def _out(self, t, n, name):
+        """A device output array of exactly n float64 entries."""
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise ValueError(f"{name} must be a float64 CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries, {n} needed")
+        return ctypes.c_void_p(t.data_ptr())
+
     def cell_contract(self, level, lam, x, refs, kptr, kidx, kw, tw, out):
         """out[T] = sum_l tw[l] lam_T,l . K_T x_T,l, K_T = sum kw refs[kidx] (device out)."""
         refs = np.ascontiguousarray(refs, dtype=np.float64)
@@ -337,17 +348,29 @@ class Solver:
         kidx = np.ascontiguousarray(kidx, dtype=np.int32)
         kw = np.ascontiguousarray(kw, dtype=np.float64)
         tw = np.ascontiguousarray(tw, dtype=np.float64)
+        n_cells = self.level_info(level)["n_cells"]
+        if kptr.shape != (n_cells + 1,):
+            raise ValueError(f"kptr needs {n_cells + 1} entries")
+        if kidx.size != kw.size or (kptr.size and kptr[-1] > kidx.size):
+            raise ValueError("kidx and kw must have kptr[-1] entries")
+        if refs.ndim != 3 or tw.size != self.b:
+            raise ValueError("refs must be (n_ref, n_ls, n_ls) and tw have k+1 entries")
+        optr = self._out(out, n_cells, "out")
         self._check(_lib.stv_cell_contract(
             self._h, level, self._vec(lam, level, "lam"), self._vec(x, level, "x"),
             int(refs.shape[0]), refs.ctypes.data, kptr.ctypes.data, kidx.ctypes.data,
-            kw.ctypes.data, tw.ctypes.data, ctypes.c_void_p(out.data_ptr())))
+            kw.ctypes.data, tw.ctypes.data, optr))
 
     def cell_dot(self, level, lam, cells, f, out):
-        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        """out[j] = sum over cell cells[j]'s DoFs of lam times f[j] (device out)."""
+        cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1)
         f = np.ascontiguousarray(f, dtype=np.float64)
+        n_loc = self.level_info(level)["n_loc"]
+        if f.size != cells.size * n_loc:
+            raise ValueError(f"f must hold {cells.size} x {n_loc} values")
+        optr = self._out(out, int(cells.size), "out")
         self._check(_lib.stv_cell_dot(self._h, level, self._vec(lam, level, "lam"),
-                                      int(cells.size), cells.ctypes.data, f.ctypes.data,
-                                      ctypes.c_void_p(out.data_ptr())))
+                                      int(cells.size), cells.ctypes.data, f.ctypes.data, optr))
 
     def dot(self, a, b):
         """Per-instance dot products of two finest-level vectors (host list)."""

@@ -53,6 +53,8 @@ class SolveOptions:
         self.restart, self.max_it = restart, max_it
         self.solver = None
         self.last_info = {}
+        # the forward call whose hierarchy and inverses the solver holds
+        self.loaded = None
 
 
 class SpaceTimeSolve(torch.autograd.Function):
@@ -66,6 +68,9 @@ class SpaceTimeSolve(torch.autograd.Function):
         s = opts.solver
         s.set_hierarchy(levels, data.dim, data.k)
         s.build_cell_inverses(fp32=opts.fp32, full=True)
+        token = object()
+        opts.loaded = token
+        ctx.token, ctx.nu_h, ctx.fp32 = token, nu_h, opts.fp32
         csd = np.asarray(levels[-1].cell_sdofs)
         bhat = data.rhs_hat(nu_h, csd)
         dev = torch.device("cuda", opts.device)
@@ -83,6 +88,12 @@ class SpaceTimeSolve(torch.autograd.Function):
     def backward(ctx, gx):
         x, bh = ctx.saved_tensors
         data, opts, s = ctx.data, ctx.opts, ctx.opts.solver
+        if opts.loaded is not ctx.token:
+            # another forward has replaced the operator since this one ran:
+            # reload J(nu) of this forward before the adjoint solve
+            s.set_hierarchy(data.build(ctx.nu_h), data.dim, data.k)
+            s.build_cell_inverses(fp32=ctx.fp32, full=True)
+            opts.loaded = ctx.token
         lam = torch.zeros_like(x)
         info = s.gmres_solve_transposed(gx.contiguous().to(torch.float64), lam,
                                         restart=opts.restart, max_it=opts.max_it, rtol=opts.rtol)

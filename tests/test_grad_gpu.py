@@ -195,3 +195,29 @@ def test_finite_differences_on_20_cells(stv):
         fd = (vals[0] - vals[1]) / (2 * h)
         log(f"[fd] cell {int(c)}: fd {fd:.8e} adjoint {g[c]:.8e}")
         assert abs(fd - g[c]) <= 1e-6 * np.abs(g).max()
+
+
+def test_backward_after_a_second_forward(stv):
+    """A second forward with another viscosity replaces the operator the
+    solver holds; the backward of the first output must still use J(nu) of
+    the first forward (equal to a lone forward + backward)."""
+    import torch
+    from paper_2107_10561_amd.autograd import SolveOptions, SpaceTimeSolve
+    p = diff_problem((16, 4), 2)
+    data = adjoint_data(p)
+    q = torch.from_numpy(p.loss).to("cuda:0")
+    _, g_ref, gU_ref, _ = _grad_gpu(stv, p, False, 1e-12)
+    opts = SolveOptions(0, rtol=1e-12)
+    nu1 = torch.tensor(p.nu_cell, dtype=torch.float64, requires_grad=True)
+    U1 = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    x1 = SpaceTimeSolve.apply(nu1, U1, data, opts)
+    nu2 = torch.tensor(p.nu_cell * 1.7, dtype=torch.float64, requires_grad=True)
+    x2 = SpaceTimeSolve.apply(nu2, torch.tensor(0.5, dtype=torch.float64), data, opts)
+    (q * x1).sum().backward()
+    e = np.abs(nu1.grad.numpy() - g_ref).max() / np.abs(g_ref).max()
+    log(f"[grad] backward after a second forward: max rel err {e:.2e}")
+    assert e <= 1e-9
+    assert abs(float(U1.grad) - gU_ref) <= 1e-9 * abs(gU_ref)
+    # the second output's backward reloads its own operator
+    (q * x2).sum().backward()
+    assert np.isfinite(nu2.grad.numpy()).all()
