@@ -1,0 +1,127 @@
+"""Helpers of the full-size parity tests: a solver set up exactly as bench.py
+sets up its timed steps, and sampled comparisons with the oracle computed one
+cell at a time.  Inputs come from the seeded generator; expected values from
+the oracle (and a sparse direct solve) only."""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+from gpu_common import log, relerr, to_dev, to_host
+from stgen import fe
+from stgen.problem import spatial_factors
+
+
+def _J(L, b):
+    return sp.bsr_matrix((np.asarray(L.val).reshape(-1, b, b), L.col, L.rowptr),
+                         shape=(L.n_sdofs * b,) * 2)
+
+
+def bench_solver(p, fp32=False):
+    """A solver set up exactly as bench.py sets up its timed steps."""
+    import paper_2107_10561_amd as stv
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    _, w, C, _ = fe.time_matrices(p.k)
+    tw = p.tau * np.asarray(w, dtype=np.float64)
+    for g, L in enumerate(p.levels):
+        m, a = spatial_factors(L)
+        s.set_kron_factors(g, m, a, np.asarray(C), tw)
+    s.build_cell_inverses(fp32=fp32)
+    shapes = s.autotune()
+    log(f"[bench-path] autotuned shapes {shapes}")
+    return s, stv
+
+
+def sample_cells(n_cells, rng, extra=()):
+    base = [0, n_cells - 1] + [c for c in extra if c < n_cells]
+    pick = rng.choice(n_cells, min(n_cells, 20), replace=False)
+    return np.unique(np.concatenate([np.asarray(base, dtype=np.int64), pick]))
+
+
+def check_inverse_rows(p, s, rng, extra=(), tol=1e-10):
+    """Owned rows of sampled cells on every smoothed level against the oracle's
+    inverse of the extracted J_T (relative Frobenius error per cell)."""
+    b = p.b
+    worst = 0.0
+    for g in range(1, len(p.levels)):
+        L = p.levels[g]
+        own = oracle.owner_cells(L.cell_sdofs, L.n_sdofs)
+        nls = L.cell_sdofs.shape[1]
+        for T in sample_cells(L.n_cells, rng, extra):
+            JT = oracle.extract_cell_matrix_blocks(L.rowptr, L.col, L.val, b, L.cell_sdofs[T])
+            O = oracle.cell_inverse(JT)
+            G = s.get_cell_inverse(g, int(T))
+            rows = [l * nls + a for l in range(b) for a in range(nls)
+                    if own[L.cell_sdofs[T, a]] == T]
+            e = np.linalg.norm(G[rows] - O[rows]) / np.linalg.norm(O[rows])
+            worst = max(worst, e)
+            assert e <= tol, (g, int(T), e)
+    return worst
+
+
+def check_residual_rows(p, s, g, rng, n_rows=4000):
+    L = p.levels[g]
+    n = L.n_sdofs * p.b
+    r, d = rng.standard_normal(n), rng.standard_normal(n)
+    out = to_dev(np.zeros(n))
+    s.residual(g, to_dev(r), to_dev(d), out)
+    got = to_host(out)
+    J = _J(L, p.b).tocsr()
+    rows = np.concatenate([rng.choice(n, min(n, n_rows), replace=False), [0, n - 1]])
+    ref = r[rows] - J[rows] @ d
+    e = np.abs(got[rows] - ref).max() / np.abs(ref).max()
+    assert e <= 1e-13, (g, e)
+    return e
+
+
+def check_sweep(p, s, g, rng, tol, n_sdofs=200):
+    """d_new[j] = d[j] + omega (J_T^-1 rho_T)[loc(j)] for the owner T of j."""
+    b = p.b
+    L = p.levels[g]
+    n = L.n_sdofs * b
+    r, d = rng.standard_normal(n), rng.standard_normal(n)
+    dd = to_dev(d)
+    s.vanka_sweep(g, to_dev(r), dd, 1, 0.7)
+    got = to_host(dd)
+    rho = r - _J(L, b) @ d
+    own = oracle.owner_cells(L.cell_sdofs, L.n_sdofs)
+    nls = L.cell_sdofs.shape[1]
+    sdofs = np.unique(np.concatenate([rng.choice(L.n_sdofs, n_sdofs, replace=False),
+                                      [0, L.n_sdofs - 1]]))
+    worst = 0.0
+    for sd in sdofs:
+        T = int(own[sd])
+        idx = oracle.cell_dofs(L.cell_sdofs[T:T + 1], b)[0]
+        JT = oracle.extract_cell_matrix_blocks(L.rowptr, L.col, L.val, b, L.cell_sdofs[T])
+        c = oracle.cell_inverse(JT) @ rho[idx]
+        a = int(np.nonzero(L.cell_sdofs[T] == sd)[0][0])
+        for l in range(b):
+            ref = d[sd * b + l] + 0.7 * c[l * nls + a]
+            worst = max(worst, abs(got[sd * b + l] - ref) / max(1.0, abs(ref)))
+    assert worst <= tol, (g, worst)
+    return worst
+
+
+def check_coarse(p, s, rng):
+    L0 = p.levels[0]
+    n = L0.n_sdofs * p.b
+    r = rng.standard_normal(n)
+    x = to_dev(np.zeros(n))
+    s.coarse_solve(to_dev(r), x)
+    ref = spla.splu(_J(L0, p.b).tocsc()).solve(r)
+    e = relerr(to_host(x), ref)
+    assert e <= 1e-11, e
+    return e
+
+
+def check_gmres(p, s):
+    L = p.levels[-1]
+    n = L.n_sdofs * p.b
+    x = to_dev(np.zeros(n))
+    info = s.gmres_solve(to_dev(p.rhs), x, restart=30, rtol=1e-8)
+    xg = to_host(x)
+    true = np.linalg.norm(p.rhs - _J(L, p.b) @ xg) / np.linalg.norm(p.rhs)
+    assert info["converged"] and true <= 1e-8, (info, true)
+    assert abs(info["true_relres"] - true) <= 1e-3 * true
+    return info["iters"], true

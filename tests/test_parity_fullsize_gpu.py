@@ -1,6 +1,8 @@
-"""Parity at the benchmark's full size (2d channel 512x128, dG(2), 6 levels,
-FP64 inverses, the launch configuration bench.py times), on outputs the
-oracle computes one by one, and on properties that hold at any size."""
+"""Parity on the 2d channel 512x128, dG(2), 6 levels, FP64 inverses, without
+spatial factors: the block residual, the plain sweep and the plain (not
+time-decoupled) store; the launch configuration bench.py times is
+checked in test_parity_bench_path_gpu.py.  Outputs the oracle computes one by
+one, and properties that hold at any size."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
