@@ -236,6 +236,23 @@ int stv_coarse_solve(stv_ctx* ctx, const double* r, double* d);
  * original r_g).  r and d are finest-level device vectors, d must not alias r. */
 int stv_vcycle(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p);
 
+/* For callers that cannot allocate device memory (code under stream or HIP
+ * graph capture, allocation-free serving loops): stv_vcycle with its level
+ * work vectors (per level the residual, and the restricted right-hand side
+ * and correction of every level below the finest; with STV_POU/STV_ADDITIVE
+ * also the per-cell corrections) taken from a fixed device workspace of
+ * 64 MiB that the library holds on every device it runs on until the process
+ * ends, instead of the context's own buffers.  The call allocates nothing,
+ * launches eagerly on the context's stream (never the captured graph) and is
+ * not recorded by stv_set_timing.  Same arguments and results as stv_vcycle
+ * (bitwise).  Every call on one device shares that workspace and leaves the
+ * last call's values in it: calls that overlap on one device (several
+ * contexts or streams) race, so the caller orders them.  Errors: as
+ * stv_vcycle; STV_EINVAL if the hierarchy's work vectors exceed 64 MiB (the
+ * message gives both sizes); STV_EHIP if the workspace has no address on the
+ * context's device. */
+int stv_vcycle_noalloc(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p);
+
 /* Solve J x = b on the finest level by right-preconditioned flexible GMRES
  * (x = x0 + Z y with z_j = MG(v_j)), FP64 throughout: the linear solver of
  * every Newton step of Section 3 (its Newton linear system), preconditioned

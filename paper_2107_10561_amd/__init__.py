@@ -81,6 +81,7 @@ def _load():
         "stv_prolongate_add": (I, [P, I, P, P]),
         "stv_coarse_solve": (I, [P, P, P]),
         "stv_vcycle": (I, [P, P, P, ctypes.POINTER(_MG)]),
+        "stv_vcycle_noalloc": (I, [P, P, P, ctypes.POINTER(_MG)]),
         "stv_gmres_solve": (I, [P, P, P, ctypes.POINTER(_GP), ctypes.POINTER(_GI)]),
         "stv_get_cell_inverse": (I, [P, I, I, P]),
         "stv_level_info": (I, [P, I, I64P, I64P, I64P, I64P]),
@@ -115,7 +116,7 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_kernel_stats", "stv_set_option", "stv_set_batch", "stv_instance_layout",
             "stv_instance_info", "stv_set_launch", "stv_autotune", "stv_vcycle_transposed",
             "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot",
-            "stv_set_kron_factors", "stv_set_timing_filter")
+            "stv_set_kron_factors", "stv_set_timing_filter", "stv_vcycle_noalloc")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2, "tournament": 3}
 
@@ -291,6 +292,14 @@ class Solver:
         mg = _MG(nu1, nu2, omega, mode)
         self._check(_lib.stv_vcycle(self._h, self._vec(r, top, "r"), self._vec(d, top, "d"),
                                     ctypes.byref(mg)))
+
+    def vcycle_noalloc(self, r, d, nu1=2, nu2=2, omega=0.7, mode=STV_LAST_WRITER):
+        """The same V-cycle with its work vectors in the library's fixed device
+        workspace: the call allocates no device memory."""
+        top = self.n_levels - 1
+        mg = _MG(nu1, nu2, omega, mode)
+        self._check(_lib.stv_vcycle_noalloc(self._h, self._vec(r, top, "r"),
+                                            self._vec(d, top, "d"), ctypes.byref(mg)))
 
     def gmres_solve(self, b, x, restart=30, max_it=1000, rtol=1e-8, use_x0=False,
                     fixed_iters=0, nu1=2, nu2=2, omega=0.7, mode=STV_LAST_WRITER,

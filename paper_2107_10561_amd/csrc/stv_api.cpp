@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -25,9 +26,37 @@ using namespace stv;
 
 thread_local stv::LaunchEvents stv::g_launch_events;
 
+// Fixed device workspace of stv_vcycle_noalloc: the level work vectors of a
+// V-cycle, so that the call allocates nothing.  Every device the library runs
+// on holds its own copy until the process ends; host code reaches it only
+// through the per-device address resolved at context creation (the name
+// itself is a host-side stand-in, not a device address).
+constexpr size_t kNoAllocDoubles = size_t(8) << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
 namespace {
 
 std::string g_create_err;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved once per
+// device, with that device current).
+hipError_t resolve_scratch(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
 
 int fail(stv_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -867,6 +896,12 @@ int stv_create(stv_ctx** out, int device, void* hip_stream) {
     delete ctx;
     return STV_EHIP;
   }
+  // the fixed workspace's address on this device; without it only
+  // stv_vcycle_noalloc is unavailable (it then reports STV_EHIP)
+  if (resolve_scratch(device, &ctx->noalloc_ws) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->noalloc_ws = nullptr;
+  }
   if (ensure_scalars(ctx, 1) != STV_OK) {
     g_create_err = "allocation of the scalar buffers failed";
     dfree(ctx->scal);
@@ -1624,6 +1659,62 @@ int stv_vcycle(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p)
   STV_TRY(check_mg(ctx, p));
   if (!r || !d || r == d) return fail(ctx, STV_EINVAL, "r, d must be distinct non-NULL vectors");
   return precond_apply(ctx, r, d, *p);
+}
+
+int stv_vcycle_noalloc(stv_ctx* ctx, const double* r, double* d, const stv_mg_params* p) {
+  STV_TRY(check_ctx(ctx, true, true));
+  STV_TRY(check_mg(ctx, p));
+  if (!r || !d || r == d) return fail(ctx, STV_EINVAL, "r, d must be distinct non-NULL vectors");
+  if (!ctx->noalloc_ws)
+    return fail(ctx, STV_EHIP, "the fixed V-cycle workspace has no address on this device");
+  // the work vectors the context's own V-cycle keeps per level, carved from
+  // the fixed workspace in 256-byte aligned pieces
+  const int b = ctx->b;
+  const bool corr = p->mode != STV_LAST_WRITER;
+  auto piece = [](size_t n) { return (n + 31) / 32 * 32; };
+  size_t need = 0;
+  for (int g = 0; g < ctx->n_levels; ++g) {
+    const DevLevel& L = ctx->lv[g];
+    const size_t nst = (size_t)L.n_s * b;
+    need += piece(nst);                                   // rho
+    if (g < ctx->n_levels - 1) need += 2 * piece(nst);    // r, d
+    if (corr && g > 0 && L.n_cells > 0) need += piece((size_t)L.n_cells * L.n_ls * b);
+  }
+  if (need > kNoAllocDoubles)
+    return fail(ctx, STV_EINVAL,
+                "the V-cycle needs " + std::to_string(need * 8) + " bytes of work vectors; "
+                "stv_vcycle_noalloc holds at most " + std::to_string(kNoAllocDoubles * 8));
+  struct Saved { double *rho, *r, *d, *corr; };
+  Saved saved[kMaxLevels];
+  double* cur = ctx->noalloc_ws;
+  for (int g = 0; g < ctx->n_levels; ++g) {
+    DevLevel& L = ctx->lv[g];
+    saved[g] = Saved{L.rho, L.r, L.d, L.corr};
+    const size_t nst = (size_t)L.n_s * b;
+    L.rho = cur; cur += piece(nst);
+    if (g < ctx->n_levels - 1) {
+      L.r = cur; cur += piece(nst);
+      L.d = cur; cur += piece(nst);
+    }
+    if (corr && g > 0 && L.n_cells > 0) {
+      L.corr = cur;
+      cur += piece((size_t)L.n_cells * L.n_ls * b);
+    }
+  }
+  // eager launches on the caller's stream; no event records (the timer's
+  // event pool may allocate), no graph
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  const int rc = vcycle_level(ctx, ctx->n_levels - 1, r, d, *p);
+  ctx->timing = timing;
+  for (int g = 0; g < ctx->n_levels; ++g) {
+    DevLevel& L = ctx->lv[g];
+    L.rho = saved[g].rho;
+    L.r = saved[g].r;
+    L.d = saved[g].d;
+    L.corr = saved[g].corr;
+  }
+  return rc;
 }
 
 int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres_params* p,

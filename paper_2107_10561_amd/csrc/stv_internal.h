@@ -202,6 +202,7 @@ struct TimerPair { hipEvent_t a, b; int cls; int level; };
 
 struct stv_ctx {
   int device = 0;
+  double* noalloc_ws = nullptr;   // this device's address of the fixed workspace (or NULL)
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;     // internal stream: coarse factorisation overlaps the cell inverses
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
