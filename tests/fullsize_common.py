@@ -75,8 +75,16 @@ def check_residual_rows(p, s, g, rng, n_rows=4000):
     return e
 
 
-def check_sweep(p, s, g, rng, tol, n_sdofs=200):
-    """d_new[j] = d[j] + omega (J_T^-1 rho_T)[loc(j)] for the owner T of j."""
+def check_sweep(p, s, g, rng, fp32, n_sdofs=200):
+    """d_new[j] = d[j] + omega (J_T^-1 rho_T)[loc(j)] for the owner T of j.
+
+    FP64 store: |error| <= 1e-11 max(1, |d_new[j]|).  FP32 store: every stored
+    value carries a relative rounding of 2^-24, the (time-decoupled) store's
+    recombination can amplify it by the condition of the time basis, and the
+    row product accumulates n_loc such terms; the bound is therefore taken
+    relative to the absolute row sum: |error| <= 5e-5 omega sum_i
+    |(J_T^-1)_{ji} rho_i| (n_loc 2^-24 is 3.8e-6 for n_loc = 63 and 1.0e-5 for
+    170)."""
     b = p.b
     L = p.levels[g]
     n = L.n_sdofs * b
@@ -94,12 +102,19 @@ def check_sweep(p, s, g, rng, tol, n_sdofs=200):
         T = int(own[sd])
         idx = oracle.cell_dofs(L.cell_sdofs[T:T + 1], b)[0]
         JT = oracle.extract_cell_matrix_blocks(L.rowptr, L.col, L.val, b, L.cell_sdofs[T])
-        c = oracle.cell_inverse(JT) @ rho[idx]
+        inv = oracle.cell_inverse(JT)
+        c = inv @ rho[idx]
         a = int(np.nonzero(L.cell_sdofs[T] == sd)[0][0])
         for l in range(b):
-            ref = d[sd * b + l] + 0.7 * c[l * nls + a]
-            worst = max(worst, abs(got[sd * b + l] - ref) / max(1.0, abs(ref)))
-    assert worst <= tol, (g, worst)
+            j = l * nls + a
+            ref = d[sd * b + l] + 0.7 * c[j]
+            if fp32:
+                scale = 0.7 * np.abs(inv[j] * rho[idx]).sum()
+                e = abs(got[sd * b + l] - ref) / scale / 5e-5
+            else:
+                e = abs(got[sd * b + l] - ref) / max(1.0, abs(ref)) / 1e-11
+            worst = max(worst, e)
+    assert worst <= 1.0, (g, worst)
     return worst
 
 

@@ -61,8 +61,8 @@ def test_3d_sweep(bench3d, fp32):
     try:
         rng = np.random.default_rng(43)
         for g in (len(p.levels) - 1, 1):
-            e = check_sweep(p, s, g, rng, 1e-5 if fp32 else 1e-11, n_sdofs=100)
-            log(f"[3d-fullsize] sweep fp32={fp32} level {g}: worst err {e:.2e}")
+            e = check_sweep(p, s, g, rng, fp32, n_sdofs=100)
+            log(f"[3d-fullsize] sweep fp32={fp32} level {g}: worst err / tolerance {e:.2f}")
     finally:
         if fp32:
             s.build_cell_inverses(fp32=False)

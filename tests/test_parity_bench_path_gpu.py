@@ -64,8 +64,8 @@ def test_2d_decoupled_sweep(bench2d, fp32):
     try:
         rng = np.random.default_rng(33)
         for g in (len(p.levels) - 1, 1):
-            e = check_sweep(p, s, g, rng, 1e-5 if fp32 else 1e-11)
-            log(f"[bench-path] 2d sweep fp32={fp32} level {g}: worst err {e:.2e}")
+            e = check_sweep(p, s, g, rng, fp32)
+            log(f"[bench-path] 2d sweep fp32={fp32} level {g}: worst err / tolerance {e:.2f}")
     finally:
         if fp32:
             s.build_cell_inverses(fp32=False)
