@@ -6,9 +6,12 @@ multigrid preconditioner to relative residual 1e-8.  The reported value is
 Vanka cell-sweeps per second over the whole step (sweeps on all smoothed
 levels, divided by the wall time of the step including the inverse build).
 
-Default workload: the 2d channel [0,2.2]x[0,0.41], 512x128 Q2/P1disc cells,
-6 levels, dG(2) in time, Oseen at a seeded divergence-free convection field,
-nu = 1e-3, tau = 0.005, seeded N(0,1) right-hand side, FP64.
+Default workload: the 3d channel [0,2.5]x[0,0.41]^2, 128x24x24 Q2/P1disc
+cells, 4 levels, dG(1) in time (170 local DoFs per cell), Oseen at a seeded
+divergence-free convection field, nu = 1e-3, tau = 0.01, seeded N(0,1)
+right-hand side; FP64-stored inverses timed, FP32-stored inverses as the
+second leg.  The 2d channel 512x128, 6 levels, dG(2) (tau = 0.005) is timed
+the same way and reported as "secondary_workload".
 """
 from __future__ import annotations
 
@@ -24,7 +27,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_2d512x128_dG2.json")
+# the 3d precision workload (FP64- vs FP32-stored 170 x 170 cell inverses) is
+# the largest single-GPU workload; the 2d dG(2) channel is reported beside it
+DEFAULT_WORKLOAD = "3d-128x24x24-dG1"
+SECONDARY_WORKLOAD = "2d-512x128-dG2"
+# counter-measured HBM bytes per launch (profiles/), one record per workload
+TRAFFIC_RECORDS = {
+    "2d-512x128-dG2": os.path.join(ROOT, "profiles", "traffic_2d512x128_dG2.json"),
+    "3d-128x24x24-dG1": os.path.join(ROOT, "profiles", "traffic_3d128x24x24_dG1.json"),
+}
 
 
 def measured_traffic(workload: str, kernel: str, launches_per_level):
@@ -33,8 +44,10 @@ def measured_traffic(workload: str, kernel: str, launches_per_level):
     None when there is no record for this workload and kernel, a level is
     missing, or the kernel source changed since the counters were taken."""
     import hashlib
+    if workload not in TRAFFIC_RECORDS:
+        return None
     try:
-        rec = json.load(open(TRAFFIC_RECORD))
+        rec = json.load(open(TRAFFIC_RECORDS[workload]))
     except (OSError, ValueError):
         return None
     if rec.get("workload") != workload or kernel not in rec:
@@ -63,7 +76,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="2d-512x128-dG2",
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     choices=["2d-512x128-dG2", "2d-16x4-dG1", "3d-128x24x24-dG1",
                              "batched-256-2d-dG1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -78,6 +91,10 @@ def parse():
     ap.add_argument("--no-kron", action="store_true",
                     help="residual from the stored blocks instead of the spatial factors")
     ap.add_argument("--no-graph-leg", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 2d dG(2) workload that the default run reports beside the 3d one")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the measured copy and FP64 GEMM reference rates")
     ap.add_argument("--nu-sweep", action="store_true",
                     help="instead of the timing line: FGMRES iterations of the batched "
                          "instances against viscosity, undamped and damped smoother")
@@ -103,7 +120,7 @@ WORKLOADS = {
                     ((16, 4), 2)),
     "3d-128x24x24-dG1": (3, (128, 24, 24), 4, 1, 0.01, 1e-3, 1003,
                          "3d channel 128x24x24 Q2/P1disc x dG(1), 4 levels, Oseen nu=1e-3, tau=0.01",
-                         ((32, 8, 8), 3)),
+                         ((48, 12, 12), 3)),
 }
 # 256 independent 2d dG(1) instances (finest 32x8 .. 128x32, nu in [5e-4, 5e-3],
 # seeds 2000 + j), one batch, FP32-stored inverses, FP64 FGMRES
@@ -448,33 +465,93 @@ def newton_bench(args):
         "fp64": r64, "fp32_inverses": r32, "cpu_baseline": cpu}), flush=True)
 
 
-def main():
-    args = parse()
-    if args.newton:
-        if args.gpus != 1:
-            print("bench.py runs on one GPU only.", file=sys.stderr)
-            sys.exit(2)
-        newton_bench(args)
-        return
-    if args.nu_sweep:
-        nu_sweep(args)
-        return
-    if args.gradient:
-        if args.gpus != 1:
-            print("bench.py runs on one GPU only.", file=sys.stderr)
-            sys.exit(2)
-        gradient_bench(args)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "sharding is a design note, not a measured path.", file=sys.stderr)
-        sys.exit(2)
+FP64_PEAK_TFLOPS = 78.6
+
+
+def inverse_flops_per_cell(dim, k, n_ls, dec, cx=False):
+    """Flops of the Gauss-Jordan inversion(s) one cell's build runs: 2 n^3 for
+    an explicit inverse of order n.  The time-decoupled build (2d levels with
+    spatial factors) inverts one block of order n_ls per real eigenvalue of the
+    time matrix and the real form (order 2 n_ls) of one block per complex
+    pair instead of the whole J_T of order (k+1) n_ls; the complex build (3d
+    dG(1) levels with spatial factors) inverts the complex block of order n_ls
+    in complex arithmetic, 8 n_ls^3 real flops."""
+    b = k + 1
+    if cx:
+        return 8 * n_ls ** 3
+    if dec:
+        n_pairs = b // 2
+        n_real = b - 2 * n_pairs
+        return n_real * 2 * n_ls ** 3 + n_pairs * 2 * (2 * n_ls) ** 3
+    return 2 * (b * n_ls) ** 3
+
+
+def coarse_flops(k, n_s, kron):
+    """Flops of the coarse Gauss-Jordan inverse: 2 N^3 for the whole matrix of
+    order N = (k+1) n_s; with spatial factors the eliminated matrices are the
+    real forms (order 2 n_s) of the pair blocks, and of the real eigenvalues'
+    blocks padded into the same launches (one real-form block per two real
+    eigenvalues, rounded up)."""
+    b = k + 1
+    if not kron:
+        return 2 * (b * n_s) ** 3
+    n_pairs = b // 2
+    n_real = b - 2 * n_pairs
+    blocks = n_pairs + (n_real + 1) // 2
+    return blocks * 2 * (2 * n_s) ** 3
+
+
+def measured_peaks():
+    """A plain copy (1 GiB read + 1 GiB written, torch's copy kernel) and a
+    plain FP64 GEMM (8192^3, the vendor BLAS through torch) on this GPU."""
+    import torch
+    dev = torch.device("cuda", 0)
+    n = 1 << 27
+    x = torch.empty(n, dtype=torch.float64, device=dev).normal_()
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    reps = 10
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 8 * n * reps / (a.elapsed_time(b) / 1e3) / 1e9
+    del x, y
+    m = 8192
+    A = torch.randn(m, m, dtype=torch.float64, device=dev)
+    B = torch.randn(m, m, dtype=torch.float64, device=dev)
+    C = A @ B
+    torch.cuda.synchronize()
+    a.record()
+    reps = 5
+    for _ in range(reps):
+        C = A @ B
+    b.record()
+    torch.cuda.synchronize()
+    dgemm = 2 * m ** 3 * reps / (a.elapsed_time(b) / 1e3) / 1e12
+    del A, B, C
+    torch.cuda.empty_cache()
+    return dict(copy_GBps=round(copy_gbs, 1), dgemm_TFLOPs=round(dgemm, 2),
+                copy="torch copy_ of 1 GiB float64, read + write bytes",
+                dgemm="torch float64 matmul 8192 x 8192 x 8192")
+
+
+def run_workload(args, name, legs=True):
+    """Set up one workload (resident hierarchy, spatial factors, autotuned
+    shapes), time args.steps steps after args.warmup untimed ones, and return
+    the measurements: throughput, phase split, rooflines of the sweep, the
+    residual and the inverse build, and (legs) the other storage precision of
+    the inverses and the graph-replay step."""
     import torch
 
     import paper_2107_10561_amd as stv
 
     t0 = time.time()
-    probs, dim, k, desc, primary_fp32 = load_workload(args.workload)
+    probs, dim, k, desc, primary_fp32 = load_workload(name)
     b = k + 1
     print(f"[bench] generated {desc} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     s = stv.Solver(0)
@@ -507,9 +584,10 @@ def main():
     mg = dict(nu1=args.nu1, nu2=args.nu2, omega=args.omega)
     cells_smoothed = [sum(L.n_cells for L in p.levels[1:]) for p in probs]
 
-    def step(fp32):
+    def step(fp32, out=None):
         s.build_cell_inverses(fp32=fp32)
-        return s.gmres_solve(rhs, x, restart=30, max_it=1000, rtol=1e-8, **mg)
+        return s.gmres_solve(rhs, x if out is None else out, restart=30, max_it=1000, rtol=1e-8,
+                             **mg)
 
     def useful_sweeps():
         return sum(s.instance_info(i)["iters"] * c for i, c in enumerate(cells_smoothed)) * \
@@ -550,17 +628,9 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
-    iters = infos[-1]["iters"]
-    relres = infos[-1]["true_relres"]
-    sweeps_per_step = useful_sweeps()
     value = total_sweeps / elapsed
 
-    # per-kernel statistics (HIP events on the library's stream, timed region only)
     top = G - 1
-    stats = {}
-    for cls in stv.KERNEL_CLASSES:
-        nl, ms = s.kernel_stats(cls)
-        stats[cls] = dict(launches=nl, ms=ms)
     zi = 1.0 / (args.nu1 + args.nu2) if args.nu1 > 0 else 0.0
     inv_b = {g: s.level_info(g)["inverse_bytes"] for g in range(G)}
 
@@ -578,7 +648,7 @@ def main():
         gbs_f = bytes_of(top) / (ms_f / n_f / 1e3) / 1e9 if n_f else 0.0
         return dict(bound="hbm", achieved=round(gbs_f, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(gbs_f / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(args.workload, traffic_key, {top: n_f}),
+                    traffic=measured_traffic(name, traffic_key, {top: n_f}),
                     kernel=kernel + f", finest level ({top})",
                     bytes_per_launch=int(bytes_of(top)), avg_launch_ms=round(ms_f / max(n_f, 1), 5),
                     launches=n_f)
@@ -601,13 +671,22 @@ def main():
                  else "block-sparse level residual (k_spmv_rows)")
     # with spatial factors the library stores the owned rows of 2d cell
     # problems (n_loc = 21, B <= 3) time-decoupled and sweeps with k_vanka_dec
+    # (one row per owned spatial DoF), and those of 3d dG(1) levels (one complex
+    # pair: k_inverse_cx) as complex rows swept by k_vanka_cx
     dec = kron and dim == 2 and 2 <= b <= 3
-    roof_sweep = (roofline("sweep", sweep_bytes_packed,
-                           "Vanka cell sweep on time-decoupled inverses (k_vanka_dec)", "k_vanka_dec")
-                  if dec else roofline("sweep", sweep_bytes_packed, "Vanka cell sweep (k_vanka)", "k_vanka"))
+    cx = kron and dim == 3 and b == 2
+    if dec:
+        roof_sweep = roofline("sweep", sweep_bytes_packed,
+                              "Vanka cell sweep on time-decoupled inverses (k_vanka_dec)",
+                              "k_vanka_dec")
+    elif cx:
+        roof_sweep = roofline("sweep", sweep_bytes_packed,
+                              "Vanka cell sweep on complex time-decoupled inverses (k_vanka_cx)",
+                              "k_vanka_cx")
+    else:
+        roof_sweep = roofline("sweep", sweep_bytes_packed, "Vanka cell sweep (k_vanka)", "k_vanka")
     roof_res = roofline("residual", residual_bytes_packed, kname_res,
                         "k_spmv_kron" if kron else "k_spmv")
-    dominant = roof_sweep if stats["sweep"]["ms"] >= stats["residual"]["ms"] else roof_res
     # time per kernel class (and both kernels over every level) from one more
     # step with every class and level timed, outside the timed region: the
     # event records around the classes that are not stamped by their launch
@@ -618,29 +697,73 @@ def main():
     breakdown = {cls: round(s.kernel_stats(cls)[1], 3) for cls in stv.KERNEL_CLASSES}
     roof_sweep["all_levels_instrumented_step"] = all_levels("sweep", sweep_bytes_packed)
     roof_res["all_levels_instrumented_step"] = all_levels("residual", residual_bytes_packed)
-    s.set_timing(False)
+    # the inverse build against the FP64 matrix peak: cell inverses of every
+    # smoothed level (one launch class on the caller's stream) and the coarse
+    # chain (its own stream, concurrent with them)
+    inv_flops = 0
+    for g in range(1, G):
+        for L, sm in members[g]:
+            if sm:
+                inv_flops += L.n_cells * inverse_flops_per_cell(dim, k, L.cell_sdofs.shape[1], dec,
+                                                                cx=cx)
+    crs_flops = sum(coarse_flops(k, p.levels[0].n_sdofs, kron) for p in probs)
+    n_inv, ms_inv = s.kernel_stats("inverse")
+    n_crs, ms_crs = s.kernel_stats("coarse_factor")
 
-    # the other storage precision of the inverses, same solve
-    other = None
-    if not args.no_fp32:
+    def flop_roof(fl, ms, kernel, launches):
+        tf = fl / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+        return dict(bound="mfma", achieved=round(tf, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(tf / FP64_PEAK_TFLOPS, 4), flops_per_build=int(fl),
+                    ms_per_build=round(ms, 3), launches=launches, kernel=kernel)
+    inv_roof = dict(
+        cell_inverses=flop_roof(inv_flops, ms_inv, "cell inverses, every smoothed level "
+                                "(k_inverse_cx)" if cx else "cell inverses, every smoothed level "
+                                "(k_inverse_wave / k_inverse_mfma)", n_inv),
+        coarse=flop_roof(crs_flops, ms_crs, "coarse Gauss-Jordan inverse chain "
+                         "(k_gj_tour_cx / k_gj_slab_update and helpers)", n_crs),
+        concurrent="the coarse chain runs on a second stream beside the cell inverses; "
+                   "each class's time includes the contention")
+    s.set_timing(False)
+    res = dict(workload=desc, value=round(value, 1), unit="cell-sweeps/s",
+               ms_per_step=round(ms_per_step, 3),
+               t_inv_ms=round(1e3 * t_inv / args.steps, 3),
+               t_gmres_ms=round(1e3 * t_gm / args.steps, 3), t_set_hierarchy_s=round(t_set, 3),
+               gmres_iters=infos[-1]["iters"], true_relres=infos[-1]["true_relres"],
+               cell_sweeps_per_step=useful_sweeps(), kernel_ms_per_step=breakdown,
+               roofline=roof_sweep, roofline_residual=roof_res, inverse_roofline=inv_roof,
+               launch_shapes=shapes, residual_from_spatial_factors=kron,
+               config={"workload": desc, "instances": len(probs),
+                       "cells_finest": int(sum(p.levels[-1].n_cells for p in probs)),
+                       "levels": G,
+                       "spacetime_dofs_finest": int(sum(p.levels[-1].n_sdofs for p in probs) * b),
+                       "k": k, "cycle": f"V({args.nu1},{args.nu2})", "omega": args.omega,
+                       "restart": 30, "rtol": 1e-8, "parallelism": "single GPU"},
+               primary_fp32=primary_fp32)
+    if legs and not args.no_fp32:
+        # the other storage precision of the inverses, same solve; the two
+        # solutions are compared (equal accuracy: both reach the same true
+        # residual; their difference is within the solve tolerance)
         alt = not primary_fp32
-        step(alt)
+        x_alt = torch.zeros_like(x)
+        step(alt, x_alt)
         torch.cuda.synchronize()
         a = time.perf_counter()
         reps = max(1, min(3, args.steps))
         for _ in range(reps):
-            inf_alt = step(alt)
+            inf_alt = step(alt, x_alt)
         torch.cuda.synchronize()
         t_alt = (time.perf_counter() - a) / reps
-        other = dict(ms_per_step=round(1e3 * t_alt, 3), iters=inf_alt["iters"],
-                     true_relres=inf_alt["true_relres"],
-                     inverse_bytes_finest=s.level_info(top)["inverse_bytes"])
+        diff = float(torch.linalg.vector_norm(x_alt - x) / torch.linalg.vector_norm(x))
+        res["fp64_inverses" if primary_fp32 else "fp32_inverses"] = dict(
+            ms_per_step=round(1e3 * t_alt, 3), iters=inf_alt["iters"],
+            true_relres=inf_alt["true_relres"],
+            rel_diff_to_primary_solution=diff,
+            inverse_bytes_finest=s.level_info(top)["inverse_bytes"],
+            speedup_vs_primary=round(ms_per_step / (1e3 * t_alt), 4))
         print(f"[bench] {'fp32' if alt else 'fp64'} step {1e3 * t_alt:.2f} ms "
               f"iters {inf_alt['iters']}", file=sys.stderr, flush=True)
-
-    # the same step with the V-cycle replayed from a captured HIP graph
-    graph_leg = None
-    if not args.no_graph_leg:
+    if legs and not args.no_graph_leg:
+        # the same step with the V-cycle replayed from a captured HIP graph
         s.set_graph(True)
         step(primary_fp32)
         torch.cuda.synchronize()
@@ -651,11 +774,52 @@ def main():
         torch.cuda.synchronize()
         t_g = (time.perf_counter() - a) / reps
         s.set_graph(False)
-        graph_leg = dict(ms_per_step=round(1e3 * t_g, 3), iters=inf_g["iters"],
-                         true_relres=inf_g["true_relres"])
+        res["graph_replay"] = dict(ms_per_step=round(1e3 * t_g, 3), iters=inf_g["iters"],
+                                   true_relres=inf_g["true_relres"])
         print(f"[bench] graph step {1e3 * t_g:.2f} ms iters {inf_g['iters']}", file=sys.stderr,
               flush=True)
+    s.close()
+    del s, rhs, x
+    torch.cuda.empty_cache()
+    return res
 
+
+def main():
+    args = parse()
+    if args.newton:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        newton_bench(args)
+        return
+    if args.nu_sweep:
+        nu_sweep(args)
+        return
+    if args.gradient:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        gradient_bench(args)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    main_res = run_workload(args, args.workload)
+    secondary = None
+    if args.workload == DEFAULT_WORKLOAD and not args.no_secondary:
+        print(f"[bench] secondary workload {SECONDARY_WORKLOAD}", file=sys.stderr, flush=True)
+        sec = run_workload(args, SECONDARY_WORKLOAD)
+        secondary = {k_: v for k_, v in sec.items() if k_ not in ("primary_fp32",)}
+    peaks = None
+    if not args.no_peaks:
+        peaks = measured_peaks()
+        peaks["sweep_frac_of_copy"] = round(main_res["roofline"]["achieved"] / peaks["copy_GBps"], 4)
+        peaks["cell_inverses_frac_of_dgemm"] = round(
+            main_res["inverse_roofline"]["cell_inverses"]["achieved"] / peaks["dgemm_TFLOPs"], 4)
+        peaks["coarse_frac_of_dgemm"] = round(
+            main_res["inverse_roofline"]["coarse"]["achieved"] / peaks["dgemm_TFLOPs"], 4)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -663,44 +827,43 @@ def main():
         cpu = {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in cb.items()
                if k_ in ("value", "unit", "cores", "kind", "sample")}
 
+    r = main_res
     out = {
         "metric": "GMG-GMRES time to rel. residual 1e-8; Vanka cell-sweeps/s + HBM GB/s, FP64 vs FP32",
-        "value": round(value, 1),
+        "value": r["value"],
         "unit": "cell-sweeps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64, inverses stored f32" if primary_fp32 else "f64",
+        "dtype": "f64, inverses stored f32" if r["primary_fp32"] else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "instances": len(probs),
-                   "cells_finest": int(sum(p.levels[-1].n_cells for p in probs)), "levels": G,
-                   "spacetime_dofs_finest": int(sum(p.levels[-1].n_sdofs for p in probs) * b),
-                   "k": k, "cycle": f"V({args.nu1},{args.nu2})", "omega": args.omega,
-                   "restart": 30, "rtol": 1e-8, "parallelism": "single GPU"},
-        "time_to_solution_ms": round(ms_per_step, 3),
-        "t_inv_ms": round(1e3 * t_inv / args.steps, 3),
-        "t_gmres_ms": round(1e3 * t_gm / args.steps, 3),
-        "t_set_hierarchy_s": round(t_set, 3),
-        "gmres_iters": iters,
-        "true_relres": relres,
-        "cell_sweeps_per_step": sweeps_per_step,
-        "kernel_ms_per_step": breakdown,
+        "config": r["config"],
+        "time_to_solution_ms": r["ms_per_step"],
+        "t_inv_ms": r["t_inv_ms"],
+        "t_gmres_ms": r["t_gmres_ms"],
+        "t_set_hierarchy_s": r["t_set_hierarchy_s"],
+        "gmres_iters": r["gmres_iters"],
+        "true_relres": r["true_relres"],
+        "cell_sweeps_per_step": r["cell_sweeps_per_step"],
+        "kernel_ms_per_step": r["kernel_ms_per_step"],
         "kernel_ms_per_step_from": "one extra step after the timed region, every class timed",
-        "roofline": dominant,
-        "roofline_sweep": roof_sweep,
-        "roofline_residual": roof_res,
-        ("fp64_inverses" if primary_fp32 else "fp32_inverses"): other,
-        "graph_replay": graph_leg,
-        "launch_shapes": shapes,
-        "residual_from_spatial_factors": kron,
+        "roofline": r["roofline"],
+        "roofline_residual": r["roofline_residual"],
+        "inverse_roofline": r["inverse_roofline"],
+        "measured_peaks": peaks,
+        ("fp64_inverses" if r["primary_fp32"] else "fp32_inverses"):
+            r.get("fp64_inverses" if r["primary_fp32"] else "fp32_inverses"),
+        "graph_replay": r.get("graph_replay"),
+        "launch_shapes": r["launch_shapes"],
+        "residual_from_spatial_factors": r["residual_from_spatial_factors"],
+        "secondary_workload": secondary,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    s.close()
 
 
 if __name__ == "__main__":

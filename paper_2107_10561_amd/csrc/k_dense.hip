@@ -472,6 +472,101 @@ __global__ void __launch_bounds__(256) k_gj_slab_update(double* __restrict__ A, 
       }
 }
 
+// The same rank-NO update for the real form of a complex matrix (rows and
+// columns in pairs, every 2 x 2 block [[x, -y], [y, x]]): the left factor,
+// the pivot rows and the result keep that structure exactly, so only the
+// even row of each pair is computed, and the odd row is written from it
+// (odd[2c] = -even[2c + 1], odd[2c + 1] = even[2c]; the partner column sits
+// in the neighbouring lane).  Half the MFMAs of k_gj_slab_update: each
+// wavefront owns 16 row pairs x 32 columns of the 64 x 64 tile.
+template <int NO>
+__global__ void __launch_bounds__(256) k_gj_slab_update_cx(double* __restrict__ A, int64_t sA,
+                                                           int64_t n, int64_t j0,
+                                                           const int* __restrict__ rp, int64_t sV,
+                                                           const double* __restrict__ Sb,
+                                                           double* __restrict__ Snext, int64_t sS,
+                                                           const double* __restrict__ Bg,
+                                                           int64_t sB, int ct0, int skip_at,
+                                                           int skip_n) {
+  constexpr int KC = 32;
+  chain_priority();
+  A += blockIdx.z * sA;
+  rp += blockIdx.z * sV;
+  Sb += blockIdx.z * sS;
+  Snext += blockIdx.z * sS;
+  Bg += blockIdx.z * sB;
+  __shared__ double Ws[32][KC + 1];   // even rows of the tile
+  __shared__ double Bs[KC][64 + 2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // column tile: ct0 + x, skipping skip_n tiles from skip_at on (the launch
+  // for the next slab's tiles and the one for all others)
+  const int ct = ct0 + (int)blockIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, jt = (int64_t)(ct < skip_at ? ct : ct + skip_n) * 64;
+  if (jt >= j0 && jt < j0 + NO) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      *(double2*)&A[(i0 + r) * n + jt + c] = *(const double2*)&Sb[(i0 + r) * NO + (jt - j0) + c];
+    }
+    return;
+  }
+  const int rb = 16 * (w >> 1), cb = 32 * (w & 1), lr = lane >> 4, lc = lane & 15;
+  stv_d4 acc[2];
+#pragma unroll
+  for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      acc[tj][v] = A[(i0 + 2 * (rb + 4 * v + lr)) * n + jt + cb + 16 * tj + lc];
+  for (int kc = 0; kc < NO; kc += KC) {
+    if (kc) __syncthreads();
+#pragma unroll
+    for (int e = tid; e < 32 * KC / 2; e += 256) {
+      const int r = e / (KC / 2), c = 2 * (e % (KC / 2));
+      const double2 x = *(const double2*)&Sb[(i0 + 2 * r) * NO + kc + c];
+      Ws[r][c] = x.x;
+      Ws[r][c + 1] = x.y;
+    }
+#pragma unroll
+    for (int e = tid; e < KC * 32; e += 256) {
+      const int r = e >> 5, c = 2 * (e & 31);
+      *(double2*)&Bs[r][c] = *(const double2*)&Bg[(int64_t)(kc + r) * n + jt + c];
+    }
+    __syncthreads();
+    if (tid < KC) {
+      const int r = rp[kc + tid];
+      if (r >= i0 && r < i0 + 64 && !(r & 1)) Ws[(r - i0) >> 1][tid] -= 1.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const double a = Ws[rb + lc][4 * kk + lr];
+      double bv[2];
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) bv[tj] = Bs[4 * kk + lr][cb + 16 * tj + lc];
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+        acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[tj], acc[tj], 0, 0, 0);
+    }
+  }
+  const bool nxt = (jt >= j0 + NO && jt < j0 + 2 * NO);
+#pragma unroll
+  for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + 2 * (rb + 4 * v + lr);
+      const int64_t j = jt + cb + 16 * tj + lc;
+      const double x = acc[tj][v];
+      const double partner = __shfl_xor(x, 1, 64);
+      const double odd = (j & 1) ? partner : -partner;
+      A[i * n + j] = x;
+      A[(i + 1) * n + j] = odd;
+      if (nxt) {
+        const int64_t c = j - j0 - NO;
+        Snext[i * NO + c] = x;
+        Snext[(i + 1) * NO + c] = odd;
+      }
+    }
+}
+
 template <int RPT, int NB, int TPB, int NO>
 static hipError_t gj_slab(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
   double* sb[2] = {w.S, w.S + n * NO};
@@ -585,7 +680,7 @@ __global__ void __launch_bounds__(1024) k_gj_tour(double* __restrict__ S, int64_
                                                   const double* __restrict__ Zc,
                                                   double* __restrict__ Zn, int64_t sZ,
                                                   int* __restrict__ cand, int64_t sC,
-                                                  unsigned* __restrict__ counter) {
+                                                  unsigned* __restrict__ counter, int64_t sK) {
   constexpr int RW = 256, NW = 16, FAN = 64 / NB, MAXL = 64, NH = NO / 64, RB = NH == 1 ? 16 : 4;
   chain_priority();
   static_assert(NB == 8 || NB == 16, "panel width");
@@ -711,10 +806,10 @@ __global__ void __launch_bounds__(1024) k_gj_tour(double* __restrict__ S, int64_
   __syncthreads();
   if (tid == 0) {
     __threadfence();
-    const unsigned last = (atomicAdd(counter + z, 1u) == gridDim.x - 1) ? 1u : 0u;
+    const unsigned last = (atomicAdd(counter + z * sK, 1u) == gridDim.x - 1) ? 1u : 0u;
     if (last) {
       __threadfence();
-      atomicExch(counter + z, 0u);
+      atomicExch(counter + z * sK, 0u);
     }
     s_last = last;
   }
@@ -810,12 +905,12 @@ static hipError_t gj_tour(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
   for (int64_t j0 = 0; j0 < n; j0 += NO, cs ^= 1) {
     k_gj_tour<NB, NO, false><<<dim3(nwg, 1, cnt), 1024, 0, s>>>(
         sb[cs], w.sS, n, j0, 0, w.rpiv, w.used, w.sV, nullptr, zb[cz], w.sZ, w.cand, w.sC,
-        w.counter);
+        w.counter, w.sK);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int q0 = 0; q0 < NO; q0 += NB, cz ^= 1) {
       k_gj_tour<NB, NO, true><<<dim3(nwg, 1, cnt), 1024, 0, s>>>(
           sb[cs], w.sS, n, j0, q0, w.rpiv, w.used, w.sV, zb[cz], zb[cz ^ 1], w.sZ, w.cand, w.sC,
-          w.counter);
+          w.counter, w.sK);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
@@ -910,8 +1005,8 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
                                                      const double* __restrict__ Zc,
                                                      double* __restrict__ Zn, int64_t sZ,
                                                      int* __restrict__ cand, int64_t sC,
-                                                     unsigned* __restrict__ counter) {
-  constexpr int NB = 16, RC = 64, NW = 4, NT = 64 * NW, FAN = 64 / NB, MAXL = 128;
+                                                     unsigned* __restrict__ counter, int64_t sK) {
+  constexpr int NB = 16, RC = 64, NW = 4, NT = 64 * NW, FAN = 64 / NB;
   chain_priority();
   constexpr int NOC = NO / 2;                  // complex columns of the slab
   constexpr int LPR = NOC < 64 ? NOC : 64;     // lanes per row in the panel step
@@ -923,7 +1018,6 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
   double2(*Acur)[NB] = reinterpret_cast<double2(*)[NB]>(smem);
   double2(*Anx)[NB + 1] = reinterpret_cast<double2(*)[NB + 1]>(smem + RC * NB);
   double2* Brow = smem;
-  __shared__ int tl[2][MAXL * NB];
   __shared__ int rootg[64];
   __shared__ double2 LUs[NB][NB + 1];
   __shared__ int Ll[NB];
@@ -934,6 +1028,7 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
   used += z * sV;
   Zn += z * sZ;
   cand += z * sC;
+  counter += z * sK;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t c0 = (int64_t)blockIdx.x * RC, nc = n / 2;
@@ -1033,26 +1128,37 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
     wave_select_cx<NB, false>(wr, wi, av, mine, zf, step);
     if (lane < NB) cand[(int64_t)blockIdx.x * NB + lane] = mine >= 0 ? (int)(c0 + mine) : -1;
   }
-  // the workgroup that arrives last merges every workgroup's list
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const unsigned last = (atomicAdd(counter + z, 1u) == gridDim.x - 1) ? 1u : 0u;
-    if (last) {
+  // merge tree over the workgroups' lists, FAN children per node: the last
+  // child to arrive at a node merges the children's lists into the node's
+  // (partial pivoting on their rows, children in index order), so the nodes
+  // of one level merge in parallel; the last arrival at the top level (at
+  // most FAN lists) goes on to the root.  Lists of level l follow those of
+  // level l - 1 in cand; counters of a level follow those of the level below.
+  int m = (int)gridDim.x;        // lists at the current level
+  int node = (int)blockIdx.x;    // this workgroup's list there
+  int64_t lev = 0, cb = 0;       // first list and first counter of the level
+  for (;;) {
+    const bool top = m <= FAN;
+    const int parent = top ? 0 : node / FAN;
+    const int nchild = top ? m : min(FAN, m - parent * FAN);
+    __syncthreads();
+    if (tid == 0) {
       __threadfence();
-      atomicExch(counter + z, 0u);
+      unsigned* cn = counter + cb + parent;
+      const unsigned last = (atomicAdd(cn, 1u) == (unsigned)nchild - 1u) ? 1u : 0u;
+      if (last) {
+        __threadfence();
+        atomicExch(cn, 0u);
+      }
+      s_last = last;
     }
-    s_last = last;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  int m = (int)gridDim.x, cur = -1;           // cur < 0: lists in cand
-  while (m > FAN) {
-    const int nodes = (m + FAN - 1) / FAN, nxt = cur == 0 ? 1 : 0;
-    for (int j = wv; j < nodes; j += NW) {
-      const int lx = j * FAN + lane / NB, sl = lane % NB;
-      int g = -1;
-      if (lx < m) g = cur < 0 ? cand[(int64_t)lx * NB + sl] : tl[cur][lx * NB + sl];
+    __syncthreads();
+    if (!s_last) return;
+    if (top) break;
+    const int64_t nlev = lev + m;
+    if (wv == 0) {
+      const int k = lane / NB, sl = lane % NB;
+      const int g = k < nchild ? cand[(lev + parent * FAN + k) * NB + sl] : -1;
       double wr[NB], wi[NB];
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
@@ -1062,15 +1168,16 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
       }
       wave_select_cx<NB, false>(wr, wi, g >= 0, mine, zf, step);
       const int gs = __shfl(g, mine >= 0 ? mine : 0, 64);
-      if (lane < NB) tl[nxt][j * NB + lane] = mine >= 0 ? gs : -1;
+      if (lane < NB) cand[(nlev + parent) * NB + lane] = mine >= 0 ? gs : -1;
     }
-    __syncthreads();
-    cur = nxt;
-    m = nodes;
+    cb += (m + FAN - 1) / FAN;
+    lev = nlev;
+    node = parent;
+    m = (m + FAN - 1) / FAN;
   }
   if (tid < 64) {
-    const int lx = tid / NB;
-    rootg[tid] = lx < m ? (cur < 0 ? cand[(int64_t)lx * NB + tid % NB] : tl[cur][lx * NB + tid % NB]) : -1;
+    const int k = tid / NB;
+    rootg[tid] = k < m ? cand[(lev + k) * NB + tid % NB] : -1;
   }
   __syncthreads();
   if (wv == 0) {
@@ -1152,7 +1259,8 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
 }
 
 template <int NO>
-static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
+static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt,
+                             const GjAux* aux) {
   constexpr int NBR = 32;                      // real columns per panel
   double* sb[2] = {w.S, w.S + n * NO};
   double* zb[2] = {w.Z, w.Z + NBR * NO};
@@ -1165,22 +1273,41 @@ static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt)
   for (int64_t j0 = 0; j0 < n; j0 += NO, cs ^= 1) {
     k_gj_tour_cx<NO, false><<<dim3(nwg, 1, cnt), 256, 0, s>>>(
         sb[cs], w.sS, n, j0, 0, w.rpiv, w.used, w.sV, nullptr, zb[cz], w.sZ, w.cand, w.sC,
-        w.counter);
+        w.counter, w.sK);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int q0 = 0; q0 < NO; q0 += NBR, cz ^= 1) {
       k_gj_tour_cx<NO, true><<<dim3(nwg, 1, cnt), 256, 0, s>>>(
           sb[cs], w.sS, n, j0, q0, w.rpiv, w.used, w.sV, zb[cz], zb[cz ^ 1], w.sZ, w.cand, w.sC,
-          w.counter);
+          w.counter, w.sK);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // the gather reads whole rows of A: the previous slab's update of the
+    // other columns must have finished
+    if (aux && j0 > 0 && (e = hipStreamWaitEvent(s, aux->done_rest, 0)) != hipSuccess) return e;
     k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
         w.A, w.sA, n, (int)j0, w.rpiv, w.sV, w.B, w.sB);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_gj_slab_update<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
-        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, sb[cs ^ 1],
-        w.sS, 0);
+    const int nst = (int)(NO / 64), nxt0 = (int)((j0 + NO) / 64);
+    const int nnext = j0 + NO < n ? nst : 0;
+    if (!aux || nnext == 0) {
+      k_gj_slab_update_cx<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
+          w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, 0, (int)nt, 0);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      continue;
+    }
+    // look-ahead: the next slab's columns first (its panels start at once),
+    // the other columns on the second stream, concurrent with those panels
+    k_gj_slab_update_cx<NO><<<dim3((unsigned)nnext, nt, cnt), 256, 0, s>>>(
+        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, nxt0, (int)nt, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(aux->next_ready, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(aux->s2, aux->next_ready, 0)) != hipSuccess) return e;
+    k_gj_slab_update_cx<NO><<<dim3(nt - (unsigned)nnext, nt, cnt), 256, 0, aux->s2>>>(
+        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, 0, nxt0, nnext);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(aux->done_rest, aux->s2)) != hipSuccess) return e;
   }
+  if (aux && n > NO && (e = hipStreamWaitEvent(s, aux->done_rest, 0)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -1220,7 +1347,8 @@ GjPlan gj_plan(int64_t n, int algo, bool pair) {
 
 // cnt matrices of order n (a multiple of plan.pad, at most plan.max_n) at
 // the strides of w.
-hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt) {
+hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt,
+                     const GjAux* aux) {
   if (n > p.max_n || n % p.pad || cnt < 1 || (p.pair && (p.algo != 3 || n % 2)))
     return hipErrorInvalidValue;
   if (p.algo == 1) {
@@ -1231,7 +1359,7 @@ hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n,
     }
   }
   if (p.algo == 3 && p.pair)
-    return p.cfg ? gj_tour_cx<128>(s, w, n, cnt) : gj_tour_cx<64>(s, w, n, cnt);
+    return p.cfg ? gj_tour_cx<128>(s, w, n, cnt, aux) : gj_tour_cx<64>(s, w, n, cnt, aux);
   if (p.algo == 3)
     return p.cfg ? gj_tour<16, 128>(s, w, n, cnt) : gj_tour<16, 64>(s, w, n, cnt);
   switch (p.cfg) {

@@ -541,6 +541,351 @@ k_inverse_wave(const int32_t* __restrict__ posmap, const double* __restrict__ va
   }
 }
 
+// Stores the row of the complex block held in local tile row rl >> 4,
+// register (rl >> 2) & 3 by the lanes of group rl & 3 (rl uniform, < 16 TR)
+// into dst[16 tj + lc] for the TC local tile columns, as (re, im) pairs.  As
+// in store_row, every case reads its own registers.
+template <int TR, int TC>
+__device__ __forceinline__ void store_row_cx(const stv_d4 (&ar)[TR][TC],
+                                             const stv_d4 (&ai)[TR][TC], int rl,
+                                             double2* dst, int lr, int lc) {
+  if (lr != (rl & 3)) return;
+  switch (rl >> 2) {
+#define STV_CX_CASE(S)                                                                   \
+  case S:                                                                                \
+    if constexpr (S < 4 * TR) {                                                          \
+      _Pragma("unroll") for (int tj = 0; tj < TC; ++tj)                                  \
+        dst[16 * tj + lc] = make_double2(ar[S >> 2][tj][S & 3], ai[S >> 2][tj][S & 3]);  \
+      asm volatile("; cx row case %0" ::"n"(S));                                         \
+    }                                                                                    \
+    break;
+    STV_CX_CASE(0) STV_CX_CASE(1) STV_CX_CASE(2) STV_CX_CASE(3)
+    STV_CX_CASE(4) STV_CX_CASE(5) STV_CX_CASE(6) STV_CX_CASE(7)
+    STV_CX_CASE(8) STV_CX_CASE(9) STV_CX_CASE(10) STV_CX_CASE(11)
+#undef STV_CX_CASE
+    default: break;
+  }
+}
+
+// Cell inverses of a dG(1) level with spatial factors through its complex
+// time-decoupled block (Section 4.3's J_T^-1, computed in half the pivot
+// steps and half the flops of the real block).  With D^-1 C = V T V^-1 and
+// T = [[t00, t01], [t10, t00]] (one complex pair),
+//   J_T^-1 = (I (x) V) Q^-1 (I (x) W),  Q = M_T (x) T + A_T (x) I,  W = V^-1 D^-1,
+// and Q is the real form of the complex matrix X = (t00 M_T + A_T) + i t10 M_T
+// of order n_ls, so Q^-1 is the real form of Y = X^-1 and
+//   J_T^-1[(a, i), (c, l)] = V_i0 (Re Y_ac W_0l - Im Y_ac W_1l)
+//                          + V_i1 (Im Y_ac W_0l + Re Y_ac W_1l).
+// Y is computed by Gauss-Jordan elimination with complex partial pivoting
+// (largest |Re| + |Im| among the rows not yet used, lowest row on ties; no
+// row interchanges, as in k_inverse_mfma).  dec = 0: the rows of J_T^-1 are
+// stored in the plain layout (owned or all rows, FP64 or FP32), the same rows
+// the real elimination stores; dec = 1: the owned-rows layout keeps, per
+// owned spatial DoF a, the row Y_a. as [Re Y_a0 .. Re Y_a,n-1, Im Y_a0 ..
+// Im Y_a,n-1] (half the values of a's two rows of J_T^-1; the sweep applies
+// V and W).
+// Four wavefronts per cell on a 2 x 2 grid of the tiles: X, identity-padded
+// to NP = 16 NT, sits in their accumulators in the v_mfma_f64_16x16x4f64
+// layout, wave (wr, wc) holding tile rows TR wr .. and tile columns TC wc ..
+// (real and imaginary parts in separate tiles).  Per panel of 4 columns
+// every wavefront reads the panel from LDS and chooses the same pivots (no
+// broadcast needed), the owners publish the pivot rows as they were before
+// the panel, and the rank-4 complex update is four real MFMAs per tile.
+// The grid strides over the cells.
+template <int NLS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_inverse_cx(const int32_t* __restrict__ posmap, const double* __restrict__ ma,
+             const int32_t* __restrict__ own_ptr, const uint8_t* __restrict__ own_loc, int full,
+             const int64_t* __restrict__ inv_off, int ld, void* store, int fp32,
+             uint8_t* status, int n_cells, CellSplit sp, int dec) {
+  constexpr int N = NLS;
+  constexpr int NT = (N + 15) / 16;
+  constexpr int NP = 16 * NT;
+  constexpr int NW = 4;
+  constexpr int TR = NT / 2, TC = NT / 2;   // local tile rows and columns
+  constexpr int RPW = 16 * TR;              // rows (and columns) per wavefront
+  static_assert(NT % 2 == 0 && NP <= 128 && TR <= 3, "2 x 2 wavefronts, at most 96 rows");
+  __shared__ double2 pin[NP][4];            // panel columns before elimination
+  __shared__ double2 pw[NW][NP][4];         // each wavefront's eliminated panel
+  __shared__ double2 brow[4][NP];           // the pivot rows before the panel
+  __shared__ int rpiv[NP];
+  __shared__ int rinv[NP];
+  __shared__ int rowmap[2 * NP];            // local DoF a * 2 + i -> stored row (-1: none)
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = w >> 1, wc = w & 1;
+  const double t00 = sp.T[0], t10 = sp.T[2];
+  for (int T = blockIdx.x; T < n_cells; T += gridDim.x) {
+    int lane = tid & 63;
+    asm volatile("" : "+v"(lane));
+    const int lr = lane >> 4;
+    const int lc = lane & 15;
+
+    // X from the spatial factors (m, a) of every cell pair, identity padding
+    const int32_t* pos = posmap + (int64_t)T * (NLS * NLS);
+    stv_d4 ar[TR][TC], ai[TR][TC];
+#pragma unroll
+    for (int ti = 0; ti < TR; ++ti) {
+      int32_t q[TC][4];
+#pragma unroll
+      for (int tj = 0; tj < TC; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = RPW * wr + 16 * ti + 4 * v + lr, col = RPW * wc + 16 * tj + lc;
+          const int rc = row < N ? row : N - 1, cc = col < N ? col : N - 1;
+          q[tj][v] = pos[rc * NLS + cc];
+        }
+#pragma unroll
+      for (int tj = 0; tj < TC; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = RPW * wr + 16 * ti + 4 * v + lr, col = RPW * wc + 16 * tj + lc;
+          const int32_t qq = q[tj][v];
+          const double2 mav = *reinterpret_cast<const double2*>(&ma[2 * (int64_t)(qq > 0 ? qq : 0)]);
+          const bool inb = (row < N) & (col < N);
+          const bool keep = inb & (qq >= 0);
+          const double pad = ((!inb) & (row == col)) ? 1.0 : 0.0;
+          ar[ti][tj][v] = keep ? fma(t00, mav.x, mav.y) : pad;
+          ai[ti][tj][v] = keep ? t10 * mav.x : 0.0;
+        }
+    }
+
+    // candidate rows of this lane in the pivot searches: lane and lane + 64
+    const bool has1 = lane + 64 < NP;
+    const int l1 = has1 ? lane + 64 : 0;
+    bool used0 = false, used1 = !has1;
+    int mypiv0 = 0, mypiv1 = 0;             // pivot rows of columns lane, lane + 64
+    bool sing = false;
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) {
+      const bool own_tc = wc == tc / TC;     // this wavefront holds tile column tc
+#pragma unroll 1
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int c0 = 4 * q4, p0 = 16 * tc + c0;
+        if (p0 >= N) continue;                 // identity columns of the padding (below)
+        const bool pcol = (unsigned)(lc - c0) < 4u;   // lane holds a panel column
+        if (own_tc && pcol) {
+#pragma unroll
+          for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              pin[RPW * wr + 16 * ti + 4 * v + lr][lc - c0] =
+                  make_double2(ar[ti][tc % TC][v], ai[ti][tc % TC][v]);
+        }
+        __syncthreads();
+        double2 pv0[4], pv1[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          pv0[c] = pin[lane][c];
+          pv1[c] = has1 ? pin[l1][c] : make_double2(0.0, 0.0);
+        }
+        int rk[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double m0 = fabs(pv0[t].x) + fabs(pv0[t].y);
+          const double m1 = fabs(pv1[t].x) + fabs(pv1[t].y);
+          const double b0 = (!used0 && m0 == m0) ? m0 : -1.0;
+          const double b1 = (!used1 && m1 == m1) ? m1 : -1.0;
+          const double mx = wave_max_f64(fmax(b0, b1));
+          int r;
+          if (mx > 0.0) {
+            const uint64_t k0 = __builtin_amdgcn_ballot_w64(b0 == mx);
+            r = k0 ? (int)__builtin_ctzll(k0)
+                   : 64 + (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(b1 == mx));
+          } else {
+            // no nonzero finite candidate: the lowest unused row (singular)
+            const uint64_t u0 = __builtin_amdgcn_ballot_w64(!used0);
+            r = u0 ? (int)__builtin_ctzll(u0)
+                   : 64 + (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(!used1));
+            sing = true;
+          }
+          r = __builtin_amdgcn_readfirstlane(r);
+          double2 pr[4];
+          if (r < 64) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              pr[c] = make_double2(readlane_f64(pv0[c].x, r), readlane_f64(pv0[c].y, r));
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              pr[c] = make_double2(readlane_f64(pv1[c].x, r - 64), readlane_f64(pv1[c].y, r - 64));
+          }
+          const double2 piv = pr[t];
+          const double den = fma(piv.x, piv.x, piv.y * piv.y);
+          if (!(den > 0.0)) sing = true;
+          const double id = den > 0.0 ? recip_f64(den) : 0.0;
+          const double2 ip = make_double2(piv.x * id, -piv.y * id);   // 1 / piv
+          // pivot row: pr * ip (ip in column t); other rows: pv - f pr (-f in
+          // column t), f = pv[t] ip; both as pv' - g pr with pv' = 0 in the
+          // pivot row and g = -ip there
+          const bool me0 = lane == r, me1 = lane + 64 == r;
+          const double2 g0 = me0 ? make_double2(-ip.x, -ip.y)
+                                 : make_double2(fma(pv0[t].x, ip.x, -pv0[t].y * ip.y),
+                                                fma(pv0[t].x, ip.y, pv0[t].y * ip.x));
+          const double2 g1 = me1 ? make_double2(-ip.x, -ip.y)
+                                 : make_double2(fma(pv1[t].x, ip.x, -pv1[t].y * ip.y),
+                                                fma(pv1[t].x, ip.y, pv1[t].y * ip.x));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double2 a0 = me0 ? make_double2(0.0, 0.0) : pv0[c];
+            const double2 a1 = me1 ? make_double2(0.0, 0.0) : pv1[c];
+            pv0[c] = (c == t) ? make_double2(-g0.x, -g0.y)
+                              : make_double2(fma(-g0.x, pr[c].x, fma(g0.y, pr[c].y, a0.x)),
+                                             fma(-g0.x, pr[c].y, fma(-g0.y, pr[c].x, a0.y)));
+            pv1[c] = (c == t) ? make_double2(-g1.x, -g1.y)
+                              : make_double2(fma(-g1.x, pr[c].x, fma(g1.y, pr[c].y, a1.x)),
+                                             fma(-g1.x, pr[c].y, fma(-g1.y, pr[c].x, a1.y)));
+          }
+          used0 = used0 || me0;
+          used1 = used1 || me1;
+          if (lane == p0 + t) mypiv0 = r;
+          if (lane + 64 == p0 + t) mypiv1 = r;
+          rk[t] = r;
+        }
+        // the pivot rows as they were before the panel (from their owners,
+        // each wavefront its tile columns)
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+          const int r = k == 0 ? rk[0] : k == 1 ? rk[1] : k == 2 ? rk[2] : rk[3];
+          if (r / RPW == wr)
+            store_row_cx<TR, TC>(ar, ai, r - RPW * wr, &brow[k][RPW * wc], lr, lc);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          pw[w][lane][c] = pv0[c];
+          if (has1) pw[w][l1][c] = pv1[c];
+        }
+        __syncthreads();
+        // W = (E - I)(:, pivot rows) and B in the operand layouts; the panel
+        // columns take the eliminated values and see B = 0
+        const int rsel = lr == 0 ? rk[0] : lr == 1 ? rk[1] : lr == 2 ? rk[2] : rk[3];
+        double wre[TR], wim[TR], nwi[TR];
+#pragma unroll
+        for (int ti = 0; ti < TR; ++ti) {
+          const int rho = RPW * wr + 16 * ti + lc;
+          const double2 e = pw[w][rho][lr];
+          wre[ti] = e.x - ((rho == rsel) ? 1.0 : 0.0);
+          wim[ti] = e.y;
+          nwi[ti] = -e.y;
+        }
+        double br[TC], bi[TC];
+#pragma unroll
+        for (int tj = 0; tj < TC; ++tj) {
+          const double2 bv = brow[lr][RPW * wc + 16 * tj + lc];
+          const bool z = own_tc && (tj == tc % TC) && pcol;
+          br[tj] = z ? 0.0 : bv.x;
+          bi[tj] = z ? 0.0 : bv.y;
+        }
+        if (own_tc && pcol) {
+#pragma unroll
+          for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const double2 e = pw[w][RPW * wr + 16 * ti + 4 * v + lr][lc - c0];
+              ar[ti][tc % TC][v] = e.x;
+              ai[ti][tc % TC][v] = e.y;
+            }
+        }
+        // the panel's own tile column first (the next panel reads it)
+#pragma unroll
+        for (int k = 0; k < TC; ++k) {
+          const int tj = (tc % TC + k) % TC;
+#pragma unroll
+          for (int ti = 0; ti < TR; ++ti) {
+            ar[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(wre[ti], br[tj], ar[ti][tj], 0, 0, 0);
+            ar[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(nwi[ti], bi[tj], ar[ti][tj], 0, 0, 0);
+            ai[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(wre[ti], bi[tj], ai[ti][tj], 0, 0, 0);
+            ai[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(wim[ti], br[tj], ai[ti][tj], 0, 0, 0);
+          }
+        }
+      }
+    }
+
+    // the padding columns after the last panel are identity columns: each
+    // pivots on its own (never used) row
+    constexpr int PEND = (N + 3) / 4 * 4;
+    if (lane >= PEND) mypiv0 = lane;
+    if (lane + 64 >= PEND) mypiv1 = lane + 64;
+    // element (rho, q) of the in-place result is Y[rinv[rho]][rpiv[q]]
+    if (w == 0) {
+      rpiv[lane] = mypiv0;
+      rinv[mypiv0] = lane;
+      if (has1) {
+        rpiv[l1] = mypiv1;
+        rinv[mypiv1] = l1;
+      }
+    }
+    for (int e = tid; e < 2 * NP; e += 64 * NW) rowmap[e] = (full && e < 2 * N) ? e : -1;
+    if (tid == 0) status[T] = (uint8_t)sing;
+    __syncthreads();
+    if (!full) {
+      const int o0 = own_ptr[T], no = own_ptr[T + 1] - o0;
+      if (dec) {
+        for (int e = tid; e < no; e += 64 * NW) rowmap[own_loc[o0 + e]] = e;
+      } else {
+        for (int e = tid; e < no * 2; e += 64 * NW) rowmap[own_loc[o0 + (e >> 1)] * 2 + (e & 1)] = e;
+      }
+    }
+    __syncthreads();
+    const int64_t off = inv_off[T];
+    if (dec) {
+#pragma unroll
+      for (int tj = 0; tj < TC; ++tj) {
+        const int c = rpiv[RPW * wc + 16 * tj + lc];
+#pragma unroll
+        for (int ti = 0; ti < TR; ++ti) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = rinv[RPW * wr + 16 * ti + 4 * v + lr];
+            const int o = (a < N && c < N) ? rowmap[a] : -1;
+            if (o >= 0) {
+              const int64_t e = off + (int64_t)o * ld + c;
+              if (fp32) {
+                ((float*)store)[e] = (float)ar[ti][tj][v];
+                ((float*)store)[e + N] = (float)ai[ti][tj][v];
+              } else {
+                ((double*)store)[e] = ar[ti][tj][v];
+                ((double*)store)[e + N] = ai[ti][tj][v];
+              }
+            }
+          }
+        }
+      }
+      continue;
+    }
+#pragma unroll
+    for (int tj = 0; tj < TC; ++tj) {
+      const int c = rpiv[RPW * wc + 16 * tj + lc];
+#pragma unroll
+      for (int ti = 0; ti < TR; ++ti) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = rinv[RPW * wr + 16 * ti + 4 * v + lr];
+          if (a < N && c < N) {
+            const double re = ar[ti][tj][v], im = ai[ti][tj][v];
+            const double x0 = fma(re, sp.W[0], -im * sp.W[2]);   // Re Y W_0l - Im Y W_1l, l = 0
+            const double y0 = fma(im, sp.W[0], re * sp.W[2]);    // Im Y W_0l + Re Y W_1l, l = 0
+            const double x1 = fma(re, sp.W[1], -im * sp.W[3]);
+            const double y1 = fma(im, sp.W[1], re * sp.W[3]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              const int o = rowmap[a * 2 + i];
+              if (o < 0) continue;
+              const double v0 = fma(sp.V[2 * i], x0, sp.V[2 * i + 1] * y0);
+              const double v1 = fma(sp.V[2 * i], x1, sp.V[2 * i + 1] * y1);
+              const int64_t e = off + (int64_t)o * ld + 2 * c;
+              if (fp32)
+                *reinterpret_cast<float2*>(&((float*)store)[e]) = make_float2((float)v0, (float)v1);
+              else
+                *reinterpret_cast<double2*>(&((double*)store)[e]) = make_double2(v0, v1);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Fallback for blocks too large for registers (n > 256): the same
 // elimination on a global scratch copy, one persistent workgroup per slot.
 __global__ void __launch_bounds__(256) k_inverse_global(
@@ -722,6 +1067,18 @@ static hipError_t inv_mfma(hipStream_t s, const DevLevel& L, int fp32, int full,
 hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,
                                 uint8_t* status, double* gscratch, int n_slots, int n_cu,
                                 int reserve) {
+  if (L.cx) {
+    // the complex decoupled build of a 3d dG(1) level: four wavefronts of
+    // up to 512 registers per cell, one cell per compute unit at a time
+    if (b != 2 || L.n_ls != 85 || !L.kron_ma || L.split.nblk != 1 || L.split.sz[0] != 2)
+      return hipErrorInvalidValue;
+    (void)n_cu;
+    (void)reserve;
+    k_inverse_cx<85><<<L.n_cells, 256, 0, s>>>(L.posmap, L.kron_ma, L.own_ptr, L.own_loc, full,
+                                                L.inv_off, L.inv_ld, L.inv_store, fp32, status,
+                                                L.n_cells, L.split, L.dec && !full ? 1 : 0);
+    return hipGetLastError();
+  }
   if (L.n_ls == 21) {
     switch (b) {
       case 1: return inv_mfma<1, 21>(s, L, fp32, full, status, n_cu, reserve);

@@ -658,6 +658,122 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vanka cell sweep on the complex time-decoupled store of a dG(1) level with
+// one complex pair (built by k_inverse_cx): the stored row of owned spatial
+// DoF a is Y_a. = (X^-1)_a. as [Re Y_a0 .. Re Y_a,n-1, Im Y_a0 .. Im Y_a,n-1],
+// and with u = (I (x) W) rho_T (u_0 + i u_1 per spatial DoF c)
+//   y_a = sum_c Y_ac (u_0c + i u_1c),  c_(a, i) = V_i0 Re y_a + V_i1 Im y_a:
+// the same J_T^-1 rho_T = (I (x) V) Q^-1 (I (x) W) rho_T as the two plain rows
+// of a, from half the stored values.  One wavefront per cell: lane c (and
+// c + 64) holds u_c, from one 16-byte load of the time-inner pair rho_(c, 0..1);
+// each stored row is two coalesced reads; G rows at a time give 2G sums
+// (real and imaginary parts) folded by one transpose-reduce.  Output
+// r = 2 os + i of the os-th owned DoF lands in lane r % 64, which fetched the
+// DoF's old value at the start; stores as in k_vanka.
+template <int NLS, typename TS>
+__global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho,
+                                                 double* __restrict__ d,
+                                                 const int32_t* __restrict__ csd,
+                                                 const int32_t* __restrict__ own_ptr,
+                                                 const uint8_t* __restrict__ own_loc,
+                                                 const int64_t* __restrict__ inv_off, int ld,
+                                                 const TS* __restrict__ store, double omega,
+                                                 int zero_init, int n_cells, CellSplit sp) {
+  constexpr int B = 2;
+  constexpr int NCC = (NLS + 63) / 64;       // 64-lane chunks of the complex columns
+  constexpr int NOC = (NLS + 63) / 64;       // 64-lane chunks of the owned DoFs
+  constexpr int RC = (B * NLS + 63) / 64;    // 64-lane chunks of the outputs
+  constexpr int G = 8;                       // stored rows per transpose-reduce
+  const int lane = threadIdx.x & 63;
+  const double w00 = sp.W[0], w01 = sp.W[1], w10 = sp.W[2], w11 = sp.W[3];
+  const double v00 = sp.V[0], v01 = sp.V[1], v10 = sp.V[2], v11 = sp.V[3];
+  const int T0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  for (int T = T0; T < n_cells; T += gridDim.x * 4) {
+    const int32_t* sd = csd + (int64_t)T * NLS;
+    const int o0 = own_ptr[T];
+    const int no = own_ptr[T + 1] - o0;
+    if (no <= 0) continue;
+    const int R = no * B;
+    const TS* A = store + inv_off[T];
+    double ur[NCC], ui[NCC];
+#pragma unroll
+    for (int cc = 0; cc < NCC; ++cc) {
+      const int c = lane + 64 * cc;
+      const int cl = c < NLS ? c : NLS - 1;
+      const double2 rr = *reinterpret_cast<const double2*>(&rho[(int64_t)sd[cl] * B]);
+      ur[cc] = c < NLS ? fma(w00, rr.x, w01 * rr.y) : 0.0;
+      ui[cc] = c < NLS ? fma(w10, rr.x, w11 * rr.y) : 0.0;
+    }
+    int gs[NOC];
+#pragma unroll
+    for (int c = 0; c < NOC; ++c) {
+      const int k = lane + 64 * c;
+      gs[c] = sd[own_loc[o0 + (k < no ? k : no - 1)]];
+    }
+    int64_t gi[RC];
+    double dold[RC], res[RC];
+#pragma unroll
+    for (int rc = 0; rc < RC; ++rc) {
+      const int r = lane + 64 * rc;
+      const int rcl = r < R ? r : R - 1;
+      const int os = rcl / B;
+      int g = __shfl(gs[0], os & 63, 64);
+      if constexpr (NOC > 1) {
+        const int g1 = __shfl(gs[NOC - 1], os & 63, 64);
+        g = os < 64 ? g : g1;
+      }
+      gi[rc] = (int64_t)g * B + (rcl - os * B);
+      dold[rc] = zero_init ? 0.0 : d[gi[rc]];
+      res[rc] = 0.0;
+    }
+    for (int k0 = 0; k0 < no; k0 += G) {
+      TS ar[G][NCC], ai[G][NCC];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const int row = min(k0 + t, no - 1);
+        const unsigned ro = (unsigned)(row * ld);
+#pragma unroll
+        for (int cc = 0; cc < NCC; ++cc) {
+          const int c = lane + 64 * cc;
+          const unsigned cl = (unsigned)(c < NLS ? c : NLS - 1);
+          ar[t][cc] = A[ro + cl];
+          ai[t][cc] = A[ro + NLS + cl];
+        }
+      }
+      double p[2 * G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < NCC; ++cc) {
+          const double yr = (double)ar[t][cc], yi = (double)ai[t][cc];
+          re = fma(yr, ur[cc], fma(-yi, ui[cc], re));
+          im = fma(yr, ui[cc], fma(yi, ur[cc], im));
+        }
+        p[2 * t] = re;
+        p[2 * t + 1] = im;
+      }
+      const double sum = fold_swap<2 * G>(p, lane);   // value e in lanes 4e .. 4e + 3
+#pragma unroll
+      for (int rc = 0; rc < RC; ++rc) {
+        const int r = lane + 64 * rc;
+        const int t = (r >> 1) - k0;
+        const int tc = t < 0 ? 0 : (t >= G ? G - 1 : t);
+        const double re = __shfl(sum, 4 * (2 * tc), 64);
+        const double im = __shfl(sum, 4 * (2 * tc + 1), 64);
+        const double val = (r & 1) ? fma(v10, re, v11 * im) : fma(v00, re, v01 * im);
+        if (t >= 0 && t < G) res[rc] = val;
+      }
+    }
+#pragma unroll
+    for (int rc = 0; rc < RC; ++rc) {
+      const int r = lane + 64 * rc;
+      if (r < R) d[gi[rc]] = zero_init ? omega * res[rc] : fma(omega, res[rc], dold[rc]);
+    }
+  }
+}
+
 template <int B, int NLS>
 static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, double* d,
                            double omega, int zero_init, int fp32, int full) {
@@ -674,6 +790,20 @@ static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, 
         launch(k_vanka_dec<B, NLS, double>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
                L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const double*)L.inv_store, omega,
                zero_init, L.n_cells, (const double*)L.dec_tab, (const int32_t*)L.dec_code);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (B == 2 && NLS == 85) {
+    if (L.dec && L.cx) {
+      if (full) return hipErrorInvalidValue;
+      if (fp32)
+        launch(k_vanka_cx<NLS, float>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
+               L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const float*)L.inv_store, omega,
+               zero_init, L.n_cells, L.split);
+      else
+        launch(k_vanka_cx<NLS, double>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
+               L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const double*)L.inv_store, omega,
+               zero_init, L.n_cells, L.split);
       return hipGetLastError();
     }
   }

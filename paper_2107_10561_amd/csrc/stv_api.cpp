@@ -887,6 +887,9 @@ int stv_create(stv_ctx** out, int device, void* hip_stream) {
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
   if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->side2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_gj[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_gj[1], hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
@@ -935,6 +938,12 @@ void stv_destroy(stv_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->cap_stream);
     (void)hipStreamDestroy(ctx->cap_stream);
   }
+  if (ctx->side2) {
+    (void)hipStreamSynchronize(ctx->side2);
+    (void)hipStreamDestroy(ctx->side2);
+  }
+  for (auto e : ctx->ev_gj)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   for (auto e : ctx->ev_step)
@@ -1299,11 +1308,14 @@ static int make_coarse_groups(stv_ctx* ctx) {
       STV_TRY(dalloc(ctx, &w.Bin, (size_t)(cnt * w.sBin)));
     }
     if (G.plan.algo == 3) {
-      w.sC = (np + 255) / 256 * G.plan.nb;
+      // the workgroups' lists and, for the merge tree, the lists and
+      // arrival counters of its nodes (fewer than a third more)
+      w.sC = 2 * ((np + 255) / 256 * G.plan.nb);
       w.sZ = 2 * (int64_t)G.plan.nb * G.plan.no;
+      w.sK = np / 64 + 8;
       STV_TRY(dalloc(ctx, &w.cand, (size_t)(cnt * w.sC)));
       STV_TRY(dalloc(ctx, &w.Z, (size_t)(cnt * w.sZ)));
-      STV_TRY(dalloc(ctx, &w.counter, (size_t)cnt));
+      STV_TRY(dalloc(ctx, &w.counter, (size_t)(cnt * w.sK)));
     }
   }
   // recombination descriptors: the device addresses of every block inverse
@@ -1340,6 +1352,7 @@ static int make_inverse_stores(stv_ctx* ctx, int fp32, int full) {
     dfree(L.dec_code);
     L.inv_elems = 0;
     L.dec = 0;
+    L.cx = 0;
     if (L.n_cells == 0) continue;
     const int n = L.n_ls * b;
     // with spatial factors, the owned-row layout of a level whose cell
@@ -1400,6 +1413,28 @@ static int make_inverse_stores(stv_ctx* ctx, int fp32, int full) {
       STV_TRY(upload(ctx, &L.dec_tab, tab.data(), tab.size()));
       STV_TRY(upload(ctx, &L.dec_code, code.data(), code.size()));
       L.dec = 1;
+    }
+    // a 3d dG(1) level with spatial factors whose time matrix has one complex
+    // pair: the inverses are computed from the complex decoupled block (half
+    // the pivot steps and flops of the real elimination); the owned-rows
+    // layout stores them time-decoupled (one complex row per owned spatial
+    // DoF, as the 2d split does), the full layout plainly
+    if (!L.dec && L.kron_ma && b == 2 && L.n_ls == 85 && time_split(L.kron_C, L.kron_tw, b, S) &&
+        S.nblk == 1 && S.sz[0] == 2 && S.T[0] == S.T[3] && S.T[1] == -S.T[2]) {
+      CellSplit& c = L.split;
+      c = CellSplit{};
+      c.b = b;
+      c.nblk = 1;
+      c.sz[0] = 2;
+      c.first[0] = 0;
+      c.off[0] = 0;
+      for (int e = 0; e < 16; ++e) {
+        c.T[e] = S.T[e];
+        c.V[e] = S.V[e];
+        c.W[e] = S.W[e];
+      }
+      L.cx = 1;
+      L.dec = full ? 0 : 1;
     }
     // rows stored densely (padding each row to a 128-byte boundary was
     // measured slower: the sweep reads whole cells as one contiguous stream)
@@ -1549,8 +1584,9 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (e == hipSuccess) e = launch_set_diag(side, G.d_desc, cnt, gb, G.w.A, G.w.sA, G.np);
     if (e == hipSuccess) e = hipMemsetAsync(G.w.used, 0, (size_t)(cnt * G.w.sV), side);
     if (e == hipSuccess && G.w.counter)
-      e = hipMemsetAsync(G.w.counter, 0, sizeof(unsigned) * (size_t)cnt, side);
-    if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt);
+      e = hipMemsetAsync(G.w.counter, 0, sizeof(unsigned) * (size_t)(cnt * G.w.sK), side);
+    const GjAux aux{ctx->side2, ctx->ev_gj[0], ctx->ev_gj[1]};
+    if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt, &aux);
     // pivot records -> inverse permutations and verdicts, then the
     // unpermuted inverses (a block's into the group's block store)
     if (e == hipSuccess)
@@ -1579,9 +1615,10 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->h_report, rep, sizeof(int) * (size_t)nrep, hipMemcpyDeviceToHost, s);
   {
-    // both streams drain on every path
+    // every stream drains on every path
     const hipError_t e1 = hipStreamSynchronize(s);
     const hipError_t e2 = hipStreamSynchronize(side);
+    (void)hipStreamSynchronize(ctx->side2);
     if (e == hipSuccess) e = (e1 != hipSuccess) ? e1 : e2;
   }
   if (e != hipSuccess) {

@@ -83,6 +83,7 @@ struct DevLevel {
   // spatial factors (optional): blocks = C[i][l] M + delta_il tw[i] A
   double* kron_ma = nullptr;      // spatial factors (m, a), interleaved per block
   int dec = 0;                    // the inverse store holds time-decoupled rows (CellSplit)
+  int cx = 0;                     // inverses built from the complex decoupled block (plain store)
   CellSplit split{};
   // per lane j of the decoupled sweep: W[j % B][.] and V[j % B][.] (2B x 64,
   // row-major), and a code word: source lanes of u (bits 0-5, 6-11) and the
@@ -116,11 +117,12 @@ struct GjWork {
   double* P; int64_t sP;          // two panel buffers, 2 x n x nb
   double* S; int64_t sS;          // two slab buffers, 2 x n x no
   double* Bin; int64_t sBin;      // pivot rows of a slab, nb x no
-  // tournament schedule: candidate pivot rows of each 256-row group, the
-  // two panel right factors (2 x nb x no) and one arrival counter per matrix
+  // tournament schedule: candidate pivot rows of each workgroup and of the
+  // merge tree's nodes, the two panel right factors (2 x nb x no) and the
+  // arrival counters of the merge tree (sK per matrix)
   int* cand; int64_t sC;
   double* Z; int64_t sZ;
-  unsigned* counter;
+  unsigned* counter; int64_t sK;
 };
 
 // Dense Gauss-Jordan plan: algo 1 = one level of panels (width nb), 2 = slabs
@@ -205,6 +207,8 @@ struct stv_ctx {
   double* noalloc_ws = nullptr;   // this device's address of the fixed workspace (or NULL)
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;     // internal stream: coarse factorisation overlaps the cell inverses
+  hipStream_t side2 = nullptr;    // internal stream: look-ahead updates of the coarse chain
+  hipEvent_t ev_gj[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_step[2] = {nullptr, nullptr};   // Arnoldi coefficients of a step reached the host
   std::string err;
@@ -332,7 +336,16 @@ hipError_t launch_copy(hipStream_t s, const double* x, double* y, int64_t n);
 hipError_t launch_bsr_to_dense(hipStream_t s, int b, const CoarseDesc* desc, int cnt,
                                int32_t max_rows, double* A, int64_t sA, int64_t n);
 GjPlan gj_plan(int64_t n, int algo /* 0 = choose by size */, bool pair);
-hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt);
+// Second stream and events of the look-ahead of the complex-pivot slab
+// schedule: the update of the columns other than the next slab's runs on s2
+// beside the next slab's panels (next_ready: the next slab's columns are
+// updated; done_rest: the other columns are).
+struct GjAux {
+  hipStream_t s2;
+  hipEvent_t next_ready, done_rest;
+};
+hipError_t launch_gj(hipStream_t s, const GjPlan& p, const GjWork& w, int64_t n, int cnt,
+                     const GjAux* aux = nullptr);
 hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b, double* A,
                            int64_t sA, int64_t n);
 // dense blocks of time-decoupled coarse members (member z: kdesc[z])
