@@ -87,6 +87,11 @@ def parse():
     ap.add_argument("--coarse-algo", default="auto", choices=["auto", "panels", "slabs", "tournament"])
     ap.add_argument("--coarse-overlap", type=int, default=1, choices=[0, 1],
                     help="coarse factorisation concurrent with the cell inverses (1) or before (0)")
+    ap.add_argument("--inverse-cus", type=int, default=None,
+                    help="compute units the 3d complex cell-inverse kernel may hold beside the "
+                         "coarse factorisation (0: no cap; default: the library's)")
+    ap.add_argument("--coarse-lookahead", type=int, default=1, choices=[0, 1],
+                    help="look-ahead updates in the complex-pivot coarse chain (1) or not (0)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-kron", action="store_true",
                     help="residual from the stored blocks instead of the spatial factors")
@@ -557,6 +562,9 @@ def run_workload(args, name, legs=True):
     s = stv.Solver(0)
     s.set_coarse_algorithm(args.coarse_algo)
     s.set_coarse_overlap(bool(args.coarse_overlap))
+    s.set_coarse_lookahead(bool(args.coarse_lookahead))
+    if args.inverse_cus is not None:
+        s.set_inverse_cus(args.inverse_cus)
     t0 = time.time()
     if len(probs) == 1:
         s.set_hierarchy(probs[0].levels, dim, k)

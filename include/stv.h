@@ -347,6 +347,17 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
  *   an internal stream concurrently with the cell inverses; 0 = they run on
  *   the caller's stream before the cell inverses.  Same results. */
 #define STV_OPT_COARSE_OVERLAP 3
+/*   STV_OPT_INVERSE_CUS: while the coarse factorisation runs concurrently,
+ *   the 3d complex cell-inverse kernel (one cell per compute unit) runs as at
+ *   most this many resident workgroups striding over the cells, leaving the
+ *   remaining compute units to the coarse chain; 0 (default) = no cap.  Same
+ *   results. */
+#define STV_OPT_INVERSE_CUS 4
+/*   STV_OPT_COARSE_LOOKAHEAD: 1 (default) = in the complex-pivot coarse
+ *   chain the next slab's columns are updated first and the other columns on
+ *   an internal stream, concurrent with the next slab's panels; 0 = one
+ *   update per slab on the chain's stream.  Same results. */
+#define STV_OPT_COARSE_LOOKAHEAD 5
 int stv_set_option(stv_ctx* ctx, int option, int64_t value);
 
 /* Spatial factors of a level whose operator has time-independent

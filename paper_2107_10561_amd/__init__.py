@@ -435,6 +435,15 @@ class Solver:
         """Coarse factorisation concurrent with the cell inverses (default) or before them."""
         self._check(_lib.stv_set_option(self._h, 3, int(bool(on))))
 
+    def set_inverse_cus(self, n: int):
+        """Compute units the 3d complex cell-inverse kernel may hold while the
+        coarse factorisation runs beside it (0: no cap)."""
+        self._check(_lib.stv_set_option(self._h, 4, int(n)))
+
+    def set_coarse_lookahead(self, on: bool):
+        """Look-ahead updates in the complex-pivot coarse chain (default on)."""
+        self._check(_lib.stv_set_option(self._h, 5, int(bool(on))))
+
     def set_graph(self, on: bool):
         """Replay the V-cycle from a captured HIP graph (identical results)."""
         self._check(_lib.stv_set_option(self._h, 2, int(bool(on))))

@@ -567,6 +567,96 @@ __global__ void __launch_bounds__(256) k_gj_slab_update_cx(double* __restrict__ 
     }
 }
 
+// The even-row update with 128 x 128 tiles (n a multiple of 128): each
+// wavefront owns 16 row pairs x 128 columns (8 accumulator tiles), and the
+// factors pass through LDS 32 columns of K at a time.  Per multiply-add half
+// the factor traffic of the 64 x 64 tiling, a quarter of its workgroups.
+template <int NO>
+__global__ void __launch_bounds__(256) k_gj_slab_update_cx128(double* __restrict__ A, int64_t sA,
+                                                              int64_t n, int64_t j0,
+                                                              const int* __restrict__ rp,
+                                                              int64_t sV,
+                                                              const double* __restrict__ Sb,
+                                                              double* __restrict__ Snext,
+                                                              int64_t sS,
+                                                              const double* __restrict__ Bg,
+                                                              int64_t sB, int ct0, int skip_at,
+                                                              int skip_n) {
+  constexpr int KC = 32, TW = 128;
+  chain_priority();
+  A += blockIdx.z * sA;
+  rp += blockIdx.z * sV;
+  Sb += blockIdx.z * sS;
+  Snext += blockIdx.z * sS;
+  Bg += blockIdx.z * sB;
+  __shared__ double Ws[64][KC + 1];      // even rows of the tile
+  __shared__ double Bs[KC][TW + 2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ct = ct0 + (int)blockIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * TW, jt = (int64_t)(ct < skip_at ? ct : ct + skip_n) * TW;
+  if (jt >= j0 && jt < j0 + NO) {
+    for (int e = tid; e < TW * TW / 2; e += 256) {
+      const int r = e / (TW / 2), c = 2 * (e % (TW / 2));
+      *(double2*)&A[(i0 + r) * n + jt + c] = *(const double2*)&Sb[(i0 + r) * NO + (jt - j0) + c];
+    }
+    return;
+  }
+  const int rb = 16 * w, lr = lane >> 4, lc = lane & 15;
+  stv_d4 acc[8];
+#pragma unroll
+  for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      acc[tj][v] = A[(i0 + 2 * (rb + 4 * v + lr)) * n + jt + 16 * tj + lc];
+  for (int kc = 0; kc < NO; kc += KC) {
+    if (kc) __syncthreads();
+#pragma unroll
+    for (int e = tid; e < 64 * KC / 2; e += 256) {
+      const int r = e / (KC / 2), c = 2 * (e % (KC / 2));
+      const double2 x = *(const double2*)&Sb[(i0 + 2 * r) * NO + kc + c];
+      Ws[r][c] = x.x;
+      Ws[r][c + 1] = x.y;
+    }
+#pragma unroll
+    for (int e = tid; e < KC * TW / 2; e += 256) {
+      const int r = e / (TW / 2), c = 2 * (e % (TW / 2));
+      *(double2*)&Bs[r][c] = *(const double2*)&Bg[(int64_t)(kc + r) * n + jt + c];
+    }
+    __syncthreads();
+    if (tid < KC) {
+      const int r = rp[kc + tid];
+      if (r >= i0 && r < i0 + TW && !(r & 1)) Ws[(r - i0) >> 1][tid] -= 1.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const double a = Ws[rb + lc][4 * kk + lr];
+#pragma unroll
+      for (int tj = 0; tj < 8; ++tj)
+        acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[4 * kk + lr][16 * tj + lc], acc[tj],
+                                                       0, 0, 0);
+    }
+  }
+  const bool nxt = (jt >= j0 + NO && jt < j0 + 2 * NO);
+#pragma unroll
+  for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + 2 * (rb + 4 * v + lr);
+      const int64_t j = jt + 16 * tj + lc;
+      const double x = acc[tj][v];
+      const double partner = __shfl_xor(x, 1, 64);
+      const double odd = (j & 1) ? partner : -partner;
+      A[i * n + j] = x;
+      A[(i + 1) * n + j] = odd;
+      if (nxt) {
+        const int64_t c = j - j0 - NO;
+        Snext[i * NO + c] = x;
+        Snext[(i + 1) * NO + c] = odd;
+      }
+    }
+}
+
 template <int RPT, int NB, int TPB, int NO>
 static hipError_t gj_slab(hipStream_t s, const GjWork& w, int64_t n, int cnt) {
   double* sb[2] = {w.S, w.S + n * NO};
@@ -1287,24 +1377,33 @@ static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt,
     k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
         w.A, w.sA, n, (int)j0, w.rpiv, w.sV, w.B, w.sB);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int nst = (int)(NO / 64), nxt0 = (int)((j0 + NO) / 64);
+    // 128 x 128 tiles when the order allows (slabs of 128), else 64 x 64
+    const bool big = NO % 128 == 0 && n % 128 == 0;
+    const int TS = big ? 128 : 64;
+    const unsigned ntt = (unsigned)(n / TS);
+    const int nst = (int)(NO / TS), nxt0 = (int)((j0 + NO) / TS);
     const int nnext = j0 + NO < n ? nst : 0;
+    auto update = [&](unsigned gx, int ct0, int skip_at, int skip_n, hipStream_t st) {
+      if (big)
+        k_gj_slab_update_cx128<NO><<<dim3(gx, ntt, cnt), 256, 0, st>>>(
+            w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, ct0, skip_at,
+            skip_n);
+      else
+        k_gj_slab_update_cx<NO><<<dim3(gx, ntt, cnt), 256, 0, st>>>(
+            w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, ct0, skip_at,
+            skip_n);
+      return hipGetLastError();
+    };
     if (!aux || nnext == 0) {
-      k_gj_slab_update_cx<NO><<<dim3(nt, nt, cnt), 256, 0, s>>>(
-          w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, 0, (int)nt, 0);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = update(ntt, 0, (int)ntt, 0, s)) != hipSuccess) return e;
       continue;
     }
     // look-ahead: the next slab's columns first (its panels start at once),
     // the other columns on the second stream, concurrent with those panels
-    k_gj_slab_update_cx<NO><<<dim3((unsigned)nnext, nt, cnt), 256, 0, s>>>(
-        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, nxt0, (int)nt, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = update((unsigned)nnext, nxt0, (int)ntt, 0, s)) != hipSuccess) return e;
     if ((e = hipEventRecord(aux->next_ready, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(aux->s2, aux->next_ready, 0)) != hipSuccess) return e;
-    k_gj_slab_update_cx<NO><<<dim3(nt - (unsigned)nnext, nt, cnt), 256, 0, aux->s2>>>(
-        w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, 0, nxt0, nnext);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = update(ntt - (unsigned)nnext, 0, nxt0, nnext, aux->s2)) != hipSuccess) return e;
     if ((e = hipEventRecord(aux->done_rest, aux->s2)) != hipSuccess) return e;
   }
   if (aux && n > NO && (e = hipStreamWaitEvent(s, aux->done_rest, 0)) != hipSuccess) return e;

@@ -1562,7 +1562,7 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
       if (L.n_cells == 0) continue;
       Timed t(ctx, KC_INVERSE, g, inv);
       e = launch_cell_inverses(inv, b, L, fp32, full, ctx->inv_status[g], ctx->inv_scratch[g],
-                               ctx->inv_slots[g], n_cu, STV_CHAIN_VGPRS);
+                               ctx->inv_slots[g], n_cu, STV_CHAIN_VGPRS, ctx->inverse_cus);
       if (e == hipSuccess) e = launch_first_flag(inv, ctx->inv_status[g], L.n_cells, rep + g);
       t.done();
     }
@@ -1586,7 +1586,7 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     if (e == hipSuccess && G.w.counter)
       e = hipMemsetAsync(G.w.counter, 0, sizeof(unsigned) * (size_t)(cnt * G.w.sK), side);
     const GjAux aux{ctx->side2, ctx->ev_gj[0], ctx->ev_gj[1]};
-    if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt, &aux);
+    if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt, ctx->coarse_lookahead ? &aux : nullptr);
     // pivot records -> inverse permutations and verdicts, then the
     // unpermuted inverses (a block's into the group's block store)
     if (e == hipSuccess)
@@ -2384,6 +2384,14 @@ int stv_set_option(stv_ctx* ctx, int option, int64_t value) {
     case STV_OPT_GRAPH:
       if (value < 0 || value > 1) return fail(ctx, STV_EINVAL, "graph option must be 0 or 1");
       ctx->use_graph = (int)value;
+      return STV_OK;
+    case STV_OPT_COARSE_LOOKAHEAD:
+      if (value < 0 || value > 1) return fail(ctx, STV_EINVAL, "look-ahead option must be 0 or 1");
+      ctx->coarse_lookahead = (int)value;
+      return STV_OK;
+    case STV_OPT_INVERSE_CUS:
+      if (value < 0 || value > 65536) return fail(ctx, STV_EINVAL, "compute-unit cap must be in [0, 65536]");
+      ctx->inverse_cus = (int)value;
       return STV_OK;
     default:
       return fail(ctx, STV_EINVAL, "unknown option");

@@ -253,6 +253,8 @@ struct stv_ctx {
   int n_report = 0;
   int coarse_algo = 0;          // STV_OPT_COARSE_ALGO
   int coarse_overlap = 1;       // STV_OPT_COARSE_OVERLAP
+  int inverse_cus = 0;          // STV_OPT_INVERSE_CUS
+  int coarse_lookahead = 1;     // STV_OPT_COARSE_LOOKAHEAD
   int64_t scal_segs = 0;        // instances the scalar buffers are sized for
   // V-cycle replayed from a captured HIP graph (STV_OPT_GRAPH): the graph
   // reads g_in and writes g_out; it is captured on cap_stream and replayed
@@ -325,7 +327,7 @@ hipError_t launch_vanka_combine(hipStream_t s, int b, const DevLevel& L, double*
 // stream find room beside it.
 hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,
                                 uint8_t* status, double* gscratch, int n_slots, int n_cu,
-                                int reserve);
+                                int reserve, int cu_cap = 0);
 hipError_t launch_restrict(hipStream_t s, int b, const DevLevel& L, const double* rho,
                            double* r_c);
 hipError_t launch_prolongate_add(hipStream_t s, int b, const DevLevel& L, const double* d_c,
