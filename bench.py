@@ -755,19 +755,34 @@ def run_workload(args, name, legs=True):
         x_alt = torch.zeros_like(x)
         step(alt, x_alt)
         torch.cuda.synchronize()
+        # the leg's own finest-level sweep launches are stamped as in the
+        # timed region, for the roofline of the other storage precision
+        s.set_timing(True, classes=["sweep"], levels=[top])
+        torch.cuda.synchronize()
         a = time.perf_counter()
         reps = max(1, min(3, args.steps))
         for _ in range(reps):
             inf_alt = step(alt, x_alt)
         torch.cuda.synchronize()
         t_alt = (time.perf_counter() - a) / reps
+        n_f, ms_f = s.kernel_stats("sweep", top)
+        inv_b_alt = s.level_info(top)["inverse_bytes"]
+        s.set_timing(False)
+        b_alt = inv_b_alt + sum(sweep_bytes(L, b, 0, zi) for L, sm in members[top] if sm)
+        gbs_alt = b_alt / (ms_f / n_f / 1e3) / 1e9 if n_f else 0.0
         diff = float(torch.linalg.vector_norm(x_alt - x) / torch.linalg.vector_norm(x))
         res["fp64_inverses" if primary_fp32 else "fp32_inverses"] = dict(
             ms_per_step=round(1e3 * t_alt, 3), iters=inf_alt["iters"],
             true_relres=inf_alt["true_relres"],
             rel_diff_to_primary_solution=diff,
-            inverse_bytes_finest=s.level_info(top)["inverse_bytes"],
-            speedup_vs_primary=round(ms_per_step / (1e3 * t_alt), 4))
+            inverse_bytes_finest=inv_b_alt,
+            speedup_vs_primary=round(ms_per_step / (1e3 * t_alt), 4),
+            roofline_sweep=dict(bound="hbm", achieved=round(gbs_alt, 1), peak=HBM_PEAK_GBS,
+                                unit="GB/s", frac=round(gbs_alt / HBM_PEAK_GBS, 4),
+                                bytes_per_launch=int(b_alt),
+                                avg_launch_ms=round(ms_f / max(n_f, 1), 5), launches=n_f,
+                                kernel=roof_sweep["kernel"].replace("inverses (", "inverses, "
+                                                                    "other precision (")))
         print(f"[bench] {'fp32' if alt else 'fp64'} step {1e3 * t_alt:.2f} ms "
               f"iters {inf_alt['iters']}", file=sys.stderr, flush=True)
     if legs and not args.no_graph_leg:
