@@ -14,39 +14,64 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Partner value for lane ^ M inside a row of 16 lanes (M <= 8): DPP lane
 // permutations (xor 1, xor 2 as quad permutations, xor 8 as a rotation of the
-// row by 8) and, for xor 4, a swizzle in bit-mask mode.
+// row by 8) and, for xor 4, a swizzle in bit-mask mode.  Every source lane
+// is inside the row, so the permutations need no old value.
 template <int M>
-__device__ __forceinline__ double xor_f64(double v) {
+__device__ __forceinline__ int xor_i32(int v) {
   static_assert(M == 1 || M == 2 || M == 4 || M == 8, "inside a row");
-  if constexpr (M == 1) return dpp_f64<0xB1>(v);          // quad_perm [1,0,3,2]
-  if constexpr (M == 2) return dpp_f64<0x4E>(v);          // quad_perm [2,3,0,1]
-  if constexpr (M == 8) return dpp_f64<0x128>(v);         // row_ror:8
-  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x101F);   // xor 4
-  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x101F);
+  if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+  if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+  if constexpr (M == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);  // row_ror:8
+  return __builtin_amdgcn_ds_swizzle(v, 0x101F);                                   // xor 4
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane(double v) {
+  const int lo = xor_i32<M>(__double2loint(v));
+  const int hi = xor_i32<M>(__double2hiint(v));
   return __hiloint2double(hi, lo);
+}
+
+template <int M>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __int_as_float(xor_i32<M>(__float_as_int(v)));
 }
 
 // x, y <- the lanes with bit M clear keep x and receive y's values of the
 // partner lanes (lane ^ M) in y, and vice versa: one v_permlane{16,32}_swap
-// per 32-bit half (M = 16: odd rows of x with even rows of y; M = 32: upper
+// per 32-bit word (M = 16: odd rows of x with even rows of y; M = 32: upper
 // half of x with lower half of y).  Afterwards x + y is, in every lane, its
 // own kept value plus its partner's sent one.
 template <int M>
-__device__ __forceinline__ void swap_halves(double& x, double& y) {
+__device__ __forceinline__ void swap_words(unsigned& x, unsigned& y) {
   static_assert(M == 16 || M == 32, "across rows");
-  const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
-  const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
   if constexpr (M == 32) {
-    const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
-    const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
-    x = __hiloint2double((int)h[0], (int)l[0]);
-    y = __hiloint2double((int)h[1], (int)l[1]);
+    const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
   } else {
-    const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
-    const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
-    x = __hiloint2double((int)h[0], (int)l[0]);
-    y = __hiloint2double((int)h[1], (int)l[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
   }
+}
+
+template <int M>
+__device__ __forceinline__ void swap_halves(double& x, double& y) {
+  unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+  unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+  swap_words<M>(xl, yl);
+  swap_words<M>(xh, yh);
+  x = __hiloint2double((int)xh, (int)xl);
+  y = __hiloint2double((int)yh, (int)yl);
+}
+
+template <int M>
+__device__ __forceinline__ void swap_halves(float& x, float& y) {
+  unsigned xw = __float_as_uint(x), yw = __float_as_uint(y);
+  swap_words<M>(xw, yw);
+  x = __uint_as_float(xw);
+  y = __uint_as_float(yw);
 }
 
 // Transpose-reduce: NV (a power of two, 2..64) per-lane partial sums are
@@ -76,45 +101,60 @@ __device__ __forceinline__ double fold(double (&p)[NV], int lane) {
   return u;
 }
 
-// The same transpose-reduce with the exchanges done without LDS: across
-// rows by lane-half swaps, inside a row by DPP and swizzle.  Every sum takes
-// the same two operands as in fold, so the results are identical.
-template <int CNT, int M, int NV>
-__device__ __forceinline__ void fold_swap_level(double (&p)[NV], int lane) {
-  if constexpr (CNT > 1) {
-    if constexpr (M >= 16) {
-#pragma unroll
-      for (int t = 0; t < CNT / 2; ++t) {
-        double x = p[t], y = p[t + CNT / 2];
-        swap_halves<M>(x, y);
-        p[t] = x + y;
-      }
+// The same transpose-reduce (FP64 or FP32 values) with the exchanges done
+// without LDS: across rows by lane-half swaps, inside a row by DPP and
+// swizzle.  Every sum takes the same two operands as in fold, so the FP64
+// results are identical.  LIVE marks the values that can be nonzero (bit v
+// for value v): a pair of slots that are both known to be zero is not
+// exchanged, which saves the padding of outputs per row up to a power of two.
+template <int M, unsigned long long NEXT, int T, int H, int NV, typename V>
+__device__ __forceinline__ void fold_swap_pairs(V (&p)[NV], int lane) {
+  if constexpr (T < H) {
+    if constexpr (((NEXT >> T) & 1ull) == 0) {
+      p[T] = V(0);
+    } else if constexpr (M >= 16) {
+      V x = p[T], y = p[T + H];
+      swap_halves<M>(x, y);
+      p[T] = x + y;
     } else {
       const bool hi = lane & M;
-#pragma unroll
-      for (int t = 0; t < CNT / 2; ++t) {
-        const double keep = hi ? p[t + CNT / 2] : p[t];
-        const double send = hi ? p[t] : p[t + CNT / 2];
-        p[t] = keep + xor_f64<M>(send);
-      }
+      const V keep = hi ? p[T + H] : p[T];
+      const V send = hi ? p[T] : p[T + H];
+      p[T] = keep + xor_lane<M>(send);
     }
-    fold_swap_level<CNT / 2, M / 2, NV>(p, lane);
+    fold_swap_pairs<M, NEXT, T + 1, H, NV>(p, lane);
   }
 }
 
-template <int NV>
-__device__ __forceinline__ double fold_swap(double (&p)[NV], int lane) {
-  static_assert(NV >= 4, "the final exchanges stay inside a row");
-  fold_swap_level<NV, 32, NV>(p, lane);
-  double u = p[0];
-#pragma unroll
-  for (int m = 32 / NV; m >= 1; m >>= 1) {
-    if (m == 8) u += xor_f64<8>(u);
-    else if (m == 4) u += xor_f64<4>(u);
-    else if (m == 2) u += xor_f64<2>(u);
-    else u += xor_f64<1>(u);
+template <int CNT, int M, int NV, unsigned long long LIVE, typename V>
+__device__ __forceinline__ void fold_swap_level(V (&p)[NV], int lane) {
+  if constexpr (CNT > 1) {
+    constexpr int H = CNT / 2;
+    constexpr unsigned long long NEXT = (LIVE | (LIVE >> H)) & ((1ull << H) - 1ull);
+    fold_swap_pairs<M, NEXT, 0, H, NV>(p, lane);
+    fold_swap_level<H, M / 2, NV, NEXT>(p, lane);
   }
+}
+
+template <int NV, unsigned long long LIVE = (NV >= 64 ? ~0ull : (1ull << NV) - 1ull),
+          typename V>
+__device__ __forceinline__ V fold_swap(V (&p)[NV], int lane) {
+  static_assert(NV >= 4 && NV <= 64, "the final exchanges stay inside a row");
+  fold_swap_level<NV, 32, NV, LIVE>(p, lane);
+  V u = p[0];
+  if constexpr (NV <= 4) u += xor_lane<8>(u);
+  if constexpr (NV <= 8) u += xor_lane<4>(u);
+  if constexpr (NV <= 16) u += xor_lane<2>(u);
+  if constexpr (NV <= 32) u += xor_lane<1>(u);
   return u;
+}
+
+// Live-value mask of G groups of P slots of which the first U are used.
+constexpr unsigned long long live_slots(int G, int P, int U) {
+  unsigned long long m = 0;
+  for (int g = 0; g < G; ++g)
+    for (int o = 0; o < U; ++o) m |= 1ull << (g * P + o);
+  return m;
 }
 
 // ---------------------------------------------------------------------------
@@ -418,7 +458,10 @@ hipError_t launch_bsr_transpose_vals(hipStream_t s, int b, const double* val, co
 // stored in one pass (d_j += omega c_j, or = omega c_j for a zero initial
 // iterate).  Every DoF has exactly one owner, so the stores are disjoint (no
 // atomics, deterministic).  FULL: the store keeps every row of J_T^-1 and the
-// owned ones are picked by their local index.
+// owned ones are picked by their local index.  The row products and the
+// transpose-reduce are in the precision of the store (FP32 products of an
+// FP32 store and the residual rounded to FP32, summed in FP32), the update
+// of the iterate in FP64.
 template <int B, int NLS, typename TS, bool FULL>
 __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
                                               double* __restrict__ d,
@@ -454,6 +497,10 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
       const double v = rho[(int64_t)sd[be] * B + (jc - be * B)];
       x[c] = j < N ? v : 0.0;
     }
+    // the row products are in the precision of the store (see k_vanka_dec)
+    TS xs[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xs[c] = (TS)x[c];
     // owned DoFs, lane = owned index: local index and spatial DoF
     int ol[NOC], gs[NOC];
 #pragma unroll
@@ -503,19 +550,19 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
           a[t][c] = A[ro + (unsigned)(j < N ? j : N - 1)];
         }
       }
-      double p[G];
+      TS p[G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        double acc = 0.0;
+        TS acc = TS(0);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc = fma((double)a[t][c], x[c], acc);
+        for (int c = 0; c < NC; ++c) acc = fma(a[t][c], xs[c], acc);
         p[t] = acc;
       }
-      const double sum = fold<G>(p, lane);   // row r0 + t in lanes t * (64 / G) ..
+      const TS sum = fold_swap<G>(p, lane);   // row r0 + t in lanes t * (64 / G) ..
       // row r0 + t goes to lane (r0 + t) % 64 of chunk r0 / 64 (a group never
       // straddles two chunks: G divides 64)
       const int t = lane - (r0 & 63);
-      const double v = __shfl(sum, (t & (G - 1)) * (64 / G), 64);
+      const double v = (double)__shfl(sum, (t & (G - 1)) * (64 / G), 64);
       const int rcg = r0 >> 6;
 #pragma unroll
       for (int rc = 0; rc < RC; ++rc)
@@ -543,10 +590,24 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
 // the complex product (the lane's constants come from the level's table,
 // made with the store).  Each stored row (one owned spatial DoF) is one
 // coalesced read and gives B per-lane products; 16 / BP rows at a time are
-// folded by one transpose-reduce, and the lane of DoF (k, i) combines the
-// B outputs of row k with row i of V.  Stores as in k_vanka.
+// folded by one transpose-reduce (slots of the padding outputs skipped),
+// and the lane of DoF (k, i) combines the B outputs of row k with row i of
+// V in FP64.  The products and the transpose-reduce are in the precision of
+// the store: an FP32 store multiplies its values by the multipliers rounded
+// to FP32 and sums in FP32, which halves the exchanges; the error this adds
+// is of the order of the rounding of the stored values themselves.  Stores
+// as in k_vanka.
+// Occupancy the register allocation must leave room for (waves per SIMD):
+// the sweep hides its load latency with waves, and the FP32 form, with half
+// the registers for its values, fits 7 (B = 3) or 8 waves without spills.
+template <int B, typename TS>
+constexpr int dec_waves() {
+  return sizeof(TS) == 4 ? (B == 3 ? 7 : 8) : 5;
+}
+
 template <int B, int NLS, typename TS>
-__global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rho,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dec_waves<B, TS>())))
+k_vanka_dec(const double* __restrict__ rho,
                                                   double* __restrict__ d,
                                                   const int32_t* __restrict__ csd,
                                                   const int32_t* __restrict__ own_ptr,
@@ -560,13 +621,11 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
   static_assert(N <= 64 && NLS <= 64, "one wavefront per cell");
   constexpr int BP = B <= 2 ? 2 : 4;       // outputs per stored row, padded to a power of two
   constexpr int GN = 16 / BP;              // stored rows per transpose-reduce
+  constexpr unsigned long long LIVE = live_slots(GN, BP, B);
   // stored rows loaded together: an interior cell owns about n_loc / 2
   // spatial DoFs, so one round of loads usually covers the cell (every load
   // in flight at once; each transpose-reduce waits only for its own rows)
-#ifndef STV_DEC_FPR
-#define STV_DEC_FPR (B == 2 ? 2 : 3)
-#endif
-  constexpr int GL = STV_DEC_FPR * GN;
+  constexpr int GL = (B == 2 ? 2 : 3) * GN;
   const int lane = threadIdx.x & 63;
   const int jl = lane < N ? lane : N - 1;
   const int al = jl / B, cl = jl - al * B;   // spatial DoF and time component of lane j
@@ -586,6 +645,8 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
     ca[o] = ea == 1 ? 1.0 : (ea == 3 ? -1.0 : 0.0);
     cb[o] = eb == 1 ? 1.0 : (eb == 3 ? -1.0 : 0.0);
   }
+  // byte offset of the lane's column in a stored row, and of one row
+  const unsigned jb = (unsigned)(jl * sizeof(TS)), rb = (unsigned)(ld * sizeof(TS));
   // the cell's offsets and its DoF list are fetched one cell ahead (a
   // persistent grid strides over the cells), so that a cell starts with its
   // row loads and its gather instead of a chain of dependent loads
@@ -601,7 +662,7 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
   }
   for (; T < n_cells; T += stride) {
     const int o0 = o0n, no = nxn - o0n, sdv = sdn;
-    const TS* A = store + offn;
+    const char* A = reinterpret_cast<const char*>(store + offn);
     const int Tn = T + stride;
     if (Tn < n_cells) {
       o0n = own_ptr[Tn];
@@ -617,9 +678,9 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
 #pragma unroll
     for (int l = 0; l < B; ++l) u = fma(wl[l], __shfl(x, al * B + l, 64), u);
     const double ua = __shfl(u, srca, 64), ub = __shfl(u, srcb, 64);
-    double m[B];
+    TS m[B];
 #pragma unroll
-    for (int o = 0; o < B; ++o) m[o] = fma(ca[o], ua, cb[o] * ub);
+    for (int o = 0; o < B; ++o) m[o] = (TS)fma(ca[o], ua, cb[o] * ub);
     // the owned DoF of each stored row (lane = owned index; its spatial
     // index from the lanes of its local DoF), the row this lane stores
     // (r = lane = k * B + i), its global index and old value
@@ -634,23 +695,25 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
       TS a[GL];
 #pragma unroll
       for (int t = 0; t < GL; ++t) {
-        const int row = min(k0 + t, no - 1);
-        a[t] = A[(unsigned)(row * ld + jl)];
+        const unsigned row = (unsigned)min(k0 + t, no - 1);
+        a[t] = *reinterpret_cast<const TS*>(A + (row * rb + jb));
       }
 #pragma unroll
       for (int h = 0; h < GL / GN; ++h) {
-        double pp[16];
+        TS pp[16];
 #pragma unroll
         for (int t = 0; t < GN; ++t)
 #pragma unroll
-          for (int o = 0; o < BP; ++o) pp[t * BP + o] = o < B ? (double)a[h * GN + t] * m[o] : 0.0;
-        const double sum = fold_swap<16>(pp, lane);   // value t * BP + o in lanes 4 (t * BP + o) ..
+          for (int o = 0; o < BP; ++o) pp[t * BP + o] = o < B ? a[h * GN + t] * m[o] : TS(0);
+        // value t * BP + o in lanes 4 (t * BP + o) .. + 3
+        const TS sum = fold_swap<16, LIVE>(pp, lane);
         const int kb = k0 + h * GN;
         const int kk = kl - kb;                  // this lane's row within the group
         const int kc = kk < 0 ? 0 : (kk >= GN ? GN - 1 : kk);
         double val = 0.0;
 #pragma unroll
-        for (int o = 0; o < B; ++o) val = fma(vl[o], __shfl(sum, 4 * (kc * BP + o), 64), val);
+        for (int o = 0; o < B; ++o)
+          val = fma(vl[o], (double)__shfl(sum, 4 * (kc * BP + o), 64), val);
         if (kk >= 0 && kk < GN) res = val;
       }
     }
@@ -670,7 +733,9 @@ __global__ void __launch_bounds__(256) k_vanka_dec(const double* __restrict__ rh
 // each stored row is two coalesced reads; G rows at a time give 2G sums
 // (real and imaginary parts) folded by one transpose-reduce.  Output
 // r = 2 os + i of the os-th owned DoF lands in lane r % 64, which fetched the
-// DoF's old value at the start; stores as in k_vanka.
+// DoF's old value at the start; stores as in k_vanka.  The complex products
+// and the transpose-reduce are in the precision of the store, the
+// recombination with V and the update in FP64.
 template <int NLS, typename TS>
 __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho,
                                                  double* __restrict__ d,
@@ -704,6 +769,13 @@ __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho
       const double2 rr = *reinterpret_cast<const double2*>(&rho[(int64_t)sd[cl] * B]);
       ur[cc] = c < NLS ? fma(w00, rr.x, w01 * rr.y) : 0.0;
       ui[cc] = c < NLS ? fma(w10, rr.x, w11 * rr.y) : 0.0;
+    }
+    // the row products in the precision of the store (see k_vanka_dec)
+    TS urs[NCC], uis[NCC];
+#pragma unroll
+    for (int cc = 0; cc < NCC; ++cc) {
+      urs[cc] = (TS)ur[cc];
+      uis[cc] = (TS)ui[cc];
     }
     int gs[NOC];
 #pragma unroll
@@ -741,27 +813,27 @@ __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho
           ai[t][cc] = A[ro + NLS + cl];
         }
       }
-      double p[2 * G];
+      TS p[2 * G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        double re = 0.0, im = 0.0;
+        TS re = TS(0), im = TS(0);
 #pragma unroll
         for (int cc = 0; cc < NCC; ++cc) {
-          const double yr = (double)ar[t][cc], yi = (double)ai[t][cc];
-          re = fma(yr, ur[cc], fma(-yi, ui[cc], re));
-          im = fma(yr, ui[cc], fma(yi, ur[cc], im));
+          const TS yr = ar[t][cc], yi = ai[t][cc];
+          re = fma(yr, urs[cc], fma(-yi, uis[cc], re));
+          im = fma(yr, uis[cc], fma(yi, urs[cc], im));
         }
         p[2 * t] = re;
         p[2 * t + 1] = im;
       }
-      const double sum = fold_swap<2 * G>(p, lane);   // value e in lanes 4e .. 4e + 3
+      const TS sum = fold_swap<2 * G>(p, lane);   // value e in lanes 4e .. 4e + 3
 #pragma unroll
       for (int rc = 0; rc < RC; ++rc) {
         const int r = lane + 64 * rc;
         const int t = (r >> 1) - k0;
         const int tc = t < 0 ? 0 : (t >= G ? G - 1 : t);
-        const double re = __shfl(sum, 4 * (2 * tc), 64);
-        const double im = __shfl(sum, 4 * (2 * tc + 1), 64);
+        const double re = (double)__shfl(sum, 4 * (2 * tc), 64);
+        const double im = (double)__shfl(sum, 4 * (2 * tc + 1), 64);
         const double val = (r & 1) ? fma(v10, re, v11 * im) : fma(v00, re, v01 * im);
         if (t >= 0 && t < G) res[rc] = val;
       }
