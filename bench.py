@@ -20,6 +20,7 @@ import json
 import os
 import sys
 import time
+from types import SimpleNamespace
 
 import numpy as np
 
@@ -320,8 +321,7 @@ def gradient_bench(args):
     x = torch.zeros_like(b)
     lam = torch.zeros_like(b)
     nc = m.n_cells
-    con = torch.empty(nc, dtype=torch.float64, device=dev)
-    fdot = torch.empty(len(in_cells), dtype=torch.float64, device=dev)
+    grad = torch.empty(nc, dtype=torch.float64, device=dev)
     fcf = Fc.reshape(len(in_cells), -1)
     cells_smoothed = sum(L.n_cells for L in p.levels[1:])
 
@@ -329,8 +329,8 @@ def gradient_bench(args):
         s.build_cell_inverses(fp32=fp32, full=True)
         fi = s.gmres_solve(b, x, restart=30, max_it=1000, rtol=1e-8)
         ai = s.gmres_solve_transposed(q, lam, restart=30, max_it=1000, rtol=1e-8)
-        s.cell_contract(G - 1, lam, x, refs, ptr, idx, w, tw, con)
-        s.cell_dot(G - 1, lam, in_cells, fcf, fdot)
+        # dL/dnu_c = -lam_c^T (W (x) K_c) x_c + U lam_c^T F_c (U = 1), one device pass
+        s.cell_gradient(G - 1, lam, x, refs, ptr, idx, w, tw, -1.0, in_cells, fcf, 1.0, grad)
         return fi, ai
 
     def leg(fp32):
@@ -344,8 +344,7 @@ def gradient_bench(args):
             sweeps += (fi["iters"] + ai["iters"]) * cells_smoothed * (args.nu1 + args.nu2)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        g = -con.cpu().numpy()
-        g[in_cells] += fdot.cpu().numpy()
+        g = grad.cpu().numpy()
         return dict(ms_per_step=round(1e3 * el / args.steps, 3),
                     gradients_per_s=round(args.steps / el, 3),
                     cell_sweeps_per_s=round(sweeps / el, 1), forward_iters=fi["iters"],
@@ -368,7 +367,8 @@ def gradient_bench(args):
         "config": {"workload": "2d channel 256x64 Q2/P1disc x dG(1), 5 levels, per-cell "
                                "viscosity 1e-3 exp(0.3 z), tau=0.01, outflow-flux loss",
                    "cells_finest": nc, "levels": G, "parallelism": "single GPU"},
-        "fp64": r64, "fp32_inverses": r32, "cpu_baseline": cpu}), flush=True)
+        "fp64": r64, "fp32_inverses": r32,
+        "cpu_baseline": cpu}), flush=True)
 
 
 def newton_system(n_fine, G):
@@ -434,10 +434,19 @@ def newton_bench(args):
     du = torch.zeros_like(rhs)
     cells = sum(int(np.asarray(L["cell_sdofs"]).shape[0]) for L in H[1:])
 
+    top = s.n_levels - 1
+    Lt = H[top]
+    fine = SimpleNamespace(n_sdofs=int(Lt["n_sdofs"]), cell_sdofs=np.asarray(Lt["cell_sdofs"]),
+                           n_cells=int(np.asarray(Lt["cell_sdofs"]).shape[0]))
+    zi = 1.0 / (args.nu1 + args.nu2) if args.nu1 > 0 else 0.0
+
     def leg(fp32):
         for _ in range(args.warmup):
             s.build_cell_inverses(fp32=fp32)
             s.gmres_solve(rhs, du, restart=30, max_it=1000, rtol=1e-8)
+        # the finest-level sweep launches of the timed steps are stamped by the
+        # kernels' own start/end records (no event records between launches)
+        s.set_timing(True, classes=["sweep"], levels=[top])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sweeps = 0
@@ -447,15 +456,26 @@ def newton_bench(args):
             sweeps += info["iters"] * cells * (args.nu1 + args.nu2)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        n_sw, ms_sw = s.kernel_stats("sweep", top)
+        s.set_timing(False)
+        byt = sweep_bytes(fine, P.b, s.level_info(top)["inverse_bytes"], zi)
+        gbs = byt / (ms_sw / n_sw / 1e3) / 1e9 if n_sw else 0.0
         r1 = P.residual(u + du.cpu().numpy(), F)
         return dict(ms_per_step=round(1e3 * el / args.steps, 3),
                     cell_sweeps_per_s=round(sweeps / el, 1), iters=info["iters"],
                     true_relres=info["true_relres"],
                     newton_residual_before=float(np.linalg.norm(R) / np.linalg.norm(F)),
-                    newton_residual_after=float(np.linalg.norm(r1) / np.linalg.norm(F)))
+                    newton_residual_after=float(np.linalg.norm(r1) / np.linalg.norm(F)),
+                    roofline_sweep=dict(
+                        bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(byt),
+                        avg_launch_ms=round(ms_sw / max(n_sw, 1), 5), launches=n_sw,
+                        kernel=f"Vanka cell sweep on the full-row store (k_vanka), finest "
+                               f"level ({top}), {'FP32' if fp32 else 'FP64'} store"))
 
     r64 = leg(False)
     r32 = None if args.no_fp32 else leg(True)
+    roof = r64.pop("roofline_sweep")
     cpu = None if args.no_cpu_baseline else newton_cpu_baseline((128, 32), 4)
     print(json.dumps({
         "metric": "Newton-step linear solve: GMG-GMRES time to rel. residual 1e-8; Vanka "
@@ -467,7 +487,8 @@ def newton_bench(args):
                                "Newton Jacobian, nu=1e-3, tau=0.01, parabolic inflow ramp",
                    "cells_finest": n_fine[0] * n_fine[1], "levels": G,
                    "parallelism": "single GPU"},
-        "fp64": r64, "fp32_inverses": r32, "cpu_baseline": cpu}), flush=True)
+        "roofline": dict(roof, traffic=None), "fp64": r64, "fp32_inverses": r32,
+        "cpu_baseline": cpu}), flush=True)
 
 
 FP64_PEAK_TFLOPS = 78.6

@@ -298,6 +298,34 @@ int stv_cell_contract(stv_ctx* ctx, int level, const double* lam, const double* 
 int stv_cell_dot(stv_ctx* ctx, int level, const double* lam, int n, const int32_t* cells,
                  const double* f, double* out);
 
+/* The cellwise gradient terms in one pass: for every smoothed cell T of
+ * `level`,
+ *   out[T] = sc * (the stv_cell_contract form of T) + sf * lam_T . f[k]
+ * where the second term is present only for T = cells[k] (cells distinct,
+ * f a host array of n x n_loc values in the cell-local order
+ * alpha*(k+1) + l).  For an operator affine in each cell's viscosity, the
+ * viscosity derivative of the local matrices of Sec. 2.3 eq. (2.5) as K_T,
+ * sc = -1 and f the viscosity derivative of the right-hand side scaled by
+ * sf, this is the adjoint gradient dL/dnu_T = -lam^T (dJ/dnu_T) x +
+ * lam^T (db/dnu_T).  Host arrays are copied; lam, x, out are device arrays
+ * (out: one double per cell).  Synchronises.  Errors: STV_EINVAL (a cell
+ * out of range or listed twice, a non-finite scale, bad kptr/kidx). */
+int stv_cell_gradient(stv_ctx* ctx, int level, const double* lam, const double* x, int n_ref,
+                      const double* Kref, const int32_t* kptr, const int32_t* kidx,
+                      const double* kw, const double* tw, double sc, int n,
+                      const int32_t* cells, const double* f, double sf, double* out);
+
+/* Cellwise terms added into a device vector y of `level` (time-inner):
+ *   y[DoF j of cell cells[k]] += coef[k] * f[k][j]
+ * for k < n (f: host, n x n_loc in the cell-local order alpha*(k+1) + l;
+ * coef: host, n values) - the assembly of a right-hand side whose cell
+ * contributions scale with a per-cell coefficient (Sec. 2.3: the load
+ * vector of eq. (2.5) with a cellwise viscosity).  The terms of a DoF are
+ * summed in list order by one thread (deterministic).  Synchronises.
+ * Errors: STV_EINVAL. */
+int stv_cell_scatter(stv_ctx* ctx, int level, int n, const int32_t* cells, const double* coef,
+                     const double* f, double* y);
+
 /* out[i] = a_i . b_i for every instance i of two finest-level device vectors
  * (out: host array of n_inst doubles).  Synchronises. */
 int stv_dot(stv_ctx* ctx, const double* a, const double* b, double* out);

@@ -96,6 +96,8 @@ def _load():
         "stv_gmres_solve_transposed": (I, [P, P, P, ctypes.POINTER(_GP), ctypes.POINTER(_GI)]),
         "stv_cell_contract": (I, [P, I, P, P, I, P, P, P, P, P, P]),
         "stv_cell_dot": (I, [P, I, P, I, P, P, P]),
+        "stv_cell_gradient": (I, [P, I, P, P, I, P, P, P, P, P, D, I, P, P, D, P]),
+        "stv_cell_scatter": (I, [P, I, I, P, P, P, P]),
         "stv_dot": (I, [P, P, P, P]),
         "stv_set_kron_factors": (I, [P, I, P, P, P, P]),
         "stv_autotune": (I, [P, ctypes.POINTER(I), I]),
@@ -116,7 +118,8 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_kernel_stats", "stv_set_option", "stv_set_batch", "stv_instance_layout",
             "stv_instance_info", "stv_set_launch", "stv_autotune", "stv_vcycle_transposed",
             "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot",
-            "stv_set_kron_factors", "stv_set_timing_filter", "stv_vcycle_noalloc")
+            "stv_set_kron_factors", "stv_set_timing_filter", "stv_vcycle_noalloc",
+            "stv_cell_gradient", "stv_cell_scatter")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2, "tournament": 3}
 
@@ -380,6 +383,45 @@ class Solver:
         optr = self._out(out, int(cells.size), "out")
         self._check(_lib.stv_cell_dot(self._h, level, self._vec(lam, level, "lam"),
                                       int(cells.size), cells.ctypes.data, f.ctypes.data, optr))
+
+    def cell_gradient(self, level, lam, x, refs, kptr, kidx, kw, tw, sc, cells, f, sf, out):
+        """out[T] = sc * (cell_contract form of T) + sf * lam_T . f[k] for T = cells[k]
+        (device out, one value per cell)."""
+        refs = np.ascontiguousarray(refs, dtype=np.float64)
+        kptr = np.ascontiguousarray(kptr, dtype=np.int32)
+        kidx = np.ascontiguousarray(kidx, dtype=np.int32)
+        kw = np.ascontiguousarray(kw, dtype=np.float64)
+        tw = np.ascontiguousarray(tw, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        info = self.level_info(level)
+        n_cells = info["n_cells"]
+        if kptr.shape != (n_cells + 1,):
+            raise ValueError(f"kptr needs {n_cells + 1} entries")
+        if kidx.size != kw.size or (kptr.size and kptr[-1] > kidx.size):
+            raise ValueError("kidx and kw must have kptr[-1] entries")
+        if refs.ndim != 3 or tw.size != self.b:
+            raise ValueError("refs must be (n_ref, n_ls, n_ls) and tw have k+1 entries")
+        if f.size != cells.size * info["n_loc"]:
+            raise ValueError(f"f must hold {cells.size} x {info['n_loc']} values")
+        optr = self._out(out, n_cells, "out")
+        self._check(_lib.stv_cell_gradient(
+            self._h, level, self._vec(lam, level, "lam"), self._vec(x, level, "x"),
+            int(refs.shape[0]), refs.ctypes.data, kptr.ctypes.data, kidx.ctypes.data,
+            kw.ctypes.data, tw.ctypes.data, float(sc), int(cells.size), cells.ctypes.data,
+            f.ctypes.data, float(sf), optr))
+
+    def cell_scatter(self, level, cells, coef, f, y):
+        """y[DoF j of cell cells[k]] += coef[k] * f[k][j] (y: device vector of the level)."""
+        cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1)
+        coef = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        n_loc = self.level_info(level)["n_loc"]
+        if coef.size != cells.size or f.size != cells.size * n_loc:
+            raise ValueError(f"coef must hold {cells.size} values and f {cells.size} x {n_loc}")
+        self._check(_lib.stv_cell_scatter(self._h, level, int(cells.size), cells.ctypes.data,
+                                          coef.ctypes.data, f.ctypes.data,
+                                          self._vec(y, level, "y")))
 
     def dot(self, a, b):
         """Per-instance dot products of two finest-level vectors (host list)."""

@@ -9,10 +9,11 @@ Vanka-GMG (the stored inverses read transposed) and forms
   dL/dU    = lam^T (F_0 + sum_c nu_c F_c),
 
 for an operator affine in each cell's viscosity, J = J_0 + sum_c nu_c
-(W_tau (x) K_c), and a right-hand side b = U (F_0 + sum_c nu_c F_c); the
-cellwise terms are computed on the device by the library's contraction
-kernels.  `data` describes the problem (attributes below); the hierarchy for
-a given viscosity comes from data.build(nu).
+(W_tau (x) K_c), and a right-hand side b = U (F_0 + sum_c nu_c F_c).  The
+right-hand side is assembled on the device (stv_cell_scatter) and the
+gradient of every cell in one device pass (stv_cell_gradient).  `data`
+describes the problem (attributes below); the hierarchy for a given
+viscosity comes from data.build(nu).
 """
 from __future__ import annotations
 
@@ -37,14 +38,9 @@ class AdjointData:
         self.refs, self.kptr, self.kidx, self.kw, self.tw = refs, kptr, kidx, kw, tw
         self.F0, self.in_cells, self.Fc = F0, np.asarray(in_cells, np.int32), Fc
 
-    def rhs_hat(self, nu, cell_sdofs):
-        """F0 + sum_c nu_c F_c (U = 1), time-inner."""
-        b = self.k + 1
-        out = self.F0.copy()
-        for i in range(b):
-            np.add.at(out, cell_sdofs[self.in_cells].reshape(-1).astype(np.int64) * b + i,
-                      (nu[self.in_cells][:, None] * self.Fc[:, :, i]).reshape(-1))
-        return out
+    def fc_rows(self):
+        """F_c of the listed cells as rows in the cell-local order alpha*(k+1) + l."""
+        return np.ascontiguousarray(self.Fc.reshape(len(self.in_cells), -1))
 
 
 class SolveOptions:
@@ -72,9 +68,11 @@ class SpaceTimeSolve(torch.autograd.Function):
         opts.loaded = token
         ctx.token, ctx.nu_h, ctx.fp32 = token, nu_h, opts.fp32
         csd = np.asarray(levels[-1].cell_sdofs)
-        bhat = data.rhs_hat(nu_h, csd)
         dev = torch.device("cuda", opts.device)
-        bh = torch.from_numpy(bhat).to(dev)
+        # F0 + sum_c nu_c F_c on the device
+        G = s.n_levels - 1
+        bh = torch.from_numpy(np.ascontiguousarray(data.F0, dtype=np.float64)).to(dev)
+        s.cell_scatter(G, data.in_cells, nu_h[data.in_cells], data.fc_rows(), bh)
         b = U_h * bh
         x = torch.zeros_like(b)
         info = s.gmres_solve(b, x, restart=opts.restart, max_it=opts.max_it, rtol=opts.rtol)
@@ -99,14 +97,10 @@ class SpaceTimeSolve(torch.autograd.Function):
                                         restart=opts.restart, max_it=opts.max_it, rtol=opts.rtol)
         opts.last_info["adjoint"] = info
         G = s.n_levels - 1
-        con = torch.empty(ctx.n_cells, dtype=torch.float64, device=x.device)
-        s.cell_contract(G, lam, x, data.refs, data.kptr, data.kidx, data.kw, data.tw, con)
-        fdot = torch.empty(len(data.in_cells), dtype=torch.float64, device=x.device)
-        nin = len(data.in_cells)
-        s.cell_dot(G, lam, data.in_cells, data.Fc.reshape(nin, -1), fdot)
-        grad_nu = -con
-        grad_nu.index_add_(0, torch.from_numpy(data.in_cells.astype(np.int64)).to(x.device),
-                           ctx.U * fdot)
+        # -lam_c^T (W (x) K_c) x_c + U lam_c^T F_c for every cell, one device pass
+        grad_nu = torch.empty(ctx.n_cells, dtype=torch.float64, device=x.device)
+        s.cell_gradient(G, lam, x, data.refs, data.kptr, data.kidx, data.kw, data.tw, -1.0,
+                        data.in_cells, data.fc_rows(), ctx.U, grad_nu)
         gU = s.dot(lam, bh)[0]
         return (grad_nu.to(ctx.nu_dev, ctx.nu_dtype),
                 torch.tensor(gU, dtype=torch.float64), None, None)

@@ -1061,12 +1061,19 @@ hipError_t launch_vanka_cells_t(hipStream_t s, int b, const DevLevel& L, const d
 // K_T = sum_e kw[e] Kref[kidx[e]] (e in [kptr[T], kptr[T+1]); n_ls x n_ls
 // spatial reference matrices): one wavefront per cell, lane j = alpha*B + l
 // forms (K_T x)_j with x broadcast from its lane, then a wavefront sum.
+// With fidx (per cell: the row k of f that belongs to it, or -1) the cell's
+// right-hand-side term is added in the same pass:
+//   out[T] = sc * (the form above) + sf * sum_j lam[T's DoF j] f[k][j],
+// f in the cell-local order alpha*B + l (the gradient of an outflow loss
+// with respect to cell viscosities and an inflow amplitude).
 template <int B, int NLS>
 __global__ void __launch_bounds__(256) k_cell_contract(
     const double* __restrict__ lam, const double* __restrict__ x,
     const int32_t* __restrict__ csd, int n_cells, const double* __restrict__ Kref,
     const int32_t* __restrict__ kptr, const int32_t* __restrict__ kidx,
-    const double* __restrict__ kw, const double* __restrict__ tw, double* __restrict__ out) {
+    const double* __restrict__ kw, const double* __restrict__ tw, double sc,
+    const int32_t* __restrict__ fidx, const double* __restrict__ f, double sf,
+    double* __restrict__ out) {
   constexpr int N = B * NLS;
   constexpr int NC = (N + 63) / 64;
   const int lane = threadIdx.x & 63;
@@ -1110,7 +1117,17 @@ __global__ void __launch_bounds__(256) k_cell_contract(
     if (o < N) sacc = fma(tw[o - (o / B) * B] * lv[c], y[c], sacc);
   }
   sacc = wave_sum(sacc);
-  if (lane == 0) out[T] = sacc;
+  double facc = 0.0;
+  const int fk = fidx ? fidx[T] : -1;
+  if (fk >= 0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int o = lane + 64 * c;
+      if (o < N) facc = fma(lv[c], f[(int64_t)fk * N + o], facc);
+    }
+    facc = wave_sum(facc);
+  }
+  if (lane == 0) out[T] = fk >= 0 ? fma(sc, sacc, sf * facc) : sc * sacc;
 }
 
 // out[k] = sum_j lam[cell k's DoF j] f[k*N + j] (f in the cell-local order
@@ -1138,11 +1155,12 @@ __global__ void __launch_bounds__(256) k_cell_dot(const double* __restrict__ lam
 hipError_t launch_cell_contract(hipStream_t s, int b, const DevLevel& L, const double* lam,
                                 const double* x, const double* Kref, const int32_t* kptr,
                                 const int32_t* kidx, const double* kw, const double* tw,
+                                double sc, const int32_t* fidx, const double* f, double sf,
                                 double* out) {
   const unsigned grid = (unsigned)((L.n_cells + 3) / 4);
 #define STV_CC(BB, NN)                                                                    \
   k_cell_contract<BB, NN><<<grid, 256, 0, s>>>(lam, x, L.cell_sdofs, L.n_cells, Kref, kptr, \
-                                               kidx, kw, tw, out)
+                                               kidx, kw, tw, sc, fidx, f, sf, out)
   if (L.n_ls == 21) {
     switch (b) { case 1: STV_CC(1, 21); break; case 2: STV_CC(2, 21); break;
                  case 3: STV_CC(3, 21); break; case 4: STV_CC(4, 21); break;
@@ -1175,6 +1193,29 @@ hipError_t launch_cell_dot(hipStream_t s, int b, const DevLevel& L, const double
     return hipErrorInvalidValue;
   }
 #undef STV_CD
+  return hipGetLastError();
+}
+
+// y[dof[i]] += sum_{e = ptr[i]}^{ptr[i+1]-1} coef[ck[e]] * f[fi[e]]: cellwise
+// terms added into a vector by gathering, one thread per touched DoF, the
+// terms of a DoF in the order of its list (deterministic, no atomics).
+__global__ void k_cell_scatter(const int64_t* __restrict__ dof, const int32_t* __restrict__ ptr,
+                               const int32_t* __restrict__ ck, const int64_t* __restrict__ fi,
+                               const double* __restrict__ coef, const double* __restrict__ f,
+                               int n_dof, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_dof) return;
+  double acc = y[dof[i]];
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) acc = fma(coef[ck[e]], f[fi[e]], acc);
+  y[dof[i]] = acc;
+}
+
+hipError_t launch_cell_scatter(hipStream_t s, const int64_t* dof, const int32_t* ptr,
+                               const int32_t* ck, const int64_t* fi, const double* coef,
+                               const double* f, int n_dof, double* y) {
+  if (n_dof <= 0) return hipSuccess;
+  k_cell_scatter<<<(unsigned)((n_dof + 255) / 256), 256, 0, s>>>(dof, ptr, ck, fi, coef, f,
+                                                                 n_dof, y);
   return hipGetLastError();
 }
 

@@ -782,6 +782,7 @@ int setup_packed(stv_ctx* ctx, int n_inst, int dim, int k, const int* nlev,
           iloc[(size_t)fillp[(size_t)r]++] = (uint8_t)a;
         }
       STV_TRY(upload(ctx, &L.cell_sdofs, csd.data(), csd.size()));
+      L.h_csd = std::move(csd);
       STV_TRY(upload(ctx, &L.own_ptr, L.h_own_ptr.data(), L.h_own_ptr.size()));
       STV_TRY(upload(ctx, &L.own_loc, L.h_own_loc.data(), L.h_own_loc.size()));
       STV_TRY(upload(ctx, &L.inc_ptr, ip.data(), ip.size()));
@@ -2068,11 +2069,113 @@ int stv_cell_contract(stv_ctx* ctx, int level, const double* lam, const double* 
   if (rc == STV_OK) rc = upload(ctx, &dw, kw, (size_t)std::max(ne, 1));
   if (rc == STV_OK) rc = upload(ctx, &dtw, tw, (size_t)ctx->b);
   if (rc != STV_OK) { cleanup(); return rc; }
-  hipError_t e = launch_cell_contract(ctx->stream, ctx->b, L, lam, x, dK, dp, di, dw, dtw, out);
+  hipError_t e = launch_cell_contract(ctx->stream, ctx->b, L, lam, x, dK, dp, di, dw, dtw, 1.0,
+                                      nullptr, nullptr, 0.0, out);
   const hipError_t es = hipStreamSynchronize(ctx->stream);
   cleanup();
   if (e == hipSuccess) e = es;
   if (e != hipSuccess) return fail(ctx, STV_EHIP, std::string("cell contraction failed: ") + hipGetErrorString(e));
+  return STV_OK;
+}
+
+int stv_cell_gradient(stv_ctx* ctx, int level, const double* lam, const double* x, int n_ref,
+                      const double* Kref, const int32_t* kptr, const int32_t* kidx,
+                      const double* kw, const double* tw, double sc, int n,
+                      const int32_t* cells, const double* f, double sf, double* out) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (level < 0 || level >= ctx->n_levels || ctx->lv[level].n_cells == 0)
+    return fail(ctx, STV_EINVAL, "level out of range or without smoothed cells");
+  if (!lam || !x || !Kref || !kptr || !kidx || !kw || !tw || !out || n_ref < 1)
+    return fail(ctx, STV_EINVAL, "NULL argument or n_ref < 1");
+  if (n < 0 || (n > 0 && (!cells || !f))) return fail(ctx, STV_EINVAL, "bad cell list");
+  if (!std::isfinite(sc) || !std::isfinite(sf)) return fail(ctx, STV_EINVAL, "sc and sf must be finite");
+  const DevLevel& L = ctx->lv[level];
+  const int nls = L.n_ls, N = nls * ctx->b;
+  if (kptr[0] != 0) return fail(ctx, STV_EINVAL, "kptr[0] must be 0");
+  for (int32_t c = 0; c < L.n_cells; ++c)
+    if (kptr[c + 1] < kptr[c]) return fail(ctx, STV_EINVAL, "kptr must be non-decreasing");
+  const int32_t ne = kptr[L.n_cells];
+  for (int32_t e = 0; e < ne; ++e)
+    if (kidx[e] < 0 || kidx[e] >= n_ref) return fail(ctx, STV_EINVAL, "kidx out of range");
+  // the row of f that belongs to each cell (-1: none)
+  std::vector<int32_t> fidx((size_t)L.n_cells, -1);
+  for (int k = 0; k < n; ++k) {
+    if (cells[k] < 0 || cells[k] >= L.n_cells) return fail(ctx, STV_EINVAL, "cell out of range");
+    if (fidx[(size_t)cells[k]] >= 0) return fail(ctx, STV_EINVAL, "cells must be distinct");
+    fidx[(size_t)cells[k]] = k;
+  }
+  double *dK = nullptr, *dw = nullptr, *dtw = nullptr, *df = nullptr;
+  int32_t *dp = nullptr, *di = nullptr, *dfi = nullptr;
+  auto cleanup = [&]() {
+    dfree(dK); dfree(dw); dfree(dtw); dfree(dp); dfree(di); dfree(df); dfree(dfi);
+  };
+  int rc = upload(ctx, &dK, Kref, (size_t)n_ref * nls * nls);
+  if (rc == STV_OK) rc = upload(ctx, &dp, kptr, (size_t)L.n_cells + 1);
+  if (rc == STV_OK) rc = upload(ctx, &di, kidx, (size_t)std::max(ne, 1));
+  if (rc == STV_OK) rc = upload(ctx, &dw, kw, (size_t)std::max(ne, 1));
+  if (rc == STV_OK) rc = upload(ctx, &dtw, tw, (size_t)ctx->b);
+  if (rc == STV_OK) rc = upload(ctx, &dfi, fidx.data(), fidx.size());
+  if (rc == STV_OK && n > 0) rc = upload(ctx, &df, f, (size_t)n * N);
+  if (rc != STV_OK) { cleanup(); return rc; }
+  hipError_t e = launch_cell_contract(ctx->stream, ctx->b, L, lam, x, dK, dp, di, dw, dtw, sc,
+                                      dfi, df, sf, out);
+  const hipError_t es = hipStreamSynchronize(ctx->stream);
+  cleanup();
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return fail(ctx, STV_EHIP, std::string("cell gradient failed: ") + hipGetErrorString(e));
+  return STV_OK;
+}
+
+int stv_cell_scatter(stv_ctx* ctx, int level, int n, const int32_t* cells, const double* coef,
+                     const double* f, double* y) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (level < 0 || level >= ctx->n_levels || ctx->lv[level].n_cells == 0)
+    return fail(ctx, STV_EINVAL, "level out of range or without smoothed cells");
+  if (n < 0 || !y || (n > 0 && (!cells || !coef || !f))) return fail(ctx, STV_EINVAL, "bad arguments");
+  if (n == 0) return STV_OK;
+  const DevLevel& L = ctx->lv[level];
+  const int b = ctx->b, nls = L.n_ls, N = nls * b;
+  for (int k = 0; k < n; ++k)
+    if (cells[k] < 0 || cells[k] >= L.n_cells) return fail(ctx, STV_EINVAL, "cell out of range");
+  // (global DoF, list position k, entry of f) for every term, grouped by DoF
+  // in the order of the list
+  std::vector<std::pair<int64_t, int64_t>> terms;   // (global DoF, k * N + j)
+  terms.reserve((size_t)n * N);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < N; ++j) {
+      const int a = j / b, l = j - a * b;
+      const int64_t g = (int64_t)L.h_csd[(size_t)cells[k] * nls + a] * b + l;
+      terms.emplace_back(g, (int64_t)k * N + j);
+    }
+  std::stable_sort(terms.begin(), terms.end(),
+                   [](const auto& u, const auto& v) { return u.first < v.first; });
+  std::vector<int64_t> dof, fi;
+  std::vector<int32_t> ptr(1, 0), ck;
+  for (size_t t = 0; t < terms.size(); ++t) {
+    if (t == 0 || terms[t].first != terms[t - 1].first) {
+      if (t) ptr.push_back((int32_t)fi.size());
+      dof.push_back(terms[t].first);
+    }
+    fi.push_back(terms[t].second);
+    ck.push_back((int32_t)(terms[t].second / N));
+  }
+  ptr.push_back((int32_t)fi.size());
+  double *dc = nullptr, *df = nullptr;
+  int64_t *dd = nullptr, *dfi = nullptr;
+  int32_t *dp = nullptr, *dk = nullptr;
+  auto cleanup = [&]() { dfree(dc); dfree(df); dfree(dd); dfree(dfi); dfree(dp); dfree(dk); };
+  int rc = upload(ctx, &dc, coef, (size_t)n);
+  if (rc == STV_OK) rc = upload(ctx, &df, f, (size_t)n * N);
+  if (rc == STV_OK) rc = upload(ctx, &dd, dof.data(), dof.size());
+  if (rc == STV_OK) rc = upload(ctx, &dfi, fi.data(), fi.size());
+  if (rc == STV_OK) rc = upload(ctx, &dp, ptr.data(), ptr.size());
+  if (rc == STV_OK) rc = upload(ctx, &dk, ck.data(), ck.size());
+  if (rc != STV_OK) { cleanup(); return rc; }
+  hipError_t e = launch_cell_scatter(ctx->stream, dd, dp, dk, dfi, dc, df, (int)dof.size(), y);
+  const hipError_t es = hipStreamSynchronize(ctx->stream);
+  cleanup();
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return fail(ctx, STV_EHIP, std::string("cell scatter failed: ") + hipGetErrorString(e));
   return STV_OK;
 }
 

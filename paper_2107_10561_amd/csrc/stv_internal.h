@@ -76,6 +76,7 @@ struct DevLevel {
   // host copies kept for validation / export
   std::vector<int32_t> h_own_ptr;
   std::vector<uint8_t> h_own_loc;
+  std::vector<int32_t> h_csd;     // cell DoF lists (n_cells x n_ls)
   int64_t n_cells_all = 0;        // cells of every member, the coarse ones included
   // launch shapes (chosen by the autotuner or set explicitly)
   // transposed level matrix (built on first use by a transposed solve)
@@ -309,7 +310,11 @@ hipError_t launch_vanka_cells_t(hipStream_t s, int b, const DevLevel& L, const d
 hipError_t launch_cell_contract(hipStream_t s, int b, const DevLevel& L, const double* lam,
                                 const double* x, const double* Kref, const int32_t* kptr,
                                 const int32_t* kidx, const double* kw, const double* tw,
+                                double sc, const int32_t* fidx, const double* f, double sf,
                                 double* out);
+hipError_t launch_cell_scatter(hipStream_t s, const int64_t* dof, const int32_t* ptr,
+                               const int32_t* ck, const int64_t* fi, const double* coef,
+                               const double* f, int n_dof, double* y);
 hipError_t launch_cell_dot(hipStream_t s, int b, const DevLevel& L, const double* lam,
                            const int32_t* cells, int n, const double* f, double* out);
 hipError_t launch_dense_gemv_t(hipStream_t s, const CoarseDesc* desc, int cnt, int b,

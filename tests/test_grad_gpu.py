@@ -221,3 +221,51 @@ def test_backward_after_a_second_forward(stv):
     # the second output's backward reloads its own operator
     (q * x2).sum().backward()
     assert np.isfinite(nu2.grad.numpy()).all()
+
+
+def test_cell_gradient_and_rhs_scatter(stv):
+    """stv_cell_gradient and stv_cell_scatter on random vectors against the
+    oracle's cellwise contraction, cell dot and right-hand side assembly
+    (every cell's row of f, cells sharing DoFs, a list out of cell order)."""
+    import torch
+    p = diff_problem((32, 8), 3)
+    m = p.levels[-1].mesh
+    refs, ptr, idx, w = gadj.nu_derivative_refs(m)
+    tw = gadj.time_weights(p.k, p.tau)
+    F0, in_cells, Fc = gadj.inflow_rhs_parts(m, p.k, p.tau)
+    rng = np.random.default_rng(44)
+    csd = m.cell_sdofs()
+    # the inflow cells and 40 more, in shuffled order, with random rows of f
+    extra = rng.choice(np.setdiff1d(np.arange(m.n_cells), in_cells), 40, replace=False)
+    cells = rng.permutation(np.concatenate([in_cells, extra])).astype(np.int32)
+    f = rng.standard_normal((len(cells), csd.shape[1], p.b))
+    s = stv.Solver(0)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    G = s.n_levels - 1
+    n = p.levels[-1].n_sdofs * p.b
+    lam, x = rng.standard_normal(n), rng.standard_normal(n)
+    U, coef = 1.7, rng.uniform(0.5, 2.0, len(cells))
+    # right-hand side: y = F0 + sum_k coef_k f_k
+    y = to_dev(F0)
+    s.cell_scatter(G, cells, coef, f.reshape(len(cells), -1), y)
+    ref = F0.copy()
+    for kk, c in enumerate(cells):
+        sd = csd[c].astype(np.int64)
+        for i in range(p.b):
+            ref[sd * p.b + i] += coef[kk] * f[kk, :, i]
+    e = np.abs(to_host(y) - ref).max() / np.abs(ref).max()
+    log(f"[grad] cell scatter: max rel err {e:.2e}")
+    assert e <= 1e-14
+    # gradient: -contraction + U * (lam . f) on the listed cells
+    out = torch.empty(m.n_cells, dtype=torch.float64, device="cuda:0")
+    s.cell_gradient(G, to_dev(lam), to_dev(x), refs, ptr, idx, w, tw, -1.0, cells,
+                    f.reshape(len(cells), -1), U, out)
+    g = -oadj.cell_contraction(lam, x, csd, p.b, refs, ptr, idx, w, tw)
+    g[cells] += U * oadj.cell_dot(lam, cells, csd, p.b, f)
+    e = np.abs(to_host(out) - g).max() / np.abs(g).max()
+    log(f"[grad] cell gradient: max rel err {e:.2e}")
+    assert e <= 1e-12
+    # a cell listed twice is rejected
+    with pytest.raises(stv.StvError, match="distinct"):
+        s.cell_gradient(G, to_dev(lam), to_dev(x), refs, ptr, idx, w, tw, -1.0,
+                        np.array([cells[0], cells[0]], np.int32), f[:2].reshape(2, -1), U, out)
