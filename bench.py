@@ -145,13 +145,18 @@ def sweep_bytes(L, b, inv_bytes, zero_init_fraction):
     return inv_bytes + idx + vec
 
 
-def residual_bytes(L, b, kron=False):
-    """Algorithmic bytes of one level residual: blocks (or the two spatial
-    factor values per block), columns, row pointers, x, r and y once each."""
+def residual_bytes(L, b, kron=False, n_mass=None):
+    """Algorithmic bytes of one level residual: blocks (or the spatial factor
+    values of each block: (m, a) where the mass entry m is nonzero, a alone
+    elsewhere; n_mass = number of blocks with m != 0), columns, row
+    pointers, x, r and y once each."""
     nnzb = int(L.col.shape[0])
     n_st = L.n_sdofs * b
-    per_block = 2 * 8 if kron else b * b * 8
-    return nnzb * (per_block + 4) + (L.n_sdofs + 1) * 4 + 3 * n_st * 8
+    vec = 3 * n_st * 8
+    if not kron:
+        return nnzb * (b * b * 8 + 4) + (L.n_sdofs + 1) * 4 + vec
+    n1 = nnzb if n_mass is None else int(n_mass)
+    return n1 * (16 + 4) + (nnzb - n1) * (8 + 4) + 2 * (L.n_sdofs + 1) * 4 + vec
 
 
 def cpu_baseline(workload, nu1, nu2, omega):
@@ -595,6 +600,7 @@ def run_workload(args, name, legs=True):
     G = s.n_levels
     members = packed_members(probs)
     kron = not args.no_kron
+    n_mass = {}
     if kron:
         from stgen import fe
         from stgen.problem import spatial_factors
@@ -605,6 +611,7 @@ def run_workload(args, name, legs=True):
             parts = [spatial_factors(L) for L, _ in members[g]]
             s.set_kron_factors(g, np.concatenate([m_ for m_, _ in parts]),
                                np.concatenate([a_ for _, a_ in parts]), np.asarray(C), tw)
+            n_mass[g] = [int(np.count_nonzero(m_)) for m_, _ in parts]
         print(f"[bench] spatial factors of every level in {time.time() - t0:.1f} s",
               file=sys.stderr, flush=True)
     rhs_h = np.concatenate([p.rhs for p in probs])
@@ -667,7 +674,11 @@ def run_workload(args, name, legs=True):
         return inv_b[g] + sum(sweep_bytes(L, b, 0, zi) for L, sm in members[g] if sm)
 
     def residual_bytes_packed(g):
-        return sum(residual_bytes(L, b, kron) for L, _ in members[g])
+        # the split lists (shapes 7..12) stream a alone where m = 0
+        split = kron and shapes is not None and shapes.get(str(g), [0])[0] >= 7
+        nm = n_mass.get(g) if split else None
+        nm = nm or [None] * len(members[g])
+        return sum(residual_bytes(L, b, kron, q) for (L, _), q in zip(members[g], nm))
 
     def roofline(cls, bytes_of, kernel, traffic_key):
         """The finest level's launches of the kernel in the timed region: the

@@ -378,8 +378,8 @@ int stv_level_info(stv_ctx* ctx, int level, int64_t* n_sdofs, int64_t* n_cells,
 /*   STV_OPT_INVERSE_CUS: while the coarse factorisation runs concurrently,
  *   the 3d complex cell-inverse kernel (one cell per compute unit) runs as at
  *   most this many resident workgroups striding over the cells, leaving the
- *   remaining compute units to the coarse chain; 0 (default) = no cap.  Same
- *   results. */
+ *   remaining compute units to the coarse chain; 0 (default) = no cap, -1 =
+ *   five eighths of the device's compute units.  Same results. */
 #define STV_OPT_INVERSE_CUS 4
 /*   STV_OPT_COARSE_LOOKAHEAD: 1 (default) = in the complex-pivot coarse
  *   chain the next slab's columns are updated first and the other columns on
@@ -403,9 +403,12 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
                          const double* C, const double* tw);
 
 /* Launch shapes of the level kernels of one level: spmv_rows = shape of the
- * residual (1..6, default 2): with the blocks, block rows per wavefront (5
- * and 6 act as 4); with spatial factors, (lanes per block row, blocks per
- * lane and round) = (4,4), (8,3), (8,4), (16,2), (16,4), (32,2); sweep_wgs = workgroups
+ * residual (1..12, default 2): with the blocks, block rows per wavefront (5
+ * to 12 act as 4); with spatial factors, (lanes per block row, blocks per
+ * lane and round) = (4,4), (8,3), (8,4), (16,2), (16,4), (32,2) over one
+ * list of (m, a) pairs per row (1..6), or the same six over two lists per
+ * row, the blocks with a mass entry as (m, a) pairs and the others as a
+ * alone (7..12: fewer bytes, more rounds); sweep_wgs = workgroups
  * of the Vanka sweep, 0 (default) for one wavefront per cell, otherwise a
  * persistent launch of that many workgroups whose wavefronts stride over the
  * cells.  The residual's summation order depends on spmv_rows (results

@@ -479,7 +479,8 @@ class Solver:
 
     def set_inverse_cus(self, n: int):
         """Compute units the 3d complex cell-inverse kernel may hold while the
-        coarse factorisation runs beside it (0: no cap)."""
+        coarse factorisation runs beside it (0: no cap, the default; -1: five
+        eighths of the device's)."""
         self._check(_lib.stv_set_option(self._h, 4, int(n)))
 
     def set_coarse_lookahead(self, on: bool):

@@ -1071,12 +1071,14 @@ hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp3
     // the complex decoupled build of a 3d dG(1) level: four wavefronts of
     // up to 512 registers per cell, one cell per compute unit at a time;
     // beside a concurrent coarse chain (n_cu > 0) a cap leaves the other
-    // compute units to the chain (the grid then strides over the cells)
+    // compute units to the chain (the grid then strides over the cells);
+    // cu_cap < 0: five eighths of the compute units
     if (b != 2 || L.n_ls != 85 || !L.kron_ma || L.split.nblk != 1 || L.split.sz[0] != 2)
       return hipErrorInvalidValue;
     (void)reserve;
     int grid = L.n_cells;
-    if (n_cu > 0 && cu_cap > 0) grid = std::min(grid, cu_cap);
+    const int cap = cu_cap < 0 ? (n_cu * 5) / 8 : cu_cap;
+    if (n_cu > 0 && cap > 0) grid = std::min(grid, cap);
     k_inverse_cx<85><<<grid, 256, 0, s>>>(L.posmap, L.kron_ma, L.own_ptr, L.own_loc, full,
                                                 L.inv_off, L.inv_ld, L.inv_store, fp32, status,
                                                 L.n_cells, L.split, L.dec && !full ? 1 : 0);

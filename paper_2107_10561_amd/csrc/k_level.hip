@@ -249,20 +249,27 @@ hipError_t launch_spmv(hipStream_t s, int b, const DevLevel& L, const double* r,
 
 // Level residual from the spatial factors of an operator whose blocks are
 // C[i][l] M + delta_il tw[i] A (time-independent coefficients): per block only
-// the two scalars m = M(s, s') and a = A(s, s') are streamed, as one 16-byte
-// pair.  LPR lanes per block row (64 / LPR rows per wavefront): lane `sub` of
-// a row takes the row's blocks sub, sub + LPR, ..., U of them per round, with
-// every load of a round issued before the first is used (indices clamped
-// into the row, the blocks past its end weighted by zero, instead of
-// branches), and keeps only the B partial sums of its own row; the row's
-// lanes then add their sums (butterfly over the LPR lanes).  LPR x U slots
-// per round are matched to the typical row length by the autotuner.
+// the two scalars m = M(s, s') and a = A(s, s') are streamed.  SPLIT: a row's
+// blocks come in two lists, those with m != 0 as one 16-byte (m, a) pair,
+// then those with m = 0 (the velocity-pressure couplings of a mass matrix
+// that acts on the velocity only) as a only, 8 bytes; otherwise one list of
+// (m, a) pairs in the level's block order.  LPR lanes per block row
+// (64 / LPR rows per wavefront): lane `sub` of a row takes the list's blocks
+// sub, sub + LPR, ..., U of them per round, with every load of a round issued
+// before the first is used (indices clamped into the list, the blocks past
+// its end weighted by zero, instead of branches), and keeps only the B
+// partial sums of its own row; the row's lanes then add their sums
+// (butterfly over the LPR lanes).  LPR x U slots per round are matched to
+// the typical row length by the autotuner.
 struct KronCoef { double C[16]; double tw[4]; };
 
-template <int B, int LPR, int U>
-__global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col,
+template <int B, int LPR, int U, bool SPLIT>
+__global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ rp1,
+                                                   const int32_t* __restrict__ col1,
                                                    const double2* __restrict__ ma,
+                                                   const int32_t* __restrict__ rp2,
+                                                   const int32_t* __restrict__ col2,
+                                                   const double* __restrict__ a2,
                                                    const double* __restrict__ r,
                                                    const double* __restrict__ x,
                                                    double* __restrict__ y, int32_t n_rows,
@@ -272,41 +279,72 @@ __global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ r
   const int row = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPWV + lane / LPR;
   const bool live = row < n_rows;
   const int rr = live ? row : n_rows - 1;
-  const int32_t q0 = rowptr[rr], q1 = rowptr[rr + 1];
   double rv = 0.0;
   if (r && live && sub < B) rv = r[(int64_t)rr * B + sub];
   double acc[B];
 #pragma unroll
   for (int i = 0; i < B; ++i) acc[i] = 0.0;
-  const int nit = (q1 - q0 + U * LPR - 1) / (U * LPR);
-  for (int it = 0; it < nit; ++it) {
-    const int32_t qb = q0 + it * U * LPR + sub;
-    int64_t c[U];
-    double m[U], a[U];
+  // blocks with a mass entry: (m, a)
+  {
+    const int32_t q0 = rp1[rr], q1 = rp1[rr + 1];
+    const int nit = (q1 - q0 + U * LPR - 1) / (U * LPR);
+    for (int it = 0; it < nit; ++it) {
+      const int32_t qb = q0 + it * U * LPR + sub;
+      int64_t c[U];
+      double m[U], a[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t q = qb + u * LPR;
-      const bool v = q < q1;
-      const int32_t qc = v ? q : q1 - 1;
-      c[u] = col[qc];
-      const double2 f = ma[qc];
-      m[u] = v ? f.x : 0.0;
-      a[u] = v ? f.y : 0.0;
-    }
-    double xl[U][B];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int l = 0; l < B; ++l) xl[u][l] = x[c[u] * B + l];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        double ci = 0.0;
-#pragma unroll
-        for (int l = 0; l < B; ++l) ci = fma(K.C[i * B + l], xl[u][l], ci);
-        acc[i] = fma(m[u], ci, fma(a[u] * K.tw[i], xl[u][i], acc[i]));
+      for (int u = 0; u < U; ++u) {
+        const int32_t q = qb + u * LPR;
+        const bool v = q < q1;
+        const int32_t qc = v ? q : q1 - 1;
+        c[u] = col1[qc];
+        const double2 f = ma[qc];
+        m[u] = v ? f.x : 0.0;
+        a[u] = v ? f.y : 0.0;
       }
+      double xl[U][B];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int l = 0; l < B; ++l) xl[u][l] = x[c[u] * B + l];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          double ci = 0.0;
+#pragma unroll
+          for (int l = 0; l < B; ++l) ci = fma(K.C[i * B + l], xl[u][l], ci);
+          acc[i] = fma(m[u], ci, fma(a[u] * K.tw[i], xl[u][i], acc[i]));
+        }
+    }
+  }
+  // blocks without one: a only
+  if constexpr (SPLIT) {
+    const int32_t q0 = rp2[rr], q1 = rp2[rr + 1];
+    const int nit = (q1 - q0 + U * LPR - 1) / (U * LPR);
+    for (int it = 0; it < nit; ++it) {
+      const int32_t qb = q0 + it * U * LPR + sub;
+      int64_t c[U];
+      double a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t q = qb + u * LPR;
+        const bool v = q < q1;
+        const int32_t qc = v ? q : q1 - 1;
+        c[u] = col2[qc];
+        const double f = a2[qc];
+        a[u] = v ? f : 0.0;
+      }
+      double xl[U][B];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int l = 0; l < B; ++l) xl[u][l] = x[c[u] * B + l];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < B; ++i) acc[i] = fma(a[u] * K.tw[i], xl[u][i], acc[i]);
+    }
   }
 #pragma unroll
   for (int off = LPR / 2; off >= 1; off >>= 1)
@@ -321,9 +359,10 @@ __global__ void __launch_bounds__(256) k_spmv_kron(const int32_t* __restrict__ r
 }
 
 // residual shapes from the factors: (lanes per block row, blocks per lane and round)
-static constexpr int kKronShapes = 6;
-static constexpr int kKronLpr[kKronShapes] = {4, 8, 8, 16, 16, 32};
-static constexpr int kKronU[kKronShapes] = {4, 3, 4, 2, 4, 2};
+// (shapes 7-12: the same on the split lists)
+static constexpr int kKronShapes = 12;
+static constexpr int kKronLpr[kKronShapes] = {4, 8, 8, 16, 16, 32, 4, 8, 8, 16, 16, 32};
+static constexpr int kKronU[kKronShapes] = {4, 3, 4, 2, 4, 2, 4, 3, 4, 2, 4, 2};
 
 int residual_shapes(const DevLevel& L) { return L.kron_ma ? kKronShapes : 4; }
 
@@ -337,15 +376,25 @@ static hipError_t spmv_kron_b(hipStream_t s, const DevLevel& L, const double* r,
   if (sh < 0 || sh >= kKronShapes) return hipErrorInvalidValue;
   const int lpr = kKronLpr[sh], rows_per_wg = 4 * (64 / lpr);
   dim3 grid((L.n_s + rows_per_wg - 1) / rows_per_wg), block(256);
-  const double2* ma = (const double2*)L.kron_ma;
-#define STV_KRON(S, LP, UU)                                                                  \
+  const bool split = sh >= kKronShapes / 2;
+  if (split && (!L.kx_ptr || !L.kx_col || !L.kx_val)) return hipErrorInvalidValue;
+  const int64_t n1 = L.kx_n1;
+  const int32_t* rp1 = split ? L.kx_ptr : L.rowptr;
+  const int32_t* c1 = split ? L.kx_col : L.col;
+  const double2* ma = (const double2*)(split ? L.kx_val : L.kron_ma);
+  const int32_t* rp2 = split ? L.kx_ptr + (L.n_s + 1) : nullptr;
+  const int32_t* c2 = split ? L.kx_col + n1 : nullptr;
+  const double* a2 = split ? L.kx_val + 2 * n1 : nullptr;
+#define STV_KRON(S, LP, UU, SP)                                                              \
   case S:                                                                                   \
-    launch(k_spmv_kron<B, LP, UU>, dim3(grid), dim3(block), 0, s, L.rowptr, L.col, ma, r, x, \
-           y, L.n_s, sx, K);                                                                \
+    launch(k_spmv_kron<B, LP, UU, SP>, dim3(grid), dim3(block), 0, s, rp1, c1, ma, rp2, c2, a2, \
+           r, x, y, L.n_s, sx, K);                                                          \
     break;
   switch (sh) {
-    STV_KRON(0, 4, 4) STV_KRON(1, 8, 3) STV_KRON(2, 8, 4)
-    STV_KRON(3, 16, 2) STV_KRON(4, 16, 4) STV_KRON(5, 32, 2)
+    STV_KRON(0, 4, 4, false) STV_KRON(1, 8, 3, false) STV_KRON(2, 8, 4, false)
+    STV_KRON(3, 16, 2, false) STV_KRON(4, 16, 4, false) STV_KRON(5, 32, 2, false)
+    STV_KRON(6, 4, 4, true) STV_KRON(7, 8, 3, true) STV_KRON(8, 8, 4, true)
+    STV_KRON(9, 16, 2, true) STV_KRON(10, 16, 4, true) STV_KRON(11, 32, 2, true)
     default: return hipErrorInvalidValue;
   }
 #undef STV_KRON

@@ -159,7 +159,7 @@ void free_level(DevLevel& L) {
   dfree(L.inv_off); dfree(L.inv_store); dfree(L.posmap); dfree(L.dec_tab); dfree(L.dec_code);
   dfree(L.rho); dfree(L.r); dfree(L.d); dfree(L.corr);
   dfree(L.rowptr_t); dfree(L.col_t); dfree(L.val_t);
-  dfree(L.kron_ma);
+  dfree(L.kron_ma); dfree(L.kx_ptr); dfree(L.kx_col); dfree(L.kx_val);
   L = DevLevel();
 }
 
@@ -2320,7 +2320,7 @@ int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info) {
 int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs) {
   STV_TRY(check_ctx(ctx, true, false));
   if (level < 0 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level out of range");
-  if (spmv_rows < 1 || spmv_rows > 6) return fail(ctx, STV_EINVAL, "spmv_rows must be in [1, 6]");
+  if (spmv_rows < 1 || spmv_rows > 12) return fail(ctx, STV_EINVAL, "spmv_rows must be in [1, 12]");
   if (sweep_wgs < 0) return fail(ctx, STV_EINVAL, "sweep_wgs must be >= 0");
   STV_HIP(hipStreamSynchronize(ctx->stream));
   ctx->lv[level].spmv_rpw = spmv_rows;
@@ -2416,7 +2416,8 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
   DevLevel& L = ctx->lv[level];
   if (!mval && !aval) {   // drop the factors: back to the stored blocks
     STV_HIP(hipStreamSynchronize(ctx->stream));
-    dfree(L.kron_ma);
+    dfree(L.kron_ma); dfree(L.kx_ptr); dfree(L.kx_col); dfree(L.kx_val);
+    L.kx_n1 = 0;
     ctx->cgroups_algo = -1;   // the coarse groups may refer to the factors
     ctx->inv_layout = -1;     // and the cell-inverse layout of the level
     ++ctx->generation;
@@ -2462,8 +2463,54 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
     return fail(ctx, STV_EINVAL, "the factors do not reproduce the level's blocks (max deviation " +
                                      std::to_string(dev) + " of " + std::to_string(mag) + ")");
   }
-  dfree(L.kron_ma);
+  // the residual's split lists: per row the blocks with m != 0, then the
+  // others (row order kept within each list)
+  const int64_t ns = L.n_s;
+  std::vector<int32_t> hrp((size_t)ns + 1), hcol((size_t)L.nnzb);
+  e = hipMemcpy(hrp.data(), L.rowptr, sizeof(int32_t) * hrp.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(hcol.data(), L.col, sizeof(int32_t) * hcol.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    drop();
+    return fail(ctx, STV_EHIP, std::string("reading the level pattern failed: ") + hipGetErrorString(e));
+  }
+  std::vector<int32_t> xptr((size_t)(2 * (ns + 1)), 0);
+  int64_t n1 = 0;
+  for (int64_t q = 0; q < L.nnzb; ++q) n1 += mval[q] != 0.0;
+  const int64_t n2 = L.nnzb - n1;
+  std::vector<int32_t> xcol((size_t)L.nnzb);
+  std::vector<double> xval((size_t)(2 * n1 + n2));
+  int64_t p1 = 0, p2 = 0;
+  for (int64_t i = 0; i < ns; ++i) {
+    xptr[(size_t)i] = (int32_t)p1;
+    xptr[(size_t)(ns + 1 + i)] = (int32_t)p2;
+    for (int32_t q = hrp[(size_t)i]; q < hrp[(size_t)i + 1]; ++q) {
+      if (mval[q] != 0.0) {
+        xcol[(size_t)p1] = hcol[(size_t)q];
+        xval[(size_t)(2 * p1)] = mval[q];
+        xval[(size_t)(2 * p1 + 1)] = aval[q];
+        ++p1;
+      } else {
+        xcol[(size_t)(n1 + p2)] = hcol[(size_t)q];
+        xval[(size_t)(2 * n1 + p2)] = aval[q];
+        ++p2;
+      }
+    }
+  }
+  xptr[(size_t)ns] = (int32_t)p1;
+  xptr[(size_t)(2 * ns + 1)] = (int32_t)p2;
+  int32_t *dxp = nullptr, *dxc = nullptr;
+  double* dxv = nullptr;
+  rc = upload(ctx, &dxp, xptr.data(), xptr.size());
+  if (rc == STV_OK) rc = upload(ctx, &dxc, xcol.data(), xcol.size());
+  if (rc == STV_OK) rc = upload(ctx, &dxv, xval.data(), xval.size());
+  if (rc != STV_OK) { drop(); dfree(dxp); dfree(dxc); dfree(dxv); return rc; }
+  dfree(L.kron_ma); dfree(L.kx_ptr); dfree(L.kx_col); dfree(L.kx_val);
   L.kron_ma = dma;
+  L.kx_ptr = dxp;
+  L.kx_col = dxc;
+  L.kx_val = dxv;
+  L.kx_n1 = n1;
   ctx->cgroups_algo = -1;   // the coarse groups are regrouped at the next build
   ctx->inv_layout = -1;     // the cell inverses may be stored time-decoupled
   for (int i = 0; i < 16; ++i) L.kron_C[i] = i < b * b ? C[i] : 0.0;
@@ -2493,7 +2540,7 @@ int stv_set_option(stv_ctx* ctx, int option, int64_t value) {
       ctx->coarse_lookahead = (int)value;
       return STV_OK;
     case STV_OPT_INVERSE_CUS:
-      if (value < 0 || value > 65536) return fail(ctx, STV_EINVAL, "compute-unit cap must be in [0, 65536]");
+      if (value < -1 || value > 65536) return fail(ctx, STV_EINVAL, "compute-unit cap must be in [-1, 65536]");
       ctx->inverse_cus = (int)value;
       return STV_OK;
     default:

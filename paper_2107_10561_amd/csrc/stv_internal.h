@@ -83,6 +83,14 @@ struct DevLevel {
   int32_t* rowptr_t = nullptr; int32_t* col_t = nullptr; double* val_t = nullptr;
   // spatial factors (optional): blocks = C[i][l] M + delta_il tw[i] A
   double* kron_ma = nullptr;      // spatial factors (m, a), interleaved per block
+  // the factors split per row for the residual: the blocks with m != 0 as
+  // (m, a) pairs, then those with m = 0 as a only; kx_ptr holds both row
+  // pointer arrays (n_s + 1 each), kx_col the two column lists (kx_n1 + the
+  // rest), kx_val the 2 kx_n1 pair values followed by the a-only values
+  int32_t* kx_ptr = nullptr;
+  int32_t* kx_col = nullptr;
+  double* kx_val = nullptr;
+  int64_t kx_n1 = 0;
   int dec = 0;                    // the inverse store holds time-decoupled rows (CellSplit)
   int cx = 0;                     // inverses built from the complex decoupled block (plain store)
   CellSplit split{};
@@ -93,7 +101,7 @@ struct DevLevel {
   double* dec_tab = nullptr;
   int32_t* dec_code = nullptr;
   double kron_C[16] = {}, kron_tw[4] = {};
-  int spmv_rpw = 2;               // residual shape: 1..4 (blocks), 1..6 (factors)
+  int spmv_rpw = 2;               // residual shape: 1..4 (blocks), 1..12 (factors)
   int sweep_wgs = 0;              // workgroups of a persistent sweep (0: one wavefront per cell)
 };
 
@@ -254,7 +262,7 @@ struct stv_ctx {
   int n_report = 0;
   int coarse_algo = 0;          // STV_OPT_COARSE_ALGO
   int coarse_overlap = 1;       // STV_OPT_COARSE_OVERLAP
-  int inverse_cus = 0;          // STV_OPT_INVERSE_CUS
+  int inverse_cus = 0;          // STV_OPT_INVERSE_CUS (0: no cap)
   int coarse_lookahead = 1;     // STV_OPT_COARSE_LOOKAHEAD
   int64_t scal_segs = 0;        // instances the scalar buffers are sized for
   // V-cycle replayed from a captured HIP graph (STV_OPT_GRAPH): the graph

@@ -64,7 +64,7 @@ def test_autotuned_solver_matches_oracle(stv, name):
     log(f"[autotune] {name}: {choice}")
     for g in range(1, len(ol)):
         rows, wgs = choice[g]
-        assert 1 <= rows <= 6 and wgs >= 0
+        assert 1 <= rows <= 12 and wgs >= 0
     rng = np.random.default_rng(6)
     r = rng.standard_normal(ol[-1].n_st)
     d = to_dev(np.zeros(ol[-1].n_st))
@@ -81,6 +81,6 @@ def test_autotuned_solver_matches_oracle(stv, name):
 
 def test_set_launch_rejects_bad_shapes(stv):
     s, p, ol = solver(stv, "c1_2d_dg1")
-    for args in ((1, 0, 0), (1, 7, 0), (1, 2, -1), (9, 2, 0)):
+    for args in ((1, 0, 0), (1, 13, 0), (1, 2, -1), (9, 2, 0)):
         with pytest.raises(stv.StvError):
             s.set_launch(*args)

@@ -45,7 +45,7 @@ def test_kron_residual_vcycle_gmres(stv, name):
     G = len(ol) - 1
     rng = np.random.default_rng(12)
     r, d = rng.standard_normal(ol[G].n_st), rng.standard_normal(ol[G].n_st)
-    for rows in (1, 2, 3, 4, 5, 6):   # (lanes per row, blocks per lane) shapes
+    for rows in range(1, 13):   # (lanes per row, blocks per lane) shapes, one or two lists
         s.set_launch(G, rows, 0)
         out = to_dev(np.zeros(ol[G].n_st))
         s.residual(G, to_dev(r), to_dev(d), out)
