@@ -777,15 +777,19 @@ k_vanka_dec(const double* __restrict__ rho,
 // and with u = (I (x) W) rho_T (u_0 + i u_1 per spatial DoF c)
 //   y_a = sum_c Y_ac (u_0c + i u_1c),  c_(a, i) = V_i0 Re y_a + V_i1 Im y_a:
 // the same J_T^-1 rho_T = (I (x) V) Q^-1 (I (x) W) rho_T as the two plain rows
-// of a, from half the stored values.  One wavefront per cell: lane c (and
-// c + 64) holds u_c, from one 16-byte load of the time-inner pair rho_(c, 0..1);
-// each stored row is two coalesced reads; G rows at a time give 2G sums
-// (real and imaginary parts) folded by one transpose-reduce.  Output
+// of a, from half the stored values.  One wavefront per cell.  A stored row
+// is read as one flat run of 2 NLS values, NF = 2 NLS / 64 (rounded up)
+// coalesced loads: value v = 64 k + lane is Re Y_ac (v < NLS, c = v) or
+// Im Y_ac (c = v - NLS), and the lane holds, per load, the two multipliers
+// that put it into Re y_a and Im y_a (u_0c and u_1c for a real part, -u_1c
+// and u_0c for an imaginary one), formed once per cell from its own
+// 16-byte load of the time-inner pair rho_(c, 0..1).  G rows at a time give
+// 2G sums (real and imaginary parts) folded by one transpose-reduce.  Output
 // r = 2 os + i of the os-th owned DoF lands in lane r % 64, which fetched the
 // DoF's old value at the start; stores as in k_vanka.  The complex products
 // and the transpose-reduce are in the precision of the store, the
 // recombination with V and the update in FP64.
-template <int NLS, typename TS>
+template <int NLS, typename TS, int G>
 __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho,
                                                  double* __restrict__ d,
                                                  const int32_t* __restrict__ csd,
@@ -795,13 +799,20 @@ __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho
                                                  const TS* __restrict__ store, double omega,
                                                  int zero_init, int n_cells, CellSplit sp) {
   constexpr int B = 2;
-  constexpr int NCC = (NLS + 63) / 64;       // 64-lane chunks of the complex columns
+  constexpr int NF = (2 * NLS + 63) / 64;    // flat 64-lane loads of a stored row
   constexpr int NOC = (NLS + 63) / 64;       // 64-lane chunks of the owned DoFs
   constexpr int RC = (B * NLS + 63) / 64;    // 64-lane chunks of the outputs
-  constexpr int G = 8;                       // stored rows per transpose-reduce
   const int lane = threadIdx.x & 63;
   const double w00 = sp.W[0], w01 = sp.W[1], w10 = sp.W[2], w11 = sp.W[3];
   const double v00 = sp.V[0], v01 = sp.V[1], v10 = sp.V[2], v11 = sp.V[3];
+  // byte offsets of the lane's values in a stored row
+  unsigned vb[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int v = 64 * k + lane;
+    vb[k] = (unsigned)((v < 2 * NLS ? v : 2 * NLS - 1) * sizeof(TS));
+  }
+  const unsigned rb = (unsigned)(ld * sizeof(TS));
   const int T0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   for (int T = T0; T < n_cells; T += gridDim.x * 4) {
     const int32_t* sd = csd + (int64_t)T * NLS;
@@ -809,22 +820,19 @@ __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho
     const int no = own_ptr[T + 1] - o0;
     if (no <= 0) continue;
     const int R = no * B;
-    const TS* A = store + inv_off[T];
-    double ur[NCC], ui[NCC];
+    const char* A = reinterpret_cast<const char*>(store + inv_off[T]);
+    // the multipliers of the lane's values: (into Re y, into Im y)
+    TS mre[NF], mim[NF];
 #pragma unroll
-    for (int cc = 0; cc < NCC; ++cc) {
-      const int c = lane + 64 * cc;
-      const int cl = c < NLS ? c : NLS - 1;
-      const double2 rr = *reinterpret_cast<const double2*>(&rho[(int64_t)sd[cl] * B]);
-      ur[cc] = c < NLS ? fma(w00, rr.x, w01 * rr.y) : 0.0;
-      ui[cc] = c < NLS ? fma(w10, rr.x, w11 * rr.y) : 0.0;
-    }
-    // the row products in the precision of the store (see k_vanka_dec)
-    TS urs[NCC], uis[NCC];
-#pragma unroll
-    for (int cc = 0; cc < NCC; ++cc) {
-      urs[cc] = (TS)ur[cc];
-      uis[cc] = (TS)ui[cc];
+    for (int k = 0; k < NF; ++k) {
+      const int v = 64 * k + lane;
+      const bool ok = v < 2 * NLS;
+      const bool im = v >= NLS;
+      const int c = ok ? (im ? v - NLS : v) : 0;
+      const double2 rr = *reinterpret_cast<const double2*>(&rho[(int64_t)sd[c] * B]);
+      const double u0 = fma(w00, rr.x, w01 * rr.y), u1 = fma(w10, rr.x, w11 * rr.y);
+      mre[k] = (TS)(ok ? (im ? -u1 : u0) : 0.0);
+      mim[k] = (TS)(ok ? (im ? u0 : u1) : 0.0);
     }
     int gs[NOC];
 #pragma unroll
@@ -849,40 +857,33 @@ __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho
       res[rc] = 0.0;
     }
     for (int k0 = 0; k0 < no; k0 += G) {
-      TS ar[G][NCC], ai[G][NCC];
+      TS a[G][NF];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
-        const int row = min(k0 + t, no - 1);
-        const unsigned ro = (unsigned)(row * ld);
+        const unsigned ro = (unsigned)min(k0 + t, no - 1) * rb;
 #pragma unroll
-        for (int cc = 0; cc < NCC; ++cc) {
-          const int c = lane + 64 * cc;
-          const unsigned cl = (unsigned)(c < NLS ? c : NLS - 1);
-          ar[t][cc] = A[ro + cl];
-          ai[t][cc] = A[ro + NLS + cl];
-        }
+        for (int k = 0; k < NF; ++k) a[t][k] = *reinterpret_cast<const TS*>(A + (ro + vb[k]));
       }
       TS p[2 * G];
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         TS re = TS(0), im = TS(0);
 #pragma unroll
-        for (int cc = 0; cc < NCC; ++cc) {
-          const TS yr = ar[t][cc], yi = ai[t][cc];
-          re = fma(yr, urs[cc], fma(-yi, uis[cc], re));
-          im = fma(yr, uis[cc], fma(yi, urs[cc], im));
+        for (int k = 0; k < NF; ++k) {
+          re = fma(a[t][k], mre[k], re);
+          im = fma(a[t][k], mim[k], im);
         }
         p[2 * t] = re;
         p[2 * t + 1] = im;
       }
-      const TS sum = fold_swap<2 * G>(p, lane);   // value e in lanes 4e .. 4e + 3
+      const TS sum = fold_swap<2 * G>(p, lane);   // value e in lanes e (64 / 2G) ..
 #pragma unroll
       for (int rc = 0; rc < RC; ++rc) {
         const int r = lane + 64 * rc;
         const int t = (r >> 1) - k0;
         const int tc = t < 0 ? 0 : (t >= G ? G - 1 : t);
-        const double re = (double)__shfl(sum, 4 * (2 * tc), 64);
-        const double im = (double)__shfl(sum, 4 * (2 * tc + 1), 64);
+        const double re = (double)__shfl(sum, (64 / (2 * G)) * (2 * tc), 64);
+        const double im = (double)__shfl(sum, (64 / (2 * G)) * (2 * tc + 1), 64);
         const double val = (r & 1) ? fma(v10, re, v11 * im) : fma(v00, re, v01 * im);
         if (t >= 0 && t < G) res[rc] = val;
       }
@@ -894,6 +895,12 @@ __global__ void __launch_bounds__(256) k_vanka_cx(const double* __restrict__ rho
     }
   }
 }
+
+// rows per transpose-reduce of the complex sweep: 8 in FP64 (115 registers,
+// four wavefronts per SIMD), 16 in FP32 (twice the rows in flight in about
+// the same registers)
+template <typename TS>
+constexpr int cx_group() { return sizeof(TS) == 4 ? 16 : 8; }
 
 template <int B, int NLS>
 static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, double* d,
@@ -918,13 +925,13 @@ static hipError_t vanka_bn(hipStream_t s, const DevLevel& L, const double* rho, 
     if (L.dec && L.cx) {
       if (full) return hipErrorInvalidValue;
       if (fp32)
-        launch(k_vanka_cx<NLS, float>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
-               L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const float*)L.inv_store, omega,
-               zero_init, L.n_cells, L.split);
+        launch(k_vanka_cx<NLS, float, cx_group<float>()>, dim3(grid), dim3(256), 0, s, rho, d,
+               L.cell_sdofs, L.own_ptr, L.own_loc, L.inv_off, L.inv_ld,
+               (const float*)L.inv_store, omega, zero_init, L.n_cells, L.split);
       else
-        launch(k_vanka_cx<NLS, double>, dim3(grid), dim3(256), 0, s, rho, d, L.cell_sdofs,
-               L.own_ptr, L.own_loc, L.inv_off, L.inv_ld, (const double*)L.inv_store, omega,
-               zero_init, L.n_cells, L.split);
+        launch(k_vanka_cx<NLS, double, cx_group<double>()>, dim3(grid), dim3(256), 0, s, rho, d,
+               L.cell_sdofs, L.own_ptr, L.own_loc, L.inv_off, L.inv_ld,
+               (const double*)L.inv_store, omega, zero_init, L.n_cells, L.split);
       return hipGetLastError();
     }
   }
