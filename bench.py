@@ -36,6 +36,7 @@ SECONDARY_WORKLOAD = "2d-512x128-dG2"
 TRAFFIC_RECORDS = {
     "2d-512x128-dG2": os.path.join(ROOT, "profiles", "traffic_2d512x128_dG2.json"),
     "3d-128x24x24-dG1": os.path.join(ROOT, "profiles", "traffic_3d128x24x24_dG1.json"),
+    "batched-256-2d-dG1": os.path.join(ROOT, "profiles", "traffic_batched256_2d_dG1.json"),
 }
 
 
@@ -155,7 +156,9 @@ def residual_bytes(L, b, kron=False, n_mass=None):
     vec = 3 * n_st * 8
     if not kron:
         return nnzb * (b * b * 8 + 4) + (L.n_sdofs + 1) * 4 + vec
-    n1 = nnzb if n_mass is None else int(n_mass)
+    if n_mass is None:     # one list of (m, a) pairs
+        return nnzb * (16 + 4) + (L.n_sdofs + 1) * 4 + vec
+    n1 = int(n_mass)
     return n1 * (16 + 4) + (nnzb - n1) * (8 + 4) + 2 * (L.n_sdofs + 1) * 4 + vec
 
 
@@ -725,8 +728,12 @@ def run_workload(args, name, legs=True):
                               "k_vanka_cx")
     else:
         roof_sweep = roofline("sweep", sweep_bytes_packed, "Vanka cell sweep (k_vanka)", "k_vanka")
+    split_top = kron and shapes is not None and shapes.get(str(top), [0])[0] >= 7
+    if split_top:
+        kname_res = "level residual from spatial factors, split lists (k_spmv_kron)"
     roof_res = roofline("residual", residual_bytes_packed, kname_res,
-                        "k_spmv_kron" if kron else "k_spmv")
+                        ("k_spmv_kron_split" if split_top else "k_spmv_kron") if kron
+                        else "k_spmv")
     # time per kernel class (and both kernels over every level) from one more
     # step with every class and level timed, outside the timed region: the
     # event records around the classes that are not stamped by their launch
