@@ -647,11 +647,11 @@ __global__ void __launch_bounds__(256) k_vanka(const double* __restrict__ rho,
 // is of the order of the rounding of the stored values themselves.  Stores
 // as in k_vanka.
 // Occupancy the register allocation must leave room for (waves per SIMD):
-// the sweep hides its load latency with waves, and the FP32 form, with half
-// the registers for its values, fits 7 (B = 3) or 8 waves without spills.
+// the sweep hides its load latency with waves; without spills the FP32 form
+// fits 8, the FP64 form 6 (B = 1, 3) or 5 (B = 2).
 template <int B, typename TS>
 constexpr int dec_waves() {
-  return sizeof(TS) == 4 ? (B == 3 ? 7 : 8) : 5;
+  return sizeof(TS) == 4 ? 8 : (B == 2 ? 5 : 6);
 }
 
 template <int B, int NLS, typename TS>
@@ -680,7 +680,7 @@ k_vanka_dec(const double* __restrict__ rho,
   const int al = jl / B, cl = jl - al * B;   // spatial DoF and time component of lane j
   // per-lane constants of the level: W[cl][.], V[lane % B][.], the source
   // lanes of u and the multipliers of stored column j = lane
-  double wl[B], vl[B], ca[B], cb[B];
+  double wl[B], vl[B];
 #pragma unroll
   for (int l = 0; l < B; ++l) {
     wl[l] = tab[l * 64 + lane];
@@ -688,8 +688,13 @@ k_vanka_dec(const double* __restrict__ rho,
   }
   const int cd = code[lane];
   const int srca = cd & 63, srcb = (cd >> 6) & 63;
+  // the multipliers 0, +1 or -1 of the two sources (2 bits each in the code
+  // word): kept as constants for B <= 2, decoded per cell for B = 3, where
+  // the registers they would hold cost a wavefront per SIMD
+  constexpr bool DECODE = B == 3;
+  double ca[DECODE ? 1 : B], cb[DECODE ? 1 : B];
 #pragma unroll
-  for (int o = 0; o < B; ++o) {
+  for (int o = 0; o < (DECODE ? 1 : B); ++o) {
     const int ea = (cd >> (12 + 2 * o)) & 3, eb = (cd >> (12 + 2 * B + 2 * o)) & 3;
     ca[o] = ea == 1 ? 1.0 : (ea == 3 ? -1.0 : 0.0);
     cb[o] = eb == 1 ? 1.0 : (eb == 3 ? -1.0 : 0.0);
@@ -729,7 +734,16 @@ k_vanka_dec(const double* __restrict__ rho,
     const double ua = __shfl(u, srca, 64), ub = __shfl(u, srcb, 64);
     TS m[B];
 #pragma unroll
-    for (int o = 0; o < B; ++o) m[o] = (TS)fma(ca[o], ua, cb[o] * ub);
+    for (int o = 0; o < B; ++o) {
+      if constexpr (DECODE) {
+        const int ea = (cd >> (12 + 2 * o)) & 3, eb = (cd >> (12 + 2 * B + 2 * o)) & 3;
+        const double ta = ea == 1 ? ua : (ea == 3 ? -ua : 0.0);
+        const double tb = eb == 1 ? ub : (eb == 3 ? -ub : 0.0);
+        m[o] = (TS)(ta + tb);
+      } else {
+        m[o] = (TS)fma(ca[o], ua, cb[o] * ub);
+      }
+    }
     // the owned DoF of each stored row (lane = owned index; its spatial
     // index from the lanes of its local DoF), the row this lane stores
     // (r = lane = k * B + i), its global index and old value
