@@ -95,6 +95,9 @@ def parse():
     ap.add_argument("--coarse-lookahead", type=int, default=1, choices=[0, 1],
                     help="look-ahead updates in the complex-pivot coarse chain (1) or not (0)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--shapes", default=None,
+                    help='launch shapes instead of the autotuner\'s, as JSON {"level": [residual '
+                         'shape, sweep workgroups], ...} (levels not named keep the defaults)')
     ap.add_argument("--no-kron", action="store_true",
                     help="residual from the stored blocks instead of the spatial factors")
     ap.add_argument("--no-graph-leg", action="store_true")
@@ -633,7 +636,12 @@ def run_workload(args, name, legs=True):
             (args.nu1 + args.nu2)
 
     shapes = None
-    if not args.no_autotune:
+    if args.shapes:
+        shapes = {str(g): list(v) for g, v in json.loads(args.shapes).items()}
+        for g, (rows, wgs) in shapes.items():
+            s.set_launch(int(g), int(rows), int(wgs))
+        print(f"[bench] launch shapes set: {shapes}", file=sys.stderr, flush=True)
+    elif not args.no_autotune:
         s.build_cell_inverses(fp32=primary_fp32)
         t0 = time.time()
         shapes = {str(g): list(v) for g, v in s.autotune().items() if g > 0}
