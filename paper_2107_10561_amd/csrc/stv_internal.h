@@ -17,6 +17,7 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxB = 4;             // k <= 3
 constexpr int kMaxRestart = 256;
 constexpr int kDotBlocks = 1024;     // partial sums per Krylov reduction
+constexpr int kKrylovFuse = 8;       // basis vectors of a fused Gram-Schmidt update + products
 
 enum KernelClass {
   KC_SWEEP = 0, KC_RESIDUAL, KC_TRANSFER, KC_COARSE, KC_KRYLOV, KC_INVERSE, KC_COARSE_FACTOR,
@@ -391,6 +392,12 @@ struct Segs { const int64_t* seg; int nseg; int64_t max_seg; };
 int seg_blocks(const Segs& g);   // partial-sum blocks per segment
 hipError_t launch_multidot(hipStream_t s, const double* V, int m, const double* w, int64_t n,
                            const Segs& g, double* partial, double* out, int64_t ostride);
+hipError_t launch_multiaxpy_dot(hipStream_t s, const double* V, int m, const double* coef,
+                                int64_t cstride, double sign, double* w, int64_t n,
+                                const Segs& g, double* partial, double* out, int64_t ostride);
+hipError_t launch_multiaxpy_nrm(hipStream_t s, const double* V, int m, const double* coef,
+                                int64_t cstride, double sign, double* w, int64_t n,
+                                const Segs& g, double* partial, double* out, int64_t ostride);
 hipError_t launch_multiaxpy(hipStream_t s, const double* V, int m, const double* coef,
                             int64_t cstride, double sign, double* w, int64_t n, const Segs& g);
 hipError_t launch_scale_by_norm(hipStream_t s, const double* w, const double* nrm2,
