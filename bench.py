@@ -97,7 +97,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--shapes", default=None,
                     help='launch shapes instead of the autotuner\'s, as JSON {"level": [residual '
-                         'shape, sweep workgroups], ...} (levels not named keep the defaults)')
+                         'shape, sweep workgroups(, transfer shapes of P and P^T)], ...} (levels '
+                         'not named keep the defaults)')
     ap.add_argument("--no-kron", action="store_true",
                     help="residual from the stored blocks instead of the spatial factors")
     ap.add_argument("--no-graph-leg", action="store_true")
@@ -638,13 +639,17 @@ def run_workload(args, name, legs=True):
     shapes = None
     if args.shapes:
         shapes = {str(g): list(v) for g, v in json.loads(args.shapes).items()}
-        for g, (rows, wgs) in shapes.items():
-            s.set_launch(int(g), int(rows), int(wgs))
+        for g, v in shapes.items():
+            s.set_launch(int(g), int(v[0]), int(v[1]))
+            if len(v) >= 4:
+                s.transfer_shapes(int(g), int(v[2]), int(v[3]))
         print(f"[bench] launch shapes set: {shapes}", file=sys.stderr, flush=True)
     elif not args.no_autotune:
         s.build_cell_inverses(fp32=primary_fp32)
         t0 = time.time()
-        shapes = {str(g): list(v) for g, v in s.autotune().items() if g > 0}
+        # per level: residual shape, sweep workgroups, transfer shapes (P, P^T)
+        shapes = {str(g): list(v) + list(s.transfer_shapes(g))
+                  for g, v in s.autotune().items() if g > 0}
         print(f"[bench] autotuned launch shapes in {time.time() - t0:.2f} s: {shapes}",
               file=sys.stderr, flush=True)
     for i in range(args.warmup):

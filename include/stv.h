@@ -416,11 +416,26 @@ int stv_set_kron_factors(stv_ctx* ctx, int level, const double* mval, const doub
  * Errors: STV_ESTATE (no hierarchy), STV_EINVAL. */
 int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs);
 
+/* Launch shapes of the transfers between `level` >= 1 and level-1: shape t
+ * in 1..5 takes 2^(t-1) lanes per row (1, 2, 4, 8, 16), p_shape for the
+ * prolongation P (rows of `level`), pt_shape for the restriction by its
+ * transpose (rows of level-1); 0 keeps the current shape.  cur_p and cur_pt,
+ * when non-NULL, receive the shapes in force afterwards.  The summation order
+ * of a row depends on its shape (results agree to rounding).  Errors:
+ * STV_ESTATE (no hierarchy), STV_EINVAL. */
+int stv_transfer_shapes(stv_ctx* ctx, int level, int p_shape, int pt_shape, int* cur_p,
+                        int* cur_pt);
+
 /* Autotuner: on every smoothed level, time each residual shape (1..4 with
- * the blocks, 1..6 with spatial factors) and
+ * the blocks, 1..12 with spatial factors) and
  * each sweep shape (one wavefront per cell, or persistent
  * grids of 2, 4, 8, 16, 32 workgroups per compute unit) on the device, five
- * launches each after one untimed launch, and keep the fastest.  Needs the
+ * launches each after one untimed launch, and keep the fastest.  The same
+ * for the transfers of every level with a prolongation: 1, 2, 4, 8 or 16
+ * lanes per row, for P and for its transpose separately (without the
+ * autotuner, the lanes follow the mean row length: 1 below 3 entries, then
+ * 2, 4, 8, 16 below 6, 12, 24 and above; the transfers' summation order
+ * depends on the lanes, results agree to rounding).  Needs the
  * inverses (the sweep is timed with the stored ones); uses temporary device
  * vectors; the hierarchy's data are not modified.  If choices is non-NULL
  * it receives, for level g < cap/2, choices[2g] = residual shape and

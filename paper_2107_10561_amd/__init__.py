@@ -101,6 +101,7 @@ def _load():
         "stv_dot": (I, [P, P, P, P]),
         "stv_set_kron_factors": (I, [P, I, P, P, P, P]),
         "stv_autotune": (I, [P, ctypes.POINTER(I), I]),
+        "stv_transfer_shapes": (I, [P, I, I, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "stv_kernel_stats": (I, [P, I, I, I64P, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
@@ -119,7 +120,7 @@ EXPORTED = ("stv_create", "stv_destroy", "stv_last_error", "stv_validate_hierarc
             "stv_instance_info", "stv_set_launch", "stv_autotune", "stv_vcycle_transposed",
             "stv_gmres_solve_transposed", "stv_cell_contract", "stv_cell_dot", "stv_dot",
             "stv_set_kron_factors", "stv_set_timing_filter", "stv_vcycle_noalloc",
-            "stv_cell_gradient", "stv_cell_scatter")
+            "stv_cell_gradient", "stv_cell_scatter", "stv_transfer_shapes")
 
 COARSE_ALGOS = {"auto": 0, "panels": 1, "slabs": 2, "tournament": 3}
 
@@ -464,6 +465,14 @@ class Solver:
     def set_launch(self, level: int, spmv_rows: int, sweep_wgs: int):
         """Launch shapes of one level's residual and sweep kernels."""
         self._check(_lib.stv_set_launch(self._h, level, spmv_rows, sweep_wgs))
+
+    def transfer_shapes(self, level: int, p_shape: int = 0, pt_shape: int = 0):
+        """Set (when > 0) and return the transfer shapes (P, P^T) between
+        `level` and level-1: shape t takes 2^(t-1) lanes per row."""
+        cp, ct = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(_lib.stv_transfer_shapes(self._h, level, p_shape, pt_shape,
+                                             ctypes.byref(cp), ctypes.byref(ct)))
+        return cp.value, ct.value
 
     def autotune(self):
         """Time the launch shapes on the device and keep the fastest; returns

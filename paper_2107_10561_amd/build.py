@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(LIBDIR, "libstv.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["stv_api.cpp", "k_level.hip", "k_inverse.hip", "k_dense.hip", "k_krylov.hip"]
+SOURCES = ["stv_api.cpp", "k_level.hip", "k_inverse.hip", "k_dense.hip", "k_krylov.hip", "k_transfer.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -1371,77 +1371,6 @@ hipError_t launch_vanka_combine(hipStream_t s, int b, const DevLevel& L, double*
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Transfers: y (+)= (P (x) I_B) x for a spatial CSR matrix P (identity in
-// time).  Restriction uses the stored transpose of P, so both directions are
-// gathers (no atomics).  One thread per spatial row and all B time levels: the
-// row's column indices and values are read once for the B levels (four
-// entries at a time, every load in flight), the B entries of x at a column
-// are adjacent, and the row's B outputs are stored together; per level the
-// entries are summed in row order.
-template <int B>
-__global__ void __launch_bounds__(256) k_csr_rows(const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ col,
-                                                  const double* __restrict__ val,
-                                                  const double* __restrict__ x,
-                                                  double* __restrict__ y, int32_t n_rows,
-                                                  int accumulate) {
-  constexpr int U = 4;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n_rows) return;
-  const int32_t e0 = rp[row], e1 = rp[row + 1];
-  double acc[B];
-#pragma unroll
-  for (int l = 0; l < B; ++l) acc[l] = 0.0;
-  for (int32_t e = e0; e < e1; e += U) {
-    int64_t c[U];
-    double v[U], xv[U][B];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool ok = e + u < e1;
-      const int32_t ec = ok ? e + u : e1 - 1;
-      c[u] = col[ec];
-      const double w = val[ec];
-      v[u] = ok ? w : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int l = 0; l < B; ++l) xv[u][l] = x[c[u] * B + l];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int l = 0; l < B; ++l) acc[l] = fma(v[u], xv[u][l], acc[l]);
-  }
-  double* yr = y + row * B;
-#pragma unroll
-  for (int l = 0; l < B; ++l) yr[l] = accumulate ? yr[l] + acc[l] : acc[l];
-}
-
-static hipError_t csr_time(hipStream_t s, int b, const int32_t* rp, const int32_t* col,
-                           const double* val, const double* x, double* y, int32_t n_rows,
-                           int acc) {
-  dim3 grid((unsigned)(((int64_t)n_rows + 255) / 256)), block(256);
-  switch (b) {
-    case 1: launch(k_csr_rows<1>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
-    case 2: launch(k_csr_rows<2>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
-    case 3: launch(k_csr_rows<3>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
-    case 4: launch(k_csr_rows<4>, dim3(grid), dim3(block), 0, s, rp, col, val, x, y, n_rows, acc); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_restrict(hipStream_t s, int b, const DevLevel& L, const double* rho,
-                           double* r_c) {
-  return csr_time(s, b, L.Pt_rowptr, L.Pt_col, L.Pt_val, rho, r_c, L.n_s_coarse, 0);
-}
-
-hipError_t launch_prolongate_add(hipStream_t s, int b, const DevLevel& L, const double* d_c,
-                                 double* d) {
-  return csr_time(s, b, L.P_rowptr, L.P_col, L.P_val, d_c, d, L.n_s, 1);
-}
-
 __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;

@@ -839,6 +839,8 @@ int setup_packed(stv_ctx* ctx, int n_inst, int dim, int k, const int* nlev,
       STV_TRY(upload(ctx, &L.Pt_rowptr, tp.data(), tp.size()));
       STV_TRY(upload(ctx, &L.Pt_col, tc.data(), tc.size()));
       STV_TRY(upload(ctx, &L.Pt_val, tv.data(), tv.size()));
+      L.p_shape = transfer_shape_for(pnz, ns);
+      L.pt_shape = transfer_shape_for(pnz, nc);
     }
     // the members solved directly on this level
     for (int i = 0; i < n_inst; ++i) {
@@ -2347,6 +2349,25 @@ int stv_set_launch(stv_ctx* ctx, int level, int spmv_rows, int sweep_wgs) {
   return STV_OK;
 }
 
+int stv_transfer_shapes(stv_ctx* ctx, int level, int p_shape, int pt_shape, int* cur_p,
+                        int* cur_pt) {
+  STV_TRY(check_ctx(ctx, true, false));
+  if (level < 1 || level >= ctx->n_levels) return fail(ctx, STV_EINVAL, "level out of range");
+  if (p_shape < 0 || p_shape > kTransferShapes || pt_shape < 0 || pt_shape > kTransferShapes)
+    return fail(ctx, STV_EINVAL, "transfer shapes must be in [0, 5]");
+  DevLevel& L = ctx->lv[level];
+  if (p_shape > 0 || pt_shape > 0) {
+    STV_HIP(hipStreamSynchronize(ctx->stream));
+    if (p_shape > 0) L.p_shape = p_shape;
+    if (pt_shape > 0) L.pt_shape = pt_shape;
+    ++ctx->generation;   // a captured V-cycle holds the old launch shapes
+    free_graph(ctx);
+  }
+  if (cur_p) *cur_p = L.p_shape;
+  if (cur_pt) *cur_pt = L.pt_shape;
+  return STV_OK;
+}
+
 int stv_autotune(stv_ctx* ctx, int* choices, int cap) {
   STV_TRY(check_ctx(ctx, true, true));
   const int b = ctx->b;
@@ -2409,6 +2430,25 @@ int stv_autotune(stv_ctx* ctx, int* choices, int cap) {
       if (ms < best) { best = ms; best_w = cand[c]; }
     }
     L.sweep_wgs = best_w;
+  }
+  // transfer shapes of every level with a prolongation, each direction alone
+  for (int g = 1; g < ctx->n_levels && e == hipSuccess; ++g) {
+    DevLevel& L = ctx->lv[g];
+    if (!L.P_rowptr) continue;
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+      int& shape = dir ? L.pt_shape : L.p_shape;
+      int best_t = shape;
+      double best = 1e30;
+      for (int t = 1; t <= kTransferShapes && e == hipSuccess; ++t) {
+        shape = t;
+        double ms = 0;
+        e = time_it([&]() {
+          return dir ? launch_restrict(s, b, L, x, y) : launch_prolongate_add(s, b, L, x, y);
+        }, ms);
+        if (ms < best) { best = ms; best_t = t; }
+      }
+      shape = best_t;
+    }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

@@ -62,6 +62,9 @@ struct DevLevel {
   int32_t* P_rowptr = nullptr; int32_t* P_col = nullptr; double* P_val = nullptr;
   int32_t* Pt_rowptr = nullptr; int32_t* Pt_col = nullptr; double* Pt_val = nullptr;
   int32_t n_s_coarse = 0;
+  // transfer shapes (1..kTransferShapes: 2^(shape-1) lanes per row) of P and
+  // of its transpose
+  int p_shape = 1, pt_shape = 1;
   // block position of each cell DoF pair (levels >= 1), n_cells * n_ls^2
   int32_t* posmap = nullptr;
   // stored inverses (levels >= 1)
@@ -342,6 +345,10 @@ hipError_t launch_vanka_combine(hipStream_t s, int b, const DevLevel& L, double*
 hipError_t launch_cell_inverses(hipStream_t s, int b, const DevLevel& L, int fp32, int full,
                                 uint8_t* status, double* gscratch, int n_slots, int n_cu,
                                 int reserve, int cu_cap = 0);
+// transfers: shapes 1..kTransferShapes take 1, 2, 4, 8, 16 lanes per row;
+// transfer_shape_for picks one from the mean row length
+constexpr int kTransferShapes = 5;
+int transfer_shape_for(int64_t nnz, int64_t n_rows);
 hipError_t launch_restrict(hipStream_t s, int b, const DevLevel& L, const double* rho,
                            double* r_c);
 hipError_t launch_prolongate_add(hipStream_t s, int b, const DevLevel& L, const double* d_c,

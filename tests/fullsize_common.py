@@ -33,6 +33,37 @@ def bench_solver(p, fp32=False):
     return s, stv
 
 
+def check_transfers(p, s, rng, shapes=(0,)):
+    """Restriction and prolongation between every pair of levels, whole
+    vectors, against P^T rho and d + P d_c formed by scipy from the level's own
+    CSR prolongation (I_B in time); shape 0 keeps the shapes in force (the
+    autotuned ones), 1..5 force 1..16 lanes per row.  Returns the worst
+    relative error."""
+    import scipy.sparse as sp
+    b = p.b
+    worst = 0.0
+    for g in range(1, len(p.levels)):
+        L, Lc = p.levels[g], p.levels[g - 1]
+        rp, col, val = L.P
+        P = sp.csr_matrix((val, col, rp), shape=(L.n_sdofs, Lc.n_sdofs))
+        kept = s.transfer_shapes(g)
+        for t in shapes:
+            s.transfer_shapes(g, t, t)
+            rho = rng.standard_normal((L.n_sdofs, b))
+            rc = to_dev(np.zeros(Lc.n_sdofs * b))
+            s.restrict(g, to_dev(rho.ravel()), rc)
+            ref = (P.T @ rho).ravel()
+            worst = max(worst, np.abs(to_host(rc) - ref).max() / np.abs(ref).max())
+            dc = rng.standard_normal((Lc.n_sdofs, b))
+            d = rng.standard_normal((L.n_sdofs, b))
+            dd = to_dev(d.ravel())
+            s.prolongate_add(g, to_dev(dc.ravel()), dd)
+            ref = (d + P @ dc).ravel()
+            worst = max(worst, np.abs(to_host(dd) - ref).max() / np.abs(ref).max())
+        s.transfer_shapes(g, *kept)
+    return worst
+
+
 def sample_cells(n_cells, rng, extra=()):
     base = [0, n_cells - 1] + [c for c in extra if c < n_cells]
     pick = rng.choice(n_cells, min(n_cells, 20), replace=False)

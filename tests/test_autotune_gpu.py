@@ -65,6 +65,8 @@ def test_autotuned_solver_matches_oracle(stv, name):
     for g in range(1, len(ol)):
         rows, wgs = choice[g]
         assert 1 <= rows <= 12 and wgs >= 0
+        tp, tpt = s.transfer_shapes(g)
+        assert 1 <= tp <= 5 and 1 <= tpt <= 5
     rng = np.random.default_rng(6)
     r = rng.standard_normal(ol[-1].n_st)
     d = to_dev(np.zeros(ol[-1].n_st))
@@ -84,3 +86,12 @@ def test_set_launch_rejects_bad_shapes(stv):
     for args in ((1, 0, 0), (1, 13, 0), (1, 2, -1), (9, 2, 0)):
         with pytest.raises(stv.StvError):
             s.set_launch(*args)
+
+
+def test_transfer_shapes_reject_bad_arguments(stv):
+    s, p, ol = solver(stv, "c1_2d_dg1")
+    for args in ((0, 1, 1), (9, 1, 1), (1, 6, 0), (1, 0, -1)):
+        with pytest.raises(stv.StvError):
+            s.transfer_shapes(*args)
+    assert s.transfer_shapes(1, 3, 4) == (3, 4)
+    assert s.transfer_shapes(1) == (3, 4)

@@ -2,10 +2,13 @@
 Q2/P1disc x dG(1) (170 local DoFs per cell), 4 levels, set up exactly as
 bench.py times it (spatial factors on every level, autotuned shapes).
 
-Kernels reached: k_spmv_kron (residual from the factors), the 170x170 cell
-inverses (k_inverse_mfma<2, 85>, owned rows, FP64 and FP32 store), the sweep
-k_vanka<2, 85> (FP64 and FP32), the coarse inverse of order 10,854 assembled
-from the complex-pair block eliminated with complex pivots, and FGMRES.
+Kernels reached: k_spmv_kron (residual from the factors, split lists), the
+cell inverses through the complex time-decoupled block (k_inverse_cx<85>,
+owned complex rows, FP64 and FP32 store), the sweep on that store
+(k_vanka_cx, FP64 and FP32), the transfers (k_csr_lanes, autotuned and every
+shape), the coarse inverse of order 10,854 assembled from the complex-pair
+block eliminated with complex pivots (k_gj_tour_cx, k_gj_slab_update_cx128),
+and FGMRES.
 Sampled outputs are compared with the oracle computed one cell at a time, the
 coarse solve with a sparse direct solve, FGMRES with a host residual.
 """
@@ -13,7 +16,7 @@ import numpy as np
 import pytest
 
 from fullsize_common import (bench_solver, check_coarse, check_gmres, check_inverse_rows,
-                             check_residual_rows, check_sweep)
+                             check_residual_rows, check_sweep, check_transfers)
 from gpu_common import log
 from stgen.problem import make_problem
 
@@ -36,6 +39,13 @@ def test_3d_residual_from_factors(bench3d):
     for g in (len(p.levels) - 1, 1):
         e = check_residual_rows(p, s, g, rng)
         log(f"[3d-fullsize] residual level {g}: max rel err {e:.2e}")
+
+
+def test_3d_transfers_every_shape(bench3d):
+    p, s = bench3d
+    worst = check_transfers(p, s, np.random.default_rng(46), shapes=(0, 1, 2, 3, 4, 5))
+    log(f"[3d-fullsize] transfers: worst rel err {worst:.2e}")
+    assert worst <= 1e-13
 
 
 @pytest.mark.parametrize("fp32", [False, True])

@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 
 from fullsize_common import (bench_solver, check_coarse, check_gmres, check_inverse_rows,
-                             check_residual_rows, check_sweep)
+                             check_residual_rows, check_sweep, check_transfers)
 from gpu_common import log
 from stgen.problem import make_problem
 
@@ -44,6 +44,15 @@ def test_2d_residual_from_factors(bench2d):
     for g in (len(p.levels) - 1, 2, 1):
         e = check_residual_rows(p, s, g, rng)
         log(f"[bench-path] 2d residual level {g}: max rel err {e:.2e}")
+
+
+def test_2d_transfers_every_shape(bench2d):
+    """k_csr_lanes on every level pair, both directions: the autotuned shapes
+    (0) and each of 1, 2, 4, 8, 16 lanes per row, whole vectors."""
+    p, s = bench2d
+    worst = check_transfers(p, s, np.random.default_rng(36), shapes=(0, 1, 2, 3, 4, 5))
+    log(f"[bench-path] 2d transfers: worst rel err {worst:.2e}")
+    assert worst <= 1e-13
 
 
 def test_2d_decoupled_inverses_every_stride(bench2d):

@@ -134,17 +134,23 @@ def test_transfers_and_coarse(stv, name):
     s = solver(stv, name)
     rng = np.random.default_rng(5)
     G = len(ol) - 1
-    rho = rng.standard_normal(ol[G].n_st)
-    rc = to_dev(np.zeros(ol[G - 1].n_st))
-    s.restrict(G, to_dev(rho), rc)
-    ref = ol[G].P.T @ rho
-    assert np.abs(to_host(rc) - ref).max() <= 1e-13 * np.abs(ref).max()
-    dc = rng.standard_normal(ol[G - 1].n_st)
-    d = rng.standard_normal(ol[G].n_st)
-    dd = to_dev(d)
-    s.prolongate_add(G, to_dev(dc), dd)
-    ref = d + ol[G].P @ dc
-    assert np.abs(to_host(dd) - ref).max() <= 1e-13 * np.abs(ref).max()
+    # every level pair, the default shape (0) and each of 1..16 lanes per row
+    for g in range(G, 0, -1):
+        kept = s.transfer_shapes(g)
+        for t in (0, 1, 2, 3, 4, 5):
+            s.transfer_shapes(g, t, t)
+            rho = rng.standard_normal(ol[g].n_st)
+            rc = to_dev(np.zeros(ol[g - 1].n_st))
+            s.restrict(g, to_dev(rho), rc)
+            ref = ol[g].P.T @ rho
+            assert np.abs(to_host(rc) - ref).max() <= 1e-13 * np.abs(ref).max(), (g, t)
+            dc = rng.standard_normal(ol[g - 1].n_st)
+            d = rng.standard_normal(ol[g].n_st)
+            dd = to_dev(d)
+            s.prolongate_add(g, to_dev(dc), dd)
+            ref = d + ol[g].P @ dc
+            assert np.abs(to_host(dd) - ref).max() <= 1e-13 * np.abs(ref).max(), (g, t)
+        s.transfer_shapes(g, *kept)
     r0 = rng.standard_normal(ol[0].n_st)
     x0 = to_dev(np.zeros(ol[0].n_st))
     s.coarse_solve(to_dev(r0), x0)
