@@ -1510,53 +1510,159 @@ hipError_t launch_kron_block_dense(hipStream_t s, const KronBlockDesc* kdesc, in
   return hipGetLastError();
 }
 
-// Member z's inverse from its blocks' inverses (rec[z]); thread (s', s)
-// forms the b x b entries of spatial pair (s, s').
+// d = J^-1 r for time-decoupled coarse members (kc[z]) from their blocks'
+// inverses, without forming J^-1: with z(s', q) = sum_l W[q][l] r(s', l),
+//   y_p(s, a) = sum_{s', c < sz_p} Binv_p[2s + a, 2s' + c] z(s', f_p + c),
+//   d(s, i)   = sum_p sum_{a < sz_p} V[i][f_p + a] y_p(s, a).
+// The block of a complex pair is the real form of a complex matrix, every
+// 2 x 2 block [[x, -y], [y, x]] (exactly so: the elimination keeps the
+// structure), so its even row 2s holds the whole row: with
+// (e0, e1) = Binv_p[2s, 2s' .. 2s' + 1],
+//   y(s, 0) += e0 z0 + e1 z1,  y(s, 1) += e0 z1 - e1 z0.
+// The block of a real eigenvalue holds two uncoupled copies; its even rows
+// and columns are read.  So the complex inverse is read once (half the
+// bytes of the real form of order b n_s).  One workgroup per spatial row s:
+// thread t takes the columns s' = t, t + 256, ..., z is formed from r on the
+// way (r stays in the caches), the partial sums meet in LDS and the first b
+// threads form d(s, .).
 template <int B>
-__global__ void __launch_bounds__(256) k_kron_recombine(const KronRecomb* __restrict__ rec,
-                                                        double* __restrict__ out) {
-  const KronRecomb* R = rec + blockIdx.z;
-  const int32_t n_s = R->n_s;
-  const int32_t sp = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-  const int32_t s = (int32_t)blockIdx.y;
-  if (s >= n_s || sp >= n_s) return;
-  double acc[B][B];
+__global__ void __launch_bounds__(256) k_kron_coarse_gemv(const KronCoarse* __restrict__ kc,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ d) {
+  const KronCoarse* K = kc + blockIdx.z;
+  const int32_t n_s = K->n_s;
+  const int32_t s = blockIdx.x;
+  if (s >= n_s) return;
+  const int nblk = K->nblk;
+  const double* rz = r + (int64_t)K->row_off * B;
+  const int64_t ord = 2 * (int64_t)n_s;
+  double acc[B][2];
 #pragma unroll
-  for (int i = 0; i < B; ++i)
+  for (int p = 0; p < B; ++p) acc[p][0] = acc[p][1] = 0.0;
+  for (int32_t sp = threadIdx.x; sp < n_s; sp += 256) {
+    double rv[B];
 #pragma unroll
-    for (int l = 0; l < B; ++l) acc[i][l] = 0.0;
-  for (int p = 0; p < R->nblk; ++p) {
-    const int sz = R->sz[p], f = R->first[p];
-    const int64_t ord = 2 * (int64_t)n_s;
-    const double* bi = R->binv[p];
-    for (int a = 0; a < sz; ++a)
-      for (int c = 0; c < sz; ++c) {
-        const double v = bi[(2 * (int64_t)s + a) * ord + 2 * (int64_t)sp + c];
+    for (int l = 0; l < B; ++l) rv[l] = rz[(int64_t)sp * B + l];
 #pragma unroll
-        for (int i = 0; i < B; ++i) {
-          const double vi = R->V[i * B + f + a] * v;
+    for (int p = 0; p < B; ++p) {
+      if (p >= nblk) break;
+      const int f = K->first[p];
+      const double* row = K->binv[p] + 2 * (int64_t)s * ord + 2 * (int64_t)sp;
+      double z0 = 0.0;
 #pragma unroll
-          for (int l = 0; l < B; ++l) acc[i][l] = fma(vi, R->W[(f + c) * B + l], acc[i][l]);
-        }
+      for (int l = 0; l < B; ++l) z0 = fma(K->W[f * B + l], rv[l], z0);
+      if (K->sz[p] == 2) {
+        double z1 = 0.0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) z1 = fma(K->W[(f + 1) * B + l], rv[l], z1);
+        const double2 e = *reinterpret_cast<const double2*>(row);
+        acc[p][0] = fma(e.x, z0, fma(e.y, z1, acc[p][0]));
+        acc[p][1] = fma(e.x, z1, fma(-e.y, z0, acc[p][1]));
+      } else {
+        acc[p][0] = fma(row[0], z0, acc[p][0]);
       }
+    }
   }
-  const int64_t n0 = (int64_t)n_s * B;
+  __shared__ double red[4][B][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < B; ++i)
+  for (int p = 0; p < B; ++p)
 #pragma unroll
-    for (int l = 0; l < B; ++l)
-      out[R->inv_off + ((int64_t)s * B + i) * n0 + (int64_t)sp * B + l] = acc[i][l];
+    for (int a = 0; a < 2; ++a) {
+      double v = acc[p][a];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) red[wv][p][a] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x < B) {
+    const int i = threadIdx.x;
+    double out = 0.0;
+    for (int p = 0; p < nblk; ++p) {
+      const int f = K->first[p];
+      for (int a = 0; a < K->sz[p]; ++a) {
+        const double y = (red[0][p][a] + red[1][p][a]) + (red[2][p][a] + red[3][p][a]);
+        out = fma(K->V[i * B + f + a], y, out);
+      }
+    }
+    d[((int64_t)K->row_off + s) * B + i] = out;
+  }
 }
 
-hipError_t launch_kron_recombine(hipStream_t s, int b, const KronRecomb* rec, int cnt,
-                                 int32_t max_ns, double* out) {
-  dim3 grid((unsigned)((max_ns + 255) / 256), (unsigned)max_ns, (unsigned)cnt);
+// d = J^-T r for the same members (the direct solve of the transposed coarse
+// matrix): with u(s, q) = sum_i V[i][q] r(s, i),
+//   w_p(s', c) = sum_{s, a < sz_p} Binv_p[2s + a, 2s' + c] u(s, f_p + a),
+//   d(s', l)   = sum_p sum_{c < sz_p} W[f_p + c][l] w_p(s', c);
+// for a pair, from the even rows, w(s', 0) += e0 u0 - e1 u1 and
+// w(s', 1) += e1 u0 + e0 u1.  Thread per spatial column s' (coalesced over
+// the columns of each even row), the rows in order.
+template <int B>
+__global__ void __launch_bounds__(256) k_kron_coarse_gemv_t(const KronCoarse* __restrict__ kc,
+                                                           const double* __restrict__ r,
+                                                           double* __restrict__ d) {
+  const KronCoarse* K = kc + blockIdx.z;
+  const int32_t n_s = K->n_s;
+  const int32_t sp = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (sp >= n_s) return;
+  const int nblk = K->nblk;
+  const double* rz = r + (int64_t)K->row_off * B;
+  const int64_t ord = 2 * (int64_t)n_s;
+  double w[B][2];
+#pragma unroll
+  for (int p = 0; p < B; ++p) w[p][0] = w[p][1] = 0.0;
+  for (int32_t s = 0; s < n_s; ++s) {
+    double rv[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) rv[i] = rz[(int64_t)s * B + i];
+#pragma unroll
+    for (int p = 0; p < B; ++p) {
+      if (p >= nblk) break;
+      const int f = K->first[p];
+      const double* row = K->binv[p] + 2 * (int64_t)s * ord + 2 * (int64_t)sp;
+      double u0 = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) u0 = fma(K->V[i * B + f], rv[i], u0);
+      if (K->sz[p] == 2) {
+        double u1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < B; ++i) u1 = fma(K->V[i * B + f + 1], rv[i], u1);
+        const double2 e = *reinterpret_cast<const double2*>(row);
+        w[p][0] = fma(e.x, u0, fma(-e.y, u1, w[p][0]));
+        w[p][1] = fma(e.y, u0, fma(e.x, u1, w[p][1]));
+      } else {
+        w[p][0] = fma(row[0], u0, w[p][0]);
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < B; ++l) {
+    double out = 0.0;
+#pragma unroll
+    for (int p = 0; p < B; ++p) {
+      if (p >= nblk) break;
+      const int f = K->first[p];
+      out = fma(K->W[f * B + l], w[p][0], out);
+      if (K->sz[p] == 2) out = fma(K->W[(f + 1) * B + l], w[p][1], out);
+    }
+    d[((int64_t)K->row_off + sp) * B + l] = out;
+  }
+}
+
+hipError_t launch_kron_coarse_apply(hipStream_t s, int b, const KronCoarse* kc, int cnt,
+                                    int32_t max_ns, int transposed, const double* r, double* d) {
+  if (cnt < 1 || max_ns < 1) return hipSuccess;
+  const dim3 grid = transposed ? dim3((unsigned)((max_ns + 255) / 256), 1, (unsigned)cnt)
+                               : dim3((unsigned)max_ns, 1, (unsigned)cnt);
+#define STV_KCA(BB)                                                                  \
+  (transposed ? launch(k_kron_coarse_gemv_t<BB>, grid, dim3(256), 0, s, kc, r, d)    \
+              : launch(k_kron_coarse_gemv<BB>, grid, dim3(256), 0, s, kc, r, d))
   switch (b) {
-    case 2: k_kron_recombine<2><<<grid, 256, 0, s>>>(rec, out); break;
-    case 3: k_kron_recombine<3><<<grid, 256, 0, s>>>(rec, out); break;
-    case 4: k_kron_recombine<4><<<grid, 256, 0, s>>>(rec, out); break;
+    case 2: STV_KCA(2); break;
+    case 3: STV_KCA(3); break;
+    case 4: STV_KCA(4); break;
     default: return hipErrorInvalidValue;
   }
+#undef STV_KCA
   return hipGetLastError();
 }
 

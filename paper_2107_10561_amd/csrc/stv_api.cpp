@@ -120,8 +120,11 @@ void free_coarse_groups(stv_ctx* ctx) {
     dfree(G.d_kdesc); dfree(G.binv);
   }
   ctx->cgroups.clear();
-  ctx->h_krec.clear();
-  dfree(ctx->d_krec);
+  for (int g = 0; g < kMaxLevels; ++g) {
+    ctx->h_kc[g].clear();
+    dfree(ctx->d_kc[g]);
+    ctx->kc_max_ns[g] = 0;
+  }
   ctx->cgroups_algo = -1;
   dfree(ctx->coarse_inv);
   ctx->coarse_elems = 0;
@@ -175,6 +178,7 @@ void free_hierarchy(stv_ctx* ctx) {
     free_level(ctx->lv[g]);
     dfree(ctx->d_coarse[g]);
     ctx->h_coarse[g].clear();
+    ctx->n_whole[g] = 0;
     ctx->coarse_max_n0[g] = 0;
   }
   free_workspace(ctx);
@@ -423,17 +427,22 @@ int sweeps(stv_ctx* ctx, int g, const double* r, double* d, int n, double omega,
   return STV_OK;
 }
 
-// d = J_c^-1 r on the rows of every coarse member stored on level g.
+// d = J_c^-1 r on the rows of every coarse member stored on level g: the
+// members with a whole stored inverse by a dense product, the time-decoupled
+// ones from their blocks' inverses.
 int coarse_apply(stv_ctx* ctx, int g, const double* r, double* d) {
-  const int cnt = (int)ctx->h_coarse[g].size();
-  if (cnt == 0) return STV_OK;
+  const int nw = ctx->n_whole[g], nk = (int)ctx->h_kc[g].size();
+  if (nw == 0 && nk == 0) return STV_OK;
   Timed t(ctx, KC_COARSE, g, nullptr, true);
-  if (ctx->transposed)
-    STV_HIP(launch_dense_gemv_t(ctx->stream, ctx->d_coarse[g], cnt, ctx->b, ctx->coarse_max_n0[g],
+  if (nw > 0 && ctx->transposed)
+    STV_HIP(launch_dense_gemv_t(ctx->stream, ctx->d_coarse[g], nw, ctx->b, ctx->coarse_max_n0[g],
                                 ctx->coarse_inv, r, d));
-  else
-    STV_HIP(launch_dense_gemv(ctx->stream, ctx->d_coarse[g], cnt, ctx->b, ctx->coarse_max_n0[g],
+  else if (nw > 0)
+    STV_HIP(launch_dense_gemv(ctx->stream, ctx->d_coarse[g], nw, ctx->b, ctx->coarse_max_n0[g],
                               ctx->coarse_inv, r, d));
+  if (nk > 0)
+    STV_HIP(launch_kron_coarse_apply(ctx->stream, ctx->b, ctx->d_kc[g], nk, ctx->kc_max_ns[g],
+                                     ctx->transposed ? 1 : 0, r, d));
   t.done();
   return STV_OK;
 }
@@ -1185,12 +1194,15 @@ static bool time_split(const double* C, const double* tw, int b, TimeSplit& out)
 // inverted block by block: every block is built in real form of order 2 n_s
 // (a pair is the real form of a complex matrix, a real eigenvalue two
 // uncoupled copies), the blocks join one group per order, eliminated with
-// complex pivots by the tournament, and the member's inverse is recombined
-// from theirs.
+// complex pivots by the tournament, and the member is applied from their
+// inverses (KronCoarse) instead of a whole stored inverse.
 static int make_coarse_groups(stv_ctx* ctx) {
   const int b = ctx->b;
   std::vector<CoarseGroup>& groups = ctx->cgroups;
-  ctx->h_krec.clear();
+  for (int g = 0; g < kMaxLevels; ++g) ctx->h_kc[g].clear();
+  // (level, index in h_kc[level]) of each time-decoupled member, in the
+  // order of mblocks below
+  std::vector<std::pair<int, size_t>> kref;
   // split of each level's time matrix (levels with spatial factors)
   std::vector<TimeSplit> split((size_t)ctx->n_levels);
   std::vector<bool> has_split((size_t)ctx->n_levels, false);
@@ -1216,19 +1228,20 @@ static int make_coarse_groups(stv_ctx* ctx) {
     for (size_t q = 0; q < ctx->h_coarse[g].size(); ++q) {
       CoarseDesc& c = ctx->h_coarse[g][q];
       const int64_t n0 = (int64_t)c.n_s * b;
-      c.inv_off = coarse_total;
-      coarse_total += n0 * n0;
       if (!has_split[(size_t)g]) {
+        c.inv_off = coarse_total;
+        coarse_total += n0 * n0;
         CoarseGroup& G = group_of(n0, false);
         G.lev.push_back(g);
         G.idx.push_back((int)q);
         continue;
       }
+      c.inv_off = -1;                // no whole inverse
       const TimeSplit& S = split[(size_t)g];
-      KronRecomb R{};
+      KronCoarse R{};
       R.nblk = S.nblk;
       R.n_s = c.n_s;
-      R.inv_off = c.inv_off;
+      R.row_off = c.row_off;
       for (int e = 0; e < 16; ++e) { R.V[e] = S.V[e]; R.W[e] = S.W[e]; }
       std::vector<BlockRef> refs;
       for (int p = 0; p < S.nblk; ++p) {
@@ -1241,10 +1254,11 @@ static int make_coarse_groups(stv_ctx* ctx) {
         refs.push_back({(size_t)(&G - groups.data()), G.lev.size() - 1});
       }
       mblocks.push_back(refs);
-      ctx->h_krec.push_back(R);
+      kref.emplace_back(g, ctx->h_kc[g].size());
+      ctx->h_kc[g].push_back(R);
     }
   ctx->coarse_elems = coarse_total;
-  STV_TRY(dalloc(ctx, &ctx->coarse_inv, (size_t)coarse_total));
+  if (coarse_total > 0) STV_TRY(dalloc(ctx, &ctx->coarse_inv, (size_t)coarse_total));
   // per group: plan, descriptors, buffers
   std::vector<std::vector<int64_t>> boff(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -1321,24 +1335,32 @@ static int make_coarse_groups(stv_ctx* ctx) {
       STV_TRY(dalloc(ctx, &w.counter, (size_t)(cnt * w.sK)));
     }
   }
-  // recombination descriptors: the device addresses of every block inverse
-  for (size_t k = 0; k < ctx->h_krec.size(); ++k) {
-    KronRecomb& R = ctx->h_krec[k];
+  // time-decoupled members: the device addresses of their block inverses
+  for (size_t k = 0; k < kref.size(); ++k) {
+    KronCoarse& R = ctx->h_kc[kref[k].first][kref[k].second];
     for (int p = 0; p < R.nblk; ++p) {
       const BlockRef& br = mblocks[k][(size_t)p];
       R.binv[p] = groups[br.gi].binv + boff[br.gi][br.slot];
     }
   }
-  if (!ctx->h_krec.empty()) {
-    dfree(ctx->d_krec);
-    STV_TRY(upload(ctx, &ctx->d_krec, ctx->h_krec.data(), ctx->h_krec.size()));
-  }
-  ctx->krec_b = b;
-  // device descriptors of the members per level (inverse offsets now known)
+  // device descriptors per level: the members with a whole inverse (offsets
+  // now known) and the time-decoupled ones
   for (int g = 0; g < ctx->n_levels; ++g) {
     dfree(ctx->d_coarse[g]);
-    if (!ctx->h_coarse[g].empty())
-      STV_TRY(upload(ctx, &ctx->d_coarse[g], ctx->h_coarse[g].data(), ctx->h_coarse[g].size()));
+    dfree(ctx->d_kc[g]);
+    std::vector<CoarseDesc> whole;
+    ctx->coarse_max_n0[g] = 0;
+    for (const CoarseDesc& c : ctx->h_coarse[g])
+      if (c.inv_off >= 0) {
+        whole.push_back(c);
+        ctx->coarse_max_n0[g] = std::max<int64_t>(ctx->coarse_max_n0[g], (int64_t)c.n_s * b);
+      }
+    ctx->n_whole[g] = (int)whole.size();
+    if (!whole.empty()) STV_TRY(upload(ctx, &ctx->d_coarse[g], whole.data(), whole.size()));
+    ctx->kc_max_ns[g] = 0;
+    for (const KronCoarse& R : ctx->h_kc[g]) ctx->kc_max_ns[g] = std::max(ctx->kc_max_ns[g], R.n_s);
+    if (!ctx->h_kc[g].empty())
+      STV_TRY(upload(ctx, &ctx->d_kc[g], ctx->h_kc[g].data(), ctx->h_kc[g].size()));
   }
   return STV_OK;
 }
@@ -1600,14 +1622,6 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
                               gb, G.n0, G.kron ? G.binv : ctx->coarse_inv);
     t.done();
     mbase += cnt;
-  }
-  if (e == hipSuccess && !ctx->h_krec.empty()) {
-    Timed t(ctx, KC_COARSE_FACTOR, 0, side);
-    int32_t max_ns = 0;
-    for (const auto& R : ctx->h_krec) max_ns = std::max(max_ns, R.n_s);
-    e = launch_kron_recombine(side, b, ctx->d_krec, (int)ctx->h_krec.size(), max_ns,
-                              ctx->coarse_inv);
-    t.done();
   }
   if (side == s) {
     cell_inverses();

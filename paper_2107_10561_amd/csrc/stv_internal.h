@@ -160,16 +160,16 @@ struct KronBlockDesc {
   double t[4];
 };
 
-// Recombination of a member's inverse from its blocks' inverses:
-//   J^-1[(s, i), (s', l)] = sum_p sum_{a, c in block p} V[i][a] Binv_p[2s + a, 2s' + c] W[c][l]
-// (Binv_p of order 2 n_s; time-inner rows s * b + i of the member's n0 x n0
-// inverse at inv_off).
-struct KronRecomb {
+// A coarse member inverted through time decoupling: its inverse is
+//   J^-1[(s, i), (s', l)] = sum_p sum_{a, c < sz_p} V[i][f_p + a] Binv_p[2s + a, 2s' + c] W[f_p + c][l]
+// (Binv_p of order 2 n_s in real form; f_p = first[p]; time-inner rows
+// s * b + i), applied from the blocks without being formed.  The member's
+// rows start at spatial row row_off of its packed level.
+struct KronCoarse {
   const double* binv[4];
   int nblk;
   int sz[4], first[4];
-  int32_t n_s;
-  int64_t inv_off;
+  int32_t n_s, row_off;
   double V[16], W[16];
 };
 
@@ -239,11 +239,14 @@ struct stv_ctx {
   int64_t* seg_off = nullptr;         // device: first vector element per instance (+ total)
   int64_t max_seg = 0;                // longest instance vector on the finest level
   std::vector<stv::InstInfo> inst_info;
-  // dense coarse members, per packed level (host and device descriptors)
+  // dense coarse members, per packed level: host descriptors of all of
+  // them; device descriptors (and the largest order) of those whose inverse
+  // is stored whole in coarse_inv
   std::vector<stv::CoarseDesc> h_coarse[stv::kMaxLevels];
   stv::CoarseDesc* d_coarse[stv::kMaxLevels] = {};
+  int n_whole[stv::kMaxLevels] = {};
   int64_t coarse_max_n0[stv::kMaxLevels] = {};
-  double* coarse_inv = nullptr;       // every member's inverse
+  double* coarse_inv = nullptr;       // the whole inverses
   int64_t coarse_elems = 0;
   // inverse-build workspace, kept between builds of one hierarchy: the
   // store layout it was made for (full rows or owned rows, element type),
@@ -256,11 +259,12 @@ struct stv_ctx {
   int inv_slots[stv::kMaxLevels] = {};
   std::vector<stv::CoarseGroup> cgroups;
   int cgroups_algo = -1;
-  // coarse members inverted through time decoupling, recombined after the
-  // block eliminations (device descriptors, one per member)
-  std::vector<stv::KronRecomb> h_krec;
-  stv::KronRecomb* d_krec = nullptr;
-  int krec_b = 0;
+  // coarse members inverted through time decoupling, per packed level:
+  // applied from their blocks' inverses (device descriptors, one per member,
+  // and the largest spatial order)
+  std::vector<stv::KronCoarse> h_kc[stv::kMaxLevels];
+  stv::KronCoarse* d_kc[stv::kMaxLevels] = {};
+  int32_t kc_max_ns[stv::kMaxLevels] = {};
   int* inv_report = nullptr;
   int* h_report = nullptr;
   int n_report = 0;
@@ -374,9 +378,10 @@ hipError_t launch_set_diag(hipStream_t s, const CoarseDesc* desc, int cnt, int b
 // dense blocks of time-decoupled coarse members (member z: kdesc[z])
 hipError_t launch_kron_block_dense(hipStream_t s, const KronBlockDesc* kdesc, int cnt,
                                    int32_t max_rows, double* A, int64_t sA, int64_t n);
-// every member's inverse from its blocks' inverses
-hipError_t launch_kron_recombine(hipStream_t s, int b, const KronRecomb* rec, int cnt,
-                                 int32_t max_ns, double* out);
+// d = J^-1 r (transposed: d = J^-T r) on the rows of time-decoupled
+// coarse members, from their blocks' inverses
+hipError_t launch_kron_coarse_apply(hipStream_t s, int b, const KronCoarse* kc, int cnt,
+                                    int32_t max_ns, int transposed, const double* r, double* d);
 // rinv = the inverse of every member's pivot record rpiv (order n, real
 // order n0 from desc); verdict[z] = 0 when member z's record is a
 // permutation whose real columns pivot on real rows, else 1.

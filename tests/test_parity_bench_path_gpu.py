@@ -11,8 +11,8 @@ shapes before it times anything.  That routes the path through
     autotuned persistent grid),
   - the coarse inverse assembled from the real and the complex-pair blocks of
     order 1,572 eliminated with complex pivots (k_kron_block_dense,
-    k_gj_tour_cx, k_gj_slab_update, k_kron_recombine) and applied by
-    k_dense_gemv.
+    k_gj_tour_cx, k_gj_slab_update) and applied from the two blocks'
+    inverses (k_kron_coarse_gemv).
 Every sampled output is compared with the oracle computed one cell at a time
 (the oracle's own LU inverse of the extracted J_T), the coarse solve with a
 sparse direct solve, and FGMRES with an independent residual on the host.
