@@ -1514,16 +1514,24 @@ hipError_t launch_kron_block_dense(hipStream_t s, const KronBlockDesc* kdesc, in
 // inverses, without forming J^-1: with z(s', q) = sum_l W[q][l] r(s', l),
 //   y_p(s, a) = sum_{s', c < sz_p} Binv_p[2s + a, 2s' + c] z(s', f_p + c),
 //   d(s, i)   = sum_p sum_{a < sz_p} V[i][f_p + a] y_p(s, a).
+// Binv_p is read where the elimination left it, Binv_p[i, j] =
+// S_p[rpiv_p[i], rinv_p[j]]: row 2s of Binv_p is row rpiv_p[2s] of S_p, and
+// S_p's columns 2c, 2c + 1 belong to the spatial column s' = rpiv_p[2c] / 2
+// (pivot records pair real rows 2r, 2r + 1 with real columns 2t, 2t + 1).
 // The block of a complex pair is the real form of a complex matrix, every
 // 2 x 2 block [[x, -y], [y, x]] (exactly so: the elimination keeps the
-// structure), so its even row 2s holds the whole row: with
-// (e0, e1) = Binv_p[2s, 2s' .. 2s' + 1],
+// structure), so its even rows hold the whole inverse: with
+// (e0, e1) = (Binv_p[2s, 2s'], Binv_p[2s, 2s' + 1]),
 //   y(s, 0) += e0 z0 + e1 z1,  y(s, 1) += e0 z1 - e1 z0.
 // The block of a real eigenvalue holds two uncoupled copies; its even rows
 // and columns are read.  So the complex inverse is read once (half the
-// bytes of the real form of order b n_s).  One workgroup per spatial row s:
-// thread t takes the columns s' = t, t + 256, ..., z is formed from r on the
-// way (r stays in the caches), the partial sums meet in LDS and the first b
+// bytes of the real form of order b n_s).  A block eliminated with real
+// pivots (paired[p] = 0: the schedules for small orders) has no such
+// pairing: there every real column c of S_p belongs to Binv_p's column
+// j = rpiv_p[c] (s' = j / 2, time component j % 2), and both rows of the
+// pair are read.  One workgroup per spatial row s: thread t takes the
+// columns t, t + 256, ... (coalesced), z is formed from r on the way (r
+// stays in the caches), the partial sums meet in LDS and the first b
 // threads form d(s, .).
 template <int B>
 __global__ void __launch_bounds__(256) k_kron_coarse_gemv(const KronCoarse* __restrict__ kc,
@@ -1535,31 +1543,51 @@ __global__ void __launch_bounds__(256) k_kron_coarse_gemv(const KronCoarse* __re
   if (s >= n_s) return;
   const int nblk = K->nblk;
   const double* rz = r + (int64_t)K->row_off * B;
-  const int64_t ord = 2 * (int64_t)n_s;
   double acc[B][2];
 #pragma unroll
-  for (int p = 0; p < B; ++p) acc[p][0] = acc[p][1] = 0.0;
-  for (int32_t sp = threadIdx.x; sp < n_s; sp += 256) {
-    double rv[B];
+  for (int p = 0; p < B; ++p) {
+    acc[p][0] = acc[p][1] = 0.0;
+    if (p >= nblk) continue;
+    const int f = K->first[p];
+    const bool pair = K->sz[p] == 2;
+    const int* rp = K->rpiv[p];
+    const double* row = K->S[p] + (int64_t)rp[2 * s] * K->ld[p];
+    double w0[B], w1[B];
 #pragma unroll
-    for (int l = 0; l < B; ++l) rv[l] = rz[(int64_t)sp * B + l];
+    for (int l = 0; l < B; ++l) {
+      w0[l] = K->W[f * B + l];
+      w1[l] = pair ? K->W[(f + 1) * B + l] : 0.0;
+    }
+    if (!K->paired[p]) {
+      const double* row1 = pair ? K->S[p] + (int64_t)rp[2 * s + 1] * K->ld[p] : row;
+      for (int32_t c = threadIdx.x; c < 2 * n_s; c += 256) {
+        const int j = rp[c];
+        const int64_t sp = j >> 1;
+        const bool odd = j & 1;
+        if (odd && !pair) continue;            // the second copy of a real block
+        double zc = 0.0;
 #pragma unroll
-    for (int p = 0; p < B; ++p) {
-      if (p >= nblk) break;
-      const int f = K->first[p];
-      const double* row = K->binv[p] + 2 * (int64_t)s * ord + 2 * (int64_t)sp;
-      double z0 = 0.0;
+        for (int l = 0; l < B; ++l) zc = fma(odd ? w1[l] : w0[l], rz[sp * B + l], zc);
+        acc[p][0] = fma(row[c], zc, acc[p][0]);
+        if (pair) acc[p][1] = fma(row1[c], zc, acc[p][1]);
+      }
+      continue;
+    }
+    for (int32_t c = threadIdx.x; c < n_s; c += 256) {
+      const int64_t sp = rp[2 * c] >> 1;
+      double z0 = 0.0, z1 = 0.0;
 #pragma unroll
-      for (int l = 0; l < B; ++l) z0 = fma(K->W[f * B + l], rv[l], z0);
-      if (K->sz[p] == 2) {
-        double z1 = 0.0;
-#pragma unroll
-        for (int l = 0; l < B; ++l) z1 = fma(K->W[(f + 1) * B + l], rv[l], z1);
-        const double2 e = *reinterpret_cast<const double2*>(row);
+      for (int l = 0; l < B; ++l) {
+        const double v = rz[sp * B + l];
+        z0 = fma(w0[l], v, z0);
+        z1 = fma(w1[l], v, z1);
+      }
+      if (pair) {
+        const double2 e = *reinterpret_cast<const double2*>(row + 2 * (int64_t)c);
         acc[p][0] = fma(e.x, z0, fma(e.y, z1, acc[p][0]));
         acc[p][1] = fma(e.x, z1, fma(-e.y, z0, acc[p][1]));
       } else {
-        acc[p][0] = fma(row[0], z0, acc[p][0]);
+        acc[p][0] = fma(row[2 * (int64_t)c], z0, acc[p][0]);
       }
     }
   }
@@ -1589,81 +1617,113 @@ __global__ void __launch_bounds__(256) k_kron_coarse_gemv(const KronCoarse* __re
   }
 }
 
-// d = J^-T r for the same members (the direct solve of the transposed coarse
-// matrix): with u(s, q) = sum_i V[i][q] r(s, i),
+// Block p's part of d = J^-T r for the same members (the direct solve of the
+// transposed coarse matrix): with u(s, q) = sum_i V[i][q] r(s, i),
 //   w_p(s', c) = sum_{s, a < sz_p} Binv_p[2s + a, 2s' + c] u(s, f_p + a),
-//   d(s', l)   = sum_p sum_{c < sz_p} W[f_p + c][l] w_p(s', c);
-// for a pair, from the even rows, w(s', 0) += e0 u0 - e1 u1 and
-// w(s', 1) += e1 u0 + e0 u1.  Thread per spatial column s' (coalesced over
-// the columns of each even row), the rows in order.
+//   d(s', l) (+)= sum_{c < sz_p} W[f_p + c][l] w_p(s', c)
+// (assigned for p = 0, added for p > 0: one launch per block, in order).
+// For a pair, from the even rows, w(s', 0) += e0 u0 - e1 u1 and
+// w(s', 1) += e1 u0 + e0 u1.  Thread per column pair 2t, 2t + 1 of S_p
+// (coalesced), which belongs to s' = rpiv_p[2t] / 2; the even rows 2rho of
+// S_p in order, row 2rho being row 2s of Binv_p for s = rinv_p[2rho] / 2.
+// A block eliminated with real pivots: thread per s', its columns
+// rinv_p[2s'], rinv_p[2s' + 1] of S_p, every row rho of S_p (row
+// i = rinv_p[rho] of Binv_p: s = i / 2, time component i % 2).
 template <int B>
 __global__ void __launch_bounds__(256) k_kron_coarse_gemv_t(const KronCoarse* __restrict__ kc,
-                                                           const double* __restrict__ r,
+                                                           int p, const double* __restrict__ r,
                                                            double* __restrict__ d) {
   const KronCoarse* K = kc + blockIdx.z;
   const int32_t n_s = K->n_s;
-  const int32_t sp = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (sp >= n_s) return;
-  const int nblk = K->nblk;
+  const int32_t t = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= n_s || p >= K->nblk) return;
+  const int f = K->first[p];
+  const bool pair = K->sz[p] == 2;
+  const int* rp = K->rpiv[p];
+  const int* ri = K->rinv[p];
+  const double* S = K->S[p];
+  const int64_t ld = K->ld[p];
   const double* rz = r + (int64_t)K->row_off * B;
-  const int64_t ord = 2 * (int64_t)n_s;
-  double w[B][2];
+  double v0[B], v1[B];
 #pragma unroll
-  for (int p = 0; p < B; ++p) w[p][0] = w[p][1] = 0.0;
-  for (int32_t s = 0; s < n_s; ++s) {
-    double rv[B];
+  for (int i = 0; i < B; ++i) {
+    v0[i] = K->V[i * B + f];
+    v1[i] = pair ? K->V[i * B + f + 1] : 0.0;
+  }
+  double w0 = 0.0, w1 = 0.0;
+  if (!K->paired[p]) {
+    const int64_t c0 = ri[2 * t], c1 = pair ? ri[2 * t + 1] : c0;
+    for (int32_t rho = 0; rho < 2 * n_s; ++rho) {
+      const int i = ri[rho];
+      const int64_t s = i >> 1;
+      const bool odd = i & 1;
+      if (odd && !pair) continue;              // the second copy of a real block
+      double u = 0.0;
 #pragma unroll
-    for (int i = 0; i < B; ++i) rv[i] = rz[(int64_t)s * B + i];
+      for (int q = 0; q < B; ++q) u = fma(odd ? v1[q] : v0[q], rz[s * B + q], u);
+      const double* Sr = S + (int64_t)rho * ld;
+      w0 = fma(Sr[c0], u, w0);
+      if (pair) w1 = fma(Sr[c1], u, w1);
+    }
+    double* dz = d + ((int64_t)K->row_off + t) * B;
 #pragma unroll
-    for (int p = 0; p < B; ++p) {
-      if (p >= nblk) break;
-      const int f = K->first[p];
-      const double* row = K->binv[p] + 2 * (int64_t)s * ord + 2 * (int64_t)sp;
-      double u0 = 0.0;
+    for (int l = 0; l < B; ++l) {
+      double out = K->W[f * B + l] * w0;
+      if (pair) out = fma(K->W[(f + 1) * B + l], w1, out);
+      dz[l] = p > 0 ? dz[l] + out : out;
+    }
+    return;
+  }
+#pragma unroll 4
+  for (int32_t rho = 0; rho < n_s; ++rho) {
+    const int64_t s = ri[2 * rho] >> 1;
+    double u0 = 0.0, u1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) u0 = fma(K->V[i * B + f], rv[i], u0);
-      if (K->sz[p] == 2) {
-        double u1 = 0.0;
-#pragma unroll
-        for (int i = 0; i < B; ++i) u1 = fma(K->V[i * B + f + 1], rv[i], u1);
-        const double2 e = *reinterpret_cast<const double2*>(row);
-        w[p][0] = fma(e.x, u0, fma(-e.y, u1, w[p][0]));
-        w[p][1] = fma(e.y, u0, fma(e.x, u1, w[p][1]));
-      } else {
-        w[p][0] = fma(row[0], u0, w[p][0]);
-      }
+    for (int i = 0; i < B; ++i) {
+      const double v = rz[s * B + i];
+      u0 = fma(v0[i], v, u0);
+      u1 = fma(v1[i], v, u1);
+    }
+    const double* e = S + 2 * (int64_t)rho * ld + 2 * (int64_t)t;
+    if (pair) {
+      const double2 ee = *reinterpret_cast<const double2*>(e);
+      w0 = fma(ee.x, u0, fma(-ee.y, u1, w0));
+      w1 = fma(ee.y, u0, fma(ee.x, u1, w1));
+    } else {
+      w0 = fma(e[0], u0, w0);
     }
   }
+  const int64_t sp = rp[2 * t] >> 1;
+  double* dz = d + ((int64_t)K->row_off + sp) * B;
 #pragma unroll
   for (int l = 0; l < B; ++l) {
-    double out = 0.0;
-#pragma unroll
-    for (int p = 0; p < B; ++p) {
-      if (p >= nblk) break;
-      const int f = K->first[p];
-      out = fma(K->W[f * B + l], w[p][0], out);
-      if (K->sz[p] == 2) out = fma(K->W[(f + 1) * B + l], w[p][1], out);
-    }
-    d[((int64_t)K->row_off + sp) * B + l] = out;
+    double out = K->W[f * B + l] * w0;
+    if (pair) out = fma(K->W[(f + 1) * B + l], w1, out);
+    dz[l] = p > 0 ? dz[l] + out : out;
   }
 }
 
 hipError_t launch_kron_coarse_apply(hipStream_t s, int b, const KronCoarse* kc, int cnt,
-                                    int32_t max_ns, int transposed, const double* r, double* d) {
+                                    int max_blocks, int32_t max_ns, int transposed,
+                                    const double* r, double* d) {
   if (cnt < 1 || max_ns < 1) return hipSuccess;
-  const dim3 grid = transposed ? dim3((unsigned)((max_ns + 255) / 256), 1, (unsigned)cnt)
-                               : dim3((unsigned)max_ns, 1, (unsigned)cnt);
-#define STV_KCA(BB)                                                                  \
-  (transposed ? launch(k_kron_coarse_gemv_t<BB>, grid, dim3(256), 0, s, kc, r, d)    \
-              : launch(k_kron_coarse_gemv<BB>, grid, dim3(256), 0, s, kc, r, d))
-  switch (b) {
-    case 2: STV_KCA(2); break;
-    case 3: STV_KCA(3); break;
-    case 4: STV_KCA(4); break;
-    default: return hipErrorInvalidValue;
+  if (b < 2 || b > 4) return hipErrorInvalidValue;
+  if (!transposed) {
+    const dim3 grid((unsigned)max_ns, 1, (unsigned)cnt);
+    if (b == 2) launch(k_kron_coarse_gemv<2>, grid, dim3(256), 0, s, kc, r, d);
+    else if (b == 3) launch(k_kron_coarse_gemv<3>, grid, dim3(256), 0, s, kc, r, d);
+    else launch(k_kron_coarse_gemv<4>, grid, dim3(256), 0, s, kc, r, d);
+    return hipGetLastError();
   }
-#undef STV_KCA
-  return hipGetLastError();
+  const dim3 grid((unsigned)((max_ns + 255) / 256), 1, (unsigned)cnt);
+  for (int p = 0; p < max_blocks; ++p) {
+    if (b == 2) launch(k_kron_coarse_gemv_t<2>, grid, dim3(256), 0, s, kc, p, r, d);
+    else if (b == 3) launch(k_kron_coarse_gemv_t<3>, grid, dim3(256), 0, s, kc, p, r, d);
+    else launch(k_kron_coarse_gemv_t<4>, grid, dim3(256), 0, s, kc, p, r, d);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Member z's inverse (n0 x n0, row-major, at desc.inv_off of out):

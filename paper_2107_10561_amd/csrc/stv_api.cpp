@@ -117,13 +117,14 @@ void free_coarse_groups(stv_ctx* ctx) {
     dfree(G.d_desc); dfree(G.w.A); dfree(G.w.rpiv); dfree(G.w.used); dfree(G.w.B);
     dfree(G.w.P); dfree(G.w.S); dfree(G.w.Bin); dfree(G.rinv);
     dfree(G.w.cand); dfree(G.w.Z); dfree(G.w.counter);
-    dfree(G.d_kdesc); dfree(G.binv);
+    dfree(G.d_kdesc);
   }
   ctx->cgroups.clear();
   for (int g = 0; g < kMaxLevels; ++g) {
     ctx->h_kc[g].clear();
     dfree(ctx->d_kc[g]);
     ctx->kc_max_ns[g] = 0;
+    ctx->kc_max_blocks[g] = 0;
   }
   ctx->cgroups_algo = -1;
   dfree(ctx->coarse_inv);
@@ -441,8 +442,8 @@ int coarse_apply(stv_ctx* ctx, int g, const double* r, double* d) {
     STV_HIP(launch_dense_gemv(ctx->stream, ctx->d_coarse[g], nw, ctx->b, ctx->coarse_max_n0[g],
                               ctx->coarse_inv, r, d));
   if (nk > 0)
-    STV_HIP(launch_kron_coarse_apply(ctx->stream, ctx->b, ctx->d_kc[g], nk, ctx->kc_max_ns[g],
-                                     ctx->transposed ? 1 : 0, r, d));
+    STV_HIP(launch_kron_coarse_apply(ctx->stream, ctx->b, ctx->d_kc[g], nk, ctx->kc_max_blocks[g],
+                                     ctx->kc_max_ns[g], ctx->transposed ? 1 : 0, r, d));
   t.done();
   return STV_OK;
 }
@@ -1260,7 +1261,6 @@ static int make_coarse_groups(stv_ctx* ctx) {
   ctx->coarse_elems = coarse_total;
   if (coarse_total > 0) STV_TRY(dalloc(ctx, &ctx->coarse_inv, (size_t)coarse_total));
   // per group: plan, descriptors, buffers
-  std::vector<std::vector<int64_t>> boff(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     CoarseGroup& G = groups[gi];
     G.plan = gj_plan(G.n0, ctx->coarse_algo, G.kron);
@@ -1281,17 +1281,13 @@ static int make_coarse_groups(stv_ctx* ctx) {
     if (!G.kron) {
       for (size_t m = 0; m < G.lev.size(); ++m) hd.push_back(ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]]);
     } else {
-      // blocks in real form (order 2 n_s each), inverses packed in binv
+      // blocks in real form (order 2 n_s each)
       std::vector<KronBlockDesc> kd;
-      int64_t off = 0;
       for (size_t m = 0; m < G.lev.size(); ++m) {
         const CoarseDesc& c = ctx->h_coarse[G.lev[m]][(size_t)G.idx[m]];
-        const int64_t order = 2 * (int64_t)c.n_s;
         CoarseDesc cb = c;
-        cb.n_s = (int32_t)order;
-        cb.inv_off = off;
-        boff[gi].push_back(off);
-        off += order * order;
+        cb.n_s = (int32_t)(2 * (int64_t)c.n_s);
+        cb.inv_off = -1;
         hd.push_back(cb);
         const DevLevel& L = ctx->lv[G.lev[m]];
         KronBlockDesc k{};
@@ -1310,7 +1306,6 @@ static int make_coarse_groups(stv_ctx* ctx) {
         k.t[3] = pair ? S.t[p][3] : S.t[p][0];
         kd.push_back(k);
       }
-      STV_TRY(dalloc(ctx, &G.binv, (size_t)off));
       STV_TRY(upload(ctx, &G.d_kdesc, kd.data(), kd.size()));
     }
     STV_TRY(upload(ctx, &G.d_desc, hd.data(), hd.size()));
@@ -1335,12 +1330,19 @@ static int make_coarse_groups(stv_ctx* ctx) {
       STV_TRY(dalloc(ctx, &w.counter, (size_t)(cnt * w.sK)));
     }
   }
-  // time-decoupled members: the device addresses of their block inverses
+  // time-decoupled members: where their blocks' inverses and pivot records
+  // are left by the elimination
   for (size_t k = 0; k < kref.size(); ++k) {
     KronCoarse& R = ctx->h_kc[kref[k].first][kref[k].second];
     for (int p = 0; p < R.nblk; ++p) {
       const BlockRef& br = mblocks[k][(size_t)p];
-      R.binv[p] = groups[br.gi].binv + boff[br.gi][br.slot];
+      const CoarseGroup& G = groups[br.gi];
+      const int64_t slot = (int64_t)br.slot;
+      R.S[p] = G.w.A + slot * G.w.sA;
+      R.rpiv[p] = G.w.rpiv + slot * G.w.sV;
+      R.rinv[p] = G.rinv + slot * G.w.sV;
+      R.ld[p] = G.np;
+      R.paired[p] = G.plan.pair ? 1 : 0;
     }
   }
   // device descriptors per level: the members with a whole inverse (offsets
@@ -1358,7 +1360,11 @@ static int make_coarse_groups(stv_ctx* ctx) {
     ctx->n_whole[g] = (int)whole.size();
     if (!whole.empty()) STV_TRY(upload(ctx, &ctx->d_coarse[g], whole.data(), whole.size()));
     ctx->kc_max_ns[g] = 0;
-    for (const KronCoarse& R : ctx->h_kc[g]) ctx->kc_max_ns[g] = std::max(ctx->kc_max_ns[g], R.n_s);
+    ctx->kc_max_blocks[g] = 0;
+    for (const KronCoarse& R : ctx->h_kc[g]) {
+      ctx->kc_max_ns[g] = std::max(ctx->kc_max_ns[g], R.n_s);
+      ctx->kc_max_blocks[g] = std::max(ctx->kc_max_blocks[g], R.nblk);
+    }
     if (!ctx->h_kc[g].empty())
       STV_TRY(upload(ctx, &ctx->d_kc[g], ctx->h_kc[g].data(), ctx->h_kc[g].size()));
   }
@@ -1613,13 +1619,14 @@ int stv_build_cell_inverses(stv_ctx* ctx, int storage, int* bad_level, int* bad_
     const GjAux aux{ctx->side2, ctx->ev_gj[0], ctx->ev_gj[1]};
     if (e == hipSuccess) e = launch_gj(side, G.plan, G.w, G.np, cnt, ctx->coarse_lookahead ? &aux : nullptr);
     // pivot records -> inverse permutations and verdicts, then the
-    // unpermuted inverses (a block's into the group's block store)
+    // unpermuted inverses (the blocks of time-decoupled members are applied
+    // where the elimination left them, through their pivot records)
     if (e == hipSuccess)
       e = launch_gj_invert_perm(side, G.w.rpiv, G.w.sV, G.np, G.d_desc, cnt, gb, G.rinv,
                                 rep + mbase);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !G.kron)
       e = launch_gj_unpermute(side, G.w.A, G.w.sA, G.np, G.w.rpiv, G.rinv, G.w.sV, G.d_desc, cnt,
-                              gb, G.n0, G.kron ? G.binv : ctx->coarse_inv);
+                              gb, G.n0, ctx->coarse_inv);
     t.done();
     mbase += cnt;
   }

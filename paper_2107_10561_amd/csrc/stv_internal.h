@@ -163,10 +163,19 @@ struct KronBlockDesc {
 // A coarse member inverted through time decoupling: its inverse is
 //   J^-1[(s, i), (s', l)] = sum_p sum_{a, c < sz_p} V[i][f_p + a] Binv_p[2s + a, 2s' + c] W[f_p + c][l]
 // (Binv_p of order 2 n_s in real form; f_p = first[p]; time-inner rows
-// s * b + i), applied from the blocks without being formed.  The member's
-// rows start at spatial row row_off of its packed level.
+// s * b + i), applied from the blocks without being formed.  Binv_p is read
+// where the elimination left it: Binv_p[i, j] = S_p[rpiv_p[i], rinv_p[j]]
+// (S_p row-major with leading dimension ld_p; rinv_p the inverse of
+// rpiv_p).  paired[p]: the block was eliminated with complex pivots, so its
+// pivot records pair real rows 2r, 2r + 1 with real columns 2t, 2t + 1 and
+// S_p keeps the exact 2 x 2 structure of the real form.  The member's rows
+// start at spatial row row_off of its packed level.
 struct KronCoarse {
-  const double* binv[4];
+  const double* S[4];
+  const int* rpiv[4];
+  const int* rinv[4];
+  int64_t ld[4];
+  int paired[4];
   int nblk;
   int sz[4], first[4];
   int32_t n_s, row_off;
@@ -185,12 +194,11 @@ struct CoarseGroup {
   int* rinv = nullptr;
   // blocks of time-decoupled members instead of whole members, each padded
   // with the identity to the group's order n0: their descriptors (desc then
-  // holds n_s = block order, b = 1, and the offset of the block's inverse in
-  // binv)
+  // holds n_s = block order, b = 1); a block's inverse stays in its slice of
+  // w.A with its pivot records (not unpermuted)
   bool kron = false;
   std::vector<int> part;          // kron: which block of its member each slot is
   KronBlockDesc* d_kdesc = nullptr;
-  double* binv = nullptr;
 };
 
 // Start and stop events for the next kernel launched through stv::launch:
@@ -265,6 +273,7 @@ struct stv_ctx {
   std::vector<stv::KronCoarse> h_kc[stv::kMaxLevels];
   stv::KronCoarse* d_kc[stv::kMaxLevels] = {};
   int32_t kc_max_ns[stv::kMaxLevels] = {};
+  int kc_max_blocks[stv::kMaxLevels] = {};
   int* inv_report = nullptr;
   int* h_report = nullptr;
   int n_report = 0;
@@ -381,7 +390,8 @@ hipError_t launch_kron_block_dense(hipStream_t s, const KronBlockDesc* kdesc, in
 // d = J^-1 r (transposed: d = J^-T r) on the rows of time-decoupled
 // coarse members, from their blocks' inverses
 hipError_t launch_kron_coarse_apply(hipStream_t s, int b, const KronCoarse* kc, int cnt,
-                                    int32_t max_ns, int transposed, const double* r, double* d);
+                                    int max_blocks, int32_t max_ns, int transposed,
+                                    const double* r, double* d);
 // rinv = the inverse of every member's pivot record rpiv (order n, real
 // order n0 from desc); verdict[z] = 0 when member z's record is a
 // permutation whose real columns pivot on real rows, else 1.
