@@ -1089,7 +1089,7 @@ __device__ __forceinline__ void wave_select_cx(double (&wr)[NB], double (&wi)[NB
 // [16][NO / 2] pairs (re, im).  rpiv receives real rows (2r at real column
 // 2t, 2r + 1 at 2t + 1); used flags both rows.
 template <int NO, bool UPDATE>
-__global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int64_t sS, int64_t n,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gj_tour_cx(double* __restrict__ S, int64_t sS, int64_t n,
                                                      int64_t j0, int q0, int* __restrict__ rpiv,
                                                      uint8_t* __restrict__ used, int64_t sV,
                                                      const double* __restrict__ Zc,
@@ -1103,11 +1103,23 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
   constexpr int RPP = 64 / LPR;                // rows per wavefront and pass
   constexpr int NH = NOC / LPR;                // complex columns per lane
   constexpr int PASSES = RC / (NW * RPP);
-  constexpr int NSM = RC * (2 * NB + 1) > 64 * NOC ? RC * (2 * NB + 1) : 64 * NOC;
+  // wide slabs stage only the NB chosen rows, after the root's selection,
+  // so that the workgroup's LDS stays small; narrow ones stage all 64
+  // candidates beside the selection
+  constexpr bool LATE = 64 * NOC > RC * (2 * NB + 1);
+  constexpr int NBR = LATE ? NB : 64;          // rows staged in Brow
+  constexpr int NSM = RC * (2 * NB + 1) > NBR * NOC ? RC * (2 * NB + 1) : NBR * NOC;
   __shared__ double2 smem[NSM];
   double2(*Acur)[NB] = reinterpret_cast<double2(*)[NB]>(smem);
   double2(*Anx)[NB + 1] = reinterpret_cast<double2(*)[NB + 1]>(smem + RC * NB);
   double2* Brow = smem;
+  // the previous panel's Z (UPDATE), in LDS sized at launch: kept out of
+  // the static size, the register budget follows the four wavefronts per
+  // SIMD the attribute asks for (128 registers) rather than the occupancy
+  // the LDS would allow, so that a workgroup also fits beside a cell-inverse
+  // workgroup of the concurrent stream
+  extern __shared__ double2 zdyn[];
+  double2(*Zs)[NOC] = reinterpret_cast<double2(*)[NOC]>(zdyn);
   __shared__ int rootg[64];
   __shared__ double2 LUs[NB][NB + 1];
   __shared__ int Ll[NB];
@@ -1151,15 +1163,7 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
       const int64_t ic = c0 + dx;
       Acur[dx][t] = ic < nc ? cval(ic, q0c + t) : make_double2(0.0, 0.0);
     }
-    double zr[NH][NB], zi[NH][NB];
-#pragma unroll
-    for (int h = 0; h < NH; ++h)
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        const double2 v = Z2[t * NOC + cl + LPR * h];
-        zr[h][t] = v.x;
-        zi[h][t] = v.y;
-      }
+    for (int e = tid; e < NB * NOC; e += NT) Zs[e / NOC][e % NOC] = Z2[e];
     int rp[NB];
 #pragma unroll
     for (int t = 0; t < NB; ++t) rp[t] = rpiv[j0 + q0 + 2 * t] >> 1;   // -1 stays -1
@@ -1186,8 +1190,9 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
 #pragma unroll
           for (int t = 0; t < NB; ++t) {
             const double2 a = Acur[dx][t];
-            vr = fma(-a.x, zr[h][t], fma(a.y, zi[h][t], vr));
-            vi = fma(-a.x, zi[h][t], fma(-a.y, zr[h][t], vi));
+            const double2 zz = Zs[t][cc];
+            vr = fma(-a.x, zz.x, fma(a.y, zz.y, vr));
+            vi = fma(-a.x, zz.y, fma(-a.y, zz.x, vi));
           }
         }
         *reinterpret_cast<double2*>(&S[2 * ic * NO + 2 * cc]) = make_double2(vr, -vi);
@@ -1297,7 +1302,7 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
 #pragma unroll
       for (int c = 0; c < NB; ++c) LUs[step][c] = make_double2(wr[c], wi[c]);
     }
-  } else {
+  } else if constexpr (!LATE) {
     // meanwhile the other wavefronts stage the candidates' complex rows
     for (int e = tid - 64; e < 64 * NOC; e += NT - 64) {
       const int l = e / NOC, cc = e - l * NOC;
@@ -1306,6 +1311,16 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
     }
   }
   __syncthreads();
+  if constexpr (LATE) {
+    // the chosen rows only, in pivot order
+    for (int e = tid; e < NB * NOC; e += NT) {
+      const int sl = e / NOC, cc = e - sl * NOC;
+      const int l = Ll[sl];
+      const int g = l >= 0 ? rootg[l] : -1;
+      Brow[e] = g >= 0 ? cval(g, cc) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  }
   // Z = U^-1 L^-1 B'', one complex column per thread
   if (tid < NOC) {
     const int cc = tid;
@@ -1315,7 +1330,7 @@ __global__ void __launch_bounds__(256) k_gj_tour_cx(double* __restrict__ S, int6
     for (int s = 0; s < NB; ++s) {
       const int l = Ll[s];
       const double2 v = inp ? make_double2((cc - qnc == s) ? 1.0 : 0.0, 0.0)
-                            : (l >= 0 ? Brow[l * NOC + cc] : make_double2(0.0, 0.0));
+                            : (l >= 0 ? Brow[(LATE ? s : l) * NOC + cc] : make_double2(0.0, 0.0));
       yr[s] = v.x;
       yi[s] = v.y;
     }
@@ -1352,6 +1367,7 @@ template <int NO>
 static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt,
                              const GjAux* aux) {
   constexpr int NBR = 32;                      // real columns per panel
+  constexpr unsigned zbytes = (NBR / 2) * (NO / 2) * sizeof(double2);   // Z of a panel
   double* sb[2] = {w.S, w.S + n * NO};
   double* zb[2] = {w.Z, w.Z + NBR * NO};
   hipError_t e = load_panel(s, cnt, w.A, w.sA, n, n, 0, NO, sb[0], w.sS);
@@ -1366,7 +1382,7 @@ static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt,
         w.counter, w.sK);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int q0 = 0; q0 < NO; q0 += NBR, cz ^= 1) {
-      k_gj_tour_cx<NO, true><<<dim3(nwg, 1, cnt), 256, 0, s>>>(
+      k_gj_tour_cx<NO, true><<<dim3(nwg, 1, cnt), 256, zbytes, s>>>(
           sb[cs], w.sS, n, j0, q0, w.rpiv, w.used, w.sV, zb[cz], zb[cz ^ 1], w.sZ, w.cand, w.sC,
           w.counter, w.sK);
       if ((e = hipGetLastError()) != hipSuccess) return e;

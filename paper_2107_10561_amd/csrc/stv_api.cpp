@@ -16,10 +16,11 @@
 
 #include "stv_internal.h"
 
-// registers per lane that the dense elimination chain's largest kernel
-// needs on a SIMD (its workgroups run beside the cell inverses)
+// registers per lane that the complex-pivot elimination chain's largest
+// kernel needs on a SIMD (its workgroups run beside the cell inverses; the
+// panel kernel k_gj_tour_cx is held to 128)
 #ifndef STV_CHAIN_VGPRS
-#define STV_CHAIN_VGPRS 168
+#define STV_CHAIN_VGPRS 128
 #endif
 
 using namespace stv;
