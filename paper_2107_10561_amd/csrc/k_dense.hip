@@ -571,8 +571,14 @@ __global__ void __launch_bounds__(256) k_gj_slab_update_cx(double* __restrict__ 
 // wavefront owns 16 row pairs x 128 columns (8 accumulator tiles), and the
 // factors pass through LDS 32 columns of K at a time.  Per multiply-add half
 // the factor traffic of the 64 x 64 tiling, a quarter of its workgroups.
+// Held to 128 registers (a few spill) so that its workgroups also run beside
+// a cell-inverse workgroup of the concurrent stream, which leaves 128 per
+// SIMD; the pivot-row buffer is in LDS sized at launch (kCx128Lds bytes), so
+// that the register budget follows the attribute rather than the occupancy
+// the static LDS alone would allow.
+constexpr unsigned kCx128Lds = 32 * (128 + 2) * sizeof(double);
 template <int NO>
-__global__ void __launch_bounds__(256) k_gj_slab_update_cx128(double* __restrict__ A, int64_t sA,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gj_slab_update_cx128(double* __restrict__ A, int64_t sA,
                                                               int64_t n, int64_t j0,
                                                               const int* __restrict__ rp,
                                                               int64_t sV,
@@ -590,7 +596,9 @@ __global__ void __launch_bounds__(256) k_gj_slab_update_cx128(double* __restrict
   Snext += blockIdx.z * sS;
   Bg += blockIdx.z * sB;
   __shared__ double Ws[64][KC + 1];      // even rows of the tile
-  __shared__ double Bs[KC][TW + 2];
+  extern __shared__ double2 zdyn[];
+  double(*Bs)[TW + 2] = reinterpret_cast<double(*)[TW + 2]>(zdyn);   // kCx128Lds bytes
+  static_assert(KC * (TW + 2) * sizeof(double) == kCx128Lds, "launch-sized LDS");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int ct = ct0 + (int)blockIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * TW, jt = (int64_t)(ct < skip_at ? ct : ct + skip_n) * TW;
@@ -1401,7 +1409,7 @@ static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt,
     const int nnext = j0 + NO < n ? nst : 0;
     auto update = [&](unsigned gx, int ct0, int skip_at, int skip_n, hipStream_t st) {
       if (big)
-        k_gj_slab_update_cx128<NO><<<dim3(gx, ntt, cnt), 256, 0, st>>>(
+        k_gj_slab_update_cx128<NO><<<dim3(gx, ntt, cnt), 256, kCx128Lds, st>>>(
             w.A, w.sA, n, j0, w.rpiv + j0, w.sV, sb[cs], sb[cs ^ 1], w.sS, w.B, w.sB, ct0, skip_at,
             skip_n);
       else

@@ -18,7 +18,8 @@
 
 // registers per lane that the complex-pivot elimination chain's largest
 // kernel needs on a SIMD (its workgroups run beside the cell inverses; the
-// panel kernel k_gj_tour_cx is held to 128)
+// panel kernel k_gj_tour_cx and the wide update k_gj_slab_update_cx128 are
+// held to 128)
 #ifndef STV_CHAIN_VGPRS
 #define STV_CHAIN_VGPRS 128
 #endif
