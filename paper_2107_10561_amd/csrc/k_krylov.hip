@@ -11,8 +11,17 @@ namespace stv {
 constexpr int kGroup = 8;
 
 int seg_blocks(const Segs& g) {
+  // kDotBlocks shared among the instances, at least 4 each; for a batch also
+  // enough that a thread of the longest instance takes about 16 elements
+  // (instances of uneven length otherwise leave the longest ones a few
+  // blocks)
   const int per = kDotBlocks / (g.nseg > 0 ? g.nseg : 1);
-  return per < 4 ? 4 : per;
+  int nb = per < 4 ? 4 : per;
+  if (g.nseg > 1) {
+    const int64_t by_len = (g.max_seg + 16 * 256 - 1) / (16 * 256);
+    if (by_len > nb) nb = (int)(by_len < 65535 ? by_len : 65535);
+  }
+  return nb;
 }
 
 // partial[(z*nblk + blk)*kGroup + k] = sum over this block's slice of segment

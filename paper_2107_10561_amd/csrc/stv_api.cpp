@@ -1925,28 +1925,20 @@ int stv_gmres_solve(stv_ctx* ctx, const double* bvec, double* x, const stv_gmres
       STV_TRY(matvec(ctx, G, zj, ctx->w));
       {
         Timed t(ctx, KC_KRYLOV);
-        // CGS2: h1 = V'w, w -= V h1, h2 = V'w, w -= V h2, ||w||.  For one
-        // instance each update is fused with the products that follow it (one
-        // pass over V and w fewer each; same results as the separate kernels).
-        // A batch keeps the separate updates: the fused kernels run on the
-        // reductions' fixed blocks per instance, while the separate update
-        // spreads every element over its own thread.
-        const bool fuse = sg.nseg == 1;
+        // CGS2: h1 = V'w, w -= V h1, h2 = V'w, w -= V h2, ||w||.  Each update
+        // is fused with the products that follow it (one pass over V and w
+        // fewer each; the same blocks and order of operations as the separate
+        // kernels), the first while V has at most kKrylovFuse columns.
         STV_HIP(launch_multidot(s, ctx->V, j + 1, ctx->w, n, sg, ctx->partial, ctx->scal + lay.h1(0), kScalR));
-        if (fuse && j + 1 <= kKrylovFuse) {
+        if (j + 1 <= kKrylovFuse) {
           STV_HIP(launch_multiaxpy_dot(s, ctx->V, j + 1, ctx->scal + lay.h1(0), kScalR, -1.0, ctx->w, n, sg,
                                        ctx->partial, ctx->scal + lay.h2(0), kScalR));
         } else {
           STV_HIP(launch_multiaxpy(s, ctx->V, j + 1, ctx->scal + lay.h1(0), kScalR, -1.0, ctx->w, n, sg));
           STV_HIP(launch_multidot(s, ctx->V, j + 1, ctx->w, n, sg, ctx->partial, ctx->scal + lay.h2(0), kScalR));
         }
-        if (fuse) {
-          STV_HIP(launch_multiaxpy_nrm(s, ctx->V, j + 1, ctx->scal + lay.h2(0), kScalR, -1.0, ctx->w, n, sg,
-                                       ctx->partial, ctx->scal + lay.nrm(), 1));
-        } else {
-          STV_HIP(launch_multiaxpy(s, ctx->V, j + 1, ctx->scal + lay.h2(0), kScalR, -1.0, ctx->w, n, sg));
-          STV_HIP(launch_multidot(s, ctx->w, 1, ctx->w, n, sg, ctx->partial, ctx->scal + lay.nrm(), 1));
-        }
+        STV_HIP(launch_multiaxpy_nrm(s, ctx->V, j + 1, ctx->scal + lay.h2(0), kScalR, -1.0, ctx->w, n, sg,
+                                     ctx->partial, ctx->scal + lay.nrm(), 1));
         STV_HIP(launch_scale_by_norm(s, ctx->w, ctx->scal + lay.nrm(), 1, ctx->V + (int64_t)(j + 1) * n, sg));
         t.done();
       }
