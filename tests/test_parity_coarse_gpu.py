@@ -113,6 +113,41 @@ def test_time_decoupled_coarse_inverse_every_schedule(stv, name):
         assert fe <= 1e-15 * cond * 10
 
 
+@pytest.mark.parametrize("name", ["2d_16x4_dg1", "2d_32x8_dg2"])
+@pytest.mark.parametrize("algo", ["tournament", "slabs", "panels"])
+def test_time_decoupled_coarse_apply_both_directions(stv, name, algo):
+    """The time-decoupled coarse inverse is applied from the eliminated blocks
+    where the elimination left them: through paired pivot records (complex
+    pivots, tournament) or real ones (slabs, panels), forward (coarse solve)
+    and transposed (the V-cycle of the transposed one-level hierarchy is
+    J^-T r).  dG(1): one complex pair; dG(2): a real eigenvalue and a pair."""
+    p, J, lu, cond = coarse_case(name)
+    _, w, C, _ = fe_time.time_matrices(p.k)
+    s = stv.Solver(0)
+    s.set_coarse_algorithm(algo)
+    s.set_hierarchy(p.levels, p.dim, p.k)
+    m, a = spatial_factors(p.levels[0])
+    s.set_kron_factors(0, m, a, np.asarray(C, dtype=np.float64),
+                       p.tau * np.asarray(w, dtype=np.float64))
+    s.build_cell_inverses(full=True)
+    r = np.random.default_rng(23).standard_normal(J.shape[0])
+    for trans in (False, True):
+        d = to_dev(np.zeros_like(r))
+        if trans:
+            s.vcycle_transposed(to_dev(r), d)
+        else:
+            s.coarse_solve(to_dev(r), d)
+        d = to_host(d)
+        A = J.T if trans else J
+        ref = lu.solve(r, trans="T" if trans else "N")
+        res = np.linalg.norm(r - A @ d) / np.linalg.norm(r)
+        fe = relerr(d, ref)
+        log(f"[coarse] {name} {algo} transposed={trans} relres {res:.2e} forward {fe:.2e}")
+        assert res <= 1e-11
+        assert fe <= 1e-15 * cond * 10
+    s.close()
+
+
 def test_coarse_algorithm_option_rejects_unknown(stv):
     s = stv.Solver(0)
     with pytest.raises(KeyError):
