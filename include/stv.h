@@ -182,7 +182,11 @@ int stv_instance_info(stv_ctx* ctx, int inst, stv_gmres_info* info);
 /* Extract every local Jacobian J_T (the submatrix of the level matrix on the
  * cell's DoFs, Section 4.2) on levels >= 1, invert it by Gauss-Jordan
  * elimination with partial pivoting in FP64 and store it (Section 4.3);
- * factor the coarsest matrix densely (its explicit inverse) in FP64.
+ * factor the coarsest matrix densely (its explicit inverse) in FP64; with
+ * spatial factors on the coarsest level, the diagonal blocks of its
+ * time-decoupled form are inverted instead (each the real form of a complex
+ * matrix) and stv_coarse_solve applies them with the time transforms, so the
+ * whole inverse is never formed.
  * With spatial factors on a level (stv_set_kron_factors) whose cell problems
  * fit one wavefront (n_ls = 21, k + 1 <= 3) and the owned-rows layout, the
  * level's inverses are stored time-decoupled: with D^-1 C = V T V^-1 (real
