@@ -1080,11 +1080,116 @@ __device__ __forceinline__ void wave_select_cx(double (&wr)[NB], double (&wi)[NB
   }
 }
 
+// Complex partial pivoting over the 256 threads of a workgroup, one
+// candidate row per thread, with the results of wave_select_cx (mine, in the
+// threads t < NB: the thread whose row was taken at step t).  At each step
+// every wavefront proposes its best row (largest |Re| + |Im| in the column,
+// lowest lane on ties) and stages it in LDS with its magnitude; after one
+// barrier every thread takes the largest proposal (lowest wavefront on ties)
+// and gathers its row: entry c read by lane c, then by readlane.  The staging
+// alternates between two buffers: a thread writes a buffer again two steps
+// later, after the barrier between, which every thread passes only once it
+// has read the buffer.
+template <int NB>
+struct WgPickCx {
+  double2 row[2][4][NB];
+  double mag[2][4];
+  int who[2][4];   // proposing thread, -1 when the wavefront has no nonzero
+  int any[2][4];   // lowest thread of the wavefront still available, -1 if none
+};
+
+template <int NB, bool LU>
+__device__ __forceinline__ void wg_select_cx(double (&wr)[NB], double (&wi)[NB], bool avail,
+                                             int& mine, unsigned& zero, int& step,
+                                             WgPickCx<NB>& sh) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  mine = -1;
+  zero = 0;
+  step = -1;
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const int b = t & 1;
+    const double v = avail ? fabs(wr[t]) + fabs(wi[t]) : -1.0;
+    const double m = wave_max_f64(v);
+    const uint64_t hit = __builtin_amdgcn_ballot_w64(m > 0.0 && v == m);
+    const uint64_t am = __builtin_amdgcn_ballot_w64(avail);
+    const int pl = hit ? (int)__builtin_ctzll(hit) : -1;
+    if (lane == pl) {
+#pragma unroll
+      for (int c = t; c < NB; ++c) sh.row[b][wv][c] = make_double2(wr[c], wi[c]);
+    }
+    if (lane == 0) {
+      sh.mag[b][wv] = m;
+      sh.who[b][wv] = pl >= 0 ? 64 * wv + pl : -1;
+      sh.any[b][wv] = am ? 64 * wv + (int)__builtin_ctzll(am) : -1;
+    }
+    __syncthreads();
+    double best = sh.mag[b][0];
+    int bw = 0, first = sh.any[b][3];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      const double x = sh.mag[b][w];
+      if (x > best) {
+        best = x;
+        bw = w;
+      }
+    }
+#pragma unroll
+    for (int w = 2; w >= 0; --w) {
+      const int a = sh.any[b][w];
+      first = a >= 0 ? a : first;
+    }
+    const bool nz = __builtin_amdgcn_readfirstlane(best > 0.0 ? 1 : 0) != 0;
+    bw = __builtin_amdgcn_readfirstlane(bw);
+    int p;
+    if (nz) {
+      p = sh.who[b][bw];
+    } else {
+      zero |= 1u << t;
+      p = first;
+    }
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (tid == t) mine = p;
+    if (p < 0) continue;
+    if (tid == p) {
+      avail = false;
+      step = t;
+    }
+    if (nz) {
+      // the pivot row, entry c in lane c, then by readlane to every lane
+      // (entries before t are stale and not used)
+      const double2 qv = sh.row[b][bw][lane < NB ? lane : 0];
+      double qr[NB], qi[NB];
+#pragma unroll
+      for (int c = t; c < NB; ++c) {
+        qr[c] = readlane_f64(qv.x, c);
+        qi[c] = readlane_f64(qv.y, c);
+      }
+      const double d = recip_f64(fma(qr[t], qr[t], qi[t] * qi[t]));
+      const double fr = fma(wr[t], qr[t], wi[t] * qi[t]) * d;
+      const double fi = fma(wi[t], qr[t], -wr[t] * qi[t]) * d;
+      if (avail) {
+#pragma unroll
+        for (int c = t + 1; c < NB; ++c) {
+          wr[c] = fma(-fr, qr[c], fma(fi, qi[c], wr[c]));
+          wi[c] = fma(-fr, qi[c], fma(-fi, qr[c], wi[c]));
+        }
+        if (LU) {
+          wr[t] = fr;
+          wi[t] = fi;
+        }
+      }
+    }
+  }
+}
+
 // The tournament schedule of k_gj_tour on the real form of complex matrices
 // (complex row i = real rows 2i, 2i+1; see GjPlan::pair): the pivots are
 // complex, 16 per panel of 32 real columns, chosen by complex partial
-// pivoting (wave_select_cx) on each workgroup's rows and up a merge tree of
-// the workgroups' proposals; the panel step is the complex block step
+// pivoting on each workgroup's rows (wave_select_cx) and up a merge tree of
+// the workgroups' proposals, 16 lists per node (wg_select_cx over their 256
+// rows); the panel step is the complex block step
 //   Z = P^-1 B'' (P = pivot rows x panel columns, B'' = pivot rows with the
 //   panel columns replaced by the identity), pivot rows <- Z, other rows
 //   <- row - (row's panel entries) Z,
@@ -1104,23 +1209,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                      double* __restrict__ Zn, int64_t sZ,
                                                      int* __restrict__ cand, int64_t sC,
                                                      unsigned* __restrict__ counter, int64_t sK) {
-  constexpr int NB = 16, RC = 64, NW = 4, NT = 64 * NW, FAN = 64 / NB;
+  constexpr int NB = 16, RC = 64, NW = 4, NT = 64 * NW, TFAN = NT / NB;
   chain_priority();
   constexpr int NOC = NO / 2;                  // complex columns of the slab
   constexpr int LPR = NOC < 64 ? NOC : 64;     // lanes per row in the panel step
   constexpr int RPP = 64 / LPR;                // rows per wavefront and pass
   constexpr int NH = NOC / LPR;                // complex columns per lane
   constexpr int PASSES = RC / (NW * RPP);
-  // wide slabs stage only the NB chosen rows, after the root's selection,
-  // so that the workgroup's LDS stays small; narrow ones stage all 64
-  // candidates beside the selection
-  constexpr bool LATE = 64 * NOC > RC * (2 * NB + 1);
-  constexpr int NBR = LATE ? NB : 64;          // rows staged in Brow
-  constexpr int NSM = RC * (2 * NB + 1) > NBR * NOC ? RC * (2 * NB + 1) : NBR * NOC;
+  // the root stages the NB chosen rows (Brow) once they are known
+  constexpr int NSM = RC * (2 * NB + 1) > NB * NOC ? RC * (2 * NB + 1) : NB * NOC;
   __shared__ double2 smem[NSM];
   double2(*Acur)[NB] = reinterpret_cast<double2(*)[NB]>(smem);
   double2(*Anx)[NB + 1] = reinterpret_cast<double2(*)[NB + 1]>(smem + RC * NB);
   double2* Brow = smem;
+  // past Brow, once the chunk's rows (Acur, Anx) are done with: the candidate
+  // rows of a merge and the pivot exchange of its selection
+  int* candg = reinterpret_cast<int*>(smem + NB * NOC);
+  WgPickCx<NB>& pick = *reinterpret_cast<WgPickCx<NB>*>(smem + NB * NOC + NT / 4);
+  static_assert(NB * NOC + NT / 4 + (sizeof(WgPickCx<NB>) + 15) / 16 <= NSM, "LDS layout");
   // the previous panel's Z (UPDATE), in LDS sized at launch: kept out of
   // the static size, the register budget follows the four wavefronts per
   // SIMD the attribute asks for (128 registers) rather than the occupancy
@@ -1128,8 +1234,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   // workgroup of the concurrent stream
   extern __shared__ double2 zdyn[];
   double2(*Zs)[NOC] = reinterpret_cast<double2(*)[NOC]>(zdyn);
-  __shared__ int rootg[64];
   __shared__ double2 LUs[NB][NB + 1];
+  __shared__ double2 uinv[NB];                 // 1 / U(s, s)
   __shared__ int Ll[NB];
   __shared__ unsigned s_last;
   const int z = blockIdx.z;
@@ -1231,19 +1337,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     wave_select_cx<NB, false>(wr, wi, av, mine, zf, step);
     if (lane < NB) cand[(int64_t)blockIdx.x * NB + lane] = mine >= 0 ? (int)(c0 + mine) : -1;
   }
-  // merge tree over the workgroups' lists, FAN children per node: the last
+  // merge tree over the workgroups' lists, TFAN children per node: the last
   // child to arrive at a node merges the children's lists into the node's
-  // (partial pivoting on their rows, children in index order), so the nodes
-  // of one level merge in parallel; the last arrival at the top level (at
-  // most FAN lists) goes on to the root.  Lists of level l follow those of
-  // level l - 1 in cand; counters of a level follow those of the level below.
+  // (wg_select_cx over their rows, one per thread, children in index order),
+  // so the nodes of one level merge in parallel; the last arrival at the top
+  // level (at most TFAN lists) goes on to the root.  Lists of level l follow
+  // those of level l - 1 in cand; counters of a level follow those of the
+  // level below.
+  static_assert(TFAN * NB == NT, "a merge takes one candidate row per thread");
   int m = (int)gridDim.x;        // lists at the current level
   int node = (int)blockIdx.x;    // this workgroup's list there
   int64_t lev = 0, cb = 0;       // first list and first counter of the level
   for (;;) {
-    const bool top = m <= FAN;
-    const int parent = top ? 0 : node / FAN;
-    const int nchild = top ? m : min(FAN, m - parent * FAN);
+    const bool top = m <= TFAN;
+    const int parent = top ? 0 : node / TFAN;
+    const int nchild = top ? m : min(TFAN, m - parent * TFAN);
     __syncthreads();
     if (tid == 0) {
       __threadfence();
@@ -1259,9 +1367,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     if (!s_last) return;
     if (top) break;
     const int64_t nlev = lev + m;
-    if (wv == 0) {
-      const int k = lane / NB, sl = lane % NB;
-      const int g = k < nchild ? cand[(lev + parent * FAN + k) * NB + sl] : -1;
+    {
+      const int k = tid / NB;
+      const int g = k < nchild ? cand[(lev + parent * TFAN + k) * NB + tid % NB] : -1;
+      candg[tid] = g;
       double wr[NB], wi[NB];
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
@@ -1269,23 +1378,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         wr[t] = v.x;
         wi[t] = v.y;
       }
-      wave_select_cx<NB, false>(wr, wi, g >= 0, mine, zf, step);
-      const int gs = __shfl(g, mine >= 0 ? mine : 0, 64);
-      if (lane < NB) cand[(nlev + parent) * NB + lane] = mine >= 0 ? gs : -1;
+      wg_select_cx<NB, false>(wr, wi, g >= 0, mine, zf, step, pick);
+      if (tid < NB) cand[(nlev + parent) * NB + tid] = mine >= 0 ? candg[mine] : -1;
     }
-    cb += (m + FAN - 1) / FAN;
+    cb += (m + TFAN - 1) / TFAN;
     lev = nlev;
     node = parent;
-    m = (m + FAN - 1) / FAN;
+    m = (m + TFAN - 1) / TFAN;
   }
-  if (tid < 64) {
-    const int k = tid / NB;
-    rootg[tid] = k < m ? cand[(lev + k) * NB + tid % NB] : -1;
-  }
-  __syncthreads();
-  if (wv == 0) {
+  {
     // the root: its pivot rows, their complex LU factors
-    const int g = rootg[lane];
+    const int k = tid / NB;
+    const int g = k < m ? cand[(lev + k) * NB + tid % NB] : -1;
+    candg[tid] = g;
     double wr[NB], wi[NB];
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
@@ -1293,14 +1398,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       wr[t] = v.x;
       wi[t] = v.y;
     }
-    wave_select_cx<NB, true>(wr, wi, g >= 0, mine, zf, step);
-    const int gs = __shfl(g, mine >= 0 ? mine : 0, 64);
-    if (lane < NB) {
-      const bool ok = mine >= 0 && !((zf >> lane) & 1u);
-      const int r = ok ? gs : -1;
-      Ll[lane] = ok ? mine : -1;
-      rpiv[j0 + qn + 2 * lane] = ok ? 2 * r : -1;
-      rpiv[j0 + qn + 2 * lane + 1] = ok ? 2 * r + 1 : -1;
+    wg_select_cx<NB, true>(wr, wi, g >= 0, mine, zf, step, pick);
+    if (tid < NB) {
+      const bool ok = mine >= 0 && !((zf >> tid) & 1u);
+      const int r = ok ? candg[mine] : -1;
+      Ll[tid] = ok ? mine : -1;
+      rpiv[j0 + qn + 2 * tid] = ok ? 2 * r : -1;
+      rpiv[j0 + qn + 2 * tid + 1] = ok ? 2 * r + 1 : -1;
       if (ok) {
         used[2 * (int64_t)r] = 1;
         used[2 * (int64_t)r + 1] = 1;
@@ -1310,64 +1414,82 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
       for (int c = 0; c < NB; ++c) LUs[step][c] = make_double2(wr[c], wi[c]);
     }
-  } else if constexpr (!LATE) {
-    // meanwhile the other wavefronts stage the candidates' complex rows
-    for (int e = tid - 64; e < 64 * NOC; e += NT - 64) {
-      const int l = e / NOC, cc = e - l * NOC;
-      const int g = rootg[l];
-      Brow[e] = g >= 0 ? cval(g, cc) : make_double2(0.0, 0.0);
-    }
   }
   __syncthreads();
-  if constexpr (LATE) {
-    // the chosen rows only, in pivot order
-    for (int e = tid; e < NB * NOC; e += NT) {
-      const int sl = e / NOC, cc = e - sl * NOC;
-      const int l = Ll[sl];
-      const int g = l >= 0 ? rootg[l] : -1;
-      Brow[e] = g >= 0 ? cval(g, cc) : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
+  if (tid < NB) {
+    const double2 u = LUs[tid][tid];
+    const double d = 1.0 / fma(u.x, u.x, u.y * u.y);
+    uinv[tid] = make_double2(u.x * d, -u.y * d);
   }
-  // Z = U^-1 L^-1 B'', one complex column per thread
-  if (tid < NOC) {
-    const int cc = tid;
+  // the chosen rows, in pivot order
+  for (int e = tid; e < NB * NOC; e += NT) {
+    const int sl = e / NOC, cc = e - sl * NOC;
+    const int l = Ll[sl];
+    const int g = l >= 0 ? candg[l] : -1;
+    Brow[e] = g >= 0 ? cval(g, cc) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  // Z = U^-1 L^-1 B'': four threads per complex column (a quad of lanes),
+  // thread j of the quad holding rows j, j + 4, j + 8, j + 12; each
+  // substitution step takes the finished row from its owner by a quad
+  // broadcast.  Threads past the last column compute on zeros and store
+  // nothing.
+  {
+    constexpr int TPC = 4, RPT = NB / TPC;
+    static_assert(NT / TPC >= NOC, "one quad per complex column");
+    const int j = tid & (TPC - 1);
+    const int cq = tid / TPC;
+    const bool cok = cq < NOC;
+    const int cc = cok ? cq : 0;
     const bool inp = cc >= qnc && cc < qnc + NB;
-    double yr[NB], yi[NB];
+    double yr[RPT], yi[RPT];
 #pragma unroll
-    for (int s = 0; s < NB; ++s) {
-      const int l = Ll[s];
-      const double2 v = inp ? make_double2((cc - qnc == s) ? 1.0 : 0.0, 0.0)
-                            : (l >= 0 ? Brow[(LATE ? s : l) * NOC + cc] : make_double2(0.0, 0.0));
-      yr[s] = v.x;
-      yi[s] = v.y;
+    for (int r = 0; r < RPT; ++r) {
+      const int s = r * TPC + j;
+      const double2 v = !cok ? make_double2(0.0, 0.0)
+                        : inp ? make_double2((cc - qnc == s) ? 1.0 : 0.0, 0.0)
+                              : (Ll[s] >= 0 ? Brow[s * NOC + cc] : make_double2(0.0, 0.0));
+      yr[r] = v.x;
+      yi[r] = v.y;
     }
+    // forward: the multipliers below the diagonal (unit lower factor)
 #pragma unroll
-    for (int s = 1; s < NB; ++s)
+    for (int s = 0; s < NB - 1; ++s) {
+      const int ro = s / TPC, jo = s % TPC;
+      const double br = quad_bcast_f64(yr[ro], jo), bi = quad_bcast_f64(yi[ro], jo);
 #pragma unroll
-      for (int t = 0; t < s; ++t) {
-        const double2 f = LUs[s][t];
-        yr[s] = fma(-f.x, yr[t], fma(f.y, yi[t], yr[s]));
-        yi[s] = fma(-f.x, yi[t], fma(-f.y, yr[t], yi[s]));
+      for (int r = ro; r < RPT; ++r) {
+        if (r == ro && j <= jo) continue;
+        const double2 f = LUs[r * TPC + j][s];
+        yr[r] = fma(-f.x, br, fma(f.y, bi, yr[r]));
+        yi[r] = fma(-f.x, bi, fma(-f.y, br, yi[r]));
       }
+    }
+    // backward: the upper factor, its diagonal by the stored reciprocals
 #pragma unroll
     for (int s = NB - 1; s >= 0; --s) {
-#pragma unroll
-      for (int t = s + 1; t < NB; ++t) {
-        const double2 f = LUs[s][t];
-        yr[s] = fma(-f.x, yr[t], fma(f.y, yi[t], yr[s]));
-        yi[s] = fma(-f.x, yi[t], fma(-f.y, yr[t], yi[s]));
+      const int ro = s / TPC, jo = s % TPC;
+      const double2 ui = uinv[s];
+      const double qr = fma(yr[ro], ui.x, -yi[ro] * ui.y);
+      const double qi = fma(yr[ro], ui.y, yi[ro] * ui.x);
+      const double br = quad_bcast_f64(qr, jo), bi = quad_bcast_f64(qi, jo);
+      if (j == jo) {
+        yr[ro] = br;
+        yi[ro] = bi;
       }
-      const double2 u = LUs[s][s];
-      const double d = 1.0 / fma(u.x, u.x, u.y * u.y);
-      const double qr = fma(yr[s], u.x, yi[s] * u.y) * d;
-      const double qi = fma(yi[s], u.x, -yr[s] * u.y) * d;
-      yr[s] = qr;
-      yi[s] = qi;
-    }
-    double2* Z2 = reinterpret_cast<double2*>(Zn);
 #pragma unroll
-    for (int s = 0; s < NB; ++s) Z2[s * NOC + cc] = make_double2(yr[s], yi[s]);
+      for (int r = 0; r <= ro; ++r) {
+        if (r == ro && j >= jo) continue;
+        const double2 f = LUs[r * TPC + j][s];
+        yr[r] = fma(-f.x, br, fma(f.y, bi, yr[r]));
+        yi[r] = fma(-f.x, bi, fma(-f.y, br, yi[r]));
+      }
+    }
+    if (cok) {
+      double2* Z2 = reinterpret_cast<double2*>(Zn);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) Z2[(r * TPC + j) * NOC + cc] = make_double2(yr[r], yi[r]);
+    }
   }
 }
 

@@ -25,6 +25,17 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+// The value of lane k (0..3) of each quad of lanes, in every lane of the
+// quad (k a constant once the caller's loops are unrolled).
+__device__ __forceinline__ double quad_bcast_f64(double v, int k) {
+  switch (k) {
+    case 0: return dpp_f64<0x00>(v);   // quad_perm [0,0,0,0]
+    case 1: return dpp_f64<0x55>(v);   // quad_perm [1,1,1,1]
+    case 2: return dpp_f64<0xAA>(v);   // quad_perm [2,2,2,2]
+    default: return dpp_f64<0xFF>(v);  // quad_perm [3,3,3,3]
+  }
+}
+
 // Maximum over the 64 lanes, the same in every lane: within each row of 16
 // lanes by partner exchanges (lane ^ 1, lane ^ 2, the mirrored quad of 8,
 // the mirrored half of 16), then across the four rows by readlane.
