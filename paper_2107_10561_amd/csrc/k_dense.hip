@@ -243,8 +243,10 @@ __global__ void k_gj_gather_rows(const double* __restrict__ A, int64_t sA, int64
   A += blockIdx.z * sA;
   rpiv += blockIdx.z * sV;
   Bbuf += blockIdx.z * sB;
+  // a record outside [0, n) (a missing pivot) gathers zeros; the pivot-record
+  // check then reports the member
   const int r = rpiv[p0 + t];
-  Bbuf[(int64_t)t * n + j] = r >= 0 ? A[(int64_t)r * n + j] : 0.0;
+  Bbuf[(int64_t)t * n + j] = (r >= 0 && r < n) ? A[(int64_t)r * n + j] : 0.0;
 }
 
 // A(i, j) += sum_t (P(i, t) - [i == rpiv[p0+t]]) * Bbuf(t, j) for j outside the
@@ -903,10 +905,10 @@ __global__ void __launch_bounds__(1024) k_gj_tour(double* __restrict__ S, int64_
   // stores) and one acquire per workgroup
   __syncthreads();
   if (tid == 0) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned last = (atomicAdd(counter + z * sK, 1u) == gridDim.x - 1) ? 1u : 0u;
     if (last) {
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       atomicExch(counter + z * sK, 0u);
     }
     s_last = last;
@@ -1354,11 +1356,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int nchild = top ? m : min(TFAN, m - parent * TFAN);
     __syncthreads();
     if (tid == 0) {
-      __threadfence();
+      // release this workgroup's rows and list; the last arrival acquires
+      // its siblings'
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       unsigned* cn = counter + cb + parent;
       const unsigned last = (atomicAdd(cn, 1u) == (unsigned)nchild - 1u) ? 1u : 0u;
       if (last) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         atomicExch(cn, 0u);
       }
       s_last = last;
