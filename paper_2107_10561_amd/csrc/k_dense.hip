@@ -1210,9 +1210,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                      const double* __restrict__ Zc,
                                                      double* __restrict__ Zn, int64_t sZ,
                                                      int* __restrict__ cand, int64_t sC,
-                                                     unsigned* __restrict__ counter, int64_t sK) {
+                                                     unsigned* __restrict__ counter, int64_t sK,
+                                                     const double* __restrict__ A, int64_t sA,
+                                                     double* __restrict__ Bg, int64_t sB,
+                                                     int ngwg) {
   constexpr int NB = 16, RC = 64, NW = 4, NT = 64 * NW, TFAN = NT / NB;
   chain_priority();
+  // the last ngwg workgroups of the slab's last launch (ngwg > 0) gather the
+  // slab's pivot rows of A (NO / ngwg rows each) for the update that follows,
+  // beside the other workgroups' last panel step; rows without a record in
+  // [0, n) gather zeros
+  const int nwg = (int)gridDim.x - ngwg;
+  if ((int)blockIdx.x >= nwg) {
+    const int rows = NO / ngwg, z = blockIdx.z;
+    const int* rp = rpiv + z * sV + j0;
+    const double2* a2 = reinterpret_cast<const double2*>(A + z * sA);
+    double2* b2 = reinterpret_cast<double2*>(Bg + z * sB);
+    const int64_t h = n / 2;
+    for (int t = ((int)blockIdx.x - nwg) * rows, te = t + rows; t < te; ++t) {
+      const int r = rp[t];
+      const bool ok = r >= 0 && r < n;
+      for (int64_t c = threadIdx.x; c < h; c += NT)
+        b2[(int64_t)t * h + c] = ok ? a2[(int64_t)r * h + c] : make_double2(0.0, 0.0);
+    }
+    return;
+  }
   constexpr int NOC = NO / 2;                  // complex columns of the slab
   constexpr int LPR = NOC < 64 ? NOC : 64;     // lanes per row in the panel step
   constexpr int RPP = 64 / LPR;                // rows per wavefront and pass
@@ -1347,7 +1369,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   // those of level l - 1 in cand; counters of a level follow those of the
   // level below.
   static_assert(TFAN * NB == NT, "a merge takes one candidate row per thread");
-  int m = (int)gridDim.x;        // lists at the current level
+  int m = nwg;                   // lists at the current level
   int node = (int)blockIdx.x;    // this workgroup's list there
   int64_t lev = 0, cb = 0;       // first list and first counter of the level
   for (;;) {
@@ -1513,20 +1535,32 @@ static hipError_t gj_tour_cx(hipStream_t s, const GjWork& w, int64_t n, int cnt,
   for (int64_t j0 = 0; j0 < n; j0 += NO, cs ^= 1) {
     k_gj_tour_cx<NO, false><<<dim3(nwg, 1, cnt), 256, 0, s>>>(
         sb[cs], w.sS, n, j0, 0, w.rpiv, w.used, w.sV, nullptr, zb[cz], w.sZ, w.cand, w.sC,
-        w.counter, w.sK);
+        w.counter, w.sK, nullptr, 0, nullptr, 0, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // slabs of 64: the last launch also gathers the slab's pivot rows of A
+    // (one launch fewer per slab), which needs the previous slab's update of
+    // the other columns finished; slabs of 128 gather after it, so that the
+    // last panel step is not held back by that update
+    constexpr bool kFuse = NO == 64;
     for (int q0 = 0; q0 < NO; q0 += NBR, cz ^= 1) {
-      k_gj_tour_cx<NO, true><<<dim3(nwg, 1, cnt), 256, zbytes, s>>>(
+      const bool last = q0 + NBR >= NO;
+      if (kFuse && last && aux && j0 > 0 &&
+          (e = hipStreamWaitEvent(s, aux->done_rest, 0)) != hipSuccess)
+        return e;
+      const int ng = (kFuse && last) ? NO / 4 : 0;
+      k_gj_tour_cx<NO, true><<<dim3(nwg + (unsigned)ng, 1, cnt), 256, zbytes, s>>>(
           sb[cs], w.sS, n, j0, q0, w.rpiv, w.used, w.sV, zb[cz], zb[cz ^ 1], w.sZ, w.cand, w.sC,
-          w.counter, w.sK);
+          w.counter, w.sK, w.A, w.sA, w.B, w.sB, ng);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // the gather reads whole rows of A: the previous slab's update of the
-    // other columns must have finished
-    if (aux && j0 > 0 && (e = hipStreamWaitEvent(s, aux->done_rest, 0)) != hipSuccess) return e;
-    k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
-        w.A, w.sA, n, (int)j0, w.rpiv, w.sV, w.B, w.sB);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!kFuse) {
+      // the gather reads whole rows of A: the previous slab's update of the
+      // other columns must have finished
+      if (aux && j0 > 0 && (e = hipStreamWaitEvent(s, aux->done_rest, 0)) != hipSuccess) return e;
+      k_gj_gather_rows<<<dim3((unsigned)((n + 255) / 256), NO, cnt), 256, 0, s>>>(
+          w.A, w.sA, n, (int)j0, w.rpiv, w.sV, w.B, w.sB);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // 128 x 128 tiles when the order allows (slabs of 128), else 64 x 64
     const bool big = NO % 128 == 0 && n % 128 == 0;
     const int TS = big ? 128 : 64;
