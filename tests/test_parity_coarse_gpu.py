@@ -26,11 +26,14 @@ COARSE = {
     "3d_8x2x2_dg1": (3, (8, 2, 2), 1),
     "2d_32x8_dg2": (2, (32, 8), 2),
 }
+# real order 36004 of the time-decoupled block (2 n_s, n_s = 18002): past
+# 256 tournament workgroups
+LARGE = {"2d_80x20_dg1": (2, (80, 20), 1)}
 
 
 @functools.lru_cache(maxsize=None)
 def coarse_case(name):
-    dim, n, k = COARSE[name]
+    dim, n, k = {**COARSE, **LARGE}[name]
     p = make_problem(dim, n, 1, k, 0.01, 1e-3, 7)
     ol = oracle.prepare_levels(p.levels, p.b)
     J = ol[0].J.tocsc()
@@ -111,6 +114,26 @@ def test_time_decoupled_coarse_inverse_every_schedule(stv, name):
         log(f"[coarse] {name} decoupled {algo} relres {res:.2e} forward {fe:.2e} cond {cond:.1e}")
         assert res <= 1e-11
         assert fe <= 1e-15 * cond * 10
+
+
+@pytest.mark.parametrize("name", list(LARGE))
+def test_time_decoupled_coarse_two_level_merge_tree(stv, name):
+    """Real order 36004 (padded to 36096): 282 tournament workgroups of 128
+    real rows, so the complex tournament's merge tree takes two levels of
+    16-list merges (282 -> 18 -> 2 lists for the root), the only case here
+    past one level.  Complex tournament only (the real schedules' narrow
+    panels would each sweep the 10 GB matrix); the same residual and
+    forward-error bounds against SuperLU."""
+    p, J, lu, cond = coarse_case(name)
+    r = np.random.default_rng(26).standard_normal(J.shape[0])
+    ref = lu.solve(r)
+    log(f"[coarse] {name} decoupled tournament, order {J.shape[0]}")
+    d = solve_decoupled_on_gpu(stv, p, "tournament", r)
+    res = np.linalg.norm(r - J @ d) / np.linalg.norm(r)
+    fe = relerr(d, ref)
+    log(f"[coarse] {name} relres {res:.2e} forward {fe:.2e} cond {cond:.1e}")
+    assert res <= 1e-11
+    assert fe <= 1e-15 * cond * 10
 
 
 @pytest.mark.parametrize("name", ["2d_16x4_dg1", "2d_32x8_dg2"])
