@@ -1281,7 +1281,88 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   };
   unsigned zf;
   int step, mine;
-  if constexpr (UPDATE) {
+  // with a next panel, the update runs in two phases: the next panel's
+  // columns of every row first (all threads), then, while wavefront 0
+  // chooses the workgroup's proposal from them, wavefronts 1..3 update the
+  // other columns
+  const bool phased = UPDATE && qn < NO;
+  if (UPDATE && phased) {
+    Zc += z * sZ;
+    const double2* Z2 = reinterpret_cast<const double2*>(Zc);
+    constexpr int NR = NOC - NB;               // columns outside the next panel
+    constexpr int E1 = RC * NB / NT;           // next-panel entries per thread
+    constexpr int NT2 = NT - 64, G = 4;        // threads of the second phase, loads in flight
+    static_assert(RC * NB % NT == 0, "next-panel entries per thread");
+    double2 o1[E1];
+#pragma unroll
+    for (int i = 0; i < E1; ++i) {
+      const int e = tid + NT * i, dx = e / NB, t = e - dx * NB;
+      const int64_t ic = c0 + dx;
+      o1[i] = ic < nc ? cval(ic, qnc + t) : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < RC * NB; e += NT) {
+      const int dx = e / NB, t = e - dx * NB;
+      const int64_t ic = c0 + dx;
+      Acur[dx][t] = ic < nc ? cval(ic, q0c + t) : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < NB * NOC; e += NT) Zs[e / NOC][e % NOC] = Z2[e];
+    int rp[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) rp[t] = rpiv[j0 + q0 + 2 * t] >> 1;   // -1 stays -1
+    __syncthreads();
+    // entry (row dx, complex column cc) from its old value o: the pivot rows
+    // take their row of Z, the others o - (row's panel entries) Z
+    auto upd = [&](int dx, int64_t ic, int cc, double2 o) {
+      int s = -1;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) s = (rp[t] == ic) ? t : s;
+      double vr = o.x, vi = o.y;
+      if (s >= 0) {
+        const double2 v = Zs[s][cc];
+        vr = v.x;
+        vi = v.y;
+      } else {
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          const double2 a = Acur[dx][t];
+          const double2 zz = Zs[t][cc];
+          vr = fma(-a.x, zz.x, fma(a.y, zz.y, vr));
+          vi = fma(-a.x, zz.y, fma(-a.y, zz.x, vi));
+        }
+      }
+      *reinterpret_cast<double2*>(&S[2 * ic * NO + 2 * cc]) = make_double2(vr, -vi);
+      *reinterpret_cast<double2*>(&S[(2 * ic + 1) * NO + 2 * cc]) = make_double2(vi, vr);
+      return make_double2(vr, vi);
+    };
+#pragma unroll
+    for (int i = 0; i < E1; ++i) {
+      const int e = tid + NT * i, dx = e / NB, t = e - dx * NB;
+      const int64_t ic = c0 + dx;
+      Anx[dx][t] = ic < nc ? upd(dx, ic, qnc + t, o1[i]) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (wv > 0) {
+      for (int e0 = tid - 64; e0 < RC * NR; e0 += NT2 * G) {
+        double2 o2[G];
+        int dxs[G], ccs[G];
+        bool ok[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int e = e0 + NT2 * g;
+          const int dx = e < RC * NR ? e / NR : 0, k = e - dx * NR;
+          const int cc = k < qnc ? k : k + NB;
+          const int64_t ic = c0 + dx;
+          dxs[g] = dx;
+          ccs[g] = cc;
+          ok[g] = e < RC * NR && ic < nc;
+          o2[g] = (ok[g] && !(cc >= q0c && cc < q0c + NB)) ? cval(ic, cc) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (ok[g]) (void)upd(dxs[g], c0 + dxs[g], ccs[g], o2[g]);
+      }
+    }
+  } else if constexpr (UPDATE) {
     Zc += z * sZ;
     const double2* Z2 = reinterpret_cast<const double2*>(Zc);
     const int cl = lane % LPR, rl = lane / LPR;
@@ -1346,7 +1427,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       Anx[dx][t] = ic < nc ? cval(ic, qnc + t) : make_double2(0.0, 0.0);
     }
   }
-  __syncthreads();
+  if (!phased) __syncthreads();
   // the workgroup's proposal: NB rows by partial pivoting on its rows
   if (wv == 0) {
     const int64_t ic = c0 + lane;
